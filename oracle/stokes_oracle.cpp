@@ -1,0 +1,1418 @@
+// FP64 CPU oracle for the divergence-conforming B-spline Stokes solver path.
+//
+// TEST INFRASTRUCTURE ONLY.  Only tests/, the smoke check and the benchmark's CPU
+// baseline may load this library.  It shares no code with the HIP path: it does
+// its own spline evaluation, quadrature, assembly, incomplete Cholesky, PCG and
+// MINRES, written as plainly as possible so that each step can be checked by eye
+// against the paper (Cortes & Coutinho, "Performance Evaluation of Block Diagonal
+// Preconditioners for Divergence-Conforming B-Spline Discretization of Stokes
+// Equations").  Single-threaded, double precision throughout.
+//
+// Section / equation references below are to that paper:
+//   Sec. 2.1        univariate B-splines, Cox-de Boor recursion, open knot vectors
+//   Sec. 2.2        tensor-product (bivariate) B-splines; 3D is the same tensor product
+//   Sec. 3.1        Stokes problem, eq. (stokes_weak): a(w,v) = (2 nu sym grad w, sym grad v),
+//                   b(v,q) = -(div v, q)
+//   Sec. 3.2        RT-type spaces V_h, Q_h; no-penetration constraint V_{0,h}; zero-mean Q_{0,h}
+//   Sec. 4          Nitsche form eta_h (eq. nitsche_lhs), discrete system and its matrices
+//   Sec. 5          MINRES, preconditioned MINRES in the M^{-1} norm (eq. linsys_precond),
+//                   block-diagonal preconditioner (eq. general_precond_M)
+//   Sec. 6.2        C_pen = 5(k'+1), manufactured square-domain solution
+//   Sec. 6.4        zero-mean pressure filtering after the solve; IC(0) factorisation and
+//                   IC(0)-PCG inner solves.
+//
+// Readings where the paper is silent (each is listed in the design notes):
+//   * face length h_F = 1/N (element length normal to the face);
+//   * pressure block M_Q = Diag(Q)/(2 nu)  (scaled mass matrix Q_nu = Q/(2 nu), Sec. 5.1);
+//   * IC(0) in natural (component-major, x-fastest) order; on a non-positive pivot the
+//     factorisation restarts on A + alpha*diag(A), alpha = 1e-3, 1e-2, 1e-1;
+//   * inner PCG stops when ||r||_2 <= rtol ||b||_2 (x0 = 0, test after each update, <= 200 its);
+//   * MINRES stops when |eta_j| <= tol * gamma_1 (relative M^{-1}-norm residual, x0 = 0);
+//   * zero-mean pressure: p <- p - (w.p)/(w.1) with w_k = integral of phi_k.
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+namespace {
+
+const double kPi = 3.14159265358979323846;
+
+// ---------------------------------------------------------------------------
+// Gauss-Legendre rule with n points on [0,1].  Nodes are the roots of the
+// Legendre polynomial P_n found by Newton's method; weights 2/((1-x^2) P_n'(x)^2),
+// then mapped from [-1,1] to [0,1].
+// ---------------------------------------------------------------------------
+void gauss_legendre01(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double t = std::cos(kPi * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = t;  // P_0, P_1
+      for (int k = 1; k < n; ++k) {
+        double p2 = ((2.0 * k + 1.0) * t * p1 - k * p0) / (k + 1.0);
+        p0 = p1;
+        p1 = p2;
+      }
+      // p1 = P_n(t), p0 = P_{n-1}(t)
+      dp = n * (t * p1 - p0) / (t * t - 1.0);
+      double dt = p1 / dp;
+      t -= dt;
+      if (std::fabs(dt) < 1e-16) break;
+    }
+    {
+      double p0 = 1.0, p1 = t;
+      for (int k = 1; k < n; ++k) {
+        double p2 = ((2.0 * k + 1.0) * t * p1 - k * p0) / (k + 1.0);
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (t * p1 - p0) / (t * t - 1.0);
+    }
+    x[i] = 0.5 * (1.0 - t);  // ascending order on [0,1]
+    w[i] = 1.0 / ((1.0 - t * t) * dp * dp);  // = (2/((1-t^2)P'^2)) / 2
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Univariate B-spline space (Sec. 2.1): degree d, N uniform elements, open knot
+// vector with every interior breakpoint of multiplicity one (maximal continuity
+// C^{d-1}), hence n = N + d basis functions.
+// ---------------------------------------------------------------------------
+struct Space1D {
+  int deg = 0;
+  int nel = 0;
+  int nfun = 0;
+  std::vector<double> knot;
+};
+
+Space1D make_space(int deg, int nel) {
+  Space1D s;
+  s.deg = deg;
+  s.nel = nel;
+  s.nfun = nel + deg;
+  for (int i = 0; i <= deg; ++i) s.knot.push_back(0.0);
+  for (int i = 1; i < nel; ++i) s.knot.push_back(double(i) / nel);
+  for (int i = 0; i <= deg; ++i) s.knot.push_back(1.0);
+  return s;
+}
+
+// Cox-de Boor recursion for basis function i of degree d, restricted to the
+// knot span `span` (the polynomial piece living on that span, so it can be
+// evaluated on the closed span, including its end points).  Quotients with a
+// zero-length denominator are taken as zero.
+double cdb_value(const std::vector<double>& t, int i, int d, int span, double x) {
+  if (d == 0) return (i == span) ? 1.0 : 0.0;
+  double a = 0.0, b = 0.0;
+  double den1 = t[i + d] - t[i];
+  double den2 = t[i + d + 1] - t[i + 1];
+  if (den1 > 0.0) a = (x - t[i]) / den1 * cdb_value(t, i, d - 1, span, x);
+  if (den2 > 0.0) b = (t[i + d + 1] - x) / den2 * cdb_value(t, i + 1, d - 1, span, x);
+  return a + b;
+}
+
+// First derivative from the same recursion: d/dx N_{i,d} = d N_{i,d-1}/(t_{i+d}-t_i)
+//                                                         - d N_{i+1,d-1}/(t_{i+d+1}-t_{i+1}).
+double cdb_deriv(const std::vector<double>& t, int i, int d, int span, double x) {
+  if (d == 0) return 0.0;
+  double a = 0.0, b = 0.0;
+  double den1 = t[i + d] - t[i];
+  double den2 = t[i + d + 1] - t[i + 1];
+  if (den1 > 0.0) a = d / den1 * cdb_value(t, i, d - 1, span, x);
+  if (den2 > 0.0) b = d / den2 * cdb_value(t, i + 1, d - 1, span, x);
+  return a - b;
+}
+
+// Values and derivatives of the deg+1 functions that are non-zero on element e,
+// at the parameter points xs (all inside the closed element).
+// out_v[q*(deg+1)+a] is function (e+a) at point q.
+void eval_on_element(const Space1D& s, int e, const std::vector<double>& xs,
+                     std::vector<double>& out_v, std::vector<double>& out_d) {
+  int nloc = s.deg + 1;
+  out_v.assign(xs.size() * nloc, 0.0);
+  out_d.assign(xs.size() * nloc, 0.0);
+  int span = s.deg + e;
+  for (size_t q = 0; q < xs.size(); ++q)
+    for (int a = 0; a < nloc; ++a) {
+      out_v[q * nloc + a] = cdb_value(s.knot, e + a, s.deg, span, xs[q]);
+      out_d[q * nloc + a] = cdb_deriv(s.knot, e + a, s.deg, span, xs[q]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Discrete spaces (Sec. 3.2).  Velocity component c is the tensor product of
+// degree p = k'+1 in direction c and degree k' in the other directions; the two
+// functions of direction c that are non-zero on the boundary (first and last)
+// are removed (no penetration, u.n = 0).  Pressure is degree k' in every
+// direction with no constraint (the zero mean is imposed after the solve).
+// Numbering: velocity component-major, x fastest; pressure after velocity.
+// ---------------------------------------------------------------------------
+struct Problem {
+  int N = 0, kp = 0, dim = 0;
+  double nu = 1.0, cpen = 0.0, h = 0.0;
+  int pdeg = 0;                       // velocity degree p = k'+1
+  Space1D sp_hi, sp_lo;               // 1D spaces of degree p and k'
+  int vcount[3][3];                   // vcount[c][dir]: retained 1D functions
+  int64_t voff[4];                    // component offsets into the velocity numbering
+  int64_t nu_dofs = 0, np_dofs = 0;
+
+  // Assembled matrices (CSR, sorted columns).  A: n_u x n_u; B: n_p x n_u; Q: n_p x n_p.
+  std::vector<int64_t> A_ptr, B_ptr, Q_ptr;
+  std::vector<int32_t> A_col, B_col, Q_col;
+  std::vector<double> A_val, B_val, Q_val;
+  std::vector<double> diagQ, wvec;    // diag(Q) and w = Q 1 (integral of each phi_k)
+
+  // IC(0) factor of A: lower triangle of A's pattern, diagonal stored last in each row.
+  bool have_L = false;
+  int ic_shift_steps = 0;
+  double ic_alpha = 0.0;
+  std::vector<int64_t> L_ptr;
+  std::vector<int32_t> L_col;
+  std::vector<double> L_val;
+
+  // Dense Cholesky factors for the "ideal" preconditioner blocks (small meshes only).
+  bool have_dense_A = false, have_dense_Q = false;
+  std::vector<double> cholA, cholQ;
+};
+
+// 1D function index range on element e for a space of degree d: [e, e+d].
+// Velocity: translate a component-c multi-index of 1D functions to the global number.
+int64_t vel_index(const Problem& P, int c, const int* i1d) {
+  int64_t g = 0, stride = 1;
+  for (int dir = 0; dir < P.dim; ++dir) {
+    int i = i1d[dir];
+    if (dir == c) {
+      if (i == 0 || i == P.sp_hi.nfun - 1) return -1;  // removed (normal component on boundary)
+      i -= 1;
+    }
+    g += i * stride;
+    stride *= P.vcount[c][dir];
+  }
+  return P.voff[c] + g;
+}
+
+int64_t pre_index(const Problem& P, const int* i1d) {
+  int64_t g = 0, stride = 1;
+  for (int dir = 0; dir < P.dim; ++dir) {
+    g += i1d[dir] * stride;
+    stride *= P.sp_lo.nfun;
+  }
+  return g;
+}
+
+// Decode a velocity global index into (component, 1D indices in the full 1D spaces).
+void vel_decode(const Problem& P, int64_t g, int* c_out, int* i1d) {
+  int c = 0;
+  while (c + 1 < P.dim && g >= P.voff[c + 1]) ++c;
+  int64_t r = g - P.voff[c];
+  for (int dir = 0; dir < P.dim; ++dir) {
+    int i = int(r % P.vcount[c][dir]);
+    r /= P.vcount[c][dir];
+    if (dir == c) i += 1;
+    i1d[dir] = i;
+  }
+  *c_out = c;
+}
+
+void pre_decode(const Problem& P, int64_t g, int* i1d) {
+  for (int dir = 0; dir < P.dim; ++dir) {
+    i1d[dir] = int(g % P.sp_lo.nfun);
+    g /= P.sp_lo.nfun;
+  }
+}
+
+int deg_of(const Problem& P, int c, int dir) { return (dir == c) ? P.pdeg : P.kp; }
+
+// ---------------------------------------------------------------------------
+// Sparsity pattern: (i,j) is stored when the supports of the two basis functions
+// share at least one element.  Row-wise: the union of the functions living on
+// the elements of supp(i).
+// ---------------------------------------------------------------------------
+struct ElemFun {
+  std::vector<int64_t> vel;  // global velocity indices on the element (-1 entries skipped)
+  std::vector<int64_t> pre;
+};
+
+void element_functions(const Problem& P, const int* e, ElemFun& out) {
+  out.vel.clear();
+  out.pre.clear();
+  for (int c = 0; c < P.dim; ++c) {
+    int n[3] = {1, 1, 1};
+    for (int dir = 0; dir < P.dim; ++dir) n[dir] = deg_of(P, c, dir) + 1;
+    for (int a2 = 0; a2 < n[2]; ++a2)
+      for (int a1 = 0; a1 < n[1]; ++a1)
+        for (int a0 = 0; a0 < n[0]; ++a0) {
+          int a[3] = {a0, a1, a2};
+          int i1d[3] = {0, 0, 0};
+          for (int dir = 0; dir < P.dim; ++dir) i1d[dir] = e[dir] + a[dir];
+          int64_t g = vel_index(P, c, i1d);
+          if (g >= 0) out.vel.push_back(g);
+        }
+  }
+  int m = P.kp + 1;
+  int n2 = (P.dim == 3) ? m : 1;
+  for (int a2 = 0; a2 < n2; ++a2)
+    for (int a1 = 0; a1 < m; ++a1)
+      for (int a0 = 0; a0 < m; ++a0) {
+        int a[3] = {a0, a1, a2};
+        int i1d[3] = {0, 0, 0};
+        for (int dir = 0; dir < P.dim; ++dir) i1d[dir] = e[dir] + a[dir];
+        out.pre.push_back(pre_index(P, i1d));
+      }
+}
+
+// Elements in the support of 1D function i of degree d: [max(0,i-d), min(N-1,i)].
+void support_range(const Problem& P, int i, int d, int* lo, int* hi) {
+  *lo = std::max(0, i - d);
+  *hi = std::min(P.N - 1, i);
+}
+
+void build_row(const Problem& P, const int* lo, const int* hi, bool want_vel, bool want_pre,
+               std::vector<int32_t>& vcols, std::vector<int32_t>& pcols) {
+  vcols.clear();
+  pcols.clear();
+  ElemFun ef;
+  int e[3] = {0, 0, 0};
+  int lo2 = (P.dim == 3) ? lo[2] : 0, hi2 = (P.dim == 3) ? hi[2] : 0;
+  for (e[2] = lo2; e[2] <= hi2; ++e[2])
+    for (e[1] = lo[1]; e[1] <= hi[1]; ++e[1])
+      for (e[0] = lo[0]; e[0] <= hi[0]; ++e[0]) {
+        element_functions(P, e, ef);
+        if (want_vel)
+          for (int64_t g : ef.vel) vcols.push_back(int32_t(g));
+        if (want_pre)
+          for (int64_t g : ef.pre) pcols.push_back(int32_t(g));
+      }
+  std::sort(vcols.begin(), vcols.end());
+  vcols.erase(std::unique(vcols.begin(), vcols.end()), vcols.end());
+  std::sort(pcols.begin(), pcols.end());
+  pcols.erase(std::unique(pcols.begin(), pcols.end()), pcols.end());
+}
+
+void build_patterns(Problem& P) {
+  std::vector<int32_t> vc, pc;
+  P.A_ptr.assign(1, 0);
+  P.A_col.clear();
+  for (int64_t g = 0; g < P.nu_dofs; ++g) {
+    int c, i1d[3] = {0, 0, 0};
+    vel_decode(P, g, &c, i1d);
+    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int dir = 0; dir < P.dim; ++dir) support_range(P, i1d[dir], deg_of(P, c, dir), &lo[dir], &hi[dir]);
+    build_row(P, lo, hi, true, false, vc, pc);
+    P.A_col.insert(P.A_col.end(), vc.begin(), vc.end());
+    P.A_ptr.push_back(int64_t(P.A_col.size()));
+  }
+  P.B_ptr.assign(1, 0);
+  P.Q_ptr.assign(1, 0);
+  P.B_col.clear();
+  P.Q_col.clear();
+  for (int64_t g = 0; g < P.np_dofs; ++g) {
+    int i1d[3] = {0, 0, 0};
+    pre_decode(P, g, i1d);
+    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int dir = 0; dir < P.dim; ++dir) support_range(P, i1d[dir], P.kp, &lo[dir], &hi[dir]);
+    build_row(P, lo, hi, true, true, vc, pc);
+    P.B_col.insert(P.B_col.end(), vc.begin(), vc.end());
+    P.B_ptr.push_back(int64_t(P.B_col.size()));
+    P.Q_col.insert(P.Q_col.end(), pc.begin(), pc.end());
+    P.Q_ptr.push_back(int64_t(P.Q_col.size()));
+  }
+  P.A_val.assign(P.A_col.size(), 0.0);
+  P.B_val.assign(P.B_col.size(), 0.0);
+  P.Q_val.assign(P.Q_col.size(), 0.0);
+}
+
+double& csr_at(std::vector<int64_t>& ptr, std::vector<int32_t>& col, std::vector<double>& val,
+               int64_t i, int64_t j) {
+  auto b = col.begin() + ptr[i], e = col.begin() + ptr[i + 1];
+  auto it = std::lower_bound(b, e, int32_t(j));
+  return val[it - col.begin()];  // the pattern always contains (i,j) for supported pairs
+}
+
+// ---------------------------------------------------------------------------
+// Per-point evaluation of a velocity basis function: vector value Phi (component c
+// times the scalar tensor-product spline B) and its full gradient
+// G[a][b] = d Phi_a / d x_b = delta_{a c} dB/dx_b.
+// ---------------------------------------------------------------------------
+struct VelEval {
+  int64_t g;
+  int c;
+  double val[3];
+  double grad[3][3];
+};
+
+struct PreEval {
+  int64_t g;
+  double val;
+};
+
+// Tables of the 1D functions of one element in each direction, at a set of points.
+struct Tab1D {
+  std::vector<double> v, d;  // [q*(deg+1)+a]
+  int nloc;
+};
+
+void tensor_eval_velocity(const Problem& P, const int* e, const Tab1D tabs[3][2], const int* qidx,
+                          std::vector<VelEval>& out) {
+  // tabs[dir][0] = degree-k' table, tabs[dir][1] = degree-p table, for element e[dir].
+  out.clear();
+  for (int c = 0; c < P.dim; ++c) {
+    int n[3] = {1, 1, 1};
+    for (int dir = 0; dir < P.dim; ++dir) n[dir] = deg_of(P, c, dir) + 1;
+    for (int a2 = 0; a2 < n[2]; ++a2)
+      for (int a1 = 0; a1 < n[1]; ++a1)
+        for (int a0 = 0; a0 < n[0]; ++a0) {
+          int a[3] = {a0, a1, a2};
+          int i1d[3] = {0, 0, 0};
+          for (int dir = 0; dir < P.dim; ++dir) i1d[dir] = e[dir] + a[dir];
+          int64_t g = vel_index(P, c, i1d);
+          if (g < 0) continue;
+          double fv[3], fd[3];
+          for (int dir = 0; dir < P.dim; ++dir) {
+            const Tab1D& t = tabs[dir][dir == c ? 1 : 0];
+            fv[dir] = t.v[qidx[dir] * t.nloc + a[dir]];
+            fd[dir] = t.d[qidx[dir] * t.nloc + a[dir]];
+          }
+          double B = 1.0;
+          for (int dir = 0; dir < P.dim; ++dir) B *= fv[dir];
+          double dB[3] = {0, 0, 0};
+          for (int k = 0; k < P.dim; ++k) {
+            double prod = 1.0;
+            for (int dir = 0; dir < P.dim; ++dir) prod *= (dir == k) ? fd[dir] : fv[dir];
+            dB[k] = prod;
+          }
+          VelEval ve;
+          ve.g = g;
+          ve.c = c;
+          for (int r = 0; r < 3; ++r) {
+            ve.val[r] = (r == c) ? B : 0.0;
+            for (int s = 0; s < 3; ++s) ve.grad[r][s] = (r == c && s < P.dim) ? dB[s] : 0.0;
+          }
+          out.push_back(ve);
+        }
+  }
+}
+
+void tensor_eval_pressure(const Problem& P, const int* e, const Tab1D tabs[3][2], const int* qidx,
+                          std::vector<PreEval>& out) {
+  out.clear();
+  int m = P.kp + 1;
+  int n2 = (P.dim == 3) ? m : 1;
+  for (int a2 = 0; a2 < n2; ++a2)
+    for (int a1 = 0; a1 < m; ++a1)
+      for (int a0 = 0; a0 < m; ++a0) {
+        int a[3] = {a0, a1, a2};
+        int i1d[3] = {0, 0, 0};
+        double v = 1.0;
+        for (int dir = 0; dir < P.dim; ++dir) {
+          i1d[dir] = e[dir] + a[dir];
+          const Tab1D& t = tabs[dir][0];
+          v *= t.v[qidx[dir] * t.nloc + a[dir]];
+        }
+        out.push_back({pre_index(P, i1d), v});
+      }
+}
+
+// sym grad: eps = (G + G^T)/2
+void sym_grad(const VelEval& f, double eps[3][3]) {
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) eps[a][b] = 0.5 * (f.grad[a][b] + f.grad[b][a]);
+}
+
+// ---------------------------------------------------------------------------
+// Assembly (Sec. 4): for every element, Gauss quadrature with k'+2 points per
+// direction (exact for these polynomial integrands on the identity map):
+//   A_ij  += 2 nu (sym grad Phi_j : sym grad Phi_i)
+//   B_kj  += -(div Phi_j) phi_k
+//   Q_kl  += phi_k phi_l
+// and for every boundary face F with outward normal n (Nitsche, eq. nitsche_lhs,
+// a_h = a - eta_h):
+//   A_ij  += -2 nu [ (sym grad Phi_i n).Phi_j + (sym grad Phi_j n).Phi_i ]
+//            + 2 nu (C_pen/h_F) Phi_i.Phi_j
+// ---------------------------------------------------------------------------
+void build_tabs_for_element(const Problem& P, const int* e, const std::vector<double>& xq01,
+                            Tab1D tabs[3][2]) {
+  for (int dir = 0; dir < P.dim; ++dir) {
+    std::vector<double> xs(xq01.size());
+    for (size_t q = 0; q < xq01.size(); ++q) xs[q] = (e[dir] + xq01[q]) * P.h;
+    eval_on_element(P.sp_lo, e[dir], xs, tabs[dir][0].v, tabs[dir][0].d);
+    tabs[dir][0].nloc = P.sp_lo.deg + 1;
+    eval_on_element(P.sp_hi, e[dir], xs, tabs[dir][1].v, tabs[dir][1].d);
+    tabs[dir][1].nloc = P.sp_hi.deg + 1;
+  }
+}
+
+void assemble(Problem& P) {
+  int nq = P.kp + 2;
+  std::vector<double> xq, wq;
+  gauss_legendre01(nq, xq, wq);
+  P.diagQ.assign(P.np_dofs, 0.0);
+  P.wvec.assign(P.np_dofs, 0.0);
+  double vol = 1.0;
+  for (int d = 0; d < P.dim; ++d) vol *= P.h;  // element measure
+
+  int nE[3] = {P.N, P.N, P.dim == 3 ? P.N : 1};
+  Tab1D tabs[3][2];
+  std::vector<VelEval> ve;
+  std::vector<PreEval> pe;
+  int e[3] = {0, 0, 0};
+  for (e[2] = 0; e[2] < nE[2]; ++e[2])
+    for (e[1] = 0; e[1] < nE[1]; ++e[1])
+      for (e[0] = 0; e[0] < nE[0]; ++e[0]) {
+        build_tabs_for_element(P, e, xq, tabs);
+        int nq2 = (P.dim == 3) ? nq : 1;
+        int q[3] = {0, 0, 0};
+        for (q[2] = 0; q[2] < nq2; ++q[2])
+          for (q[1] = 0; q[1] < nq; ++q[1])
+            for (q[0] = 0; q[0] < nq; ++q[0]) {
+              double wt = vol;
+              for (int dir = 0; dir < P.dim; ++dir) wt *= wq[q[dir]];
+              tensor_eval_velocity(P, e, tabs, q, ve);
+              tensor_eval_pressure(P, e, tabs, q, pe);
+              std::vector<std::array<std::array<double, 3>, 3>> eps(ve.size());
+              for (size_t i = 0; i < ve.size(); ++i) {
+                double t[3][3];
+                sym_grad(ve[i], t);
+                for (int a = 0; a < 3; ++a)
+                  for (int b = 0; b < 3; ++b) eps[i][a][b] = t[a][b];
+              }
+              for (size_t i = 0; i < ve.size(); ++i)
+                for (size_t j = 0; j < ve.size(); ++j) {
+                  double s = 0.0;
+                  for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) s += eps[j][a][b] * eps[i][a][b];
+                  csr_at(P.A_ptr, P.A_col, P.A_val, ve[i].g, ve[j].g) += wt * 2.0 * P.nu * s;
+                }
+              for (size_t k = 0; k < pe.size(); ++k) {
+                for (size_t j = 0; j < ve.size(); ++j) {
+                  double div = 0.0;
+                  for (int a = 0; a < P.dim; ++a) div += ve[j].grad[a][a];
+                  csr_at(P.B_ptr, P.B_col, P.B_val, pe[k].g, ve[j].g) += -wt * div * pe[k].val;
+                }
+                for (size_t l = 0; l < pe.size(); ++l)
+                  csr_at(P.Q_ptr, P.Q_col, P.Q_val, pe[k].g, pe[l].g) += wt * pe[k].val * pe[l].val;
+                P.wvec[pe[k].g] += wt * pe[k].val;
+              }
+            }
+
+        // Boundary faces of this element.
+        for (int fdir = 0; fdir < P.dim; ++fdir)
+          for (int side = 0; side < 2; ++side) {
+            if (side == 0 && e[fdir] != 0) continue;
+            if (side == 1 && e[fdir] != P.N - 1) continue;
+            double nrm[3] = {0, 0, 0};
+            nrm[fdir] = side == 0 ? -1.0 : 1.0;
+            // Face points: tensor Gauss rule in the tangential directions, fixed coordinate
+            // 0 or 1 in direction fdir.
+            Tab1D ftabs[3][2];
+            for (int dir = 0; dir < P.dim; ++dir) {
+              std::vector<double> xs;
+              if (dir == fdir) {
+                xs.push_back(side == 0 ? 0.0 : 1.0);
+              } else {
+                for (int qq = 0; qq < nq; ++qq) xs.push_back((e[dir] + xq[qq]) * P.h);
+              }
+              eval_on_element(P.sp_lo, e[dir], xs, ftabs[dir][0].v, ftabs[dir][0].d);
+              ftabs[dir][0].nloc = P.sp_lo.deg + 1;
+              eval_on_element(P.sp_hi, e[dir], xs, ftabs[dir][1].v, ftabs[dir][1].d);
+              ftabs[dir][1].nloc = P.sp_hi.deg + 1;
+            }
+            double farea = 1.0;
+            for (int dir = 0; dir < P.dim; ++dir)
+              if (dir != fdir) farea *= P.h;
+            double hF = P.h;
+            int nqd[3] = {1, 1, 1};
+            for (int dir = 0; dir < P.dim; ++dir) nqd[dir] = (dir == fdir) ? 1 : nq;
+            int qf[3] = {0, 0, 0};
+            for (qf[2] = 0; qf[2] < nqd[2]; ++qf[2])
+              for (qf[1] = 0; qf[1] < nqd[1]; ++qf[1])
+                for (qf[0] = 0; qf[0] < nqd[0]; ++qf[0]) {
+                  double wt = farea;
+                  for (int dir = 0; dir < P.dim; ++dir)
+                    if (dir != fdir) wt *= wq[qf[dir]];
+                  tensor_eval_velocity(P, e, ftabs, qf, ve);
+                  std::vector<std::array<double, 3>> tr(ve.size());  // (sym grad Phi) n
+                  for (size_t i = 0; i < ve.size(); ++i) {
+                    double t[3][3];
+                    sym_grad(ve[i], t);
+                    for (int a = 0; a < 3; ++a) {
+                      double s = 0.0;
+                      for (int b = 0; b < 3; ++b) s += t[a][b] * nrm[b];
+                      tr[i][a] = s;
+                    }
+                  }
+                  for (size_t i = 0; i < ve.size(); ++i)
+                    for (size_t j = 0; j < ve.size(); ++j) {
+                      double ti_vj = 0.0, tj_vi = 0.0, vi_vj = 0.0;
+                      for (int a = 0; a < 3; ++a) {
+                        ti_vj += tr[i][a] * ve[j].val[a];
+                        tj_vi += tr[j][a] * ve[i].val[a];
+                        vi_vj += ve[i].val[a] * ve[j].val[a];
+                      }
+                      double contrib = -2.0 * P.nu * (ti_vj + tj_vi) + 2.0 * P.nu * (P.cpen / hF) * vi_vj;
+                      csr_at(P.A_ptr, P.A_col, P.A_val, ve[i].g, ve[j].g) += wt * contrib;
+                    }
+                }
+          }
+      }
+  for (int64_t k = 0; k < P.np_dofs; ++k)
+    P.diagQ[k] = csr_at(P.Q_ptr, P.Q_col, P.Q_val, k, k);
+}
+
+// ---------------------------------------------------------------------------
+// Forcing functions.  Problem 1 (default): u = curl of psi with
+// psi = x^2(1-x)^2 y^2(1-y)^2 (2D: u = (psi_y, -psi_x)), or u = curl(g,g,g) with
+// g = phi(x)phi(y)phi(z), phi(t) = t^2(1-t)^2 (3D); p = prod cos(pi x_d); and
+// f = -div(2 nu sym grad u) + grad p = -nu Lap u + grad p (u is divergence free).
+// Problem 2: the paper's square-domain solution (Sec. 6.2) with the sign of the
+// second velocity component chosen so that the field is divergence free.
+// Problem 3: a pure gradient f = grad(phi), phi = sin(2 pi x) cos(pi y) [cos(pi z)].
+// Optional sinusoid modes are added: f_d += a_{d,m} sin(pi k_m . x + ph_{d,m}).
+// ---------------------------------------------------------------------------
+struct Phi1 {  // phi(t) = t^2 (1-t)^2 and derivatives
+  static double f0(double t) { return t * t * (1 - t) * (1 - t); }
+  static double f1(double t) { return 2 * t - 6 * t * t + 4 * t * t * t; }
+  static double f2(double t) { return 2 - 12 * t + 12 * t * t; }
+  static double f3(double t) { return -12 + 24 * t; }
+};
+
+// Exact fields for error norms: velocity, velocity gradient, pressure.
+void exact_solution(int problem, int dim, const double* x, double* u, double g[3][3], double* p) {
+  for (int a = 0; a < 3; ++a) {
+    u[a] = 0;
+    for (int b = 0; b < 3; ++b) g[a][b] = 0;
+  }
+  *p = 0;
+  if (problem == 1 && dim == 2) {
+    double X0 = Phi1::f0(x[0]), X1 = Phi1::f1(x[0]), X2 = Phi1::f2(x[0]);
+    double Y0 = Phi1::f0(x[1]), Y1 = Phi1::f1(x[1]), Y2 = Phi1::f2(x[1]);
+    u[0] = X0 * Y1;
+    u[1] = -X1 * Y0;
+    g[0][0] = X1 * Y1;
+    g[0][1] = X0 * Y2;
+    g[1][0] = -X2 * Y0;
+    g[1][1] = -X1 * Y1;
+    *p = std::cos(kPi * x[0]) * std::cos(kPi * x[1]);
+  } else if (problem == 1 && dim == 3) {
+    double F0[3], F1[3], F2[3];
+    for (int d = 0; d < 3; ++d) {
+      F0[d] = Phi1::f0(x[d]);
+      F1[d] = Phi1::f1(x[d]);
+      F2[d] = Phi1::f2(x[d]);
+    }
+    // grad g and Hessian of g = F0[0] F0[1] F0[2]
+    double dg[3], H[3][3];
+    for (int a = 0; a < 3; ++a) {
+      double v = 1;
+      for (int d = 0; d < 3; ++d) v *= (d == a) ? F1[d] : F0[d];
+      dg[a] = v;
+      for (int b = 0; b < 3; ++b) {
+        double w = 1;
+        for (int d = 0; d < 3; ++d) {
+          int order = (d == a) + (d == b);
+          w *= order == 0 ? F0[d] : (order == 1 ? F1[d] : F2[d]);
+        }
+        H[a][b] = w;
+      }
+    }
+    // u = curl(g,g,g) = (g_y - g_z, g_z - g_x, g_x - g_y)
+    u[0] = dg[1] - dg[2];
+    u[1] = dg[2] - dg[0];
+    u[2] = dg[0] - dg[1];
+    for (int b = 0; b < 3; ++b) {
+      g[0][b] = H[1][b] - H[2][b];
+      g[1][b] = H[2][b] - H[0][b];
+      g[2][b] = H[0][b] - H[1][b];
+    }
+    *p = std::cos(kPi * x[0]) * std::cos(kPi * x[1]) * std::cos(kPi * x[2]);
+  } else if (problem == 2) {
+    // psi = X(x) Y(y), X = e^x x^2 (x-1)^2, Y = y^2 (y-1)^2; u = (psi_y, -psi_x).
+    double ex = std::exp(x[0]), xx = x[0], y = x[1];
+    double P0 = xx * xx * (xx - 1) * (xx - 1);
+    double P1 = 4 * xx * xx * xx - 6 * xx * xx + 2 * xx;
+    double P2 = 12 * xx * xx - 12 * xx + 2;
+    double X0 = ex * P0, X1 = ex * (P0 + P1), X2 = ex * (P0 + 2 * P1 + P2);
+    double Y0 = Phi1::f0(y), Y1 = Phi1::f1(y), Y2 = Phi1::f2(y);
+    u[0] = X0 * Y1;
+    u[1] = -X1 * Y0;
+    g[0][0] = X1 * Y1;
+    g[0][1] = X0 * Y2;
+    g[1][0] = -X2 * Y0;
+    g[1][1] = -X1 * Y1;
+    double q = y * y - y;
+    double G = 456 + xx * xx * (228 - 5 * q) + 2 * xx * (-228 + q) + 2 * xx * xx * xx * (-36 + q) +
+               xx * xx * xx * xx * (12 + q);
+    *p = -424 + 156 * std::exp(1.0) + q * (-456 + ex * G);
+  } else if (problem == 3) {
+    // u = 0, p = phi (up to its mean)
+    double v = std::sin(2 * kPi * x[0]) * std::cos(kPi * x[1]);
+    if (dim == 3) v *= std::cos(kPi * x[2]);
+    *p = v;
+  }
+}
+
+void forcing(int problem, int dim, double nu, const double* x, double* f) {
+  for (int a = 0; a < 3; ++a) f[a] = 0;
+  if (problem == 1 && dim == 2) {
+    double X0 = Phi1::f0(x[0]), X1 = Phi1::f1(x[0]), X2 = Phi1::f2(x[0]), X3 = Phi1::f3(x[0]);
+    double Y0 = Phi1::f0(x[1]), Y1 = Phi1::f1(x[1]), Y2 = Phi1::f2(x[1]), Y3 = Phi1::f3(x[1]);
+    // Lap u1 = X2 Y1 + X0 Y3 ; Lap u2 = -(X3 Y0 + X1 Y2)
+    double lap0 = X2 * Y1 + X0 * Y3;
+    double lap1 = -(X3 * Y0 + X1 * Y2);
+    double px = -kPi * std::sin(kPi * x[0]) * std::cos(kPi * x[1]);
+    double py = -kPi * std::cos(kPi * x[0]) * std::sin(kPi * x[1]);
+    f[0] = -nu * lap0 + px;
+    f[1] = -nu * lap1 + py;
+  } else if (problem == 1 && dim == 3) {
+    double F[4][3];
+    for (int d = 0; d < 3; ++d) {
+      F[0][d] = Phi1::f0(x[d]);
+      F[1][d] = Phi1::f1(x[d]);
+      F[2][d] = Phi1::f2(x[d]);
+      F[3][d] = Phi1::f3(x[d]);
+    }
+    // Lap of dg/dx_a = sum_b d^3 g / (dx_a dx_b dx_b)
+    double lapdg[3];
+    for (int a = 0; a < 3; ++a) {
+      double s = 0;
+      for (int b = 0; b < 3; ++b) {
+        double w = 1;
+        for (int d = 0; d < 3; ++d) {
+          int order = (d == a) + 2 * (d == b);
+          w *= F[order][d];
+        }
+        s += w;
+      }
+      lapdg[a] = s;
+    }
+    double lap[3] = {lapdg[1] - lapdg[2], lapdg[2] - lapdg[0], lapdg[0] - lapdg[1]};
+    double c0 = std::cos(kPi * x[0]), c1 = std::cos(kPi * x[1]), c2 = std::cos(kPi * x[2]);
+    double s0 = std::sin(kPi * x[0]), s1 = std::sin(kPi * x[1]), s2 = std::sin(kPi * x[2]);
+    double gp[3] = {-kPi * s0 * c1 * c2, -kPi * c0 * s1 * c2, -kPi * c0 * c1 * s2};
+    for (int a = 0; a < 3; ++a) f[a] = -nu * lap[a] + gp[a];
+  } else if (problem == 2) {
+    double ex = std::exp(x[0]), xx = x[0], y = x[1];
+    double P0 = xx * xx * (xx - 1) * (xx - 1);
+    double P1 = 4 * xx * xx * xx - 6 * xx * xx + 2 * xx;
+    double P2 = 12 * xx * xx - 12 * xx + 2;
+    double P3 = 24 * xx - 12;
+    double X0 = ex * P0, X1 = ex * (P0 + P1), X2 = ex * (P0 + 2 * P1 + P2),
+           X3 = ex * (P0 + 3 * P1 + 3 * P2 + P3);
+    double Y0 = Phi1::f0(y), Y1 = Phi1::f1(y), Y2 = Phi1::f2(y), Y3 = Phi1::f3(y);
+    double lap0 = X2 * Y1 + X0 * Y3;
+    double lap1 = -(X3 * Y0 + X1 * Y2);
+    double q = y * y - y, dq = 2 * y - 1;
+    double G = 456 + xx * xx * (228 - 5 * q) + 2 * xx * (-228 + q) + 2 * xx * xx * xx * (-36 + q) +
+               xx * xx * xx * xx * (12 + q);
+    double Gx = 2 * xx * (228 - 5 * q) + 2 * (-228 + q) + 6 * xx * xx * (-36 + q) + 4 * xx * xx * xx * (12 + q);
+    double Gq = -5 * xx * xx + 2 * xx + 2 * xx * xx * xx + xx * xx * xx * xx;
+    double px = q * ex * (G + Gx);
+    double py = dq * (-456 + ex * G) + q * ex * Gq * dq;
+    f[0] = -nu * lap0 + px;
+    f[1] = -nu * lap1 + py;
+  } else if (problem == 3) {
+    double a = std::sin(2 * kPi * x[0]), da = 2 * kPi * std::cos(2 * kPi * x[0]);
+    double b = std::cos(kPi * x[1]), db = -kPi * std::sin(kPi * x[1]);
+    double c = 1, dc = 0;
+    if (dim == 3) {
+      c = std::cos(kPi * x[2]);
+      dc = -kPi * std::sin(kPi * x[2]);
+    }
+    f[0] = da * b * c;
+    f[1] = a * db * c;
+    if (dim == 3) f[2] = a * b * dc;
+  }
+}
+
+// Load vector [f]_i = integral of f . Phi_i with k'+4 Gauss points per direction.
+void load_vector(const Problem& P, int problem, int nmodes, const double* amp, const int32_t* wave,
+                 const double* phase, double* fout) {
+  std::fill(fout, fout + P.nu_dofs, 0.0);
+  int nq = P.kp + 4;
+  std::vector<double> xq, wq;
+  gauss_legendre01(nq, xq, wq);
+  double vol = 1.0;
+  for (int d = 0; d < P.dim; ++d) vol *= P.h;
+  int nE[3] = {P.N, P.N, P.dim == 3 ? P.N : 1};
+  Tab1D tabs[3][2];
+  std::vector<VelEval> ve;
+  int e[3] = {0, 0, 0};
+  for (e[2] = 0; e[2] < nE[2]; ++e[2])
+    for (e[1] = 0; e[1] < nE[1]; ++e[1])
+      for (e[0] = 0; e[0] < nE[0]; ++e[0]) {
+        build_tabs_for_element(P, e, xq, tabs);
+        int nq2 = (P.dim == 3) ? nq : 1;
+        int q[3] = {0, 0, 0};
+        for (q[2] = 0; q[2] < nq2; ++q[2])
+          for (q[1] = 0; q[1] < nq; ++q[1])
+            for (q[0] = 0; q[0] < nq; ++q[0]) {
+              double wt = vol, x[3] = {0, 0, 0};
+              for (int dir = 0; dir < P.dim; ++dir) {
+                wt *= wq[q[dir]];
+                x[dir] = (e[dir] + xq[q[dir]]) * P.h;
+              }
+              double f[3];
+              forcing(problem, P.dim, P.nu, x, f);
+              for (int d = 0; d < P.dim; ++d)
+                for (int m = 0; m < nmodes; ++m) {
+                  double arg = phase[d * nmodes + m];
+                  for (int k = 0; k < P.dim; ++k) arg += kPi * wave[m * P.dim + k] * x[k];
+                  f[d] += amp[d * nmodes + m] * std::sin(arg);
+                }
+              tensor_eval_velocity(P, e, tabs, q, ve);
+              for (const VelEval& v : ve) {
+                double s = 0;
+                for (int a = 0; a < P.dim; ++a) s += f[a] * v.val[a];
+                fout[v.g] += wt * s;
+              }
+            }
+      }
+}
+
+// ---------------------------------------------------------------------------
+// Sparse kernels on the assembled matrices (plain loops).
+// ---------------------------------------------------------------------------
+// Saddle-point product [A B^T; B 0] [u; p].
+void saddle_matvec(const Problem& P, const double* x, double* y) {
+  const double* u = x;
+  const double* p = x + P.nu_dofs;
+  double* yu = y;
+  double* yp = y + P.nu_dofs;
+  for (int64_t i = 0; i < P.nu_dofs; ++i) {
+    double s = 0;
+    for (int64_t k = P.A_ptr[i]; k < P.A_ptr[i + 1]; ++k) s += P.A_val[k] * u[P.A_col[k]];
+    yu[i] = s;
+  }
+  for (int64_t k = 0; k < P.np_dofs; ++k) {
+    double s = 0;
+    for (int64_t m = P.B_ptr[k]; m < P.B_ptr[k + 1]; ++m) {
+      s += P.B_val[m] * u[P.B_col[m]];
+      yu[P.B_col[m]] += P.B_val[m] * p[k];  // B^T p
+    }
+    yp[k] = s;
+  }
+}
+
+void A_matvec(const Problem& P, const double* x, double* y) {
+  for (int64_t i = 0; i < P.nu_dofs; ++i) {
+    double s = 0;
+    for (int64_t k = P.A_ptr[i]; k < P.A_ptr[i + 1]; ++k) s += P.A_val[k] * x[P.A_col[k]];
+    y[i] = s;
+  }
+}
+
+double dot(const double* a, const double* b, int64_t n) {
+  double s = 0;
+  for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// IC(0) (Sec. 6.4): L L^T ~ A with pattern(L) = pattern(tril A), computed row by row
+// in natural order:
+//   L_ij = (A_ij - sum_{k<j} L_ik L_jk) / L_jj      for j < i in the pattern
+//   L_ii = sqrt(A_ii - sum_{k<i} L_ik^2)
+// where the sums run over k present in both rows.  A non-positive radicand restarts
+// the factorisation on A + alpha diag(A) with alpha = 1e-3, 1e-2, 1e-1.
+// ---------------------------------------------------------------------------
+bool ic0_try(Problem& P, double alpha) {
+  int64_t n = P.nu_dofs;
+  P.L_ptr.assign(1, 0);
+  P.L_col.clear();
+  P.L_val.clear();
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t k = P.A_ptr[i]; k < P.A_ptr[i + 1]; ++k) {
+      if (P.A_col[k] > i) break;
+      P.L_col.push_back(P.A_col[k]);
+      double v = P.A_val[k];
+      if (P.A_col[k] == i) v += alpha * P.A_val[k];
+      P.L_val.push_back(v);
+    }
+    P.L_ptr.push_back(int64_t(P.L_col.size()));
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t rb = P.L_ptr[i], re = P.L_ptr[i + 1];  // row i, last entry is the diagonal
+    for (int64_t m = rb; m < re - 1; ++m) {
+      int64_t j = P.L_col[m];
+      int64_t jb = P.L_ptr[j], je = P.L_ptr[j + 1];
+      double s = P.L_val[m];
+      // sum over k < j present in both rows i and j
+      int64_t a = rb, b = jb;
+      while (a < m && b < je - 1) {
+        if (P.L_col[a] == P.L_col[b]) {
+          s -= P.L_val[a] * P.L_val[b];
+          ++a;
+          ++b;
+        } else if (P.L_col[a] < P.L_col[b]) {
+          ++a;
+        } else {
+          ++b;
+        }
+      }
+      P.L_val[m] = s / P.L_val[je - 1];
+    }
+    double d = P.L_val[re - 1];
+    for (int64_t m = rb; m < re - 1; ++m) d -= P.L_val[m] * P.L_val[m];
+    if (!(d > 0.0)) return false;
+    P.L_val[re - 1] = std::sqrt(d);
+  }
+  return true;
+}
+
+int ic0(Problem& P) {
+  const double alphas[4] = {0.0, 1e-3, 1e-2, 1e-1};
+  for (int s = 0; s < 4; ++s) {
+    if (ic0_try(P, alphas[s])) {
+      P.have_L = true;
+      P.ic_shift_steps = s;
+      P.ic_alpha = alphas[s];
+      return 0;
+    }
+  }
+  P.have_L = false;
+  return -4;
+}
+
+// z = (L L^T)^{-1} r: forward substitution, then backward substitution with L^T
+// done column-wise from the rows of L.
+void ic0_apply(const Problem& P, const double* r, double* z) {
+  int64_t n = P.nu_dofs;
+  std::vector<double> y(n);
+  for (int64_t i = 0; i < n; ++i) {
+    double s = r[i];
+    int64_t re = P.L_ptr[i + 1];
+    for (int64_t m = P.L_ptr[i]; m < re - 1; ++m) s -= P.L_val[m] * y[P.L_col[m]];
+    y[i] = s / P.L_val[re - 1];
+  }
+  for (int64_t i = n - 1; i >= 0; --i) {
+    int64_t re = P.L_ptr[i + 1];
+    double zi = y[i] / P.L_val[re - 1];
+    z[i] = zi;
+    for (int64_t m = P.L_ptr[i]; m < re - 1; ++m) y[P.L_col[m]] -= P.L_val[m] * zi;
+  }
+}
+
+// Dense Cholesky (row-major, lower) for the ideal preconditioner blocks.
+bool dense_cholesky(std::vector<double>& a, int64_t n) {
+  for (int64_t j = 0; j < n; ++j) {
+    double d = a[j * n + j];
+    for (int64_t k = 0; k < j; ++k) d -= a[j * n + k] * a[j * n + k];
+    if (!(d > 0)) return false;
+    d = std::sqrt(d);
+    a[j * n + j] = d;
+    for (int64_t i = j + 1; i < n; ++i) {
+      double s = a[i * n + j];
+      for (int64_t k = 0; k < j; ++k) s -= a[i * n + k] * a[j * n + k];
+      a[i * n + j] = s / d;
+    }
+  }
+  return true;
+}
+
+void dense_chol_solve(const std::vector<double>& l, int64_t n, const double* r, double* z) {
+  std::vector<double> y(n);
+  for (int64_t i = 0; i < n; ++i) {
+    double s = r[i];
+    for (int64_t k = 0; k < i; ++k) s -= l[i * n + k] * y[k];
+    y[i] = s / l[i * n + i];
+  }
+  for (int64_t i = n - 1; i >= 0; --i) {
+    double s = y[i];
+    for (int64_t k = i + 1; k < n; ++k) s -= l[k * n + i] * z[k];
+    z[i] = s / l[i * n + i];
+  }
+}
+
+enum { PCA_IC0 = 0, PCA_ICPCG = 1, PCA_JACOBI = 2, PCA_EXACT = 3, PCA_JPCG = 4 };
+enum { PCQ_DIAG = 0, PCQ_EXACT = 1 };
+
+// Inner PCG on A (Sec. 6.4): x0 = 0, stop when ||r||_2 <= rtol ||b||_2, tested after
+// each update; preconditioner IC(0) (PCA_ICPCG) or Jacobi (PCA_JPCG).
+int pcg_A(const Problem& P, int which, const double* b, double* x, double rtol, int maxit) {
+  int64_t n = P.nu_dofs;
+  std::vector<double> r(b, b + n), z(n), p(n), q(n);
+  std::fill(x, x + n, 0.0);
+  double bnorm = std::sqrt(dot(b, b, n));
+  if (bnorm == 0.0) return 0;
+  auto prec = [&](const double* in, double* out) {
+    if (which == PCA_ICPCG) {
+      ic0_apply(P, in, out);
+    } else {
+      for (int64_t i = 0; i < n; ++i) out[i] = in[i] / csr_at(const_cast<Problem&>(P).A_ptr,
+                                                               const_cast<Problem&>(P).A_col,
+                                                               const_cast<Problem&>(P).A_val, i, i);
+    }
+  };
+  prec(r.data(), z.data());
+  p = z;
+  double rho = dot(r.data(), z.data(), n);
+  int it = 0;
+  while (it < maxit) {
+    A_matvec(P, p.data(), q.data());
+    double alpha = rho / dot(p.data(), q.data(), n);
+    for (int64_t i = 0; i < n; ++i) {
+      x[i] += alpha * p[i];
+      r[i] -= alpha * q[i];
+    }
+    ++it;
+    if (std::sqrt(dot(r.data(), r.data(), n)) <= rtol * bnorm) break;
+    prec(r.data(), z.data());
+    double rho_new = dot(r.data(), z.data(), n);
+    double beta = rho_new / rho;
+    rho = rho_new;
+    for (int64_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+  }
+  return it;
+}
+
+// Block-diagonal preconditioner M = blkdiag(M_A, M_Q) applied to r: z = M^{-1} r (eq.
+// general_precond_M).  M_Q = Diag(Q)/(2 nu) or Q/(2 nu) (exact).
+int apply_precond(const Problem& P, int pcA, int pcQ, double inner_tol, const double* r, double* z) {
+  int64_t nu = P.nu_dofs, np = P.np_dofs;
+  int inner = 0;
+  switch (pcA) {
+    case PCA_IC0:
+      ic0_apply(P, r, z);
+      break;
+    case PCA_ICPCG:
+    case PCA_JPCG:
+      inner = pcg_A(P, pcA, r, z, inner_tol, 200);
+      break;
+    case PCA_JACOBI:
+      for (int64_t i = 0; i < nu; ++i)
+        z[i] = r[i] / csr_at(const_cast<Problem&>(P).A_ptr, const_cast<Problem&>(P).A_col,
+                             const_cast<Problem&>(P).A_val, i, i);
+      break;
+    case PCA_EXACT:
+      dense_chol_solve(P.cholA, nu, r, z);
+      break;
+  }
+  if (pcQ == PCQ_DIAG) {
+    for (int64_t k = 0; k < np; ++k) z[nu + k] = 2.0 * P.nu * r[nu + k] / P.diagQ[k];
+  } else {
+    dense_chol_solve(P.cholQ, np, r + nu, z + nu);
+    for (int64_t k = 0; k < np; ++k) z[nu + k] *= 2.0 * P.nu;
+  }
+  return inner;
+}
+
+// ---------------------------------------------------------------------------
+// Preconditioned MINRES (Sec. 5; Paige-Saunders short recurrence with Givens QR,
+// in the form of Elman, Silvester & Wathen).  x0 = 0.  Iteration j:
+//   z_j <- z_j / gamma_j;  q = Acal z_j;  delta_j = q . z_j
+//   v_{j+1} = q - (delta_j/gamma_j) v_j - (gamma_j/gamma_{j-1}) v_{j-1}
+//   z_{j+1} = M^{-1} v_{j+1};  gamma_{j+1} = sqrt(v_{j+1} . z_{j+1})
+//   a0 = c_j delta_j - c_{j-1} s_j gamma_j;  a1 = sqrt(a0^2 + gamma_{j+1}^2)
+//   a2 = s_j delta_j + c_{j-1} c_j gamma_j;  a3 = s_{j-1} gamma_j
+//   c_{j+1} = a0/a1;  s_{j+1} = gamma_{j+1}/a1
+//   w_{j+1} = (z_j - a3 w_{j-1} - a2 w_j)/a1;  x_j = x_{j-1} + c_{j+1} eta w_{j+1}
+//   eta <- -s_{j+1} eta;  stop when |eta| <= tol gamma_1   (|eta| = ||r_j||_{M^{-1}})
+// ---------------------------------------------------------------------------
+struct MinresOut {
+  int iters = 0;
+  int inner_total = 0;
+  int status = 0;
+};
+
+MinresOut minres(const Problem& P, const double* b, double* x, double tol, int maxit, int pcA, int pcQ,
+                 double inner_tol, bool fixed_iters, double* eta_hist, double* x_hist) {
+  int64_t n = P.nu_dofs + P.np_dofs;
+  MinresOut out;
+  std::vector<double> v_prev(n, 0.0), v(b, b + n), v_next(n), z(n), z_next(n), q(n);
+  std::vector<double> w_prev(n, 0.0), w(n, 0.0), w_next(n);
+  std::fill(x, x + n, 0.0);
+  out.inner_total += apply_precond(P, pcA, pcQ, inner_tol, v.data(), z.data());
+  double g2 = dot(v.data(), z.data(), n);
+  if (g2 < 0) {
+    out.status = -4;
+    return out;
+  }
+  double gamma = std::sqrt(g2), gamma_prev = 1.0, gamma1 = gamma;
+  double eta = gamma;
+  double c_prev = 1, c = 1, s_prev = 0, s = 0;
+  if (eta_hist) eta_hist[0] = std::fabs(eta);
+  if (gamma1 == 0.0) return out;
+  int j = 0;
+  while (j < maxit) {
+    if (!fixed_iters && std::fabs(eta) <= tol * gamma1) break;
+    ++j;
+    for (int64_t i = 0; i < n; ++i) z[i] /= gamma;
+    saddle_matvec(P, z.data(), q.data());
+    double delta = dot(q.data(), z.data(), n);
+    for (int64_t i = 0; i < n; ++i)
+      v_next[i] = q[i] - (delta / gamma) * v[i] - (gamma / gamma_prev) * v_prev[i];
+    out.inner_total += apply_precond(P, pcA, pcQ, inner_tol, v_next.data(), z_next.data());
+    double gn2 = dot(v_next.data(), z_next.data(), n);
+    if (gn2 < 0) {
+      out.status = -4;
+      out.iters = j;
+      return out;
+    }
+    double gamma_next = std::sqrt(gn2);
+    double a0 = c * delta - c_prev * s * gamma;
+    double a1 = std::sqrt(a0 * a0 + gamma_next * gamma_next);
+    double a2 = s * delta + c_prev * c * gamma;
+    double a3 = s_prev * gamma;
+    double c_next = a0 / a1, s_next = gamma_next / a1;
+    for (int64_t i = 0; i < n; ++i) w_next[i] = (z[i] - a3 * w_prev[i] - a2 * w[i]) / a1;
+    for (int64_t i = 0; i < n; ++i) x[i] += c_next * eta * w_next[i];
+    eta = -s_next * eta;
+    if (eta_hist) eta_hist[j] = std::fabs(eta);
+    if (x_hist) std::memcpy(x_hist + (j - 1) * n, x, sizeof(double) * n);
+    // shift the recurrences
+    v_prev.swap(v);
+    v.swap(v_next);
+    z.swap(z_next);
+    w_prev.swap(w);
+    w.swap(w_next);
+    gamma_prev = gamma;
+    gamma = gamma_next;
+    c_prev = c;
+    c = c_next;
+    s_prev = s;
+    s = s_next;
+    if (gamma == 0.0) break;  // exact invariant subspace: x is the exact solution
+  }
+  out.iters = j;
+  if (!fixed_iters && std::fabs(eta) > tol * gamma1) out.status = 1;
+  return out;
+}
+
+// Zero-mean pressure (Sec. 3.2; imposed by filtering after the solve, Sec. 6.4): p <- p - (w.p)/(w.1).
+void project_pressure(const Problem& P, double* p) {
+  double wp = 0, w1 = 0;
+  for (int64_t k = 0; k < P.np_dofs; ++k) {
+    wp += P.wvec[k] * p[k];
+    w1 += P.wvec[k];
+  }
+  double m = wp / w1;
+  for (int64_t k = 0; k < P.np_dofs; ++k) p[k] -= m;
+}
+
+// Residual norms of the original system: ||b - Acal x||_2 / ||b||_2 and the M^{-1}-norm
+// ratio with the linear preconditioner that MINRES used (IC(0) when PCG was inner).
+void true_residuals(const Problem& P, const double* b, const double* x, int pcA, int pcQ, double* rel2,
+                    double* relM) {
+  int64_t n = P.nu_dofs + P.np_dofs;
+  std::vector<double> r(n), z(n), zb(n);
+  saddle_matvec(P, x, r.data());
+  for (int64_t i = 0; i < n; ++i) r[i] = b[i] - r[i];
+  int lin = (pcA == PCA_ICPCG) ? PCA_IC0 : (pcA == PCA_JPCG ? PCA_JACOBI : pcA);
+  apply_precond(P, lin, pcQ, 0.0, r.data(), z.data());
+  apply_precond(P, lin, pcQ, 0.0, b, zb.data());
+  double bb = dot(b, b, n), bm = dot(b, zb.data(), n);
+  *rel2 = bb > 0 ? std::sqrt(dot(r.data(), r.data(), n) / bb) : 0.0;
+  *relM = bm > 0 ? std::sqrt(std::max(0.0, dot(r.data(), z.data(), n)) / bm) : 0.0;
+}
+
+bool prepare_precond(Problem& P, int pcA, int pcQ) {
+  if ((pcA == PCA_IC0 || pcA == PCA_ICPCG) && !P.have_L) {
+    if (ic0(P) != 0) return false;
+  }
+  if (pcA == PCA_EXACT && !P.have_dense_A) {
+    int64_t n = P.nu_dofs;
+    P.cholA.assign(n * n, 0.0);
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t k = P.A_ptr[i]; k < P.A_ptr[i + 1]; ++k) P.cholA[i * n + P.A_col[k]] = P.A_val[k];
+    if (!dense_cholesky(P.cholA, n)) return false;
+    P.have_dense_A = true;
+  }
+  if (pcQ == PCQ_EXACT && !P.have_dense_Q) {
+    int64_t n = P.np_dofs;
+    P.cholQ.assign(n * n, 0.0);
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t k = P.Q_ptr[i]; k < P.Q_ptr[i + 1]; ++k) P.cholQ[i * n + P.Q_col[k]] = P.Q_val[k];
+    if (!dense_cholesky(P.cholQ, n)) return false;
+    P.have_dense_Q = true;
+  }
+  return true;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C interface used by the Python test harness (ctypes).
+// ===========================================================================
+extern "C" {
+
+// info layout for or_solve / or_minres
+// [0] iters [1] inner_total [2] status [3] ic_shift_steps [4] relres_est (|eta|/gamma1)
+// [5] relres_true_2 [6] relres_true_Minv
+// flags bit 0: build the sparsity patterns only (no quadrature), for size checks.
+void* or_setup(int N, int kp, int dim, double nu, double cpen, int flags) {
+  if (N < 1 || kp < 1 || (dim != 2 && dim != 3) || !(nu > 0)) return nullptr;
+  Problem* P = new Problem();
+  P->N = N;
+  P->kp = kp;
+  P->dim = dim;
+  P->nu = nu;
+  P->pdeg = kp + 1;
+  P->h = 1.0 / N;
+  P->cpen = (cpen < 0) ? 5.0 * (kp + 1) : cpen;
+  P->sp_hi = make_space(P->pdeg, N);
+  P->sp_lo = make_space(kp, N);
+  int64_t off = 0;
+  for (int c = 0; c < dim; ++c) {
+    int64_t cnt = 1;
+    for (int dir = 0; dir < dim; ++dir) {
+      P->vcount[c][dir] = (dir == c) ? P->sp_hi.nfun - 2 : P->sp_lo.nfun;
+      cnt *= P->vcount[c][dir];
+    }
+    P->voff[c] = off;
+    off += cnt;
+  }
+  P->voff[dim] = off;
+  P->nu_dofs = off;
+  P->np_dofs = 1;
+  for (int dir = 0; dir < dim; ++dir) P->np_dofs *= P->sp_lo.nfun;
+  build_patterns(*P);
+  if (!(flags & 1)) assemble(*P);
+  return P;
+}
+
+void or_free(void* h) { delete static_cast<Problem*>(h); }
+
+void or_sizes(void* h, int64_t* n_u, int64_t* n_p) {
+  Problem* P = static_cast<Problem*>(h);
+  *n_u = P->nu_dofs;
+  *n_p = P->np_dofs;
+}
+
+// which: 0 = A, 1 = B, 2 = Q, 3 = L (after or_ic0)
+int64_t or_nnz(void* h, int which) {
+  Problem* P = static_cast<Problem*>(h);
+  switch (which) {
+    case 0: return int64_t(P->A_col.size());
+    case 1: return int64_t(P->B_col.size());
+    case 2: return int64_t(P->Q_col.size());
+    case 3: return int64_t(P->L_col.size());
+  }
+  return -1;
+}
+
+void or_get_csr(void* h, int which, int64_t* ptr, int32_t* col, double* val) {
+  Problem* P = static_cast<Problem*>(h);
+  const std::vector<int64_t>* pp = nullptr;
+  const std::vector<int32_t>* cc = nullptr;
+  const std::vector<double>* vv = nullptr;
+  switch (which) {
+    case 0: pp = &P->A_ptr; cc = &P->A_col; vv = &P->A_val; break;
+    case 1: pp = &P->B_ptr; cc = &P->B_col; vv = &P->B_val; break;
+    case 2: pp = &P->Q_ptr; cc = &P->Q_col; vv = &P->Q_val; break;
+    case 3: pp = &P->L_ptr; cc = &P->L_col; vv = &P->L_val; break;
+    default: return;
+  }
+  if (ptr) std::memcpy(ptr, pp->data(), pp->size() * sizeof(int64_t));
+  if (col) std::memcpy(col, cc->data(), cc->size() * sizeof(int32_t));
+  if (val) std::memcpy(val, vv->data(), vv->size() * sizeof(double));
+}
+
+void or_get_diagQ_w(void* h, double* diagQ, double* w) {
+  Problem* P = static_cast<Problem*>(h);
+  if (diagQ) std::memcpy(diagQ, P->diagQ.data(), P->np_dofs * sizeof(double));
+  if (w) std::memcpy(w, P->wvec.data(), P->np_dofs * sizeof(double));
+}
+
+int or_ic0(void* h, int* shift_steps) {
+  Problem* P = static_cast<Problem*>(h);
+  int rc = P->have_L ? 0 : ic0(*P);
+  if (shift_steps) *shift_steps = P->ic_shift_steps;
+  return rc;
+}
+
+// Load vector(s).  problem: 0 none, 1 manufactured (default), 2 paper square, 3 gradient.
+// amp [nrhs][dim][nmodes], wave [nrhs][nmodes][dim], phase [nrhs][dim][nmodes]; f [nrhs][n_u].
+void or_load(void* h, int problem, int nrhs, int nmodes, const double* amp, const int32_t* wave,
+             const double* phase, double* f) {
+  Problem* P = static_cast<Problem*>(h);
+  for (int r = 0; r < nrhs; ++r) {
+    const double* a = amp ? amp + int64_t(r) * P->dim * nmodes : nullptr;
+    const int32_t* k = wave ? wave + int64_t(r) * nmodes * P->dim : nullptr;
+    const double* ph = phase ? phase + int64_t(r) * P->dim * nmodes : nullptr;
+    load_vector(*P, problem, a ? nmodes : 0, a, k, ph, f + int64_t(r) * P->nu_dofs);
+  }
+}
+
+void or_matvec(void* h, const double* x, double* y) { saddle_matvec(*static_cast<Problem*>(h), x, y); }
+
+int or_precond(void* h, int pcA, int pcQ, double inner_tol, const double* r, double* z, int* inner) {
+  Problem* P = static_cast<Problem*>(h);
+  if (!prepare_precond(*P, pcA, pcQ)) return -4;
+  int it = apply_precond(*P, pcA, pcQ, inner_tol, r, z);
+  if (inner) *inner = it;
+  return 0;
+}
+
+// Plain MINRES on Acal x = b (no projection).  fixed != 0 runs exactly maxit iterations.
+int or_minres(void* h, const double* b, double* x, double tol, int maxit, int pcA, int pcQ,
+              double inner_tol, int fixed, double* info, double* eta_hist, double* x_hist) {
+  Problem* P = static_cast<Problem*>(h);
+  if (!prepare_precond(*P, pcA, pcQ)) {
+    if (info) info[2] = -4;
+    return -4;
+  }
+  int64_t n = P->nu_dofs + P->np_dofs;
+  MinresOut o = minres(*P, b, x, tol, maxit, pcA, pcQ, inner_tol, fixed != 0, eta_hist, x_hist);
+  if (info) {
+    info[0] = o.iters;
+    info[1] = o.inner_total;
+    info[2] = o.status;
+    info[3] = P->ic_shift_steps;
+    double rel2 = 0, relM = 0;
+    true_residuals(*P, b, x, pcA, pcQ, &rel2, &relM);
+    info[4] = 0;
+    info[5] = rel2;
+    info[6] = relM;
+    (void)n;
+  }
+  return o.status;
+}
+
+// Full solve as the product path defines it: b = [f; 0], MINRES, zero-mean pressure.
+int or_solve(void* h, const double* f, double* u, double* p, double tol, int maxit, int pcA, int pcQ,
+             double inner_tol, int fixed, double* info) {
+  Problem* P = static_cast<Problem*>(h);
+  int64_t nu = P->nu_dofs, np = P->np_dofs, n = nu + np;
+  std::vector<double> b(n, 0.0), x(n);
+  std::memcpy(b.data(), f, nu * sizeof(double));
+  int rc = or_minres(h, b.data(), x.data(), tol, maxit, pcA, pcQ, inner_tol, fixed, info, nullptr, nullptr);
+  project_pressure(*P, x.data() + nu);
+  std::memcpy(u, x.data(), nu * sizeof(double));
+  std::memcpy(p, x.data() + nu, np * sizeof(double));
+  return rc;
+}
+
+void or_project(void* h, double* p) { project_pressure(*static_cast<Problem*>(h), p); }
+
+// Adjoint solve for a loss L(u, p) with p the zero-mean pressure: the right-hand side
+// is [g_u; P^T g_p] with P^T g_p = g_p - w (1.g_p)/(w.1); the system matrix is symmetric
+// so the same MINRES and preconditioner are used.  lambda_p is returned zero-mean.
+int or_adjoint(void* h, const double* g_u, const double* g_p, double* lam_u, double* lam_p, double tol,
+               int maxit, int pcA, int pcQ, double inner_tol, double* info) {
+  Problem* P = static_cast<Problem*>(h);
+  int64_t nu = P->nu_dofs, np = P->np_dofs, n = nu + np;
+  std::vector<double> b(n, 0.0), x(n);
+  std::memcpy(b.data(), g_u, nu * sizeof(double));
+  double s1 = 0, w1 = 0;
+  for (int64_t k = 0; k < np; ++k) {
+    s1 += g_p[k];
+    w1 += P->wvec[k];
+  }
+  for (int64_t k = 0; k < np; ++k) b[nu + k] = g_p[k] - P->wvec[k] * s1 / w1;
+  int rc = or_minres(h, b.data(), x.data(), tol, maxit, pcA, pcQ, inner_tol, 0, info, nullptr, nullptr);
+  project_pressure(*P, x.data() + nu);
+  std::memcpy(lam_u, x.data(), nu * sizeof(double));
+  std::memcpy(lam_p, x.data() + nu, np * sizeof(double));
+  return rc;
+}
+
+// lambda_u^T A u / nu  (A is proportional to nu, so dA/dnu = A/nu).
+double or_dnu_dot(void* h, const double* lam_u, const double* u) {
+  Problem* P = static_cast<Problem*>(h);
+  std::vector<double> au(P->nu_dofs);
+  A_matvec(*P, u, au.data());
+  return dot(lam_u, au.data(), P->nu_dofs) / P->nu;
+}
+
+// Discrete solution evaluation at physical points: velocity, its divergence, pressure.
+// pts [npts][dim]; out [npts][dim + 2] = (u_1..u_dim, div u, p).
+void or_eval(void* h, const double* u, const double* p, int64_t npts, const double* pts, double* out) {
+  Problem* P = static_cast<Problem*>(h);
+  int dim = P->dim;
+  for (int64_t t = 0; t < npts; ++t) {
+    int e[3] = {0, 0, 0};
+    for (int d = 0; d < dim; ++d) e[d] = std::min(P->N - 1, std::max(0, int(pts[t * dim + d] * P->N)));
+    Tab1D tabs[3][2];
+    for (int dir = 0; dir < dim; ++dir) {
+      std::vector<double> xs(1, pts[t * dim + dir]);
+      eval_on_element(P->sp_lo, e[dir], xs, tabs[dir][0].v, tabs[dir][0].d);
+      tabs[dir][0].nloc = P->sp_lo.deg + 1;
+      eval_on_element(P->sp_hi, e[dir], xs, tabs[dir][1].v, tabs[dir][1].d);
+      tabs[dir][1].nloc = P->sp_hi.deg + 1;
+    }
+    int q[3] = {0, 0, 0};
+    std::vector<VelEval> ve;
+    std::vector<PreEval> pe;
+    tensor_eval_velocity(*P, e, tabs, q, ve);
+    tensor_eval_pressure(*P, e, tabs, q, pe);
+    double* o = out + t * (dim + 2);
+    for (int k = 0; k < dim + 2; ++k) o[k] = 0;
+    for (const VelEval& v : ve) {
+      for (int a = 0; a < dim; ++a) o[a] += u[v.g] * v.val[a];
+      for (int a = 0; a < dim; ++a) o[dim] += u[v.g] * v.grad[a][a];
+    }
+    for (const PreEval& pp : pe) o[dim + 1] += p[pp.g] * pp.val;
+  }
+}
+
+// Error norms against the exact solution of `problem`: out = (|u-u_h|_H1, ||u-u_h||_L2, ||p-p_h||_L2)
+// with k'+4 Gauss points per direction; the exact pressure's mean is removed first.
+void or_errors(void* h, int problem, const double* u, const double* p, double* out) {
+  Problem* P = static_cast<Problem*>(h);
+  int dim = P->dim;
+  int nq = P->kp + 4;
+  std::vector<double> xq, wq;
+  gauss_legendre01(nq, xq, wq);
+  double vol = 1.0;
+  for (int d = 0; d < dim; ++d) vol *= P->h;
+  // mean of the exact pressure
+  double pmean = 0;
+  int nE[3] = {P->N, P->N, dim == 3 ? P->N : 1};
+  for (int pass = 0; pass < 2; ++pass) {
+    double h1 = 0, l2u = 0, l2p = 0, pm = 0;
+    int e[3] = {0, 0, 0};
+    Tab1D tabs[3][2];
+    std::vector<VelEval> ve;
+    std::vector<PreEval> pe;
+    for (e[2] = 0; e[2] < nE[2]; ++e[2])
+      for (e[1] = 0; e[1] < nE[1]; ++e[1])
+        for (e[0] = 0; e[0] < nE[0]; ++e[0]) {
+          build_tabs_for_element(*P, e, xq, tabs);
+          int nq2 = dim == 3 ? nq : 1;
+          int q[3] = {0, 0, 0};
+          for (q[2] = 0; q[2] < nq2; ++q[2])
+            for (q[1] = 0; q[1] < nq; ++q[1])
+              for (q[0] = 0; q[0] < nq; ++q[0]) {
+                double wt = vol, x[3] = {0, 0, 0};
+                for (int dir = 0; dir < dim; ++dir) {
+                  wt *= wq[q[dir]];
+                  x[dir] = (e[dir] + xq[q[dir]]) * P->h;
+                }
+                double ue[3], ge[3][3], pex;
+                exact_solution(problem, dim, x, ue, ge, &pex);
+                if (pass == 0) {
+                  pm += wt * pex;
+                  continue;
+                }
+                tensor_eval_velocity(*P, e, tabs, q, ve);
+                tensor_eval_pressure(*P, e, tabs, q, pe);
+                double uh[3] = {0, 0, 0}, gh[3][3] = {{0}}, ph = 0;
+                for (const VelEval& v : ve)
+                  for (int a = 0; a < 3; ++a) {
+                    uh[a] += u[v.g] * v.val[a];
+                    for (int b = 0; b < 3; ++b) gh[a][b] += u[v.g] * v.grad[a][b];
+                  }
+                for (const PreEval& pp : pe) ph += p[pp.g] * pp.val;
+                for (int a = 0; a < dim; ++a) {
+                  l2u += wt * (ue[a] - uh[a]) * (ue[a] - uh[a]);
+                  for (int b = 0; b < dim; ++b) h1 += wt * (ge[a][b] - gh[a][b]) * (ge[a][b] - gh[a][b]);
+                }
+                l2p += wt * (pex - pmean - ph) * (pex - pmean - ph);
+              }
+        }
+    if (pass == 0) {
+      pmean = pm;
+    } else {
+      out[0] = std::sqrt(h1);
+      out[1] = std::sqrt(l2u);
+      out[2] = std::sqrt(l2p);
+    }
+  }
+}
+
+}  // extern "C"
