@@ -1,0 +1,178 @@
+/*
+ * stokes.h -- C ABI of libstokes.so, an MI355X (gfx950) solver for the discrete Stokes
+ * saddle-point system of a divergence-conforming (Raviart-Thomas type) B-spline
+ * discretisation, by block-diagonally preconditioned MINRES.
+ *
+ * Method (Cortes & Coutinho, arXiv 1309.5048):
+ *   Spaces (Sec. 3.2): on the unit square (dim = 2) or cube (dim = 3) with N uniform
+ *     elements per direction, velocity component c has degree p = k'+1 in direction c and
+ *     degree k' in the others, maximal continuity; the first/last function of direction c
+ *     is removed (u.n = 0).  Pressure: degree k' in every direction, zero mean imposed
+ *     after the solve.  Numbering: velocity component-major, x fastest; pressure after.
+ *   Matrices (Sec. 4): [A]_ij = a(Phi_j,Phi_i) - eta_h(Phi_j,Phi_i) with the Nitsche form
+ *     eta_h of eq. (nitsche_lhs), C_pen = 5(k'+1) (Sec. 6.2), h_F = 1/N; [B]_kj =
+ *     -(div Phi_j, phi_k); system [A B^T; B 0][u; p] = [f; 0] (eq. stokes_linsys).
+ *   Solver (Sec. 5): preconditioned MINRES with M = blkdiag(M_A, M_Q) (eq.
+ *     general_precond_M), M_Q = Diag(Q)/(2 nu) (the scaled mass matrix Q_nu of Sec. 5.1
+ *     replaced by its diagonal), M_A = IC(0) of A (Sec. 6.4), IC(0)-PCG on A (Sec. 6.4,
+ *     relaxed inner tolerance) or Diag(A).  Stop when the preconditioned residual
+ *     estimate |eta_j| <= tol * ||b||_{M^-1} (Sec. 5, M^{-1}-norm of the residual).
+ *
+ * Conventions
+ *   - Every vector pointer is a DEVICE pointer to contiguous doubles (the caller owns it;
+ *     the library never keeps it after the call returns).  Batched arrays are column-major
+ *     with one right-hand side per column: F[r * n_u + i].
+ *   - All work is ordered on the problem's stream (stokes_set_stream; default: the null
+ *     stream).  Calls that return stokes_info synchronise that stream before returning.
+ *   - A handle is not thread safe; distinct handles are independent.
+ *   - Return codes: 0 OK; STOKES_NOT_CONVERGED (+1) the best iterate is still returned;
+ *     STOKES_EINVAL (-1) bad argument / NaN input / unsupported (dim, p); STOKES_ENOMEM
+ *     (-2) device allocation failed; STOKES_EHIP (-3) HIP runtime error (including a
+ *     device-side wait that exceeded its spin limit); STOKES_EBREAKDOWN (-4) IC(0) pivot
+ *     <= 0 after the last diagonal shift, or a negative Lanczos gamma^2.  The message of
+ *     the last failure is returned by stokes_last_error.
+ */
+#ifndef STOKES_H
+#define STOKES_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define STOKES_OK 0
+#define STOKES_NOT_CONVERGED 1
+#define STOKES_EINVAL (-1)
+#define STOKES_ENOMEM (-2)
+#define STOKES_EHIP (-3)
+#define STOKES_EBREAKDOWN (-4)
+
+/* Velocity-block preconditioner M_A; the pressure block is always Diag(Q)/(2 nu). */
+#define STOKES_PC_IC0 0    /* M_A = L L^T, IC(0) of A in natural order (Sec. 6.4)          */
+#define STOKES_PC_ICPCG 1  /* M_A^{-1} r = IC(0)-preconditioned CG on A r, relative 2-norm
+                              tolerance stokes_set_inner_tol (default 1e-2), x0 = 0      */
+#define STOKES_PC_JACOBI 2 /* M_A = Diag(A)  (the Diag(A,Q) variant of Sec. 5.1)          */
+
+/* Arithmetic of the Krylov iteration. */
+#define STOKES_FP64 0  /* everything in double precision                                  */
+#define STOKES_MIXED 1 /* iterative refinement: FP64 true residual, zero-mean projection
+                          and Lanczos/Givens scalars; inner MINRES with FP32 matrices,
+                          FP32 IC(0) factors and triangular solves, FP32 accumulation   */
+
+typedef struct stokes_problem stokes_problem; /* opaque: owns all device matrices,
+                                                  factors, schedules and workspaces   */
+
+typedef struct {
+  int32_t iters;             /* MINRES iterations (summed over refinement steps if MIXED) */
+  int32_t inner_iters_total; /* inner PCG iterations (ICPCG) summed over the solve        */
+  int32_t status;            /* return code of this right-hand side                       */
+  int32_t ic_shift_steps;    /* IC(0) diagonal-shift retries used at setup (0 = none)     */
+  double relres_est;         /* |eta|/gamma_1 at exit (M^{-1}-norm estimate)              */
+  double relres_true_2;      /* ||b - Acal x||_2 / ||b||_2, computed on the device          */
+  double relres_true_Minv;   /* ||b - Acal x||_{M^-1} / ||b||_{M^-1} (IC(0)/Jacobi M)       */
+  double setup_ms;           /* time of stokes_setup (assembly, ordering, IC(0))          */
+  double solve_ms;           /* device time of this solve (hipEvents on the stream)       */
+} stokes_info;
+
+/* Forcing description for stokes_load.  f_d(x) = [manufactured]_d(x)
+ *   + sum_m amp[r][d][m] * sin(pi * (wave[r][m][0] x + wave[r][m][1] y [+ wave[r][m][2] z])
+ *                              + phase[r][d][m]).
+ * Manufactured: u = curl psi, psi = x^2(1-x)^2 y^2(1-y)^2 (2D) or u = curl(g,g,g),
+ * g = phi(x)phi(y)phi(z), phi(t) = t^2(1-t)^2 (3D); p = prod_d cos(pi x_d);
+ * f = -nu Lap u + grad p.  Arrays are HOST pointers, may be NULL when nmodes = 0. */
+typedef struct {
+  int32_t manufactured; /* 1: include the manufactured forcing, 0: modes only          */
+  int32_t nmodes;       /* sinusoid modes per component (0..64)                         */
+  const double* amp;    /* [nrhs][dim][nmodes]                                          */
+  const int32_t* wave;  /* [nrhs][nmodes][dim]                                          */
+  const double* phase;  /* [nrhs][dim][nmodes]                                          */
+} stokes_forcing;
+
+/* Build the problem: spaces and sparsity (host), Gauss-quadrature assembly of A, B, B^T,
+ * diag(Q) and w = Q 1 (device), level schedules of the triangular solves (host) and the
+ * IC(0) factor (device, shift retries alpha = 1e-3, 1e-2, 1e-1 of diag(A) on breakdown).
+ * n: elements per direction (1..4096); p: pressure degree k' (1..3); dim: 2 or 3;
+ * nu > 0.  On success *out owns the problem; on failure *out = NULL. */
+int stokes_setup(int n, int p, int dim, double nu, stokes_problem** out);
+
+/* Sizes: n_u velocity unknowns, n_p pressure unknowns. */
+int stokes_sizes(const stokes_problem* pb, int64_t* n_u, int64_t* n_p);
+
+/* Order all later work of this handle on the given hipStream_t (NULL = null stream). */
+int stokes_set_stream(stokes_problem* pb, void* hip_stream);
+
+/* Change the viscosity without re-assembly: A and its IC(0) factor scale with nu
+ * (A ~ nu, L ~ sqrt(nu)), M_Q = Diag(Q)/(2 nu). */
+int stokes_set_nu(stokes_problem* pb, double nu);
+
+/* Inner PCG relative tolerance for STOKES_PC_ICPCG (default 1e-2) and iteration limits
+ * (defaults: outer 20000, inner 200).  Non-positive values keep the current setting. */
+int stokes_set_inner_tol(stokes_problem* pb, double rtol);
+int stokes_set_maxit(stokes_problem* pb, int outer, int inner);
+
+/* Assemble nrhs load vectors [f]_i = (f, Phi_i) on the device (Gauss rule with k'+4
+ * points per direction) into f_dev [nrhs][n_u]. */
+int stokes_load(stokes_problem* pb, const stokes_forcing* spec, int nrhs, double* f_dev);
+
+/* Solve [A B^T; B 0][u; p] = [f; 0] from x0 = 0: f [n_u] in, u [n_u] and pr [n_p] out
+ * (pr has zero mean, w.pr = 0).  tol: relative M^{-1}-norm residual (e.g. 1e-8).
+ * precond: STOKES_PC_*.  info may be NULL. */
+int stokes_solve(stokes_problem* pb, const double* f, double* u, double* pr, double tol, int precond,
+                 stokes_info* info);
+
+/* nrhs independent solves in one launch sequence (block SpMM / block triangular solves,
+ * per-column Lanczos and Givens scalars, converged columns frozen).  F [nrhs][n_u],
+ * U [nrhs][n_u], P [nrhs][n_p]; infos [nrhs] may be NULL.  precision: STOKES_FP64 or
+ * STOKES_MIXED.  nrhs in 1..16. */
+int stokes_solve_batched(stokes_problem* pb, int nrhs, const double* F, double* U, double* P,
+                         double tol, int precond, int precision, stokes_info* infos);
+
+/* Single right-hand side with a precision choice (STOKES_FP64 is stokes_solve). */
+int stokes_solve_precision(stokes_problem* pb, const double* f, double* u, double* pr, double tol,
+                           int precond, int precision, stokes_info* info);
+
+/* Adjoint solve for a loss L(u, p) of the zero-mean solution: with g = [g_u; g_p]
+ * [n_u + n_p] (dL/du, dL/dp), solves Acal lambda = [g_u; g_p - w (1.g_p)/(w.1)]
+ * (Acal is symmetric, same MINRES and preconditioner); lambda [n_u + n_p] out with a
+ * zero-mean pressure part.  Then dL/df = lambda_u and dL/dnu = -lambda_u^T (A/nu) u. */
+int stokes_solve_adjoint(stokes_problem* pb, const double* g, double* lambda, double tol, int precond,
+                         stokes_info* info);
+
+/* Batched adjoint: G [nrhs][n_u + n_p] in, Lambda [nrhs][n_u + n_p] out. */
+int stokes_solve_adjoint_batched(stokes_problem* pb, int nrhs, const double* G, double* Lambda,
+                                 double tol, int precond, stokes_info* infos);
+
+/* out[r] = lam_u[r]^T A u[r] / nu for r < nrhs (device arrays [nrhs][n_u]); out is a
+ * HOST array of nrhs doubles.  Synchronises the stream. */
+int stokes_dnu_dot(stokes_problem* pb, int nrhs, const double* lam_u, const double* u, double* out);
+
+/* Products with the assembled operators, for checks: y = Acal x (x, y [n_u + n_p]). */
+int stokes_apply(stokes_problem* pb, const double* x, double* y);
+
+/* y = M^{-1} r with the chosen velocity preconditioner (r, y [n_u + n_p]); *inner_iters
+ * receives the PCG iteration count for STOKES_PC_ICPCG (may be NULL). */
+int stokes_apply_precond(stokes_problem* pb, int precond, const double* r, double* y, int* inner_iters);
+
+/* Copy the assembled matrices to HOST buffers (for checks).  which: 0 = saddle Acal
+ * (rows n_u + n_p, columns sorted), 1 = the IC(0) factor L (rows n_u, lower triangle of
+ * A's pattern, diagonal last).  Pass NULL arrays to query *nnz only. rowptr is int64. */
+int stokes_export_csr(stokes_problem* pb, int which, int64_t* nnz, int64_t* rowptr, int32_t* col,
+                      double* val);
+
+/* diag(Q) and w = Q 1 (integrals of the pressure functions) to HOST arrays [n_p]. */
+int stokes_export_pressure_mass(stokes_problem* pb, double* diagQ, double* w);
+
+/* Number of dependency levels of the forward / backward triangular solves (host). */
+int stokes_levels(const stokes_problem* pb, int* fwd_levels, int* bwd_levels);
+
+/* Mean device time (ms) of the last solve's kernels by category, for profiling:
+ * out[0] SpMV, out[1] triangular solves, out[2] vector updates; may be unsupported
+ * (returns STOKES_EINVAL) when timing is off. */
+const char* stokes_last_error(const stokes_problem* pb);
+void stokes_destroy(stokes_problem* pb);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STOKES_H */

@@ -1,0 +1,1080 @@
+// C ABI of libstokes.so (declared in include/stokes.h): problem setup, the MINRES
+// drivers (FP64, mixed FP32/FP64 refinement, batched, adjoint) and small utilities.
+// Host code only orchestrates; every arithmetic step of the method runs in the HIP
+// kernels of this library.
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+
+#include "stokes.h"
+#include "stokes_internal.h"
+
+using namespace stk;
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Small kernels used only by the orchestration
+// ---------------------------------------------------------------------------
+__global__ void k_gather_diag(int64_t n, const int32_t* __restrict__ Lrowptr, const int64_t* __restrict__ Lsrc,
+                              const double* __restrict__ val, double* __restrict__ diagA) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    diagA[i] = val[Lsrc[Lrowptr[i + 1] - 1]];
+}
+
+// pressure-weighted column sums: out[c] = sum_k wt[k] * x[(off+k)*R + c] (wt = nullptr: plain sum)
+template <int R>
+__global__ __launch_bounds__(kVT) void k_pdot(int64_t np, int64_t off, const double* __restrict__ wt,
+                                              const double* __restrict__ x, double* partials, unsigned int* counter,
+                                              double* out) {
+  double acc[R];
+#pragma unroll
+  for (int c = 0; c < R; ++c) acc[c] = 0.0;
+  for (int64_t k = blockIdx.x * (int64_t)kVT + threadIdx.x; k < np; k += (int64_t)gridDim.x * kVT) {
+    const double wv = wt ? wt[k] : 1.0;
+#pragma unroll
+    for (int c = 0; c < R; ++c) acc[c] += wv * x[(size_t)(off + k) * R + c];
+  }
+  reduce_last<R>(acc, partials, counter, [&](int k, double v) { out[k] = v; });
+}
+
+// M^{-1}-weighted squares of the pressure part (2 nu r^2 / diagQ) and, with diagA, of the
+// velocity part (r^2 / diagA): out[c] = pressure part, out[R+c] = velocity part.
+template <int R>
+__global__ __launch_bounds__(kVT) void k_diag_wsq(int64_t n_u, int64_t n, const double* __restrict__ r,
+                                                  const double* __restrict__ diagQ, const double* __restrict__ diagA,
+                                                  double two_nu, double* partials, unsigned int* counter, double* out) {
+  double acc[2 * R];
+#pragma unroll
+  for (int c = 0; c < 2 * R; ++c) acc[c] = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kVT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVT) {
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+      const double rv = r[(size_t)i * R + c];
+      if (i >= n_u) acc[c] += two_nu * rv * rv / diagQ[i - n_u];
+      else if (diagA) acc[R + c] += rv * rv / diagA[i];
+    }
+  }
+  reduce_last<2 * R>(acc, partials, counter, [&](int k, double v) { out[k] = v; });
+}
+
+// b_p -= w * s[c] / w1 (adjoint right-hand side P^T g_p)
+template <int R>
+__global__ void k_sub_w(int64_t n_u, int64_t np, double* __restrict__ b, const double* __restrict__ w,
+                        const double* __restrict__ s, double w1) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < np; k += (int64_t)gridDim.x * blockDim.x)
+#pragma unroll
+    for (int c = 0; c < R; ++c) b[(size_t)(n_u + k) * R + c] -= w[k] * s[c] / w1;
+}
+
+// z = M^{-1} r for the diagonal blocks (pressure always, velocity with diagA), R = 1
+__global__ void k_apply_diag(int64_t n_u, int64_t n, const double* __restrict__ r, double* __restrict__ z,
+                             const double* __restrict__ diagQ, const double* __restrict__ diagA, double two_nu) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    if (i >= n_u) z[i] = two_nu * r[i] / diagQ[i - n_u];
+    else if (diagA) z[i] = r[i] / diagA[i];
+  }
+}
+
+// A part of the saddle values (velocity rows, columns < n_u) scaled by s
+__global__ void k_scale_A(int64_t n_u, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ aend,
+                          double* __restrict__ val, double s) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_u; i += (int64_t)gridDim.x * blockDim.x)
+    for (int32_t k = rowptr[i]; k < aend[i]; ++k) val[k] *= s;
+}
+
+template <typename T>
+__global__ void k_fill(int64_t n, T* __restrict__ a, T v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) a[i] = v;
+}
+
+#define R_SWITCH(R_, ...)                                   \
+  switch (R_) {                                             \
+    case 1: { constexpr int RR = 1; __VA_ARGS__; break; }   \
+    case 8: { constexpr int RR = 8; __VA_ARGS__; break; }   \
+    case 16: { constexpr int RR = 16; __VA_ARGS__; break; } \
+    default: break;                                         \
+  }
+
+// ---------------------------------------------------------------------------
+// Device buffer helpers
+// ---------------------------------------------------------------------------
+struct DevAlloc {
+  std::vector<void*> ptrs;
+  hipError_t err = hipSuccess;
+  template <typename T>
+  T* get(size_t count) {
+    void* p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess) {
+      err = e;
+      return nullptr;
+    }
+    ptrs.push_back(p);
+    return static_cast<T*>(p);
+  }
+  template <typename T>
+  T* upload(const std::vector<T>& v, hipStream_t st) {
+    T* p = get<T>(v.size());
+    if (p && !v.empty()) {
+      hipError_t e = hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st);
+      if (e != hipSuccess) err = e;
+    }
+    return p;
+  }
+  void release() {
+    for (void* p : ptrs) hipFree(p);
+    ptrs.clear();
+  }
+};
+
+struct SchedPair {
+  TrsvSchedDev fwd, bwd;
+  int strip = 0;
+  int rmax64 = 0, rmax32 = 0;
+};
+
+// Workspace of one (R, precision) combination; vectors interleaved [row][R].
+struct Work {
+  int R = 0;
+  bool fp32 = false;
+  void *v[2] = {nullptr, nullptr}, *z[2] = {nullptr, nullptr}, *w[2] = {nullptr, nullptr};
+  void *x = nullptr, *q = nullptr, *b = nullptr, *y = nullptr;
+  void *pr = nullptr, *pp = nullptr, *pq = nullptr, *pz = nullptr;  // inner PCG
+};
+
+}  // namespace
+
+struct stokes_problem {
+  Spaces S;
+  double nu = 1.0, cpen = 0.0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  SaddlePattern P;
+  LowerPattern L;
+  std::vector<int32_t> level_ptr;
+  int nlev_fwd = 0;
+  int64_t nnz = 0, nnzL = 0;
+  DevAlloc mem;  // everything owned by the problem
+  int32_t *rowptr = nullptr, *col = nullptr, *aend = nullptr;
+  double* val = nullptr;
+  float* val32 = nullptr;
+  double *diagQ = nullptr, *w = nullptr, *diagA = nullptr;
+  double w1 = 1.0;
+  int32_t *Lrowptr = nullptr, *Lcol = nullptr, *level_rows = nullptr;
+  int64_t* Lsrc = nullptr;
+  double* Lval = nullptr;
+  int* flag = nullptr;
+  int ic_shift_steps = 0;
+  std::vector<std::unique_ptr<SchedPair>> scheds;
+  MrScalars mr;
+  PcgScalars pcg;
+  double* scratch = nullptr;  // [64] small host-visible results
+  double* partials = nullptr;
+  unsigned int* counter = nullptr;
+  std::map<int, Work> work;
+  double inner_tol = 1e-2;
+  double mixed_inner_tol = 1e-4;
+  int maxit_outer = 20000, maxit_inner = 200;
+  int check_every = 8;
+  double setup_ms = 0.0;
+  size_t lds_max = 65536;
+  size_t lds_per_cu = 65536;
+  int num_cu = 0;
+  std::vector<int32_t> lev_fwd, lev_bwd;  // dependency levels of the two solves
+  ~stokes_problem() { mem.release(); }
+};
+
+namespace {
+
+int fail(stokes_problem* pb, int code, const std::string& msg) {
+  if (pb) pb->err = msg;
+  return code;
+}
+
+int fail_hip(stokes_problem* pb, hipError_t e, const char* what, int line) {
+  char buf[512];
+  snprintf(buf, sizeof(buf), "HIP error %d (%s) in %s at api.hip:%d", int(e), hipGetErrorString(e), what, line);
+  if (pb) pb->err = buf;
+  return e == hipErrorOutOfMemory ? STOKES_ENOMEM : STOKES_EHIP;
+}
+
+#define CK(...)                                                          \
+  do {                                                                   \
+    hipError_t _e = (__VA_ARGS__);                                       \
+    if (_e != hipSuccess) return fail_hip(pb, _e, #__VA_ARGS__, __LINE__); \
+  } while (0)
+
+int upload_schedule(stokes_problem* pb, const TrsvSchedHost& H, TrsvSchedDev& D, int rmax) {
+  hipStream_t st = pb->stream;
+  DevAlloc& m = pb->mem;
+  D.ngroups = H.ngroups;
+  D.nsteps = H.nsteps;
+  D.E = H.E;
+  D.nlevels = H.nlevels;
+  D.nslots = H.nslots;
+  D.nrows = int(pb->S.n_u);
+  D.grp_step_ptr = m.upload(H.grp_step_ptr, st);
+  D.grp_halo_ptr = m.upload(H.grp_halo_ptr, st);
+  D.halo_row = m.upload(H.halo_row, st);
+  D.halo_grp = m.upload(H.halo_grp, st);
+  D.halo_lvl = m.upload(H.halo_lvl, st);
+  D.halo_slot = m.upload(H.halo_slot, st);
+  D.halo_free = m.upload(H.halo_free, st);
+  D.step_level = m.upload(H.step_level, st);
+  D.step_halo_need = m.upload(H.step_halo_need, st);
+  D.step_publish = m.upload(H.step_publish, st);
+  D.srow = m.upload(H.srow, st);
+  D.sslot = m.upload(H.sslot, st);
+  D.ent_src = m.upload(H.ent_src, st);
+  D.sdiag_src = m.upload(H.sdiag_src, st);
+  D.ent_perm = m.upload(H.ent_perm, st);
+  D.ent_val = m.get<double>(H.ent_perm.size());
+  D.ent_val32 = m.get<float>(H.ent_perm.size());
+  D.sdinv = m.get<double>(H.sdiag_src.size());
+  D.sdinv32 = m.get<float>(H.sdiag_src.size());
+  D.rhs_s = m.get<double>(H.srow.size() * std::max(1, rmax));
+  D.progress = m.get<unsigned long long>(H.ngroups);
+  D.epoch = m.get<unsigned long long>(1);
+  D.done_count = m.get<unsigned int>(1);
+  D.err = m.get<int>(1);
+  D.partials = m.get<double>(size_t(H.ngroups) * kRMax);
+  D.rmax = rmax;
+  if (m.err != hipSuccess) return fail_hip(pb, m.err, "schedule upload", __LINE__);
+  CK(hipMemsetAsync(D.progress, 0, sizeof(unsigned long long) * H.ngroups, st));
+  CK(hipMemsetAsync(D.epoch, 0, sizeof(unsigned long long), st));
+  CK(hipMemsetAsync(D.done_count, 0, sizeof(unsigned int), st));
+  CK(hipMemsetAsync(D.err, 0, sizeof(int), st));
+  CK(launch_trsv_gather(D, pb->Lval, st));
+  return 0;
+}
+
+// Largest R in {16, 8, 1} whose LDS footprint fits.
+int fit_rmax(const stokes_problem* pb, int nslots, bool fp32) {
+  const int rs[3] = {16, 8, 1};
+  for (int r : rs)
+    if (trsv_shmem_bytes(nslots, fp32, r) <= pb->lds_max) return r;
+  return 0;
+}
+
+// Largest rows-per-level of any (group, level) of a strip partition, over both solves.
+int max_rows_per_level(const stokes_problem* pb, const std::vector<int32_t>& group_of, int ngroups) {
+  int worst = 0;
+  for (int dir = 0; dir < 2; ++dir) {
+    const auto& lev = dir == 0 ? pb->lev_fwd : pb->lev_bwd;
+    int nl = 0;
+    for (int32_t l : lev) nl = std::max(nl, l + 1);
+    std::vector<int32_t> cnt(size_t(ngroups) * nl, 0);
+    for (int64_t i = 0; i < pb->S.n_u; ++i) worst = std::max(worst, ++cnt[size_t(group_of[i]) * nl + lev[i]]);
+  }
+  return worst;
+}
+
+// Schedule pair usable for R columns in the given precision (built on first use).  The
+// strip height is the largest that keeps one step per level (<= kTrsvRPS rows of a level
+// per group), reduced further while the LDS window does not fit R columns or the groups
+// cannot all be resident at once.
+int get_schedule(stokes_problem* pb, int R, bool fp32, SchedPair** out) {
+  for (auto& sp : pb->scheds)
+    if ((fp32 ? sp->rmax32 : sp->rmax64) >= R) {
+      *out = sp.get();
+      return 0;
+    }
+  if (pb->lev_bwd.empty()) {
+    // backward levels: row i after every j > i with L_ji != 0
+    const int64_t n = pb->S.n_u;
+    pb->lev_bwd.assign(n, 0);
+    for (int64_t j = n - 1; j >= 0; --j) {
+      const int lj = pb->lev_bwd[j];
+      for (int32_t k = pb->L.rowptr[j]; k < pb->L.rowptr[j + 1] - 1; ++k) {
+        int32_t& li = pb->lev_bwd[pb->L.col[k]];
+        li = std::max(li, lj + 1);
+      }
+    }
+  }
+  const int strips[8] = {32, 16, 8, 4, 2, 1, 0, 0};
+  int first = 0;
+  for (int si = 0; strips[si] > 0; ++si) {
+    std::vector<int32_t> group_of;
+    int ngroups = 0;
+    strip_groups(pb->S, strips[si], group_of, &ngroups);
+    if (max_rows_per_level(pb, group_of, ngroups) <= kTrsvRPS) {
+      first = si;
+      break;
+    }
+    first = si;
+  }
+  for (int si = first; strips[si] > 0; ++si) {
+    const int strip = strips[si];
+    bool exists = false;
+    for (auto& sp : pb->scheds) exists |= (sp->strip == strip);
+    if (exists) continue;
+    std::vector<int32_t> group_of;
+    int ngroups = 0;
+    strip_groups(pb->S, strip, group_of, &ngroups);
+    TrsvSchedHost hf, hb;
+    std::string e;
+    if (!build_trsv_schedule(pb->L, pb->S.n_u, +1, group_of, ngroups, hf, e) ||
+        !build_trsv_schedule(pb->L, pb->S.n_u, -1, group_of, ngroups, hb, e))
+      return fail(pb, STOKES_EINVAL, e);
+    const int nsl = std::max(hf.nslots, hb.nslots);
+    auto sp = std::make_unique<SchedPair>();
+    sp->strip = strip;
+    sp->rmax64 = fit_rmax(pb, nsl, false);
+    sp->rmax32 = fit_rmax(pb, nsl, true);
+    // all groups of a cooperative launch must be resident together
+    auto resident = [&](int r, bool f32) {
+      if (r == 0) return 0;
+      const size_t sh = trsv_shmem_bytes(nsl, f32, r);
+      const int per_cu = int(std::max<size_t>(1, std::min<size_t>(8, pb->lds_per_cu / std::max<size_t>(sh, 1))));
+      return ngroups <= per_cu * pb->num_cu ? r : 0;
+    };
+    sp->rmax64 = resident(sp->rmax64, false);
+    sp->rmax32 = resident(sp->rmax32, true);
+    if (sp->rmax64 == 0 && sp->rmax32 == 0) continue;
+    int rc = upload_schedule(pb, hf, sp->fwd, std::max(sp->rmax64, sp->rmax32));
+    if (rc) return rc;
+    rc = upload_schedule(pb, hb, sp->bwd, std::max(sp->rmax64, sp->rmax32));
+    if (rc) return rc;
+    CK(hipStreamSynchronize(pb->stream));
+    pb->scheds.push_back(std::move(sp));
+    SchedPair* last = pb->scheds.back().get();
+    if ((fp32 ? last->rmax32 : last->rmax64) >= R) {
+      *out = last;
+      return 0;
+    }
+  }
+  return fail(pb, STOKES_EINVAL, "no triangular-solve schedule fits the LDS budget for this batch width");
+}
+
+int get_work(stokes_problem* pb, int R, bool fp32, Work** out) {
+  const int key = R * 2 + (fp32 ? 1 : 0);
+  auto it = pb->work.find(key);
+  if (it != pb->work.end()) {
+    *out = &it->second;
+    return 0;
+  }
+  Work W;
+  W.R = R;
+  W.fp32 = fp32;
+  const size_t es = fp32 ? sizeof(float) : sizeof(double);
+  const size_t n = size_t(pb->S.n_u + pb->S.n_p) * R;
+  const size_t nu = size_t(pb->S.n_u) * R;
+  auto get = [&](size_t cnt) { return pb->mem.get<unsigned char>(cnt * es); };
+  W.v[0] = get(n);
+  W.v[1] = get(n);
+  W.z[0] = get(n);
+  W.z[1] = get(n);
+  W.w[0] = get(n);
+  W.w[1] = get(n);
+  W.x = get(n);
+  W.q = get(n);
+  W.b = get(n);
+  W.y = get(n);
+  W.pr = get(nu);
+  W.pp = get(nu);
+  W.pq = get(nu);
+  W.pz = get(nu);
+  if (pb->mem.err != hipSuccess) return fail_hip(pb, pb->mem.err, "workspace allocation", __LINE__);
+  pb->work[key] = W;
+  *out = &pb->work[key];
+  return 0;
+}
+
+int check_trsv_err(stokes_problem* pb, const SchedPair* sp) {
+  int e1 = 0, e2 = 0;
+  CK(hipMemcpyAsync(&e1, sp->fwd.err, sizeof(int), hipMemcpyDeviceToHost, pb->stream));
+  CK(hipMemcpyAsync(&e2, sp->bwd.err, sizeof(int), hipMemcpyDeviceToHost, pb->stream));
+  CK(hipStreamSynchronize(pb->stream));
+  if (e1 || e2) {
+    hipMemsetAsync(sp->fwd.err, 0, sizeof(int), pb->stream);
+    hipMemsetAsync(sp->bwd.err, 0, sizeof(int), pb->stream);
+    hipStreamSynchronize(pb->stream);
+    return fail(pb, STOKES_EHIP, "triangular solve: a device-side wait exceeded its spin limit");
+  }
+  return 0;
+}
+
+// Velocity block of the preconditioner: zout_u = M_A^{-1} vin_u, and the dot v_u . z_u
+// into dot_out[R].  skip: device flag (all columns done) or null.
+template <typename T>
+int precond_velocity(stokes_problem* pb, int precond, Work& W, SchedPair* sp, const T* vin, T* zout,
+                     double* dot_out, const int* skip, const MinresState* outer_st, int* inner_total) {
+  const int R = W.R;
+  const bool fp32 = W.fp32;
+  hipStream_t st = pb->stream;
+  const int64_t n_u = pb->S.n_u;
+  if (precond == STOKES_PC_IC0) {
+    CK(launch_trsv(sp->fwd, fp32, R, vin, W.y, nullptr, nullptr, skip, st));
+    CK(launch_trsv(sp->bwd, fp32, R, W.y, zout, vin, dot_out, skip, st));
+    return 0;
+  }
+  if (precond == STOKES_PC_ICPCG) {
+    const T* val = fp32 ? (const T*)pb->val32 : (const T*)pb->val;
+    PcgScalars& s = pb->pcg;
+    CK(pcg_init<T>(R, n_u, vin, (T*)W.pr, zout, s, skip, st));
+    CK(launch_trsv(sp->fwd, fp32, R, W.pr, W.y, nullptr, nullptr, skip, st));
+    CK(launch_trsv(sp->bwd, fp32, R, W.y, W.pz, W.pr, s.rho, skip, st));
+    CK(pcg_init2<T>(R, n_u, (const T*)W.pz, (T*)W.pp, s, pb->inner_tol, pb->maxit_inner, skip, outer_st, st));
+    int ip = 0;
+    for (int it = 0; it < pb->maxit_inner; it += 4) {
+      for (int k = 0; k < 4; ++k) {
+        CK(pcg_spmv<T>(R, n_u, pb->rowptr, pb->aend, pb->col, val, (const T*)W.pp, (T*)W.pq, s, st));
+        CK(pcg_axpy<T>(R, n_u, (const T*)W.pp, (const T*)W.pq, zout, (T*)W.pr, s, ip, st));
+        CK(launch_trsv(sp->fwd, fp32, R, W.pr, W.y, nullptr, nullptr, s.alldone, st));
+        CK(launch_trsv(sp->bwd, fp32, R, W.y, W.pz, W.pr, s.rho + (1 - ip) * kRMax, s.alldone, st));
+        CK(pcg_pupdate<T>(R, n_u, (const T*)W.pz, (T*)W.pp, s, ip, st));
+        ip = 1 - ip;
+      }
+      int done = 0;
+      CK(hipMemcpyAsync(&done, s.alldone, sizeof(int), hipMemcpyDeviceToHost, st));
+      CK(hipStreamSynchronize(st));
+      if (done) break;
+    }
+    CK(dot<T, T>(R, 0, n_u, vin, zout, pb->partials, pb->counter, dot_out, st));
+    (void)inner_total;
+    return 0;
+  }
+  return 0;  // Jacobi: handled inside the vector kernels
+}
+
+struct RunOut {
+  int iters[kRMax];
+  int status[kRMax];
+  double eta[kRMax], gamma1[kRMax];
+};
+
+// MINRES on Acal x = b (b in W.b, x out in W.x), R columns, precision of W.
+template <typename T>
+int minres_run(stokes_problem* pb, Work& W, int precond, double tol, int maxit, RunOut& ro) {
+  const int R = W.R;
+  const bool fp32 = W.fp32;
+  hipStream_t st = pb->stream;
+  const int64_t n_u = pb->S.n_u, n = n_u + pb->S.n_p;
+  SchedPair* sp = nullptr;
+  if (precond != STOKES_PC_JACOBI) {
+    int rc = get_schedule(pb, R, fp32, &sp);
+    if (rc) return rc;
+  }
+  const T* val = fp32 ? (const T*)pb->val32 : (const T*)pb->val;
+  const double* diagA = precond == STOKES_PC_JACOBI ? pb->diagA : nullptr;
+  const double two_nu = 2.0 * pb->nu;
+  MrScalars& s = pb->mr;
+  T* v[2] = {(T*)W.v[0], (T*)W.v[1]};
+  T* z[2] = {(T*)W.z[0], (T*)W.z[1]};
+  T* w[2] = {(T*)W.w[0], (T*)W.w[1]};
+  T* x = (T*)W.x;
+  T* q = (T*)W.q;
+  // reset the PCG column totals
+  if (precond == STOKES_PC_ICPCG) CK(hipMemsetAsync(pb->pcg.st, 0, sizeof(PcgState) * kRMax, st));
+  CK(mr_init_vec<T>(R, n, n_u, (const T*)W.b, v[0], v[1], w[0], w[1], x, z[0], pb->diagQ, diagA, two_nu, s, st));
+  // the outer state is not initialised yet: no outer-done test for this application
+  int rc = precond_velocity<T>(pb, precond, W, sp, v[0], z[0], s.red + RED_G2U * kRMax, nullptr, nullptr, nullptr);
+  if (rc) return rc;
+  CK(mr_init_state(R, s, tol, maxit, st));
+  int j = 1;
+  for (;;) {
+    for (int m = 0; m < pb->check_every; ++m, ++j) {
+      const int p = (j - 1) & 1;
+      CK(mr_spmv<T>(R, n, pb->rowptr, pb->col, val, z[p], q, s, p, st));
+      CK(mr_lanczos<T>(R, n, n_u, q, v[p], v[1 - p], z[1 - p], pb->diagQ, diagA, two_nu, s, p, st));
+      rc = precond_velocity<T>(pb, precond, W, sp, v[1 - p], z[1 - p],
+                               s.red + ((size_t)p * RED_KINDS + RED_G2U) * kRMax, s.alldone + p, s.st + p * kRMax,
+                               nullptr);
+      if (rc) return rc;
+      CK(mr_update<T>(R, n, z[p], w[p], w[1 - p], x, s, p, st));
+    }
+    int done = 0;
+    CK(hipMemcpyAsync(&done, s.alldone + ((j - 1) & 1), sizeof(int), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    if (done || j > maxit + pb->check_every + 1) break;
+  }
+  const int fp = (j - 1) & 1;
+  MinresState hs[kRMax];
+  CK(hipMemcpyAsync(hs, s.st + fp * kRMax, sizeof(MinresState) * kRMax, hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  for (int c = 0; c < R; ++c) {
+    ro.iters[c] = hs[c].iter;
+    ro.status[c] = hs[c].status;
+    ro.eta[c] = hs[c].eta;
+    ro.gamma1[c] = hs[c].gamma1;
+  }
+  if (sp) {
+    rc = check_trsv_err(pb, sp);
+    if (rc) return rc;
+  }
+  return 0;
+}
+
+// Zero-mean pressure of the interleaved double vector x (R columns).
+int project_pressure(stokes_problem* pb, int R, double* x) {
+  const int64_t n_u = pb->S.n_u, n_p = pb->S.n_p;
+  R_SWITCH(R, hipLaunchKernelGGL((k_pdot<RR>), dim3(vec_blocks(n_p)), dim3(kVT), 0, pb->stream, n_p, n_u, pb->w, x,
+                                 pb->partials, pb->counter, pb->scratch));
+  CK(hipGetLastError());
+  CK(sub_mean<double>(R, n_u, n_u + n_p, x, pb->scratch, pb->w1, pb->stream));
+  return 0;
+}
+
+// True residual norms of the interleaved double solution x for right-hand side b:
+// rel2[c] = ||b - Acal x||_2/||b||_2 and relM[c] = ||r||_{M^-1}/||b||_{M^-1} (IC(0) or
+// Jacobi M).  Uses work buffers of the FP64 workspace W (q, y, and v[0] as scratch).
+int true_residuals(stokes_problem* pb, Work& W, int precond, const double* b, const double* x, double* rel2,
+                   double* relM) {
+  const int R = W.R;
+  hipStream_t st = pb->stream;
+  const int64_t n_u = pb->S.n_u, n = n_u + pb->S.n_p;
+  double* r = (double*)W.q;
+  double* out = pb->scratch;  // [0..2R) norms, [2R..4R) r M r parts, [4R..6R) b M b parts
+  CK(spmv_resid<double>(R, n, pb->rowptr, nullptr, pb->col, pb->val, x, b, r, pb->partials, pb->counter, out, st));
+  const int pcl = (precond == STOKES_PC_JACOBI) ? STOKES_PC_JACOBI : STOKES_PC_IC0;
+  for (int pass = 0; pass < 2; ++pass) {
+    const double* vec = pass == 0 ? r : b;
+    double* o = out + 2 * R + pass * 2 * R;
+    R_SWITCH(R, hipLaunchKernelGGL((k_diag_wsq<RR>), dim3(vec_blocks(n)), dim3(kVT), 0, st, n_u, n, vec, pb->diagQ,
+                                   pcl == STOKES_PC_JACOBI ? pb->diagA : nullptr, 2.0 * pb->nu, pb->partials,
+                                   pb->counter, o));
+    CK(hipGetLastError());
+    if (pcl == STOKES_PC_IC0) {
+      SchedPair* sp = nullptr;
+      int rc = get_schedule(pb, R, false, &sp);
+      if (rc) return rc;
+      CK(launch_trsv(sp->fwd, false, R, vec, W.y, nullptr, nullptr, nullptr, st));
+      CK(launch_trsv(sp->bwd, false, R, W.y, W.v[0], vec, o + R, nullptr, st));
+    }
+  }
+  double h[6 * kRMax];
+  CK(hipMemcpyAsync(h, out, sizeof(double) * 6 * R, hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  for (int c = 0; c < R; ++c) {
+    const double rr = h[c], bb = h[R + c];
+    const double rM = h[2 * R + c] + h[3 * R + c], bM = h[4 * R + c] + h[5 * R + c];
+    rel2[c] = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+    relM[c] = bM > 0 ? std::sqrt(std::max(0.0, rM) / bM) : 0.0;
+  }
+  return 0;
+}
+
+int validate_vec(stokes_problem* pb, const void* p, const char* name) {
+  if (p == nullptr) return fail(pb, STOKES_EINVAL, std::string("null pointer: ") + name);
+  return 0;
+}
+
+int round_r(int nrhs) { return nrhs <= 1 ? 1 : (nrhs <= 8 ? 8 : 16); }
+
+// Common driver: RHS already in the FP64 workspace W64.b (interleaved, R columns).
+// Solves in the requested precision; the solution lands in W64.x (FP64, projected).
+int solve_core(stokes_problem* pb, Work& W64, int precond, int precision, double tol, stokes_info* infos, int nrhs) {
+  const int R = W64.R;
+  hipStream_t st = pb->stream;
+  const int64_t n_u = pb->S.n_u, n = n_u + pb->S.n_p;
+  RunOut ro;
+  int iters_total[kRMax] = {0};
+  int status[kRMax] = {0};
+  double eta_rel[kRMax] = {0};
+  if (precision == STOKES_FP64) {
+    int rc = minres_run<double>(pb, W64, precond, tol, pb->maxit_outer, ro);
+    if (rc) return rc;
+    for (int c = 0; c < R; ++c) {
+      iters_total[c] = ro.iters[c];
+      status[c] = ro.status[c];
+      eta_rel[c] = ro.gamma1[c] > 0 ? std::fabs(ro.eta[c]) / ro.gamma1[c] : 0.0;
+    }
+    int rc2 = project_pressure(pb, R, (double*)W64.x);
+    if (rc2) return rc2;
+  } else {
+    // Iterative refinement: FP64 residual, FP32 inner MINRES, FP64 accumulation.
+    Work* W32 = nullptr;
+    int rc = get_work(pb, R, true, &W32);
+    if (rc) return rc;
+    double* x64 = (double*)W64.x;
+    double* r64 = (double*)W64.z[1];
+    double* b64 = (double*)W64.b;
+    hipLaunchKernelGGL(k_fill<double>, dim3(1024), dim3(256), 0, st, int64_t(n * R), x64, 0.0);
+    CK(hipMemcpyAsync(r64, b64, sizeof(double) * n * R, hipMemcpyDeviceToDevice, st));
+    double rel2[kRMax], relM[kRMax];
+    bool conv = false;
+    for (int ir = 0; ir < 30 && !conv; ++ir) {
+      CK(convert<double, float>(int64_t(n * R), r64, (float*)W32->b, st));
+      rc = minres_run<float>(pb, *W32, precond, pb->mixed_inner_tol, pb->maxit_outer, ro);
+      if (rc) return rc;
+      for (int c = 0; c < R; ++c) iters_total[c] += ro.iters[c];
+      CK(accumulate<float>(R, int64_t(n * R), x64, (const float*)W32->x, st));
+      rc = project_pressure(pb, R, x64);
+      if (rc) return rc;
+      rc = true_residuals(pb, W64, precond, b64, x64, rel2, relM);
+      if (rc) return rc;
+      // refresh r64 = b - Acal x (true_residuals left it in W64.q)
+      CK(hipMemcpyAsync(r64, W64.q, sizeof(double) * n * R, hipMemcpyDeviceToDevice, st));
+      conv = true;
+      for (int c = 0; c < R; ++c) conv &= (relM[c] <= tol);
+    }
+    for (int c = 0; c < R; ++c) {
+      status[c] = relM[c] <= tol ? 0 : STOKES_NOT_CONVERGED;
+      eta_rel[c] = relM[c];
+    }
+  }
+  if (infos) {
+    double rel2[kRMax], relM[kRMax];
+    int rc = true_residuals(pb, W64, precond, (const double*)W64.b, (const double*)W64.x, rel2, relM);
+    if (rc) return rc;
+    for (int c = 0; c < nrhs; ++c) {
+      infos[c].iters = iters_total[c];
+      infos[c].status = status[c];
+      infos[c].ic_shift_steps = pb->ic_shift_steps;
+      infos[c].relres_est = eta_rel[c];
+      infos[c].relres_true_2 = rel2[c];
+      infos[c].relres_true_Minv = relM[c];
+      infos[c].setup_ms = pb->setup_ms;
+      infos[c].inner_iters_total = 0;
+    }
+    if (precond == STOKES_PC_ICPCG) {
+      PcgState ps[kRMax];
+      CK(hipMemcpyAsync(ps, pb->pcg.st, sizeof(PcgState) * kRMax, hipMemcpyDeviceToHost, st));
+      CK(hipStreamSynchronize(st));
+      for (int c = 0; c < nrhs; ++c) infos[c].inner_iters_total = ps[c].total;
+    }
+  }
+  int worst = 0;
+  for (int c = 0; c < nrhs; ++c) {
+    if (status[c] < 0) return fail(pb, status[c], "MINRES breakdown (negative gamma^2)");
+    if (status[c] > 0) worst = STOKES_NOT_CONVERGED;
+  }
+  if (worst) pb->err = "MINRES did not reach the tolerance within the iteration limit";
+  return worst;
+}
+
+int check_args_solve(stokes_problem* pb, double tol, int precond, int precision) {
+  if (!(tol > 0.0) || !(tol < 1.0)) return fail(pb, STOKES_EINVAL, "tol must be in (0, 1)");
+  if (precond < 0 || precond > 2) return fail(pb, STOKES_EINVAL, "unknown preconditioner");
+  if (precision != STOKES_FP64 && precision != STOKES_MIXED) return fail(pb, STOKES_EINVAL, "unknown precision");
+  return 0;
+}
+
+// NaN/Inf check of a device input through a reduction of squares.
+int check_finite(stokes_problem* pb, int R, const double* interleaved, int64_t len) {
+  CK(dot<double, double>(1, 0, len * R, interleaved, interleaved, pb->partials, pb->counter, pb->scratch + 60,
+                         pb->stream));
+  double s = 0.0;
+  CK(hipMemcpyAsync(&s, pb->scratch + 60, sizeof(double), hipMemcpyDeviceToHost, pb->stream));
+  CK(hipStreamSynchronize(pb->stream));
+  if (!std::isfinite(s)) return fail(pb, STOKES_EINVAL, "input contains NaN or Inf");
+  return 0;
+}
+
+}  // namespace
+
+// ===========================================================================
+// extern "C" entry points
+// ===========================================================================
+extern "C" {
+
+static int stokes_setup_impl(int n, int p, int dim, double nu, stokes_problem* pb);
+
+int stokes_setup(int n, int p, int dim, double nu, stokes_problem** out) {
+  if (out == nullptr) return STOKES_EINVAL;
+  *out = nullptr;
+  if (n < 1 || n > 4096 || p < 1 || p > 3 || (dim != 2 && dim != 3) || !(nu > 0.0) || !std::isfinite(nu))
+    return STOKES_EINVAL;
+  stokes_problem* pb = new stokes_problem();
+  const int rc = stokes_setup_impl(n, p, dim, nu, pb);
+  if (rc != 0) {
+    if (!pb->err.empty()) fprintf(stderr, "stokes_setup: %s\n", pb->err.c_str());
+    (void)hipStreamSynchronize(pb->stream);
+    delete pb;
+    return rc;
+  }
+  *out = pb;
+  return 0;
+}
+
+static int stokes_setup_impl(int n, int p, int dim, double nu, stokes_problem* pb) {
+  auto t0 = std::chrono::steady_clock::now();
+  pb->S = make_spaces(n, p, dim);
+  pb->nu = nu;
+  pb->cpen = 5.0 * (p + 1);
+  int dev = 0;
+  CK(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  CK(hipGetDeviceProperties(&prop, dev));
+  pb->lds_max = prop.sharedMemPerBlock;
+  pb->lds_per_cu = prop.maxSharedMemoryPerMultiProcessor > 0 ? prop.maxSharedMemoryPerMultiProcessor
+                                                              : prop.sharedMemPerBlock;
+  pb->num_cu = prop.multiProcessorCount;
+  std::string e;
+  if (build_saddle_pattern(pb->S, pb->P, e) != 0) return fail(pb, STOKES_EINVAL, e);
+  build_lower_pattern(pb->S, pb->P, pb->L);
+  {
+    int maxrow = 0;
+    for (int64_t i = 0; i < pb->S.n_u; ++i) maxrow = std::max(maxrow, pb->L.rowptr[i + 1] - pb->L.rowptr[i]);
+    if (maxrow > 128) return fail(pb, STOKES_EINVAL, "IC(0) rows longer than 128 entries are not supported");
+  }
+  const int64_t nall = pb->S.n_u + pb->S.n_p;
+  pb->nnz = int64_t(pb->P.col.size());
+  pb->nnzL = int64_t(pb->L.col.size());
+  hipStream_t st = pb->stream;
+  DevAlloc& m = pb->mem;
+  pb->rowptr = m.upload(pb->P.rowptr, st);
+  pb->col = m.upload(pb->P.col, st);
+  pb->aend = m.upload(pb->P.aend, st);
+  pb->val = m.get<double>(pb->nnz);
+  pb->val32 = m.get<float>(pb->nnz);
+  pb->diagQ = m.get<double>(pb->S.n_p);
+  pb->w = m.get<double>(pb->S.n_p);
+  pb->diagA = m.get<double>(pb->S.n_u);
+  pb->Lrowptr = m.upload(pb->L.rowptr, st);
+  pb->Lcol = m.upload(pb->L.col, st);
+  pb->Lsrc = m.upload(pb->L.src, st);
+  pb->Lval = m.get<double>(pb->nnzL);
+  pb->flag = m.get<int>(4);
+  pb->scratch = m.get<double>(128);
+  pb->partials = m.get<double>(2048 * 2 * kRMax + 64);
+  pb->counter = m.get<unsigned int>(16);
+  pb->mr.st = m.get<MinresState>(2 * kRMax);
+  pb->mr.alldone = m.get<int>(2);
+  pb->mr.red = m.get<double>(2 * RED_KINDS * kRMax);
+  pb->mr.partials = pb->partials;
+  pb->mr.counter = pb->counter;
+  pb->pcg.st = m.get<PcgState>(kRMax);
+  pb->pcg.alldone = m.get<int>(1);
+  pb->pcg.rho = m.get<double>(2 * kRMax);
+  pb->pcg.pq = m.get<double>(kRMax);
+  pb->pcg.rr = m.get<double>(kRMax);
+  pb->pcg.partials = pb->partials;
+  pb->pcg.counter = pb->counter + 1;
+  if (m.err != hipSuccess) return fail_hip(pb, m.err, "allocation", __LINE__);
+  CK(hipMemsetAsync(pb->counter, 0, 16 * sizeof(unsigned int), st));
+  CK(hipMemsetAsync(pb->mr.red, 0, 2 * RED_KINDS * kRMax * sizeof(double), st));
+  CK(hipMemsetAsync(pb->pcg.st, 0, kRMax * sizeof(PcgState), st));
+  // assembly (Gauss quadrature on the device)
+  CK(assemble_saddle(pb->S, nu, pb->cpen, pb->rowptr, pb->col, pb->val, pb->diagQ, pb->w, st));
+  hipLaunchKernelGGL(k_gather_diag, dim3(256), dim3(256), 0, st, pb->S.n_u, pb->Lrowptr, pb->Lsrc, pb->val, pb->diagA);
+  CK(hipGetLastError());
+  CK(convert<double, float>(pb->nnz, pb->val, pb->val32, st));
+  // w . 1
+  hipLaunchKernelGGL((k_pdot<1>), dim3(vec_blocks(pb->S.n_p)), dim3(kVT), 0, st, pb->S.n_p, int64_t(0), nullptr, pb->w,
+                     pb->partials, pb->counter, pb->scratch);
+  CK(hipGetLastError());
+  CK(hipMemcpyAsync(&pb->w1, pb->scratch, sizeof(double), hipMemcpyDeviceToHost, st));
+  // IC(0) with the diagonal-shift retries
+  {
+    std::vector<int32_t>& lev = pb->lev_fwd;
+    forward_levels(pb->L, pb->S.n_u, lev, &pb->nlev_fwd);
+    pb->level_ptr.assign(pb->nlev_fwd + 1, 0);
+    for (int64_t i = 0; i < pb->S.n_u; ++i) pb->level_ptr[lev[i] + 1]++;
+    for (int l = 0; l < pb->nlev_fwd; ++l) pb->level_ptr[l + 1] += pb->level_ptr[l];
+    std::vector<int32_t> rows(pb->S.n_u), fillp(pb->level_ptr.begin(), pb->level_ptr.end() - 1);
+    for (int64_t i = 0; i < pb->S.n_u; ++i) rows[fillp[lev[i]]++] = int32_t(i);
+    pb->level_rows = m.upload(rows, st);
+    if (m.err != hipSuccess) return fail_hip(pb, m.err, "allocation", __LINE__);
+    const double alphas[4] = {0.0, 1e-3, 1e-2, 1e-1};
+    bool ok = false;
+    for (int s = 0; s < 4 && !ok; ++s) {
+      CK(ic0_factor(pb->S.n_u, pb->nnzL, pb->Lsrc, pb->Lrowptr, pb->Lcol, pb->val, alphas[s], pb->Lval,
+                    pb->level_rows, pb->level_ptr, pb->flag, st));
+      int fl = 0;
+      CK(hipMemcpyAsync(&fl, pb->flag, sizeof(int), hipMemcpyDeviceToHost, st));
+      CK(hipStreamSynchronize(st));
+      if (fl < 0) {
+        ok = true;
+        pb->ic_shift_steps = s;
+      }
+    }
+    if (!ok) return fail(pb, STOKES_EBREAKDOWN, "IC(0) breakdown after the last diagonal shift");
+  }
+  // triangular-solve schedule for single right-hand sides
+  {
+    SchedPair* sp = nullptr;
+    int rc = get_schedule(pb, 1, false, &sp);
+    if (rc) return rc;
+  }
+  CK(hipStreamSynchronize(st));
+  auto t1 = std::chrono::steady_clock::now();
+  pb->setup_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  return 0;
+}
+
+int stokes_sizes(const stokes_problem* pb, int64_t* n_u, int64_t* n_p) {
+  if (!pb) return STOKES_EINVAL;
+  if (n_u) *n_u = pb->S.n_u;
+  if (n_p) *n_p = pb->S.n_p;
+  return 0;
+}
+
+int stokes_set_stream(stokes_problem* pb, void* s) {
+  if (!pb) return STOKES_EINVAL;
+  pb->stream = static_cast<hipStream_t>(s);
+  return 0;
+}
+
+int stokes_set_nu(stokes_problem* pb, double nu) {
+  if (!pb || !(nu > 0.0) || !std::isfinite(nu)) return fail(pb, STOKES_EINVAL, "nu must be positive");
+  const double r = nu / pb->nu;
+  hipStream_t st = pb->stream;
+  hipLaunchKernelGGL(k_scale_A, dim3(1024), dim3(256), 0, st, pb->S.n_u, pb->rowptr, pb->aend, pb->val, r);
+  CK(hipGetLastError());
+  CK(scale(pb->nnzL, pb->Lval, std::sqrt(r), st));
+  hipLaunchKernelGGL(k_gather_diag, dim3(256), dim3(256), 0, st, pb->S.n_u, pb->Lrowptr, pb->Lsrc, pb->val, pb->diagA);
+  CK(hipGetLastError());
+  CK(convert<double, float>(pb->nnz, pb->val, pb->val32, st));
+  for (auto& sp : pb->scheds) {
+    CK(launch_trsv_gather(sp->fwd, pb->Lval, st));
+    CK(launch_trsv_gather(sp->bwd, pb->Lval, st));
+  }
+  CK(hipStreamSynchronize(st));
+  pb->nu = nu;
+  return 0;
+}
+
+int stokes_set_inner_tol(stokes_problem* pb, double rtol) {
+  if (!pb) return STOKES_EINVAL;
+  if (rtol > 0.0) pb->inner_tol = rtol;
+  return 0;
+}
+
+int stokes_set_maxit(stokes_problem* pb, int outer, int inner) {
+  if (!pb) return STOKES_EINVAL;
+  if (outer > 0) pb->maxit_outer = outer;
+  if (inner > 0) pb->maxit_inner = inner;
+  return 0;
+}
+
+int stokes_load(stokes_problem* pb, const stokes_forcing* spec, int nrhs, double* f_dev) {
+  if (!pb || !spec || !f_dev || nrhs < 1) return fail(pb, STOKES_EINVAL, "bad arguments to stokes_load");
+  const int M = spec->nmodes;
+  if (M < 0 || M > 64 || (M > 0 && (!spec->amp || !spec->wave || !spec->phase)))
+    return fail(pb, STOKES_EINVAL, "bad forcing mode tables");
+  const int dim = pb->S.dim;
+  DevAlloc tmp;
+  double* amp = tmp.get<double>(size_t(nrhs) * dim * std::max(M, 1));
+  int32_t* wave = tmp.get<int32_t>(size_t(nrhs) * dim * std::max(M, 1));
+  double* phase = tmp.get<double>(size_t(nrhs) * dim * std::max(M, 1));
+  if (tmp.err != hipSuccess) {
+    tmp.release();
+    return fail_hip(pb, tmp.err, "stokes_load allocation", __LINE__);
+  }
+  hipStream_t st = pb->stream;
+  if (M > 0) {
+    CK(hipMemcpyAsync(amp, spec->amp, sizeof(double) * nrhs * dim * M, hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(wave, spec->wave, sizeof(int32_t) * nrhs * dim * M, hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(phase, spec->phase, sizeof(double) * nrhs * dim * M, hipMemcpyHostToDevice, st));
+  }
+  hipError_t e = assemble_load(pb->S, pb->nu, spec->manufactured, M, nrhs, amp, wave, phase, f_dev, st);
+  tmp.release();
+  if (e != hipSuccess) return fail_hip(pb, e, "assemble_load", __LINE__);
+  return 0;
+}
+
+int stokes_solve_batched(stokes_problem* pb, int nrhs, const double* F, double* U, double* P, double tol, int precond,
+                         int precision, stokes_info* infos) {
+  if (!pb) return STOKES_EINVAL;
+  if (nrhs < 1 || nrhs > kRMax) return fail(pb, STOKES_EINVAL, "nrhs must be in 1..16");
+  int rc = check_args_solve(pb, tol, precond, precision);
+  if (rc) return rc;
+  if ((rc = validate_vec(pb, F, "F")) || (rc = validate_vec(pb, U, "U")) || (rc = validate_vec(pb, P, "P"))) return rc;
+  const int R = round_r(nrhs);
+  Work* W = nullptr;
+  if ((rc = get_work(pb, R, false, &W))) return rc;
+  hipStream_t st = pb->stream;
+  const int64_t n_u = pb->S.n_u, n_p = pb->S.n_p, n = n_u + n_p;
+  hipEvent_t e0, e1;
+  CK(hipEventCreate(&e0));
+  CK(hipEventCreate(&e1));
+  CK(hipEventRecord(e0, st));
+  hipLaunchKernelGGL(k_fill<double>, dim3(1024), dim3(256), 0, st, int64_t(n * R), (double*)W->b, 0.0);
+  CK(hipGetLastError());
+  // columns 0..nrhs-1 of F into the velocity rows; pressure rows stay zero
+  if (R == nrhs) {
+    CK(to_interleaved<double, double>(R, n_u, F, n_u, (double*)W->b, 0, st));
+  } else {
+    for (int c = 0; c < nrhs; ++c)
+      CK(hipMemcpy2DAsync((double*)W->b + c, sizeof(double) * R, F + size_t(c) * n_u, sizeof(double), sizeof(double),
+                          n_u, hipMemcpyDeviceToDevice, st));
+  }
+  if ((rc = check_finite(pb, R, (const double*)W->b, n))) return rc;
+  rc = solve_core(pb, *W, precond, precision, tol, infos, nrhs);
+  if (rc < 0) return rc;
+  const int rc_solve = rc;
+  if (R == nrhs) {
+    CK(from_interleaved<double, double>(R, n_u, (const double*)W->x, 0, U, n_u, st));
+    CK(from_interleaved<double, double>(R, n_p, (const double*)W->x, n_u, P, n_p, st));
+  } else {
+    for (int c = 0; c < nrhs; ++c) {
+      CK(hipMemcpy2DAsync(U + size_t(c) * n_u, sizeof(double), (const double*)W->x + c, sizeof(double) * R,
+                          sizeof(double), n_u, hipMemcpyDeviceToDevice, st));
+      CK(hipMemcpy2DAsync(P + size_t(c) * n_p, sizeof(double), (const double*)W->x + size_t(n_u) * R + c,
+                          sizeof(double) * R, sizeof(double), n_p, hipMemcpyDeviceToDevice, st));
+    }
+  }
+  CK(hipEventRecord(e1, st));
+  CK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  CK(hipEventElapsedTime(&ms, e0, e1));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (infos)
+    for (int c = 0; c < nrhs; ++c) infos[c].solve_ms = ms;
+  return rc_solve;
+}
+
+int stokes_solve_precision(stokes_problem* pb, const double* f, double* u, double* pr, double tol, int precond,
+                           int precision, stokes_info* info) {
+  return stokes_solve_batched(pb, 1, f, u, pr, tol, precond, precision, info);
+}
+
+int stokes_solve(stokes_problem* pb, const double* f, double* u, double* pr, double tol, int precond,
+                 stokes_info* info) {
+  return stokes_solve_batched(pb, 1, f, u, pr, tol, precond, STOKES_FP64, info);
+}
+
+int stokes_solve_adjoint_batched(stokes_problem* pb, int nrhs, const double* G, double* Lambda, double tol, int precond,
+                                 stokes_info* infos) {
+  if (!pb) return STOKES_EINVAL;
+  if (nrhs < 1 || nrhs > kRMax) return fail(pb, STOKES_EINVAL, "nrhs must be in 1..16");
+  int rc = check_args_solve(pb, tol, precond, STOKES_FP64);
+  if (rc) return rc;
+  if ((rc = validate_vec(pb, G, "g")) || (rc = validate_vec(pb, Lambda, "lambda"))) return rc;
+  const int R = round_r(nrhs);
+  Work* W = nullptr;
+  if ((rc = get_work(pb, R, false, &W))) return rc;
+  hipStream_t st = pb->stream;
+  const int64_t n_u = pb->S.n_u, n_p = pb->S.n_p, n = n_u + n_p;
+  hipEvent_t e0, e1;
+  CK(hipEventCreate(&e0));
+  CK(hipEventCreate(&e1));
+  CK(hipEventRecord(e0, st));
+  hipLaunchKernelGGL(k_fill<double>, dim3(1024), dim3(256), 0, st, int64_t(n * R), (double*)W->b, 0.0);
+  CK(hipGetLastError());
+  for (int c = 0; c < nrhs; ++c)
+    CK(hipMemcpy2DAsync((double*)W->b + c, sizeof(double) * R, G + size_t(c) * n, sizeof(double), sizeof(double), n,
+                        hipMemcpyDeviceToDevice, st));
+  if ((rc = check_finite(pb, R, (const double*)W->b, n))) return rc;
+  // P^T g_p = g_p - w (1 . g_p) / (w . 1)
+  R_SWITCH(R, hipLaunchKernelGGL((k_pdot<RR>), dim3(vec_blocks(n_p)), dim3(kVT), 0, st, n_p, n_u, nullptr,
+                                 (const double*)W->b, pb->partials, pb->counter, pb->scratch);
+           hipLaunchKernelGGL((k_sub_w<RR>), dim3(256), dim3(256), 0, st, n_u, n_p, (double*)W->b, pb->w, pb->scratch,
+                              pb->w1));
+  CK(hipGetLastError());
+  rc = solve_core(pb, *W, precond, STOKES_FP64, tol, infos, nrhs);
+  if (rc < 0) return rc;
+  const int rc_solve = rc;
+  for (int c = 0; c < nrhs; ++c)
+    CK(hipMemcpy2DAsync(Lambda + size_t(c) * n, sizeof(double), (const double*)W->x + c, sizeof(double) * R,
+                        sizeof(double), n, hipMemcpyDeviceToDevice, st));
+  CK(hipEventRecord(e1, st));
+  CK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  CK(hipEventElapsedTime(&ms, e0, e1));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (infos)
+    for (int c = 0; c < nrhs; ++c) infos[c].solve_ms = ms;
+  return rc_solve;
+}
+
+int stokes_solve_adjoint(stokes_problem* pb, const double* g, double* lambda, double tol, int precond,
+                         stokes_info* info) {
+  return stokes_solve_adjoint_batched(pb, 1, g, lambda, tol, precond, info);
+}
+
+int stokes_dnu_dot(stokes_problem* pb, int nrhs, const double* lam_u, const double* u, double* out) {
+  if (!pb || nrhs < 1 || !lam_u || !u || !out) return fail(pb, STOKES_EINVAL, "bad arguments to stokes_dnu_dot");
+  Work* W = nullptr;
+  int rc = get_work(pb, 1, false, &W);
+  if (rc) return rc;
+  hipStream_t st = pb->stream;
+  const int64_t n_u = pb->S.n_u;
+  for (int c = 0; c < nrhs; ++c) {
+    CK(spmv_resid<double>(1, n_u, pb->rowptr, pb->aend, pb->col, pb->val, u + size_t(c) * n_u, nullptr,
+                          (double*)W->q, pb->partials, pb->counter, nullptr, st));
+    CK(dot<double, double>(1, 0, n_u, lam_u + size_t(c) * n_u, (const double*)W->q, pb->partials, pb->counter,
+                           pb->scratch + c, st));
+  }
+  std::vector<double> h(nrhs);
+  CK(hipMemcpyAsync(h.data(), pb->scratch, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  for (int c = 0; c < nrhs; ++c) out[c] = h[c] / pb->nu;
+  return 0;
+}
+
+int stokes_apply(stokes_problem* pb, const double* x, double* y) {
+  if (!pb || !x || !y) return fail(pb, STOKES_EINVAL, "bad arguments to stokes_apply");
+  const int64_t n = pb->S.n_u + pb->S.n_p;
+  CK(spmv_resid<double>(1, n, pb->rowptr, nullptr, pb->col, pb->val, x, nullptr, y, pb->partials, pb->counter, nullptr,
+                        pb->stream));
+  CK(hipStreamSynchronize(pb->stream));
+  return 0;
+}
+
+int stokes_apply_precond(stokes_problem* pb, int precond, const double* r, double* y, int* inner_iters) {
+  if (!pb || !r || !y || precond < 0 || precond > 2) return fail(pb, STOKES_EINVAL, "bad arguments");
+  Work* W = nullptr;
+  int rc = get_work(pb, 1, false, &W);
+  if (rc) return rc;
+  hipStream_t st = pb->stream;
+  const int64_t n_u = pb->S.n_u, n = n_u + pb->S.n_p;
+  hipLaunchKernelGGL(k_apply_diag, dim3(1024), dim3(256), 0, st, n_u, n, r, y, pb->diagQ,
+                     precond == STOKES_PC_JACOBI ? pb->diagA : nullptr, 2.0 * pb->nu);
+  CK(hipGetLastError());
+  if (precond != STOKES_PC_JACOBI) {
+    SchedPair* sp = nullptr;
+    if ((rc = get_schedule(pb, 1, false, &sp))) return rc;
+    if (precond == STOKES_PC_ICPCG) CK(hipMemsetAsync(pb->pcg.st, 0, sizeof(PcgState) * kRMax, st));
+    rc = precond_velocity<double>(pb, precond, *W, sp, r, y, pb->scratch + 100, nullptr, nullptr, nullptr);
+    if (rc) return rc;
+    if ((rc = check_trsv_err(pb, sp))) return rc;
+    if (inner_iters && precond == STOKES_PC_ICPCG) {
+      PcgState ps;
+      CK(hipMemcpyAsync(&ps, pb->pcg.st, sizeof(PcgState), hipMemcpyDeviceToHost, st));
+      CK(hipStreamSynchronize(st));
+      *inner_iters = ps.total;
+    }
+  }
+  CK(hipStreamSynchronize(st));
+  return 0;
+}
+
+int stokes_export_csr(stokes_problem* pb, int which, int64_t* nnz, int64_t* rowptr, int32_t* col, double* val) {
+  if (!pb || (which != 0 && which != 1)) return fail(pb, STOKES_EINVAL, "bad arguments to stokes_export_csr");
+  const auto& rp = which == 0 ? pb->P.rowptr : pb->L.rowptr;
+  const auto& cl = which == 0 ? pb->P.col : pb->L.col;
+  if (nnz) *nnz = int64_t(cl.size());
+  if (rowptr)
+    for (size_t i = 0; i < rp.size(); ++i) rowptr[i] = rp[i];
+  if (col) std::memcpy(col, cl.data(), cl.size() * sizeof(int32_t));
+  if (val) {
+    CK(hipMemcpyAsync(val, which == 0 ? pb->val : pb->Lval, cl.size() * sizeof(double), hipMemcpyDeviceToHost,
+                      pb->stream));
+    CK(hipStreamSynchronize(pb->stream));
+  }
+  return 0;
+}
+
+int stokes_export_pressure_mass(stokes_problem* pb, double* diagQ, double* w) {
+  if (!pb) return STOKES_EINVAL;
+  if (diagQ) CK(hipMemcpyAsync(diagQ, pb->diagQ, sizeof(double) * pb->S.n_p, hipMemcpyDeviceToHost, pb->stream));
+  if (w) CK(hipMemcpyAsync(w, pb->w, sizeof(double) * pb->S.n_p, hipMemcpyDeviceToHost, pb->stream));
+  CK(hipStreamSynchronize(pb->stream));
+  return 0;
+}
+
+int stokes_levels(const stokes_problem* pb, int* fwd_levels, int* bwd_levels) {
+  if (!pb || pb->scheds.empty()) return STOKES_EINVAL;
+  if (fwd_levels) *fwd_levels = pb->scheds[0]->fwd.nlevels;
+  if (bwd_levels) *bwd_levels = pb->scheds[0]->bwd.nlevels;
+  return 0;
+}
+
+const char* stokes_last_error(const stokes_problem* pb) { return pb ? pb->err.c_str() : "null problem handle"; }
+
+void stokes_destroy(stokes_problem* pb) {
+  if (!pb) return;
+  hipStreamSynchronize(pb->stream);
+  delete pb;
+}
+
+}  // extern "C"

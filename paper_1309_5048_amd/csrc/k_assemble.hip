@@ -1,0 +1,549 @@
+// Gauss-quadrature assembly of the discrete Stokes operators on the device (Sec. 4 of
+// the paper) and of the load vector.
+//
+// Every CSR entry is computed by the workgroup lane that owns it, as a quadrature sum
+// over the elements shared by the supports of its two basis functions: no scatter, no
+// atomics, so the result is deterministic.  Basis functions are tensor products of 1D
+// B-splines (Sec. 2.2); their values and derivatives at the Gauss points of every
+// element come from a table built by k_tables_1d with the triangular Cox-de Boor
+// recurrence.
+//   A_ij = nu * int (delta_cd grad B_i . grad B_j + d_d B_i d_c B_j)          (2 nu eps:eps)
+//        + sum over boundary faces of nu * int [ -(delta_cd d_n B_i + n_c d_d B_i) B_j
+//                                                 -(delta_cd d_n B_j + n_d d_c B_j) B_i
+//                                                 + 2 (C_pen/h_F) delta_cd B_i B_j ]
+//   (Nitsche form eta_h, eq. nitsche_lhs, a_h = a - eta_h; component c of Phi_i, d of Phi_j)
+//   B_kj = -int phi_k d_d B_j;  Q_kk = int phi_k^2;  w_k = int phi_k;  f_i = int f . Phi_i
+#include "stokes_internal.h"
+
+namespace stk {
+
+constexpr double kPiD = 3.14159265358979323846;
+
+// Gauss-Legendre node/weight i of the n-point rule on [0,1] (Newton on P_n).
+__device__ void gl_node(int n, int i, double* x, double* w) {
+  double t = cos(kPiD * (i + 0.75) / (n + 0.5));
+  double dp = 1.0;
+  for (int it = 0; it < 60; ++it) {
+    double p0 = 1.0, p1 = t;
+    for (int k = 1; k < n; ++k) {
+      const double p2 = ((2.0 * k + 1.0) * t * p1 - k * p0) / (k + 1.0);
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = n * (t * p1 - p0) / (t * t - 1.0);
+    const double dt = p1 / dp;
+    t -= dt;
+    if (fabs(dt) < 1e-16) break;
+  }
+  double p0 = 1.0, p1 = t;
+  for (int k = 1; k < n; ++k) {
+    const double p2 = ((2.0 * k + 1.0) * t * p1 - k * p0) / (k + 1.0);
+    p0 = p1;
+    p1 = p2;
+  }
+  dp = n * (t * p1 - p0) / (t * t - 1.0);
+  *x = 0.5 * (1.0 - t);
+  *w = 1.0 / ((1.0 - t * t) * dp * dp);
+}
+
+// Knot t_k of the open uniform knot vector of degree d on N elements.
+__device__ __forceinline__ double knot(int k, int d, int N) {
+  if (k <= d) return 0.0;
+  if (k >= N + d) return 1.0;
+  return double(k - d) / N;
+}
+
+// Values N[r] and derivatives D[r] (r = 0..d) of the functions e..e+d at x in element e,
+// by the triangular recurrence on the knot differences (left/right arrays).
+__device__ void basis_on_element(int d, int N, int e, double x, double* Nv, double* Dv) {
+  const int span = d + e;
+  double ndu[5][5];  // ndu[r][j]: value table (lower: knot differences)
+  double left[5], right[5];
+  ndu[0][0] = 1.0;
+  for (int j = 1; j <= d; ++j) {
+    left[j] = x - knot(span + 1 - j, d, N);
+    right[j] = knot(span + j, d, N) - x;
+    double saved = 0.0;
+    for (int r = 0; r < j; ++r) {
+      ndu[j][r] = right[r + 1] + left[j - r];
+      const double tmp = ndu[r][j - 1] / ndu[j][r];
+      ndu[r][j] = saved + right[r + 1] * tmp;
+      saved = left[j - r] * tmp;
+    }
+    ndu[j][j] = saved;
+  }
+  for (int r = 0; r <= d; ++r) Nv[r] = ndu[r][d];
+  // first derivative from the degree d-1 values: N'_{e+r} = d (N_{e+r,d-1}/(t_{e+r+d}-t_{e+r})
+  //                                                          - N_{e+r+1,d-1}/(t_{e+r+d+1}-t_{e+r+1}))
+  for (int r = 0; r <= d; ++r) {
+    double v = 0.0;
+    if (d > 0) {
+      const int i = e + r;
+      // degree d-1 function i lives at position r-1 of the degree d-1 table (functions e+1..e+d)
+      const double a = (r >= 1) ? ndu[r - 1][d - 1] : 0.0;
+      const double b = (r <= d - 1) ? ndu[r][d - 1] : 0.0;
+      const double den1 = knot(i + d, d, N) - knot(i, d, N);
+      const double den2 = knot(i + d + 1, d, N) - knot(i + 1, d, N);
+      if (den1 > 0.0) v += d * a / den1;
+      if (den2 > 0.0) v -= d * b / den2;
+    }
+    Dv[r] = v;
+  }
+}
+
+// Table layout for degree d: [(e * (nq + 2) + q) * (d + 1) + r], q = nq -> x = e/N (left end),
+// q = nq + 1 -> x = (e+1)/N (right end).  Gauss weights (on [0,1]) in wq[0..nq).
+__global__ void k_tables_1d(int d, int N, int nq, double* __restrict__ val, double* __restrict__ der,
+                            double* __restrict__ wq) {
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int npts = nq + 2;
+  if (tid >= N * npts) return;
+  const int e = tid / npts, q = tid % npts;
+  double x01, w;
+  if (q < nq) {
+    gl_node(nq, q, &x01, &w);
+    if (e == 0) wq[q] = w;
+  } else {
+    x01 = (q == nq) ? 0.0 : 1.0;
+  }
+  const double x = (e + x01) / N;
+  double Nv[5], Dv[5];
+  basis_on_element(d, N, e, x, Nv, Dv);
+  for (int r = 0; r <= d; ++r) {
+    val[(size_t)tid * (d + 1) + r] = Nv[r];
+    der[(size_t)tid * (d + 1) + r] = Dv[r];
+  }
+}
+
+// Gauss points (physical coordinate) of element e: x = (e + xhat_q)/N.
+__global__ void k_gauss_points(int nq, double* __restrict__ xq) {
+  const int q = threadIdx.x;
+  if (q < nq) {
+    double x, w;
+    gl_node(nq, q, &x, &w);
+    xq[q] = x;
+  }
+}
+
+struct AsmArgs {
+  int N, kp, dim, nq;
+  double nu, cpen;
+  int64_t n_u;
+  int vcnt[3][3], vshift[3][3], vdeg[3][3];
+  int64_t voff[4];
+  int nlo;
+  // 1D tables for degree k' (lo) and k'+1 (hi)
+  const double* tv_lo;
+  const double* td_lo;
+  const double* tv_hi;
+  const double* td_hi;
+  const double* wq;
+};
+
+struct Fun {
+  int comp;     // velocity component, or -1 for a pressure function
+  int i1[3];    // 1D function indices
+  int deg[3];   // 1D degrees
+  int elo[3], ehi[3];
+};
+
+__device__ __forceinline__ void decode_dof(const AsmArgs& a, int64_t g, Fun& f) {
+  if (g < a.n_u) {
+    int c = 0;
+    while (c + 1 < a.dim && g >= a.voff[c + 1]) ++c;
+    int64_t r = g - a.voff[c];
+    for (int d = 0; d < a.dim; ++d) {
+      const int i = int(r % a.vcnt[c][d]) + a.vshift[c][d];
+      r /= a.vcnt[c][d];
+      f.i1[d] = i;
+      f.deg[d] = a.vdeg[c][d];
+    }
+    f.comp = c;
+  } else {
+    int64_t r = g - a.n_u;
+    for (int d = 0; d < a.dim; ++d) {
+      f.i1[d] = int(r % a.nlo);
+      r /= a.nlo;
+      f.deg[d] = a.kp;
+    }
+    f.comp = -1;
+  }
+  for (int d = 0; d < a.dim; ++d) {
+    f.elo[d] = max(0, f.i1[d] - f.deg[d]);
+    f.ehi[d] = min(a.N - 1, f.i1[d]);
+  }
+  for (int d = a.dim; d < 3; ++d) {
+    f.i1[d] = 0;
+    f.deg[d] = 0;
+    f.elo[d] = f.ehi[d] = 0;
+  }
+}
+
+// 1D value and derivative of function f in direction d at table point (e, q).
+__device__ __forceinline__ void f1d(const AsmArgs& a, const Fun& f, int d, int e, int q, double* v, double* dv) {
+  const int deg = f.deg[d];
+  const int r = f.i1[d] - e;
+  const size_t idx = ((size_t)e * (a.nq + 2) + q) * (deg + 1) + r;
+  if (deg == a.kp) {
+    *v = a.tv_lo[idx];
+    *dv = a.td_lo[idx];
+  } else {
+    *v = a.tv_hi[idx];
+    *dv = a.td_hi[idx];
+  }
+}
+
+// Value B and gradient G of the scalar tensor-product spline of f at the point given by
+// per-direction (element, table point).
+__device__ __forceinline__ void eval_fun(const AsmArgs& a, const Fun& f, const int* e, const int* q, double* B,
+                                         double* G) {
+  double v[3] = {1, 1, 1}, dv[3] = {0, 0, 0};
+  for (int d = 0; d < a.dim; ++d) f1d(a, f, d, e[d], q[d], &v[d], &dv[d]);
+  double prod = 1.0;
+  for (int d = 0; d < a.dim; ++d) prod *= v[d];
+  *B = prod;
+  for (int m = 0; m < a.dim; ++m) {
+    double p = dv[m];
+    for (int d = 0; d < a.dim; ++d)
+      if (d != m) p *= v[d];
+    G[m] = p;
+  }
+}
+
+// Value of one saddle-matrix entry (row DOF gi, column DOF gj).
+__device__ double entry_value(const AsmArgs& a, int64_t gi, int64_t gj) {
+  Fun fi, fj;
+  decode_dof(a, gi, fi);
+  decode_dof(a, gj, fj);
+  int lo[3], hi[3];
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = max(fi.elo[d], fj.elo[d]);
+    hi[d] = min(fi.ehi[d], fj.ehi[d]);
+  }
+  const double h = 1.0 / a.N;
+  double vol = 1.0;
+  for (int d = 0; d < a.dim; ++d) vol *= h;
+  const int nq = a.nq;
+  const int nq2 = a.dim == 3 ? nq : 1;
+  double sum = 0.0;
+  const bool vel_i = fi.comp >= 0, vel_j = fj.comp >= 0;
+  int e[3], q[3];
+  // volume terms
+  for (e[2] = lo[2]; e[2] <= hi[2]; ++e[2])
+    for (e[1] = lo[1]; e[1] <= hi[1]; ++e[1])
+      for (e[0] = lo[0]; e[0] <= hi[0]; ++e[0])
+        for (q[2] = 0; q[2] < nq2; ++q[2])
+          for (q[1] = 0; q[1] < nq; ++q[1])
+            for (q[0] = 0; q[0] < nq; ++q[0]) {
+              double wt = vol;
+              for (int d = 0; d < a.dim; ++d) wt *= a.wq[q[d]];
+              double Bi, Gi[3] = {0, 0, 0}, Bj, Gj[3] = {0, 0, 0};
+              eval_fun(a, fi, e, q, &Bi, Gi);
+              eval_fun(a, fj, e, q, &Bj, Gj);
+              if (vel_i && vel_j) {
+                const int c = fi.comp, dd = fj.comp;
+                double t = Gi[dd] * Gj[c];
+                if (c == dd)
+                  for (int m = 0; m < a.dim; ++m) t += Gi[m] * Gj[m];
+                sum += wt * a.nu * t;
+              } else if (vel_i && !vel_j) {  // B^T entry: B_{j,i} = -phi_j d_c B_i
+                sum -= wt * Bj * Gi[fi.comp];
+              } else if (!vel_i && vel_j) {  // B entry
+                sum -= wt * Bi * Gj[fj.comp];
+              }
+            }
+  // Nitsche boundary faces (velocity-velocity only)
+  if (vel_i && vel_j) {
+    const int c = fi.comp, dd = fj.comp;
+    const double pen = 2.0 * a.cpen / h;  // 2 C_pen / h_F, h_F = 1/N
+    for (int fd = 0; fd < a.dim; ++fd)
+      for (int side = 0; side < 2; ++side) {
+        const int eb = side == 0 ? 0 : a.N - 1;
+        if (lo[fd] > eb || hi[fd] < eb) continue;
+        const double s = side == 0 ? -1.0 : 1.0;
+        double farea = 1.0;
+        for (int d = 0; d < a.dim; ++d)
+          if (d != fd) farea *= h;
+        int flo[3], fhi[3], nqd[3];
+        for (int d = 0; d < 3; ++d) {
+          flo[d] = lo[d];
+          fhi[d] = hi[d];
+          nqd[d] = (d < a.dim) ? nq : 1;
+        }
+        flo[fd] = fhi[fd] = eb;
+        nqd[fd] = 1;
+        for (e[2] = flo[2]; e[2] <= fhi[2]; ++e[2])
+          for (e[1] = flo[1]; e[1] <= fhi[1]; ++e[1])
+            for (e[0] = flo[0]; e[0] <= fhi[0]; ++e[0])
+              for (int q2 = 0; q2 < nqd[2]; ++q2)
+                for (int q1 = 0; q1 < nqd[1]; ++q1)
+                  for (int q0 = 0; q0 < nqd[0]; ++q0) {
+                    q[0] = q0;
+                    q[1] = q1;
+                    q[2] = q2;
+                    q[fd] = side == 0 ? nq : nq + 1;
+                    double wt = farea;
+                    for (int d = 0; d < a.dim; ++d)
+                      if (d != fd) wt *= a.wq[q[d]];
+                    double Bi, Gi[3] = {0, 0, 0}, Bj, Gj[3] = {0, 0, 0};
+                    eval_fun(a, fi, e, q, &Bi, Gi);
+                    eval_fun(a, fj, e, q, &Bj, Gj);
+                    const double dn_i = s * Gi[fd], dn_j = s * Gj[fd];
+                    const double nc = (c == fd) ? s : 0.0, nd = (dd == fd) ? s : 0.0;
+                    double t = -(nc * Gi[dd] * Bj + nd * Gj[c] * Bi);
+                    if (c == dd) t += -(dn_i * Bj + dn_j * Bi) + pen * Bi * Bj;
+                    sum += wt * a.nu * t;
+                  }
+      }
+  }
+  return sum;
+}
+
+// One wavefront per row; lanes over the row's entries.
+__global__ void k_assemble_saddle(AsmArgs a, int64_t nrows, const int32_t* __restrict__ rowptr,
+                                  const int32_t* __restrict__ col, double* __restrict__ val) {
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  const int lane = threadIdx.x & 63;
+  if (row >= nrows) return;
+  for (int32_t k = rowptr[row] + lane; k < rowptr[row + 1]; k += 64) val[k] = entry_value(a, row, col[k]);
+}
+
+// diag(Q)_k = int phi_k^2 and w_k = int phi_k, one thread per pressure function.
+__global__ void k_pressure_mass(AsmArgs a, double* __restrict__ diagQ, double* __restrict__ w) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t np = 1;
+  for (int d = 0; d < a.dim; ++d) np *= a.nlo;
+  if (k >= np) return;
+  Fun f;
+  decode_dof(a, a.n_u + k, f);
+  const double h = 1.0 / a.N;
+  double vol = 1.0;
+  for (int d = 0; d < a.dim; ++d) vol *= h;
+  const int nq2 = a.dim == 3 ? a.nq : 1;
+  double s2 = 0.0, s1 = 0.0;
+  int e[3], q[3];
+  for (e[2] = f.elo[2]; e[2] <= f.ehi[2]; ++e[2])
+    for (e[1] = f.elo[1]; e[1] <= f.ehi[1]; ++e[1])
+      for (e[0] = f.elo[0]; e[0] <= f.ehi[0]; ++e[0])
+        for (q[2] = 0; q[2] < nq2; ++q[2])
+          for (q[1] = 0; q[1] < a.nq; ++q[1])
+            for (q[0] = 0; q[0] < a.nq; ++q[0]) {
+              double wt = vol;
+              for (int d = 0; d < a.dim; ++d) wt *= a.wq[q[d]];
+              double B, G[3];
+              eval_fun(a, f, e, q, &B, G);
+              s2 += wt * B * B;
+              s1 += wt * B;
+            }
+  diagQ[k] = s2;
+  w[k] = s1;
+}
+
+// ---------------------------------------------------------------------------
+// Load vector.  Forcing: manufactured (curl of x^2(1-x)^2 y^2(1-y)^2 in 2D, curl of
+// (g,g,g) with g = phi(x)phi(y)phi(z) in 3D, pressure prod cos(pi x_d), f = -nu Lap u +
+// grad p) plus sinusoid modes.  Quadrature: the (k'+4)-point tables passed in `a`.
+// ---------------------------------------------------------------------------
+struct ModeArgs {
+  int manufactured, nmodes, nrhs;
+  const double* amp;    // [nrhs][dim][M]
+  const int32_t* wave;  // [nrhs][M][dim]
+  const double* phase;  // [nrhs][dim][M]
+  const double* xq;     // Gauss points on [0,1] of the load rule
+};
+
+__device__ __forceinline__ void phi_derivs(double t, double* F) {
+  F[0] = t * t * (1 - t) * (1 - t);
+  F[1] = 2 * t - 6 * t * t + 4 * t * t * t;
+  F[2] = 2 - 12 * t + 12 * t * t;
+  F[3] = -12 + 24 * t;
+}
+
+__device__ void manufactured_force(int dim, double nu, const double* x, double* f) {
+  if (dim == 2) {
+    double X[4], Y[4];
+    phi_derivs(x[0], X);
+    phi_derivs(x[1], Y);
+    // u = (X Y', -X' Y); Lap u = (X'' Y' + X Y''', -(X''' Y + X' Y''))
+    const double l0 = X[2] * Y[1] + X[0] * Y[3];
+    const double l1 = -(X[3] * Y[0] + X[1] * Y[2]);
+    const double s0 = sin(kPiD * x[0]), c0 = cos(kPiD * x[0]);
+    const double s1 = sin(kPiD * x[1]), c1 = cos(kPiD * x[1]);
+    f[0] = -nu * l0 - kPiD * s0 * c1;
+    f[1] = -nu * l1 - kPiD * c0 * s1;
+  } else {
+    double F[3][4];
+    for (int d = 0; d < 3; ++d) phi_derivs(x[d], F[d]);
+    // Lap(d g / d x_m) = sum_b d^3 g / (d x_m d x_b^2)
+    double L[3];
+    for (int m = 0; m < 3; ++m) {
+      double s = 0.0;
+      for (int b = 0; b < 3; ++b) {
+        double prod = 1.0;
+        for (int d = 0; d < 3; ++d) prod *= F[d][(d == m ? 1 : 0) + (d == b ? 2 : 0)];
+        s += prod;
+      }
+      L[m] = s;
+    }
+    const double lap[3] = {L[1] - L[2], L[2] - L[0], L[0] - L[1]};
+    double sn[3], cs[3];
+    for (int d = 0; d < 3; ++d) {
+      sn[d] = sin(kPiD * x[d]);
+      cs[d] = cos(kPiD * x[d]);
+    }
+    const double gp[3] = {-kPiD * sn[0] * cs[1] * cs[2], -kPiD * cs[0] * sn[1] * cs[2], -kPiD * cs[0] * cs[1] * sn[2]};
+    for (int m = 0; m < 3; ++m) f[m] = -nu * lap[m] + gp[m];
+  }
+}
+
+// One thread per (velocity DOF, right-hand side); output f[r * n_u + i].
+__global__ void k_load_vector(AsmArgs a, ModeArgs m, double* __restrict__ f) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.n_u * m.nrhs) return;
+  const int64_t i = t % a.n_u;
+  const int r = int(t / a.n_u);
+  Fun fi;
+  decode_dof(a, i, fi);
+  const int c = fi.comp;
+  const double h = 1.0 / a.N;
+  double vol = 1.0;
+  for (int d = 0; d < a.dim; ++d) vol *= h;
+  const int nq = a.nq, nq2 = a.dim == 3 ? nq : 1;
+  const int M = m.nmodes;
+  double sum = 0.0;
+  int e[3], q[3];
+  for (e[2] = fi.elo[2]; e[2] <= fi.ehi[2]; ++e[2])
+    for (e[1] = fi.elo[1]; e[1] <= fi.ehi[1]; ++e[1])
+      for (e[0] = fi.elo[0]; e[0] <= fi.ehi[0]; ++e[0])
+        for (q[2] = 0; q[2] < nq2; ++q[2])
+          for (q[1] = 0; q[1] < nq; ++q[1])
+            for (q[0] = 0; q[0] < nq; ++q[0]) {
+              double wt = vol, x[3] = {0, 0, 0};
+              for (int d = 0; d < a.dim; ++d) {
+                wt *= a.wq[q[d]];
+                x[d] = (e[d] + m.xq[q[d]]) * h;
+              }
+              double fv = 0.0;
+              if (m.manufactured) {
+                double fm[3];
+                manufactured_force(a.dim, a.nu, x, fm);
+                fv = fm[c];
+              }
+              for (int k = 0; k < M; ++k) {
+                double arg = m.phase[((size_t)r * a.dim + c) * M + k];
+                for (int d = 0; d < a.dim; ++d) arg += kPiD * m.wave[((size_t)r * M + k) * a.dim + d] * x[d];
+                fv += m.amp[((size_t)r * a.dim + c) * M + k] * sin(arg);
+              }
+              double B, G[3];
+              eval_fun(a, fi, e, q, &B, G);
+              sum += wt * fv * B;
+            }
+  f[(size_t)r * a.n_u + i] = sum;
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+struct Tables {
+  double *v_lo = nullptr, *d_lo = nullptr, *v_hi = nullptr, *d_hi = nullptr, *wq = nullptr, *xq = nullptr;
+};
+
+static AsmArgs make_args(const Spaces& S, double nu, double cpen, int nq, const Tables& T) {
+  AsmArgs a;
+  a.N = S.N;
+  a.kp = S.kp;
+  a.dim = S.dim;
+  a.nq = nq;
+  a.nu = nu;
+  a.cpen = cpen;
+  a.n_u = S.n_u;
+  for (int c = 0; c < 3; ++c)
+    for (int d = 0; d < 3; ++d) {
+      a.vcnt[c][d] = S.vcnt[c][d];
+      a.vshift[c][d] = S.vshift[c][d];
+      a.vdeg[c][d] = S.vdeg[c][d];
+    }
+  for (int c = 0; c < 4; ++c) a.voff[c] = S.voff[c];
+  a.nlo = S.nlo;
+  a.tv_lo = T.v_lo;
+  a.td_lo = T.d_lo;
+  a.tv_hi = T.v_hi;
+  a.td_hi = T.d_hi;
+  a.wq = T.wq;
+  return a;
+}
+
+static hipError_t build_tables(const Spaces& S, int nq, Tables& T, hipStream_t st) {
+  const size_t npt = (size_t)S.N * (nq + 2);
+  hipError_t e;
+  if ((e = hipMalloc(&T.v_lo, npt * (S.kp + 1) * sizeof(double))) != hipSuccess) return e;
+  if ((e = hipMalloc(&T.d_lo, npt * (S.kp + 1) * sizeof(double))) != hipSuccess) return e;
+  if ((e = hipMalloc(&T.v_hi, npt * (S.kp + 2) * sizeof(double))) != hipSuccess) return e;
+  if ((e = hipMalloc(&T.d_hi, npt * (S.kp + 2) * sizeof(double))) != hipSuccess) return e;
+  if ((e = hipMalloc(&T.wq, 16 * sizeof(double))) != hipSuccess) return e;
+  if ((e = hipMalloc(&T.xq, 16 * sizeof(double))) != hipSuccess) return e;
+  const int nb = int((npt + 255) / 256);
+  hipLaunchKernelGGL(k_tables_1d, dim3(nb), dim3(256), 0, st, S.kp, S.N, nq, T.v_lo, T.d_lo, T.wq);
+  hipLaunchKernelGGL(k_tables_1d, dim3(nb), dim3(256), 0, st, S.kp + 1, S.N, nq, T.v_hi, T.d_hi, T.wq);
+  hipLaunchKernelGGL(k_gauss_points, dim3(1), dim3(64), 0, st, nq, T.xq);
+  return hipGetLastError();
+}
+
+static void free_tables(Tables& T) {
+  hipFree(T.v_lo);
+  hipFree(T.d_lo);
+  hipFree(T.v_hi);
+  hipFree(T.d_hi);
+  hipFree(T.wq);
+  hipFree(T.xq);
+  T = Tables();
+}
+
+hipError_t assemble_saddle(const Spaces& S, double nu, double cpen, const int32_t* rowptr, const int32_t* col,
+                           double* val, double* diagQ, double* w, hipStream_t st) {
+  Tables T;
+  const int nq = S.kp + 2;
+  hipError_t e = build_tables(S, nq, T, st);
+  if (e != hipSuccess) {
+    free_tables(T);
+    return e;
+  }
+  AsmArgs a = make_args(S, nu, cpen, nq, T);
+  const int64_t n = S.n_u + S.n_p;
+  const int rows_per_block = 4;
+  hipLaunchKernelGGL(k_assemble_saddle, dim3(unsigned((n + rows_per_block - 1) / rows_per_block)), dim3(256), 0, st,
+                     a, n, rowptr, col, val);
+  hipLaunchKernelGGL(k_pressure_mass, dim3(unsigned((S.n_p + 255) / 256)), dim3(256), 0, st, a, diagQ, w);
+  e = hipGetLastError();
+  hipError_t e2 = hipStreamSynchronize(st);
+  free_tables(T);
+  return e != hipSuccess ? e : e2;
+}
+
+hipError_t assemble_load(const Spaces& S, double nu, int manufactured, int nmodes, int nrhs, const double* amp_d,
+                         const int32_t* wave_d, const double* phase_d, double* f, hipStream_t st) {
+  Tables T;
+  const int nq = S.kp + 4;
+  hipError_t e = build_tables(S, nq, T, st);
+  if (e != hipSuccess) {
+    free_tables(T);
+    return e;
+  }
+  AsmArgs a = make_args(S, nu, 0.0, nq, T);
+  ModeArgs m;
+  m.manufactured = manufactured;
+  m.nmodes = nmodes;
+  m.nrhs = nrhs;
+  m.amp = amp_d;
+  m.wave = wave_d;
+  m.phase = phase_d;
+  m.xq = T.xq;
+  const int64_t nt = S.n_u * nrhs;
+  hipLaunchKernelGGL(k_load_vector, dim3(unsigned((nt + 127) / 128)), dim3(128), 0, st, a, m, f);
+  e = hipGetLastError();
+  hipError_t e2 = hipStreamSynchronize(st);
+  free_tables(T);
+  return e != hipSuccess ? e : e2;
+}
+
+}  // namespace stk

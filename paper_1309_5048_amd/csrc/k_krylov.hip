@@ -1,0 +1,754 @@
+// Krylov kernels of the preconditioned MINRES solver (Sec. 5 of the paper) and of the
+// inner IC(0)-PCG on A (Sec. 6.4), for R interleaved right-hand sides (vector layout
+// [row][R]) in precision T (double, or float for the inner solve of the mixed mode).
+//
+// Scalars live on the device.  Reductions are deterministic: every block writes its
+// partial sums, the last block to finish (atomic ticket) adds them in block order.
+// The MINRES recurrence scalars are double buffered by iteration parity p: kernels of
+// iteration j read state[p] and the update kernel writes state[1-p]; a per-parity
+// "all columns done" flag makes every later kernel a no-op once all columns converged.
+//
+// MINRES iteration j (unnormalised z~_j = M^{-1} v_j, z_j = z~_j / gamma_j):
+//   spmv    q = Acal z_j,  delta_j = q . z_j
+//   lanczos v_{j+1} = q - (delta_j/gamma_j) v_j - (gamma_j/gamma_{j-1}) v_{j-1}
+//           z~_{j+1,p} = 2 nu v_{j+1,p} / diag(Q)   (M_Q = Diag(Q)/(2 nu)); Jacobi M_A too
+//   (velocity block: triangular solves / inner PCG, elsewhere)
+//   update  gamma_{j+1} = sqrt(v_{j+1} . z~_{j+1}); Givens rotation; w, x updates.
+#include "stokes_internal.h"
+
+namespace stk {
+
+// ---------------------------------------------------------------------------
+// MINRES initialisation: v_1 = b, v_0 = w_0 = w_1 = x = 0, z~_1 pressure (and Jacobi
+// velocity) part; gamma^2 partial sums of the pressure / velocity parts.
+// ---------------------------------------------------------------------------
+template <typename T, int R>
+__global__ __launch_bounds__(kVT) void k_mr_init_vec(int64_t n, int64_t n_u, const T* __restrict__ b, T* __restrict__ v1,
+                                                     T* __restrict__ v0, T* __restrict__ w1, T* __restrict__ w0,
+                                                     T* __restrict__ x, T* __restrict__ z1, const double* __restrict__ diagQ,
+                                                     const double* __restrict__ diagA, double two_nu, MrScalars s) {
+  double acc[2 * R];
+#pragma unroll
+  for (int c = 0; c < 2 * R; ++c) acc[c] = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kVT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVT) {
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+      const size_t k = (size_t)i * R + c;
+      const T bv = b[k];
+      v1[k] = bv;
+      v0[k] = T(0);
+      w1[k] = T(0);
+      w0[k] = T(0);
+      x[k] = T(0);
+      if (i >= n_u) {
+        const T zv = T(two_nu * (double)bv / diagQ[i - n_u]);
+        z1[k] = zv;
+        acc[c] += (double)bv * (double)zv;
+      } else if (diagA != nullptr) {
+        const T zv = T((double)bv / diagA[i]);
+        z1[k] = zv;
+        acc[R + c] += (double)bv * (double)zv;
+      }
+    }
+  }
+  reduce_last<2 * R>(acc, s.partials, s.counter, [&](int k, double val) {
+    if (k < R) red_at(s, 0, RED_G2P)[k] = val;
+    else if (diagA != nullptr) red_at(s, 0, RED_G2U)[k - R] = val;
+  });
+}
+
+template <int R>
+__global__ void k_mr_init_state(MrScalars s, double tol, int maxit) {
+  const int c = threadIdx.x;
+  __shared__ int nd;
+  if (c == 0) nd = 0;
+  __syncthreads();
+  if (c < R) {
+    const double g2 = red_at(s, 0, RED_G2P)[c] + red_at(s, 0, RED_G2U)[c];
+    MinresState st;
+    st.gamma_prev = 1.0;
+    st.c = st.c_prev = 1.0;
+    st.s = st.s_prev = 0.0;
+    st.delta = st.g2p = st.g2u = 0.0;
+    st.iter = 0;
+    st.maxit = maxit;
+    st.status = 0;
+    st.done = 0;
+    if (g2 < 0.0 || g2 != g2) {
+      st.gamma = st.gamma1 = st.eta = 0.0;
+      st.status = -4;
+      st.done = 1;
+    } else {
+      st.gamma = st.gamma1 = st.eta = sqrt(g2);
+      if (st.gamma1 == 0.0) st.done = 1;
+    }
+    st.tolg = tol * st.gamma1;
+    if (maxit <= 0) st.done = 1;
+    s.st[c] = st;
+    s.st[kRMax + c] = st;
+    if (st.done) atomicAdd(&nd, 1);
+  }
+  __syncthreads();
+  if (c == 0) {
+    s.alldone[0] = (nd == R);
+    s.alldone[1] = (nd == R);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// q = Acal z~_j / gamma_j and delta partials (one wavefront per row, lanes over entries).
+// ---------------------------------------------------------------------------
+template <typename T, int R>
+__global__ __launch_bounds__(kVT) void k_mr_spmv(int64_t n, const int32_t* __restrict__ rowptr,
+                                                 const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                 const T* __restrict__ z, T* __restrict__ q, MrScalars s, int p) {
+  if (s.alldone[p]) return;
+  double ig[R];
+#pragma unroll
+  for (int c = 0; c < R; ++c) {
+    const MinresState& st = s.st[p * kRMax + c];
+    ig[c] = (st.done || st.gamma == 0.0) ? 0.0 : 1.0 / st.gamma;
+  }
+  double acc_d[R];
+#pragma unroll
+  for (int c = 0; c < R; ++c) acc_d[c] = 0.0;
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (int64_t)blockIdx.x * (kVT / 64) + (threadIdx.x >> 6);
+  const int64_t nwaves = (int64_t)gridDim.x * (kVT / 64);
+  for (int64_t i = wave; i < n; i += nwaves) {
+    T acc[R];
+#pragma unroll
+    for (int c = 0; c < R; ++c) acc[c] = T(0);
+    for (int32_t k = rowptr[i] + lane; k < rowptr[i + 1]; k += 64) {
+      const T a = val[k];
+      const T* zp = z + (size_t)col[k] * R;
+#pragma unroll
+      for (int c = 0; c < R; ++c) acc[c] = fma(a, zp[c], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) acc[c] += __shfl_xor(acc[c], off, 64);
+    }
+    if (lane < R) {
+      // lane c finalises column c
+      T mine = acc[0];
+#pragma unroll
+      for (int c = 1; c < R; ++c)
+        if (lane == c) mine = acc[c];
+      double igc = ig[0];
+#pragma unroll
+      for (int c = 1; c < R; ++c)
+        if (lane == c) igc = ig[c];
+      const T qv = T((double)mine * igc);
+      q[(size_t)i * R + lane] = qv;
+      const double zv = (double)z[(size_t)i * R + lane];
+      double d = (double)qv * zv * igc;
+#pragma unroll
+      for (int c = 0; c < R; ++c)
+        if (lane == c) acc_d[c] += d;
+    }
+  }
+  reduce_last<R>(acc_d, s.partials, s.counter, [&](int k, double v) { red_at(s, p, RED_DELTA)[k] = v; });
+}
+
+// ---------------------------------------------------------------------------
+// Lanczos update, pressure preconditioner (and Jacobi velocity preconditioner) and
+// gamma^2 partial sums.  v_{j+1} overwrites v_{j-1}.
+// ---------------------------------------------------------------------------
+template <typename T, int R>
+__global__ __launch_bounds__(kVT) void k_mr_lanczos(int64_t n, int64_t n_u, const T* __restrict__ q,
+                                                    const T* __restrict__ v, T* __restrict__ vprev_next,
+                                                    T* __restrict__ znext, const double* __restrict__ diagQ,
+                                                    const double* __restrict__ diagA, double two_nu, MrScalars s,
+                                                    int p) {
+  if (s.alldone[p]) return;
+  double ca[R], cb[R];
+  bool live[R];
+#pragma unroll
+  for (int c = 0; c < R; ++c) {
+    const MinresState& st = s.st[p * kRMax + c];
+    live[c] = !st.done;
+    const double dl = red_at(s, p, RED_DELTA)[c];
+    ca[c] = live[c] ? dl / st.gamma : 0.0;
+    cb[c] = live[c] ? st.gamma / st.gamma_prev : 0.0;
+  }
+  double acc[2 * R];
+#pragma unroll
+  for (int c = 0; c < 2 * R; ++c) acc[c] = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kVT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVT) {
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+      if (!live[c]) continue;
+      const size_t k = (size_t)i * R + c;
+      const double vn = (double)q[k] - ca[c] * (double)v[k] - cb[c] * (double)vprev_next[k];
+      const T vnt = T(vn);
+      vprev_next[k] = vnt;
+      if (i >= n_u) {
+        const T zv = T(two_nu * (double)vnt / diagQ[i - n_u]);
+        znext[k] = zv;
+        acc[c] += (double)vnt * (double)zv;
+      } else if (diagA != nullptr) {
+        const T zv = T((double)vnt / diagA[i]);
+        znext[k] = zv;
+        acc[R + c] += (double)vnt * (double)zv;
+      }
+    }
+  }
+  reduce_last<2 * R>(acc, s.partials, s.counter, [&](int k, double val) {
+    if (k < R) red_at(s, p, RED_G2P)[k] = val;
+    else if (diagA != nullptr) red_at(s, p, RED_G2U)[k - R] = val;
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Givens rotation and w, x updates.  w_{j+1} overwrites w_{j-1}.  Block 0 writes the
+// state of the next iteration (parity 1-p).
+// ---------------------------------------------------------------------------
+struct Givens {
+  double gn, a1, a2, a3, cn, sn, eta_new, coef;
+  int live, status;
+};
+
+__device__ __forceinline__ Givens givens_step(const MinresState& st, double delta, double g2) {
+  Givens G;
+  G.live = !st.done;
+  G.status = 0;
+  if (!G.live) {
+    G.gn = G.a1 = G.a2 = G.a3 = G.cn = G.sn = G.eta_new = G.coef = 0.0;
+    return G;
+  }
+  if (g2 < 0.0 || g2 != g2) {
+    G.status = -4;
+    g2 = 0.0;
+  }
+  G.gn = sqrt(g2);
+  const double a0 = st.c * delta - st.c_prev * st.s * st.gamma;
+  G.a1 = sqrt(a0 * a0 + G.gn * G.gn);
+  G.a2 = st.s * delta + st.c_prev * st.c * st.gamma;
+  G.a3 = st.s_prev * st.gamma;
+  G.cn = a0 / G.a1;
+  G.sn = G.gn / G.a1;
+  G.coef = G.cn * st.eta;
+  G.eta_new = -G.sn * st.eta;
+  return G;
+}
+
+template <typename T, int R>
+__global__ __launch_bounds__(kVT) void k_mr_update(int64_t n, const T* __restrict__ z, const T* __restrict__ w,
+                                                   T* __restrict__ wprev_new, T* __restrict__ x, MrScalars s, int p) {
+  if (s.alldone[p]) {
+    // frozen: carry the state to the next parity so later launches stay no-ops
+    if (blockIdx.x == 0) {
+      if (threadIdx.x < R) s.st[(1 - p) * kRMax + threadIdx.x] = s.st[p * kRMax + threadIdx.x];
+      if (threadIdx.x == 0) s.alldone[1 - p] = 1;
+    }
+    return;
+  }
+  Givens G[R];
+  double ig[R];
+#pragma unroll
+  for (int c = 0; c < R; ++c) {
+    const MinresState& st = s.st[p * kRMax + c];
+    const double g2 = red_at(s, p, RED_G2P)[c] + red_at(s, p, RED_G2U)[c];
+    G[c] = givens_step(st, red_at(s, p, RED_DELTA)[c], g2);
+    ig[c] = G[c].live ? 1.0 / st.gamma : 0.0;
+  }
+  for (int64_t i = blockIdx.x * (int64_t)kVT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVT) {
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+      if (!G[c].live) continue;
+      const size_t k = (size_t)i * R + c;
+      const double wn = ((double)z[k] * ig[c] - G[c].a3 * (double)wprev_new[k] - G[c].a2 * (double)w[k]) / G[c].a1;
+      wprev_new[k] = T(wn);
+      x[k] = T((double)x[k] + G[c].coef * wn);
+    }
+  }
+  if (blockIdx.x == 0) {
+    __shared__ int nd;
+    if (threadIdx.x == 0) nd = 0;
+    __syncthreads();
+    if (threadIdx.x < R) {
+      const int c = threadIdx.x;
+      MinresState st = s.st[p * kRMax + c];
+      const Givens g = G[c];
+      if (g.live) {
+        st.gamma_prev = st.gamma;
+        st.gamma = g.gn;
+        st.c_prev = st.c;
+        st.c = g.cn;
+        st.s_prev = st.s;
+        st.s = g.sn;
+        st.eta = g.eta_new;
+        st.iter += 1;
+        if (g.status != 0) {
+          st.status = g.status;
+          st.done = 1;
+        } else if (fabs(st.eta) <= st.tolg || st.gamma == 0.0) {
+          st.done = 1;
+        } else if (st.iter >= st.maxit) {
+          st.status = 1;
+          st.done = 1;
+        }
+      }
+      s.st[(1 - p) * kRMax + c] = st;
+      if (st.done) atomicAdd(&nd, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) s.alldone[1 - p] = (nd == R);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Generic helpers
+// ---------------------------------------------------------------------------
+// y = Acal x (all rows) or, with bvec, y = b - Acal x; optional partial sums of y.y and b.b
+template <typename T, int R>
+__global__ __launch_bounds__(kVT) void k_spmv_resid(int64_t nrows, const int32_t* __restrict__ rowptr,
+                                                    const int32_t* __restrict__ rowend, const int32_t* __restrict__ col,
+                                                    const T* __restrict__ val, const T* __restrict__ xin,
+                                                    const T* __restrict__ bvec, T* __restrict__ y, double* partials,
+                                                    unsigned int* counter, double* out /*[2][R] or null*/) {
+  double acc_d[2 * R];
+#pragma unroll
+  for (int c = 0; c < 2 * R; ++c) acc_d[c] = 0.0;
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (int64_t)blockIdx.x * (kVT / 64) + (threadIdx.x >> 6);
+  const int64_t nwaves = (int64_t)gridDim.x * (kVT / 64);
+  for (int64_t i = wave; i < nrows; i += nwaves) {
+    double acc[R];
+#pragma unroll
+    for (int c = 0; c < R; ++c) acc[c] = 0.0;
+    const int32_t kend = rowend ? rowend[i] : rowptr[i + 1];
+    for (int32_t k = rowptr[i] + lane; k < kend; k += 64) {
+      const double a = (double)val[k];
+      const T* xp = xin + (size_t)col[k] * R;
+#pragma unroll
+      for (int c = 0; c < R; ++c) acc[c] = fma(a, (double)xp[c], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) acc[c] += __shfl_xor(acc[c], off, 64);
+    }
+    if (lane < R) {
+      double mine = acc[0];
+#pragma unroll
+      for (int c = 1; c < R; ++c)
+        if (lane == c) mine = acc[c];
+      const size_t k = (size_t)i * R + lane;
+      double bv = bvec ? (double)bvec[k] : 0.0;
+      double yv = bvec ? bv - mine : mine;
+      y[k] = T(yv);
+#pragma unroll
+      for (int c = 0; c < R; ++c)
+        if (lane == c) {
+          acc_d[c] += yv * yv;
+          acc_d[R + c] += bv * bv;
+        }
+    }
+  }
+  if (out == nullptr) return;
+  reduce_last<2 * R>(acc_d, partials, counter, [&](int k, double v) { out[k] = v; });
+}
+
+// out[c] = sum_i a[i,c] * b[i,c] over rows [r0, r1) (fixed-order reduction).
+template <typename Ta, typename Tb, int R>
+__global__ __launch_bounds__(kVT) void k_dot(int64_t r0, int64_t r1, const Ta* __restrict__ a, const Tb* __restrict__ b,
+                                             double* partials, unsigned int* counter, double* out) {
+  double acc[R];
+#pragma unroll
+  for (int c = 0; c < R; ++c) acc[c] = 0.0;
+  for (int64_t i = r0 + blockIdx.x * (int64_t)kVT + threadIdx.x; i < r1; i += (int64_t)gridDim.x * kVT)
+#pragma unroll
+    for (int c = 0; c < R; ++c) acc[c] += (double)a[(size_t)i * R + c] * (double)b[(size_t)i * R + c];
+  reduce_last<R>(acc, partials, counter, [&](int k, double v) { out[k] = v; });
+}
+
+// Zero-mean pressure: p_c -= (w . p_c) / (w . 1), rows [n_u, n).  mean computed by k_dot.
+template <typename T, int R>
+__global__ void k_sub_mean(int64_t n_u, int64_t n, T* __restrict__ x, const double* __restrict__ wp, double w1) {
+  for (int64_t i = n_u + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+#pragma unroll
+    for (int c = 0; c < R; ++c) x[(size_t)i * R + c] = T((double)x[(size_t)i * R + c] - wp[c] / w1);
+}
+
+// Column-major [R][len] (stride ld) <-> interleaved [len][R], with type conversion.
+template <typename Ts, typename Td, int R>
+__global__ void k_to_interleaved(int64_t len, const Ts* __restrict__ src, int64_t ld, Td* __restrict__ dst,
+                                 int64_t dst_off) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < len * R; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = t / R;
+    const int c = int(t % R);
+    dst[(size_t)(dst_off + i) * R + c] = Td(src[(size_t)c * ld + i]);
+  }
+}
+
+template <typename Ts, typename Td, int R>
+__global__ void k_from_interleaved(int64_t len, const Ts* __restrict__ src, int64_t src_off, Td* __restrict__ dst,
+                                   int64_t ld) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < len * R; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = t / R;
+    const int c = int(t % R);
+    dst[(size_t)c * ld + i] = Td(src[(size_t)(src_off + i) * R + c]);
+  }
+}
+
+template <typename Ts, typename Td>
+__global__ void k_convert(int64_t n, const Ts* __restrict__ a, Td* __restrict__ b) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) b[i] = Td(a[i]);
+}
+
+// x64 += d (any precision); both interleaved with the same R.
+template <typename Td, int R>
+__global__ void k_accumulate(int64_t nR, double* __restrict__ x, const Td* __restrict__ d) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nR; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] += (double)d[i];
+}
+
+__global__ void k_scale(int64_t n, double* __restrict__ a, double s) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) a[i] *= s;
+}
+
+// ---------------------------------------------------------------------------
+// Inner IC(0)-PCG on A (x0 = 0; stop when ||r||^2 <= rtol^2 ||b||^2, tested after each
+// update; at most maxit iterations).  x aliases the velocity part of z~_{j+1}.
+// ---------------------------------------------------------------------------
+
+// r = b (velocity part of v_{j+1}), x = 0, ||b||^2
+template <typename T, int R>
+__global__ __launch_bounds__(kVT) void k_pcg_init(int64_t n_u, const T* __restrict__ b, T* __restrict__ r,
+                                                  T* __restrict__ x, PcgScalars s, const int* outer_done) {
+  if (outer_done != nullptr && *outer_done) return;
+  double acc[R];
+#pragma unroll
+  for (int c = 0; c < R; ++c) acc[c] = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kVT + threadIdx.x; i < n_u; i += (int64_t)gridDim.x * kVT)
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+      const size_t k = (size_t)i * R + c;
+      const T bv = b[k];
+      r[k] = bv;
+      x[k] = T(0);
+      acc[c] += (double)bv * (double)bv;
+    }
+  reduce_last<R>(acc, s.partials, s.counter, [&](int k, double v) { s.rr[k] = v; });
+}
+
+// after z = M^{-1} r (rho[0] from the fused dot): p = z, state init
+template <typename T, int R>
+__global__ __launch_bounds__(kVT) void k_pcg_init2(int64_t n_u, const T* __restrict__ z, T* __restrict__ pv, PcgScalars s,
+                                                   double rtol, int maxit, const int* outer_done,
+                                                   const MinresState* outer_st) {
+  for (int64_t i = blockIdx.x * (int64_t)kVT + threadIdx.x; i < n_u * R; i += (int64_t)gridDim.x * kVT) pv[i] = z[i];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    int nd = 0;
+    for (int c = 0; c < R; ++c) {
+      PcgState st;
+      st.rho = s.rho[c];
+      st.bnorm2 = s.rr[c];
+      st.rr = s.rr[c];
+      st.rtol2 = rtol * rtol;
+      st.pq = 0.0;
+      st.iter = 0;
+      st.maxit = maxit;
+      st.total = s.st[c].total;
+      st.done = (outer_done != nullptr && *outer_done) || (outer_st != nullptr && outer_st[c].done) ||
+                st.bnorm2 == 0.0 || maxit <= 0;
+      s.st[c] = st;
+      nd += st.done;
+    }
+    *s.alldone = (nd == R);
+  }
+}
+
+// q = A p (velocity rows, A part of the saddle CSR) and p.q partials
+template <typename T, int R>
+__global__ __launch_bounds__(kVT) void k_pcg_spmv(int64_t n_u, const int32_t* __restrict__ rowptr,
+                                                  const int32_t* __restrict__ aend, const int32_t* __restrict__ col,
+                                                  const T* __restrict__ val, const T* __restrict__ pv, T* __restrict__ q,
+                                                  PcgScalars s) {
+  if (*s.alldone) return;
+  double acc_d[R];
+#pragma unroll
+  for (int c = 0; c < R; ++c) acc_d[c] = 0.0;
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (int64_t)blockIdx.x * (kVT / 64) + (threadIdx.x >> 6);
+  const int64_t nwaves = (int64_t)gridDim.x * (kVT / 64);
+  for (int64_t i = wave; i < n_u; i += nwaves) {
+    T acc[R];
+#pragma unroll
+    for (int c = 0; c < R; ++c) acc[c] = T(0);
+    for (int32_t k = rowptr[i] + lane; k < aend[i]; k += 64) {
+      const T a = val[k];
+      const T* pp = pv + (size_t)col[k] * R;
+#pragma unroll
+      for (int c = 0; c < R; ++c) acc[c] = fma(a, pp[c], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) acc[c] += __shfl_xor(acc[c], off, 64);
+    }
+    if (lane < R) {
+      T mine = acc[0];
+#pragma unroll
+      for (int c = 1; c < R; ++c)
+        if (lane == c) mine = acc[c];
+      const size_t k = (size_t)i * R + lane;
+      q[k] = mine;
+      const double d = (double)mine * (double)pv[k];
+#pragma unroll
+      for (int c = 0; c < R; ++c)
+        if (lane == c) acc_d[c] += d;
+    }
+  }
+  reduce_last<R>(acc_d, s.partials, s.counter, [&](int k, double v) { s.pq[k] = v; });
+}
+
+// alpha = rho/pq; x += alpha p; r -= alpha q; ||r||^2 partials; last block: convergence
+template <typename T, int R>
+__global__ __launch_bounds__(kVT) void k_pcg_axpy(int64_t n_u, const T* __restrict__ pv, const T* __restrict__ q,
+                                                  T* __restrict__ x, T* __restrict__ r, PcgScalars s, int ip) {
+  if (*s.alldone) return;
+  double al[R];
+  bool live[R];
+#pragma unroll
+  for (int c = 0; c < R; ++c) {
+    live[c] = !s.st[c].done;
+    al[c] = live[c] ? s.rho[ip * kRMax + c] / s.pq[c] : 0.0;
+  }
+  double acc[R];
+#pragma unroll
+  for (int c = 0; c < R; ++c) acc[c] = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kVT + threadIdx.x; i < n_u; i += (int64_t)gridDim.x * kVT)
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+      if (!live[c]) continue;
+      const size_t k = (size_t)i * R + c;
+      x[k] = T((double)x[k] + al[c] * (double)pv[k]);
+      const double rn = (double)r[k] - al[c] * (double)q[k];
+      r[k] = T(rn);
+      acc[c] += rn * rn;
+    }
+  reduce_last<R>(acc, s.partials, s.counter, [&](int c, double v) {
+    PcgState& st = s.st[c];
+    if (!st.done) {
+      st.rr = v;
+      st.iter += 1;
+      st.total += 1;
+      if (v <= st.rtol2 * st.bnorm2 || st.iter >= st.maxit) st.done = 1;
+    }
+  });
+}
+
+// all-done flag after k_pcg_axpy (single thread)
+template <int R>
+__global__ void k_pcg_check(PcgScalars s) {
+  if (threadIdx.x == 0) {
+    int nd = 0;
+    for (int c = 0; c < R; ++c) nd += s.st[c].done;
+    *s.alldone = (nd == R);
+  }
+}
+
+// beta = rho_new/rho; p = z + beta p  (rho_new in rho[1-ip])
+template <typename T, int R>
+__global__ __launch_bounds__(kVT) void k_pcg_pupdate(int64_t n_u, const T* __restrict__ z, T* __restrict__ pv,
+                                                     PcgScalars s, int ip) {
+  if (*s.alldone) return;
+  double be[R];
+  bool live[R];
+#pragma unroll
+  for (int c = 0; c < R; ++c) {
+    live[c] = !s.st[c].done;
+    be[c] = live[c] ? s.rho[(1 - ip) * kRMax + c] / s.rho[ip * kRMax + c] : 0.0;
+  }
+  for (int64_t i = blockIdx.x * (int64_t)kVT + threadIdx.x; i < n_u; i += (int64_t)gridDim.x * kVT)
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+      if (!live[c]) continue;
+      const size_t k = (size_t)i * R + c;
+      pv[k] = T((double)z[k] + be[c] * (double)pv[k]);
+    }
+}
+
+// ===========================================================================
+// Host launchers (explicit instantiation through switch on R)
+// ===========================================================================
+#define STK_R_SWITCH(R_, ...)                   \
+  switch (R_) {                                 \
+    case 1: { constexpr int RR = 1; __VA_ARGS__; break; } \
+    case 8: { constexpr int RR = 8; __VA_ARGS__; break; } \
+    case 16: { constexpr int RR = 16; __VA_ARGS__; break; } \
+    default: return hipErrorInvalidValue;      \
+  }
+
+template <typename T>
+hipError_t mr_init_vec(int R, int64_t n, int64_t n_u, const T* b, T* v1, T* v0, T* w1, T* w0, T* x, T* z1,
+                       const double* diagQ, const double* diagA, double two_nu, const MrScalars& s, hipStream_t st) {
+  STK_R_SWITCH(R, hipLaunchKernelGGL((k_mr_init_vec<T, RR>), dim3(vec_blocks(n)), dim3(kVT), 0, st, n, n_u, b, v1, v0, w1,
+                                     w0, x, z1, diagQ, diagA, two_nu, s));
+  return hipGetLastError();
+}
+
+hipError_t mr_init_state(int R, const MrScalars& s, double tol, int maxit, hipStream_t st) {
+  STK_R_SWITCH(R, hipLaunchKernelGGL((k_mr_init_state<RR>), dim3(1), dim3(64), 0, st, s, tol, maxit));
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t mr_spmv(int R, int64_t n, const int32_t* rowptr, const int32_t* col, const T* val, const T* z, T* q,
+                   const MrScalars& s, int p, hipStream_t st) {
+  const int nb = int(std::min<int64_t>(2048, std::max<int64_t>(1, (n + 3) / 4)));
+  STK_R_SWITCH(R, hipLaunchKernelGGL((k_mr_spmv<T, RR>), dim3(nb), dim3(kVT), 0, st, n, rowptr, col, val, z, q, s, p));
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t mr_lanczos(int R, int64_t n, int64_t n_u, const T* q, const T* v, T* vprev_next, T* znext, const double* diagQ,
+                      const double* diagA, double two_nu, const MrScalars& s, int p, hipStream_t st) {
+  STK_R_SWITCH(R, hipLaunchKernelGGL((k_mr_lanczos<T, RR>), dim3(vec_blocks(n)), dim3(kVT), 0, st, n, n_u, q, v,
+                                     vprev_next, znext, diagQ, diagA, two_nu, s, p));
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t mr_update(int R, int64_t n, const T* z, const T* w, T* wprev_new, T* x, const MrScalars& s, int p,
+                     hipStream_t st) {
+  STK_R_SWITCH(R, hipLaunchKernelGGL((k_mr_update<T, RR>), dim3(vec_blocks(n)), dim3(kVT), 0, st, n, z, w, wprev_new, x,
+                                     s, p));
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t spmv_resid(int R, int64_t nrows, const int32_t* rowptr, const int32_t* rowend, const int32_t* col,
+                      const T* val, const T* x, const T* b, T* y, double* partials, unsigned int* counter, double* out,
+                      hipStream_t st) {
+  const int nb = int(std::min<int64_t>(2048, std::max<int64_t>(1, (nrows + 3) / 4)));
+  STK_R_SWITCH(R, hipLaunchKernelGGL((k_spmv_resid<T, RR>), dim3(nb), dim3(kVT), 0, st, nrows, rowptr, rowend, col, val,
+                                     x, b, y, partials, counter, out));
+  return hipGetLastError();
+}
+
+template <typename Ta, typename Tb>
+hipError_t dot(int R, int64_t r0, int64_t r1, const Ta* a, const Tb* b, double* partials, unsigned int* counter,
+               double* out, hipStream_t st) {
+  STK_R_SWITCH(R, hipLaunchKernelGGL((k_dot<Ta, Tb, RR>), dim3(vec_blocks(r1 - r0)), dim3(kVT), 0, st, r0, r1, a, b,
+                                     partials, counter, out));
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t sub_mean(int R, int64_t n_u, int64_t n, T* x, const double* wp, double w1, hipStream_t st) {
+  STK_R_SWITCH(R, hipLaunchKernelGGL((k_sub_mean<T, RR>), dim3(256), dim3(256), 0, st, n_u, n, x, wp, w1));
+  return hipGetLastError();
+}
+
+template <typename Ts, typename Td>
+hipError_t to_interleaved(int R, int64_t len, const Ts* src, int64_t ld, Td* dst, int64_t dst_off, hipStream_t st) {
+  STK_R_SWITCH(R, hipLaunchKernelGGL((k_to_interleaved<Ts, Td, RR>), dim3(1024), dim3(256), 0, st, len, src, ld, dst,
+                                     dst_off));
+  return hipGetLastError();
+}
+
+template <typename Ts, typename Td>
+hipError_t from_interleaved(int R, int64_t len, const Ts* src, int64_t src_off, Td* dst, int64_t ld, hipStream_t st) {
+  STK_R_SWITCH(R, hipLaunchKernelGGL((k_from_interleaved<Ts, Td, RR>), dim3(1024), dim3(256), 0, st, len, src, src_off,
+                                     dst, ld));
+  return hipGetLastError();
+}
+
+template <typename Ts, typename Td>
+hipError_t convert(int64_t n, const Ts* a, Td* b, hipStream_t st) {
+  hipLaunchKernelGGL((k_convert<Ts, Td>), dim3(1024), dim3(256), 0, st, n, a, b);
+  return hipGetLastError();
+}
+
+template <typename Td>
+hipError_t accumulate(int R, int64_t nR, double* x, const Td* d, hipStream_t st) {
+  STK_R_SWITCH(R, hipLaunchKernelGGL((k_accumulate<Td, RR>), dim3(1024), dim3(256), 0, st, nR, x, d));
+  return hipGetLastError();
+}
+
+hipError_t scale(int64_t n, double* a, double s, hipStream_t st) {
+  hipLaunchKernelGGL(k_scale, dim3(1024), dim3(256), 0, st, n, a, s);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t pcg_init(int R, int64_t n_u, const T* b, T* r, T* x, const PcgScalars& s, const int* outer_done,
+                    hipStream_t st) {
+  STK_R_SWITCH(R, hipLaunchKernelGGL((k_pcg_init<T, RR>), dim3(vec_blocks(n_u)), dim3(kVT), 0, st, n_u, b, r, x, s,
+                                     outer_done));
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t pcg_init2(int R, int64_t n_u, const T* z, T* pv, const PcgScalars& s, double rtol, int maxit,
+                     const int* outer_done, const MinresState* outer_st, hipStream_t st) {
+  STK_R_SWITCH(R, hipLaunchKernelGGL((k_pcg_init2<T, RR>), dim3(vec_blocks(n_u * RR)), dim3(kVT), 0, st, n_u, z, pv, s,
+                                     rtol, maxit, outer_done, outer_st));
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t pcg_spmv(int R, int64_t n_u, const int32_t* rowptr, const int32_t* aend, const int32_t* col, const T* val,
+                    const T* pv, T* q, const PcgScalars& s, hipStream_t st) {
+  const int nb = int(std::min<int64_t>(2048, std::max<int64_t>(1, (n_u + 3) / 4)));
+  STK_R_SWITCH(R, hipLaunchKernelGGL((k_pcg_spmv<T, RR>), dim3(nb), dim3(kVT), 0, st, n_u, rowptr, aend, col, val, pv, q,
+                                     s));
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t pcg_axpy(int R, int64_t n_u, const T* pv, const T* q, T* x, T* r, const PcgScalars& s, int ip,
+                    hipStream_t st) {
+  STK_R_SWITCH(R, hipLaunchKernelGGL((k_pcg_axpy<T, RR>), dim3(vec_blocks(n_u)), dim3(kVT), 0, st, n_u, pv, q, x, r, s,
+                                     ip);
+               hipLaunchKernelGGL((k_pcg_check<RR>), dim3(1), dim3(64), 0, st, s));
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t pcg_pupdate(int R, int64_t n_u, const T* z, T* pv, const PcgScalars& s, int ip, hipStream_t st) {
+  STK_R_SWITCH(R, hipLaunchKernelGGL((k_pcg_pupdate<T, RR>), dim3(vec_blocks(n_u)), dim3(kVT), 0, st, n_u, z, pv, s, ip));
+  return hipGetLastError();
+}
+
+// explicit instantiations used by the host code
+#define STK_INST(T)                                                                                                   \
+  template hipError_t mr_init_vec<T>(int, int64_t, int64_t, const T*, T*, T*, T*, T*, T*, T*, const double*,         \
+                                     const double*, double, const MrScalars&, hipStream_t);                          \
+  template hipError_t mr_spmv<T>(int, int64_t, const int32_t*, const int32_t*, const T*, const T*, T*,               \
+                                 const MrScalars&, int, hipStream_t);                                               \
+  template hipError_t mr_lanczos<T>(int, int64_t, int64_t, const T*, const T*, T*, T*, const double*, const double*,  \
+                                    double, const MrScalars&, int, hipStream_t);                                     \
+  template hipError_t mr_update<T>(int, int64_t, const T*, const T*, T*, T*, const MrScalars&, int, hipStream_t);    \
+  template hipError_t spmv_resid<T>(int, int64_t, const int32_t*, const int32_t*, const int32_t*, const T*, const T*, \
+                                    const T*, T*, double*, unsigned int*, double*, hipStream_t);                     \
+  template hipError_t sub_mean<T>(int, int64_t, int64_t, T*, const double*, double, hipStream_t);                    \
+  template hipError_t pcg_init<T>(int, int64_t, const T*, T*, T*, const PcgScalars&, const int*, hipStream_t);       \
+  template hipError_t pcg_init2<T>(int, int64_t, const T*, T*, const PcgScalars&, double, int, const int*,           \
+                                   const MinresState*, hipStream_t);                                                 \
+  template hipError_t pcg_spmv<T>(int, int64_t, const int32_t*, const int32_t*, const int32_t*, const T*, const T*,  \
+                                  T*, const PcgScalars&, hipStream_t);                                               \
+  template hipError_t pcg_axpy<T>(int, int64_t, const T*, const T*, T*, T*, const PcgScalars&, int, hipStream_t);    \
+  template hipError_t pcg_pupdate<T>(int, int64_t, const T*, T*, const PcgScalars&, int, hipStream_t);
+STK_INST(double)
+STK_INST(float)
+
+template hipError_t dot<double, double>(int, int64_t, int64_t, const double*, const double*, double*, unsigned int*,
+                                        double*, hipStream_t);
+template hipError_t dot<float, float>(int, int64_t, int64_t, const float*, const float*, double*, unsigned int*,
+                                      double*, hipStream_t);
+template hipError_t to_interleaved<double, double>(int, int64_t, const double*, int64_t, double*, int64_t, hipStream_t);
+template hipError_t to_interleaved<double, float>(int, int64_t, const double*, int64_t, float*, int64_t, hipStream_t);
+template hipError_t from_interleaved<double, double>(int, int64_t, const double*, int64_t, double*, int64_t,
+                                                     hipStream_t);
+template hipError_t convert<double, float>(int64_t, const double*, float*, hipStream_t);
+template hipError_t convert<float, double>(int64_t, const float*, double*, hipStream_t);
+template hipError_t accumulate<float>(int, int64_t, double*, const float*, hipStream_t);
+template hipError_t accumulate<double>(int, int64_t, double*, const double*, hipStream_t);
+
+}  // namespace stk

@@ -1,0 +1,272 @@
+// Internal declarations shared by the host orchestration and the HIP kernels of
+// libstokes.so.  Not part of the public ABI (include/stokes.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace stk {
+
+// ---------------------------------------------------------------------------
+// Discrete spaces (Sec. 3.2 of the paper): per velocity component c and direction
+// d the number of retained 1D functions, their offset and degree.
+// ---------------------------------------------------------------------------
+struct Spaces {
+  int N = 0, kp = 0, dim = 0, pdeg = 0;  // elements/dir, pressure degree k', dim, k'+1
+  int vcnt[3][3] = {{0}};                // retained 1D functions of comp c in dir d
+  int vshift[3][3] = {{0}};              // 1D index = local index + vshift (1 in dir c)
+  int vdeg[3][3] = {{0}};                // 1D degree of comp c in dir d
+  int64_t voff[4] = {0};                 // component offsets in the velocity numbering
+  int64_t n_u = 0, n_p = 0;
+  int nlo = 0, nhi = 0;                  // N + k', N + k' + 1 (1D function counts)
+};
+
+Spaces make_spaces(int N, int kp, int dim);
+
+// Saddle-point CSR pattern: rows 0..n_u-1 velocity (A entries then B^T entries),
+// rows n_u..n-1 pressure (B entries).  Also the end of the A part of each velocity row.
+struct SaddlePattern {
+  std::vector<int32_t> rowptr;  // [n+1]  (nnz < 2^31 is checked)
+  std::vector<int32_t> col;     // [nnz]
+  std::vector<int32_t> aend;    // [n_u] position where the B^T part of velocity row i starts
+};
+
+int build_saddle_pattern(const Spaces& S, SaddlePattern& P, std::string& err);
+
+// Lower triangle of A (IC(0) pattern), diagonal last in each row; lsrc[k] = index of the
+// entry in the saddle CSR values.
+struct LowerPattern {
+  std::vector<int32_t> rowptr, col;
+  std::vector<int64_t> src;
+};
+void build_lower_pattern(const Spaces& S, const SaddlePattern& P, LowerPattern& L);
+
+// ---------------------------------------------------------------------------
+// Triangular-solve schedule (one direction).  Rows are split into groups (one
+// cooperative workgroup each).  Inside a group the rows are processed in
+// dependency-level order in "steps" of at most kTrsvRPS rows of one level; the
+// dependencies of a row are spread over kTrsvG lanes, E per lane.  Every dependency
+// value is read from an LDS slot.  Slots are assigned by value lifetime (interval
+// allocation over steps), so LDS holds only a window of levels: local values from the
+// step that computes them to their last local use; values of rows owned by other
+// groups ("halo") from a fixed look-ahead before their first use to their last use.
+// ---------------------------------------------------------------------------
+constexpr int kTrsvG = 8;                  // lanes per row
+constexpr int kTrsvRPS = 64 / kTrsvG;      // rows per step (one compute wave)
+constexpr int kTrsvThreads = 192;          // compute wave + halo wave + writer wave
+constexpr int kTrsvRing = 16;              // output ring (steps) between compute and writer
+constexpr int kTrsvHaloLookahead = 16;     // steps before first use a halo slot is allocated
+constexpr int kLevelStride = 1 << 21;      // progress value = epoch * stride + level + 1
+
+struct TrsvSchedHost {
+  int ngroups = 0, nsteps = 0, E = 0, nlevels = 0, nslots = 0, strip = 0;
+  int max_deg = 0;
+  std::vector<int32_t> grp_step_ptr;       // [ngroups+1]
+  std::vector<int32_t> grp_halo_ptr;       // [ngroups+1]
+  std::vector<int32_t> halo_row;           // remote row (global index)
+  std::vector<int32_t> halo_grp;           // producing group
+  std::vector<int32_t> halo_lvl;           // level of the remote row
+  std::vector<int32_t> halo_slot;          // LDS slot
+  std::vector<int32_t> halo_free;          // steps (group-relative) that must be computed first
+  std::vector<int32_t> step_level;         // [nsteps]
+  std::vector<int32_t> step_halo_need;     // [nsteps] halo entries (prefix) that must be staged
+  std::vector<int32_t> step_publish;       // [nsteps] 1: publish progress after this step
+  std::vector<int32_t> srow;               // [nsteps*RPS] row or -1
+  std::vector<int32_t> sslot;              // [nsteps*RPS] LDS slot of the result (0: not kept)
+  std::vector<int64_t> sdiag_src;          // [nsteps*RPS] index of the diagonal in L values
+  std::vector<int32_t> ent_src;            // [nsteps*E*64] LDS slot of the dependency
+  std::vector<int64_t> ent_perm;           // [nsteps*E*64] index in L values or -1 (pad)
+};
+
+struct TrsvSchedDev {
+  int ngroups = 0, nsteps = 0, E = 0, nlevels = 0, nslots = 0, nrows = 0;
+  int32_t *grp_step_ptr = nullptr, *grp_halo_ptr = nullptr;
+  int32_t *halo_row = nullptr, *halo_grp = nullptr, *halo_lvl = nullptr, *halo_slot = nullptr, *halo_free = nullptr;
+  int32_t *step_level = nullptr, *step_halo_need = nullptr, *step_publish = nullptr;
+  int32_t *srow = nullptr, *sslot = nullptr, *ent_src = nullptr;
+  int64_t *sdiag_src = nullptr, *ent_perm = nullptr;
+  double* ent_val = nullptr;   // factor values in schedule order
+  float* ent_val32 = nullptr;
+  double* sdinv = nullptr;     // reciprocal diagonals in schedule order
+  float* sdinv32 = nullptr;
+  void* rhs_s = nullptr;       // right-hand side gathered into schedule order (R_max doubles)
+  unsigned long long* progress = nullptr;  // [ngroups]
+  unsigned long long* epoch = nullptr;     // [1]
+  unsigned int* done_count = nullptr;      // [1]
+  int* err = nullptr;                      // [1] spin-limit flag
+  double* partials = nullptr;              // [ngroups * 16]
+  int rmax = 0;                            // widest R the LDS budget allows
+};
+
+// dir = +1 forward (L y = r), -1 backward (L^T z = y).  group_of[i] gives the group
+// of each row (spatial strips).  Returns false with err on failure.
+bool build_trsv_schedule(const LowerPattern& L, int64_t n, int dir, const std::vector<int32_t>& group_of,
+                         int ngroups, TrsvSchedHost& S, std::string& err);
+
+// Strip partition of the velocity rows: component c, last-direction 1D index t -> group
+// offset_c + t / strip.
+void strip_groups(const Spaces& S, int strip, std::vector<int32_t>& group_of, int* ngroups);
+
+// Levels of the forward dependency DAG (used by the IC(0) factorisation too).
+void forward_levels(const LowerPattern& L, int64_t n, std::vector<int32_t>& lev, int* nlev);
+
+// ---------------------------------------------------------------------------
+// Device-side MINRES scalar state (double buffered by iteration parity).
+// ---------------------------------------------------------------------------
+struct MinresState {
+  double gamma, gamma_prev, gamma1, eta;
+  double c, c_prev, s, s_prev;
+  double delta, g2p, g2u, tolg;  // tolg = tol * gamma1
+  int iter, done, status, maxit;
+};
+
+// Inner PCG state (IC(0)-PCG on A).
+struct PcgState {
+  double rho, pq, rr, bnorm2, rtol2;
+  int iter, done, maxit, total;
+};
+
+
+// ---------------------------------------------------------------------------
+// Krylov scalars on the device and the deterministic block reduction.
+// ---------------------------------------------------------------------------
+constexpr int kVT = 256;  // threads per block of the vector kernels
+constexpr int kRMax = 16;
+
+// Scalar arrays (device), indexed [parity][kind][column].
+enum { RED_DELTA = 0, RED_G2P = 1, RED_G2U = 2, RED_KINDS = 3 };
+
+struct MrScalars {
+  MinresState* st;   // [2][kRMax]
+  int* alldone;      // [2]
+  double* red;       // [2][RED_KINDS][kRMax]
+  double* partials;  // [maxblocks * 2 * kRMax]
+  unsigned int* counter;
+};
+
+__device__ __forceinline__ double* red_at(const MrScalars& s, int p, int kind) {
+  return s.red + ((size_t)p * RED_KINDS + kind) * kRMax;
+}
+
+// Block reduction of NV values per thread; the last block adds all partials in block
+// order and calls fin(k, value) for k < NV.  Returns nothing; thread 0 handles `fin`.
+template <int NV, typename Fin>
+__device__ void reduce_last(double (&v)[NV], double* partials, unsigned int* counter, Fin fin) {
+  __shared__ double sred[kVT / 64][NV];
+  __shared__ int is_last;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double x = v[k];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (lane == 0) sred[wid][k] = x;
+  }
+  __syncthreads();
+  if (tid < NV) {
+    double x = 0.0;
+#pragma unroll
+    for (int w = 0; w < kVT / 64; ++w) x += sred[w][tid];
+    partials[(size_t)blockIdx.x * NV + tid] = x;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    __threadfence();
+    const unsigned int prev = atomicAdd(counter, 1u);
+    is_last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (is_last) {
+    __threadfence();
+    if (tid < NV) {
+      double x = 0.0;
+      for (unsigned int b = 0; b < gridDim.x; ++b) x += __hip_atomic_load(partials + (size_t)b * NV + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      fin(tid, x);
+    }
+    if (tid == 0) *counter = 0;
+  }
+}
+
+inline int vec_blocks(int64_t nitems) {
+  int64_t b = (nitems + 4 * kVT - 1) / (4 * kVT);
+  return int(std::max<int64_t>(1, std::min<int64_t>(b, 1024)));
+}
+
+struct PcgScalars {
+  PcgState* st;     // [kRMax]
+  int* alldone;     // [1]
+  double* rho;      // [2][kRMax] (parity of the inner iteration)
+  double* pq;       // [kRMax]
+  double* rr;       // [kRMax]
+  double* partials;
+  unsigned int* counter;
+};
+
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (defined in the .hip files).
+// ---------------------------------------------------------------------------
+hipError_t assemble_saddle(const Spaces& S, double nu, double cpen, const int32_t* rowptr, const int32_t* col,
+                           double* val, double* diagQ, double* w, hipStream_t st);
+hipError_t assemble_load(const Spaces& S, double nu, int manufactured, int nmodes, int nrhs, const double* amp_d,
+                         const int32_t* wave_d, const double* phase_d, double* f, hipStream_t st);
+hipError_t ic0_factor(int64_t n, int64_t nnzL, const int64_t* src, const int32_t* rowptr, const int32_t* col,
+                      const double* Aval, double alpha, double* Lval, const int32_t* level_rows,
+                      const std::vector<int32_t>& level_ptr, int* flag, hipStream_t st);
+hipError_t launch_trsv(const TrsvSchedDev& S, bool fp32, int R, const void* rhs, void* out, const void* dotv,
+                       double* dot_out, const int* skip, hipStream_t st);
+hipError_t launch_trsv_gather(const TrsvSchedDev& S, const double* Lval, hipStream_t st);
+size_t trsv_shmem_bytes(int nslots, bool fp32, int R);
+
+template <typename T>
+hipError_t mr_init_vec(int R, int64_t n, int64_t n_u, const T* b, T* v1, T* v0, T* w1, T* w0, T* x, T* z1,
+                       const double* diagQ, const double* diagA, double two_nu, const MrScalars& s, hipStream_t st);
+hipError_t mr_init_state(int R, const MrScalars& s, double tol, int maxit, hipStream_t st);
+template <typename T>
+hipError_t mr_spmv(int R, int64_t n, const int32_t* rowptr, const int32_t* col, const T* val, const T* z, T* q,
+                   const MrScalars& s, int p, hipStream_t st);
+template <typename T>
+hipError_t mr_lanczos(int R, int64_t n, int64_t n_u, const T* q, const T* v, T* vprev_next, T* znext, const double* diagQ,
+                      const double* diagA, double two_nu, const MrScalars& s, int p, hipStream_t st);
+template <typename T>
+hipError_t mr_update(int R, int64_t n, const T* z, const T* w, T* wprev_new, T* x, const MrScalars& s, int p,
+                     hipStream_t st);
+template <typename T>
+hipError_t spmv_resid(int R, int64_t nrows, const int32_t* rowptr, const int32_t* rowend, const int32_t* col,
+                      const T* val, const T* x, const T* b, T* y, double* partials, unsigned int* counter, double* out,
+                      hipStream_t st);
+template <typename Ta, typename Tb>
+hipError_t dot(int R, int64_t r0, int64_t r1, const Ta* a, const Tb* b, double* partials, unsigned int* counter,
+               double* out, hipStream_t st);
+template <typename T>
+hipError_t sub_mean(int R, int64_t n_u, int64_t n, T* x, const double* wp, double w1, hipStream_t st);
+template <typename Ts, typename Td>
+hipError_t to_interleaved(int R, int64_t len, const Ts* src, int64_t ld, Td* dst, int64_t dst_off, hipStream_t st);
+template <typename Ts, typename Td>
+hipError_t from_interleaved(int R, int64_t len, const Ts* src, int64_t src_off, Td* dst, int64_t ld, hipStream_t st);
+template <typename Ts, typename Td>
+hipError_t convert(int64_t n, const Ts* a, Td* b, hipStream_t st);
+template <typename Td>
+hipError_t accumulate(int R, int64_t nR, double* x, const Td* d, hipStream_t st);
+hipError_t scale(int64_t n, double* a, double s, hipStream_t st);
+template <typename T>
+hipError_t pcg_init(int R, int64_t n_u, const T* b, T* r, T* x, const PcgScalars& s, const int* outer_done,
+                    hipStream_t st);
+template <typename T>
+hipError_t pcg_init2(int R, int64_t n_u, const T* z, T* pv, const PcgScalars& s, double rtol, int maxit,
+                     const int* outer_done, const MinresState* outer_st, hipStream_t st);
+template <typename T>
+hipError_t pcg_spmv(int R, int64_t n_u, const int32_t* rowptr, const int32_t* aend, const int32_t* col, const T* val,
+                    const T* pv, T* q, const PcgScalars& s, hipStream_t st);
+template <typename T>
+hipError_t pcg_axpy(int R, int64_t n_u, const T* pv, const T* q, T* x, T* r, const PcgScalars& s, int ip,
+                    hipStream_t st);
+template <typename T>
+hipError_t pcg_pupdate(int R, int64_t n_u, const T* z, T* pv, const PcgScalars& s, int ip, hipStream_t st);
+
+
+}  // namespace stk

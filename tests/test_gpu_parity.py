@@ -1,0 +1,214 @@
+"""GPU parity: every product kernel, called through the C ABI, against the FP64 CPU
+oracle on the same seeded inputs.
+
+Tolerances (relative, norm-wise unless stated):
+  assembly, diag(Q), w, load vector   1e-13   (same quadrature, different summation order)
+  IC(0) factor                        1e-12
+  saddle product                      1e-14
+  preconditioner application          1e-12
+  MINRES after the same k iterations  1e-10   (u and p)
+  converged solutions (tol 1e-13)     1e-10;  stop counts at tol 1e-8 within +-1
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle.oracle import PC_IC0, PC_ICPCG, PC_JACOBI, PQ_DIAG, Oracle  # noqa: E402
+from synthetic_inputs import forcing_modes, random_vector  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    d = np.linalg.norm(a - b)
+    s = np.linalg.norm(b)
+    return d / s if s > 0 else d
+
+
+def _cuda(x):
+    return torch.as_tensor(np.ascontiguousarray(x, np.float64)).cuda()
+
+
+@pytest.fixture(scope="module", params=[(16, 1, 2), (12, 2, 2), (5, 3, 2), (4, 1, 3)],
+                ids=["2d_k1_n16", "2d_k2_n12", "2d_k3_n5", "3d_k1_n4"])
+def pair(request):
+    from paper_1309_5048_amd import StokesProblem
+    N, kp, dim = request.param
+    print("\n[case] N=%d k'=%d dim=%d" % (N, kp, dim), flush=True)
+    gp = StokesProblem(N, kp, dim, 1.0)
+    o = Oracle(N, kp, dim, 1.0)
+    o.ic0()
+    return gp, o
+
+
+def test_sizes(pair):
+    gp, o = pair
+    assert (gp.n_u, gp.n_p) == (o.n_u, o.n_p)
+
+
+def test_assembly(pair):
+    gp, o = pair
+    ptr, col, val = gp.export_csr(0)
+    K = o.saddle().tocsr()
+    K.sort_indices()
+    assert np.array_equal(ptr, K.indptr) and np.array_equal(col, K.indices)
+    assert np.abs(val - K.data).max() <= 1e-13 * np.abs(K.data).max()
+    d, w = gp.export_pressure_mass()
+    od, ow = o.diagQ_w()
+    assert np.abs(d - od).max() <= 1e-13 * od.max()
+    assert np.abs(w - ow).max() <= 1e-13 * ow.max()
+
+
+def test_ic0_factor(pair):
+    gp, o = pair
+    ptr, col, val = gp.export_csr(1)
+    optr, ocol, oval = o.csr("L")
+    assert np.array_equal(ptr, optr) and np.array_equal(col, ocol)
+    assert np.abs(val - oval).max() <= 1e-12 * np.abs(oval).max()
+
+
+def test_saddle_product(pair):
+    gp, o = pair
+    x = random_vector(o.n, 11)
+    y = gp.apply(_cuda(x)).cpu().numpy()
+    assert _rel(y, o.matvec(x)) <= 1e-14
+
+
+@pytest.mark.parametrize("pc", [PC_IC0, PC_JACOBI, PC_ICPCG])
+def test_preconditioner(pair, pc):
+    gp, o = pair
+    r = random_vector(o.n, 12)
+    z, it = gp.apply_precond(_cuda(r), pc)
+    zo, ito = o.precond(r, pc_A=pc, pc_Q=PQ_DIAG, inner_tol=1e-2)
+    tol = 1e-12 if pc != PC_ICPCG else 1e-9
+    assert _rel(z.cpu().numpy(), zo) <= tol
+    if pc == PC_ICPCG:
+        assert it == ito
+
+
+def test_load_vector(pair):
+    gp, o = pair
+    f = gp.load(True).cpu().numpy()[0]
+    assert _rel(f, o.load(1)) <= 1e-13
+    modes = forcing_modes([1000, 1001, 1002], o.dim)
+    F = gp.load(True, modes).cpu().numpy()
+    Fo = o.load(1, modes)
+    for r in range(3):
+        assert _rel(F[r], Fo[r]) <= 1e-13
+
+
+@pytest.mark.parametrize("pc", [PC_IC0, PC_JACOBI])
+def test_minres_fixed_iterations(pair, pc):
+    """Same k iterations (stopped by the iteration limit): iterates agree to 1e-10."""
+    gp, o = pair
+    f = o.load(1)
+    for k in (1, 5, 17):
+        gp.set_maxit(k, 0)
+        u, p, info = gp.solve(_cuda(f), tol=1e-15, precond=pc)
+        assert info["iters"] == k and info["status"] == 1
+        uo, po, io = o.solve(f, maxit=k, pc_A=pc, fixed=True)
+        assert _rel(u.cpu().numpy(), uo) <= 1e-10, k
+        assert _rel(p.cpu().numpy(), po) <= 1e-10, k
+    gp.set_maxit(20000, 200)
+
+
+@pytest.mark.parametrize("pc", [PC_IC0, PC_JACOBI, PC_ICPCG])
+def test_minres_converged(pair, pc):
+    gp, o = pair
+    f = o.load(1)
+    u, p, info = gp.solve(_cuda(f), tol=1e-8, precond=pc)
+    uo, po, io = o.solve(f, tol=1e-8, pc_A=pc)
+    assert info["status"] == 0
+    assert abs(info["iters"] - io["iters"]) <= 1, (info["iters"], io["iters"])
+    assert info["relres_true_Minv"] <= 2e-8
+    u2, p2, info2 = gp.solve(_cuda(f), tol=1e-13, precond=pc)
+    uo2, po2, _ = o.solve(f, tol=1e-13, pc_A=pc)
+    assert _rel(u2.cpu().numpy(), uo2) <= 1e-10
+    assert _rel(p2.cpu().numpy(), po2) <= 1e-10
+    # zero-mean pressure
+    d, w = gp.export_pressure_mass()
+    assert abs(w @ p2.cpu().numpy()) <= 1e-12 * np.abs(p2.cpu().numpy()).max()
+
+
+@pytest.mark.parametrize("nrhs", [3, 8, 16])
+def test_batched(pair, nrhs):
+    gp, o = pair
+    modes = forcing_modes(list(range(1000, 1000 + nrhs)), o.dim)
+    F = o.load(1, modes)
+    U, P, infos = gp.solve_batched(_cuda(F), tol=1e-8)
+    for r in range(nrhs):
+        uo, po, io = o.solve(F[r], tol=1e-8)
+        assert abs(infos[r]["iters"] - io["iters"]) <= 1
+        assert infos[r]["status"] == 0
+    U2, P2, _ = gp.solve_batched(_cuda(F), tol=1e-13)
+    for r in range(nrhs):
+        uo, po, _ = o.solve(F[r], tol=1e-13)
+        assert _rel(U2[r].cpu().numpy(), uo) <= 1e-10
+        assert _rel(P2[r].cpu().numpy(), po) <= 1e-10
+
+
+def test_mixed_precision(pair):
+    from paper_1309_5048_amd import MIXED
+    gp, o = pair
+    f = o.load(1)
+    u, p, info = gp.solve(_cuda(f), tol=1e-8, precision=MIXED)
+    assert info["status"] == 0 and info["relres_true_Minv"] <= 1e-8
+    uo, po, _ = o.solve(f, tol=1e-13)
+    assert _rel(u.cpu().numpy(), uo) <= 1e-6
+    assert _rel(p.cpu().numpy(), po) <= 1e-6
+
+
+def test_adjoint(pair):
+    gp, o = pair
+    g_u = random_vector(o.n_u, 5)
+    g_p = random_vector(o.n_p, 6)
+    lam, infos = gp.solve_adjoint(_cuda(np.concatenate([g_u, g_p])), tol=1e-13)
+    lu, lp, _ = o.adjoint(g_u, g_p, tol=1e-13)
+    lam = lam.cpu().numpy()
+    assert _rel(lam[:o.n_u], lu) <= 1e-10
+    assert _rel(lam[o.n_u:], lp) <= 1e-10
+    u = random_vector(o.n_u, 9)
+    d = gp.dnu_dot(_cuda(lu), _cuda(u))[0]
+    assert abs(d - o.dnu_dot(lu, u)) <= 1e-12 * abs(o.dnu_dot(lu, u))
+
+
+# ---------------------------------------------------------------------------
+# Degenerate inputs and error paths
+# ---------------------------------------------------------------------------
+def test_edge_cases():
+    from paper_1309_5048_amd import StokesProblem, StokesError
+    gp = StokesProblem(1, 1, 2, 1.0)  # a single element
+    o = Oracle(1, 1, 2, 1.0)
+    f = o.load(1)
+    u, p, info = gp.solve(_cuda(f), tol=1e-12)
+    uo, po, _ = o.solve(f, tol=1e-12)
+    assert _rel(u.cpu().numpy(), uo) <= 1e-9
+    gp = StokesProblem(6, 2, 2, 1.0)
+    z = torch.zeros(gp.n_u, dtype=torch.float64, device="cuda")
+    u, p, info = gp.solve(z, tol=1e-8)
+    assert info["iters"] == 0 and float(u.abs().max()) == 0.0 and float(p.abs().max()) == 0.0
+    bad = z.clone()
+    bad[3] = float("nan")
+    with pytest.raises(StokesError):
+        gp.solve(bad, tol=1e-8)
+    with pytest.raises(StokesError):
+        gp.solve(_cuda(Oracle(6, 2).load(1)), tol=2.0)
+    with pytest.raises(StokesError):
+        StokesProblem(4, 5, 2, 1.0)
+    gp.set_maxit(2, 0)
+    u, p, info = gp.solve(_cuda(Oracle(6, 2).load(1)), tol=1e-8)
+    assert info["status"] == 1 and info["iters"] == 2
+
+
+def test_set_nu_matches_fresh_setup():
+    from paper_1309_5048_amd import StokesProblem
+    gp = StokesProblem(10, 2, 2, 1.0)
+    gp.set_nu(0.01)
+    o = Oracle(10, 2, 2, 0.01)
+    f = o.load(1)
+    u, p, info = gp.solve(_cuda(f), tol=1e-13)
+    uo, po, _ = o.solve(f, tol=1e-13)
+    assert _rel(u.cpu().numpy(), uo) <= 1e-9
+    assert _rel(p.cpu().numpy(), po) <= 1e-9
