@@ -1,0 +1,253 @@
+"""Benchmark: time-to-solution of block-diagonally preconditioned MINRES for the
+divergence-conforming B-spline Stokes system on one MI355X.
+
+Headline workload (one "step" = one complete solve from the assembled load vector to the
+zero-mean (u, p), inputs resident in HBM): 2D unit square, N = 256 elements per
+direction, pressure degree k' = 2 (velocity degree 3), nu = 1, manufactured forcing,
+FP64, M = blkdiag(IC(0) of A, Diag(Q)/(2 nu)), relative M^{-1}-norm residual 1e-8.
+
+Printed: one JSON line with the headline value (seconds per solve), MINRES iterations/s,
+a roofline object for the dominant kernel (algorithmic bytes per launch over its average
+launch time, measured with HIP events on the solver's stream during the timed solves), the
+same for the saddle SpMV, the CPU oracle timed on one host core on a bounded sample, and
+the variant comparisons (IC(0)-PCG, mixed precision at N = 512, batched 3D, adjoint).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "time-to-solution @ rel.res 1e-8 (s), MINRES iters/s, SpMV HBM GB/s vs peak"
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def trsv_bytes(nnzL, n_u, R=1, wbytes=8):
+    """Algorithmic bytes of one triangular solve: every off-diagonal factor entry (value +
+    int32 column) and diagonal once, the right-hand side read and the result written once."""
+    return (wbytes + 4) * (nnzL - n_u) + wbytes * n_u + 2 * wbytes * n_u * R
+
+
+def spmv_bytes(nnz, n, R=1, wbytes=8):
+    """Algorithmic bytes of one saddle product q = Acal z with the fused dot q.z: values and
+    int32 columns once, row pointers, z read once, q written once."""
+    return (wbytes + 4) * nnz + 4 * (n + 1) + 2 * wbytes * n * R
+
+
+def sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def timed_solves(gp, f, steps, warmup, **kw):
+    for _ in range(warmup):
+        gp.solve(f, **kw)
+    sync()
+    t0 = time.perf_counter()
+    infos = []
+    for _ in range(steps):
+        infos.append(gp.solve(f, **kw)[2])
+    sync()
+    return (time.perf_counter() - t0) / steps, infos
+
+
+def cpu_baseline(N, kp, dim, iters_needed, sample_iters):
+    """Oracle (one host core, FP64) on a bounded sample: setup and IC(0) untimed, then
+    `sample_iters` MINRES-IC(0) iterations timed; time-to-solution extrapolated to the
+    iteration count the solve needs."""
+    from oracle.oracle import Oracle
+    import numpy as np
+    t = time.perf_counter()
+    o = Oracle(N, kp, dim, 1.0)
+    o.ic0()
+    f = o.load(1)
+    t_setup = time.perf_counter() - t
+    b = np.concatenate([f, np.zeros(o.n_p)])
+    t0 = time.perf_counter()
+    o.minres(b, maxit=sample_iters, fixed=True)
+    dt = time.perf_counter() - t0
+    ips = sample_iters / dt
+    return {"value": iters_needed / ips, "unit": "s", "cores": 1, "kind": "oracle",
+            "iters_per_s": ips,
+            "sample": "%d MINRES-IC(0) iterations of the N=%d k'=%d dim=%d system (setup %.1f s untimed), "
+                      "extrapolated to %d iterations" % (sample_iters, N, kp, dim, t_setup, iters_needed)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-extra", action="store_true", help="skip the variant comparisons")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-iters", type=int, default=150)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this solver path is built and measured on a single "
+              "MI355X (no multi-GPU path); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1309_5048_amd import StokesProblem, PC_IC0, PC_ICPCG, MIXED, FP64
+
+    torch.cuda.set_device(0)
+    N, kp, dim, tol = 256, 2, 2, 1e-8
+    log("setup N=%d k'=%d dim=%d" % (N, kp, dim))
+    t = time.perf_counter()
+    gp = StokesProblem(N, kp, dim, 1.0)
+    setup_s = time.perf_counter() - t
+    f = gp.load(True)[0]
+    nnz = gp.export_csr(0)[1].size
+    nnzL = gp.export_csr(1)[1].size
+    n = gp.n_u + gp.n_p
+    lev_f, lev_b = gp.levels()
+    log("n_u=%d n_p=%d nnz=%d nnzL=%d levels=%d/%d setup %.1fs" % (gp.n_u, gp.n_p, nnz, nnzL, lev_f, lev_b, setup_s))
+
+    # warmup, then the timed solves with live kernel timing on the solver's stream
+    for _ in range(args.warmup):
+        gp.solve(f, tol=tol, precond=PC_IC0)
+    sync()
+    gp.profile(1)
+    t0 = time.perf_counter()
+    infos = []
+    for _ in range(args.steps):
+        u, p, info = gp.solve(f, tol=tol, precond=PC_IC0)
+        infos.append(info)
+    sync()
+    sec = (time.perf_counter() - t0) / args.steps
+    prof = gp.profile(0)
+    iters = infos[-1]["iters"]
+    log("solve %.4f s, %d iterations, relres %.2e" % (sec, iters, infos[-1]["relres_true_Minv"]))
+
+    def roof(name, bytes_per_launch):
+        ms, cnt = prof[name]
+        if cnt == 0:
+            return None
+        avg_s = ms / cnt / 1e3
+        gbs = bytes_per_launch / avg_s / 1e9
+        return {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 5), "traffic": None, "kernel": name,
+                "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_bytes_per_launch": int(bytes_per_launch),
+                "launches": int(cnt)}
+
+    tb = trsv_bytes(nnzL, gp.n_u)
+    sb = spmv_bytes(nnz, n)
+    r_f, r_b, r_s = roof("trsv_fwd", tb), roof("trsv_bwd", tb), roof("spmv", sb)
+    dominant = max((r for r in (r_f, r_b, r_s) if r), key=lambda r: r["avg_launch_us"] * r["launches"])
+    kernel_ms = {k: round(v[0], 3) for k, v in prof.items()}
+
+    out = {
+        "metric": METRIC, "value": round(sec, 6), "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 3), "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "c1_2d_k2_n256", "N": N, "kprime": kp, "dim": dim, "nu": 1.0, "tol": tol,
+                   "precond": "ic0+diagQ", "n_u": gp.n_u, "n_p": gp.n_p, "nnz": int(nnz), "nnz_L": int(nnzL),
+                   "trsv_levels": [lev_f, lev_b], "forcing": "manufactured"},
+        "iters": iters, "iters_per_s": round(iters / sec, 2),
+        "relres_true_Minv": infos[-1]["relres_true_Minv"], "relres_true_2": infos[-1]["relres_true_2"],
+        "setup_s": round(setup_s, 3),
+        "roofline": dominant, "roofline_spmv": r_s,
+        "kernel_ms_in_timed_region": kernel_ms,
+    }
+
+    if not args.no_extra:
+        extra = {}
+        try:
+            gp.set_inner_tol(1e-2)
+            s_pcg, inf_pcg = timed_solves(gp, f, 1, 1, tol=tol, precond=PC_ICPCG)
+            extra["c1_icpcg_inner1e-2"] = {"s": round(s_pcg, 5), "iters": inf_pcg[-1]["iters"],
+                                           "inner_iters_total": inf_pcg[-1]["inner_iters_total"],
+                                           "relres_true_Minv": inf_pcg[-1]["relres_true_Minv"]}
+            log("icpcg", extra["c1_icpcg_inner1e-2"])
+        except Exception as e:  # report, keep the headline
+            extra["c1_icpcg_inner1e-2"] = {"error": str(e)}
+        del gp
+        torch.cuda.empty_cache()
+        try:
+            g2 = StokesProblem(512, 2, 2, 1.0)
+            f2 = g2.load(True)[0]
+            s64, i64 = timed_solves(g2, f2, 1, 1, tol=tol, precond=PC_IC0, precision=FP64)
+            s32, i32 = timed_solves(g2, f2, 1, 1, tol=tol, precond=PC_IC0, precision=MIXED)
+            u64, p64, _ = g2.solve(f2, tol=1e-13)
+            um, pm, _ = g2.solve(f2, tol=tol, precision=MIXED)
+            eu = float((um - u64).norm() / u64.norm())
+            ep = float((pm - p64).norm() / p64.norm())
+            extra["c2_n512_mixed_vs_fp64"] = {"fp64_s": round(s64, 5), "fp64_iters": i64[-1]["iters"],
+                                              "mixed_s": round(s32, 5), "mixed_iters": i32[-1]["iters"],
+                                              "speedup": round(s64 / s32, 3), "mixed_rel_err_u": eu,
+                                              "mixed_rel_err_p": ep,
+                                              "mixed_relres_true_Minv": i32[-1]["relres_true_Minv"]}
+            log("c2", extra["c2_n512_mixed_vs_fp64"])
+            del g2
+            torch.cuda.empty_cache()
+        except Exception as e:
+            extra["c2_n512_mixed_vs_fp64"] = {"error": str(e)}
+        try:
+            from synthetic_inputs import forcing_modes, WORKLOADS
+            w3 = WORKLOADS["c3_3d_k1_n32_r16"]
+            g3 = StokesProblem(w3["N"], w3["kp"], w3["dim"], 1.0)
+            F3 = g3.load(True, forcing_modes(w3["seeds"], 3))
+            g3.solve_batched(F3, tol=tol)
+            sync()
+            t = time.perf_counter()
+            U3, P3, inf3 = g3.solve_batched(F3, tol=tol)
+            sync()
+            sb3 = time.perf_counter() - t
+            t = time.perf_counter()
+            for r in range(F3.shape[0]):
+                g3.solve(F3[r].contiguous(), tol=tol)
+            sync()
+            ss3 = time.perf_counter() - t
+            extra["c3_3d_n32_16rhs"] = {"batched_s": round(sb3, 5), "sequential_s": round(ss3, 5),
+                                        "speedup": round(ss3 / sb3, 3),
+                                        "iters": [i["iters"] for i in inf3]}
+            log("c3", extra["c3_3d_n32_16rhs"])
+            del g3
+            torch.cuda.empty_cache()
+        except Exception as e:
+            extra["c3_3d_n32_16rhs"] = {"error": str(e)}
+        try:
+            from synthetic_inputs import forcing_modes, target_perturbations, WORKLOADS
+            from paper_1309_5048_amd import stokes_solve
+            w4 = WORKLOADS["c4_2d_k2_n256_r8"]
+            g4 = StokesProblem(w4["N"], w4["kp"], 2, 1.0)
+            F4 = g4.load(True, forcing_modes(w4["seeds"], 2))
+            ut = (g4.solve_batched(g4.load(True).repeat(8, 1).contiguous(), tol=tol)[0]
+                  + 1e-2 * torch.as_tensor(target_perturbations(g4.n_u, 8), device="cuda"))
+            nu = torch.tensor(1.0, dtype=torch.float64, device="cuda", requires_grad=True)
+            Fv = F4.clone().requires_grad_(True)
+            sync()
+            t = time.perf_counter()
+            U4, P4 = stokes_solve(Fv, nu, g4, tol)
+            sync()
+            tf = time.perf_counter() - t
+            loss = 0.5 * ((U4 - ut) ** 2).sum()
+            t = time.perf_counter()
+            loss.backward()
+            sync()
+            tb4 = time.perf_counter() - t
+            extra["c4_adjoint_8rhs"] = {"forward_s": round(tf, 5), "backward_s": round(tb4, 5),
+                                        "ratio_fwd_plus_bwd_over_2fwd": round((tf + tb4) / (2 * tf), 3),
+                                        "dloss_dnu": float(nu.grad)}
+            log("c4", extra["c4_adjoint_8rhs"])
+            del g4
+        except Exception as e:
+            extra["c4_adjoint_8rhs"] = {"error": str(e)}
+        out["variants"] = extra
+
+    if not args.no_cpu:
+        log("cpu baseline (oracle, 1 core)")
+        out["cpu_baseline"] = cpu_baseline(N, kp, dim, iters, args.cpu_iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

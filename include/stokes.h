@@ -166,9 +166,14 @@ int stokes_export_pressure_mass(stokes_problem* pb, double* diagQ, double* w);
 /* Number of dependency levels of the forward / backward triangular solves (host). */
 int stokes_levels(const stokes_problem* pb, int* fwd_levels, int* bwd_levels);
 
-/* Mean device time (ms) of the last solve's kernels by category, for profiling:
- * out[0] SpMV, out[1] triangular solves, out[2] vector updates; may be unsupported
- * (returns STOKES_EINVAL) when timing is off. */
+/* Live kernel timing with HIP events recorded on the problem's stream around each timed
+ * launch of the MINRES loop.  enable = 1 resets the totals and starts timing, 0 stops it,
+ * any other value only reads.  ms[5] / counts[5] (HOST, may be NULL) receive the summed
+ * device time and the number of launches per category: [0] saddle SpMV, [1] forward
+ * triangular solve, [2] backward triangular solve, [3] Lanczos update, [4] Givens and
+ * w/x update.  Synchronises the stream. */
+int stokes_profile(stokes_problem* pb, int enable, double* ms, int64_t* counts);
+
 const char* stokes_last_error(const stokes_problem* pb);
 void stokes_destroy(stokes_problem* pb);
 

@@ -24,7 +24,7 @@ EXPORTS = (
     "stokes_set_maxit", "stokes_load", "stokes_solve", "stokes_solve_batched", "stokes_solve_precision",
     "stokes_solve_adjoint", "stokes_solve_adjoint_batched", "stokes_dnu_dot", "stokes_apply",
     "stokes_apply_precond", "stokes_export_csr", "stokes_export_pressure_mass", "stokes_levels",
-    "stokes_last_error", "stokes_destroy",
+    "stokes_profile", "stokes_last_error", "stokes_destroy",
 )
 
 
@@ -76,6 +76,7 @@ def lib():
         "stokes_export_csr": (i32, [vp, i32, P(i64), vp, vp, vp]),
         "stokes_export_pressure_mass": (i32, [vp, vp, vp]),
         "stokes_levels": (i32, [vp, P(i32), P(i32)]),
+        "stokes_profile": (i32, [vp, i32, vp, vp]),
         "stokes_last_error": (ctypes.c_char_p, [vp]),
         "stokes_destroy": (None, [vp]),
     }

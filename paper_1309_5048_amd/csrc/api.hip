@@ -186,7 +186,20 @@ struct stokes_problem {
   size_t lds_per_cu = 65536;
   int num_cu = 0;
   std::vector<int32_t> lev_fwd, lev_bwd;  // dependency levels of the two solves
-  ~stokes_problem() { mem.release(); }
+  // live kernel timing (HIP events on the problem's stream), enabled by stokes_profile
+  bool prof_on = false;
+  std::vector<TrsvTiming> prof_pool;
+  std::vector<int> prof_cat;
+  size_t prof_used = 0;
+  double prof_ms[5] = {0, 0, 0, 0, 0};
+  int64_t prof_cnt[5] = {0, 0, 0, 0, 0};
+  ~stokes_problem() {
+    for (auto& t : prof_pool) {
+      (void)hipEventDestroy(t.before);
+      (void)hipEventDestroy(t.after);
+    }
+    mem.release();
+  }
 };
 
 namespace {
@@ -209,15 +222,75 @@ int fail_hip(stokes_problem* pb, hipError_t e, const char* what, int line) {
     if (_e != hipSuccess) return fail_hip(pb, _e, #__VA_ARGS__, __LINE__); \
   } while (0)
 
+// Event pair for one timed launch of category cat (0 saddle SpMV, 1 forward solve,
+// 2 backward solve, 3 Lanczos update, 4 Givens/w/x update); null when profiling is off.
+const TrsvTiming* prof_take(stokes_problem* pb, int cat) {
+  if (!pb->prof_on) return nullptr;
+  if (pb->prof_used == pb->prof_pool.size()) {
+    TrsvTiming t;
+    if (hipEventCreate(&t.before) != hipSuccess || hipEventCreate(&t.after) != hipSuccess) return nullptr;
+    pb->prof_pool.push_back(t);
+    pb->prof_cat.push_back(0);
+  }
+  pb->prof_cat[pb->prof_used] = cat;
+  return &pb->prof_pool[pb->prof_used++];
+}
+
+// Accumulate the elapsed times of the recorded pairs (call after a stream sync).
+void prof_flush(stokes_problem* pb) {
+  for (size_t k = 0; k < pb->prof_used; ++k) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, pb->prof_pool[k].before, pb->prof_pool[k].after) == hipSuccess) {
+      pb->prof_ms[pb->prof_cat[k]] += ms;
+      pb->prof_cnt[pb->prof_cat[k]] += 1;
+    }
+  }
+  pb->prof_used = 0;
+}
+
+#define PROF_BEGIN(cat)                                   \
+  const TrsvTiming* _pt = prof_take(pb, cat);             \
+  if (_pt) (void)hipEventRecord(_pt->before, pb->stream);
+#define PROF_END() \
+  if (_pt) (void)hipEventRecord(_pt->after, pb->stream);
+
 int upload_schedule(stokes_problem* pb, const TrsvSchedHost& H, TrsvSchedDev& D, int rmax) {
   hipStream_t st = pb->stream;
   DevAlloc& m = pb->mem;
+  if (H.nslots >= 65536) return fail(pb, STOKES_EINVAL, "triangular-solve schedule needs more than 65535 LDS slots");
   D.ngroups = H.ngroups;
   D.nsteps = H.nsteps;
   D.E = H.E;
+  D.EP = (H.E + 3) / 4 * 4;
+  D.ES = (D.EP + 7) / 8 * 8;
   D.nlevels = H.nlevels;
   D.nslots = H.nslots;
   D.nrows = int(pb->S.n_u);
+  const size_t ns = size_t(H.nsteps);
+  // packed per-lane records: values (via a permutation into L) and 16-bit slot ids
+  std::vector<int64_t> vperm(ns * 64 * D.EP, -1);
+  std::vector<uint16_t> ssrc(ns * 64 * D.ES, 0);
+  for (size_t s = 0; s < ns; ++s)
+    for (int e = 0; e < H.E; ++e)
+      for (int l = 0; l < 64; ++l) {
+        const size_t from = (s * H.E + e) * 64 + l;
+        vperm[(s * 64 + l) * D.EP + e] = H.ent_perm[from];
+        ssrc[(s * 64 + l) * D.ES + e] = uint16_t(H.ent_src[from]);
+      }
+  std::vector<TrsvRow64> ri(ns * kTrsvRPS);
+  std::vector<TrsvRow32> ri32(ns * kTrsvRPS);
+  for (size_t k = 0; k < ns * kTrsvRPS; ++k) {
+    const int32_t need = H.step_halo_need[k / kTrsvRPS];
+    ri[k].dinv = 0.0;
+    ri[k].slot = H.sslot[k];
+    ri[k].need = need;
+    ri32[k].dinv = 0.0f;
+    ri32[k].slot = H.sslot[k];
+    ri32[k].need = need;
+    ri32[k].pad = 0;
+  }
+  std::vector<TrsvStep> sst(ns);
+  for (size_t s = 0; s < ns; ++s) sst[s] = TrsvStep{H.step_level[s], H.step_publish[s], H.step_halo_need[s], 0};
   D.grp_step_ptr = m.upload(H.grp_step_ptr, st);
   D.grp_halo_ptr = m.upload(H.grp_halo_ptr, st);
   D.halo_row = m.upload(H.halo_row, st);
@@ -225,18 +298,15 @@ int upload_schedule(stokes_problem* pb, const TrsvSchedHost& H, TrsvSchedDev& D,
   D.halo_lvl = m.upload(H.halo_lvl, st);
   D.halo_slot = m.upload(H.halo_slot, st);
   D.halo_free = m.upload(H.halo_free, st);
-  D.step_level = m.upload(H.step_level, st);
-  D.step_halo_need = m.upload(H.step_halo_need, st);
-  D.step_publish = m.upload(H.step_publish, st);
   D.srow = m.upload(H.srow, st);
-  D.sslot = m.upload(H.sslot, st);
-  D.ent_src = m.upload(H.ent_src, st);
-  D.sdiag_src = m.upload(H.sdiag_src, st);
-  D.ent_perm = m.upload(H.ent_perm, st);
-  D.ent_val = m.get<double>(H.ent_perm.size());
-  D.ent_val32 = m.get<float>(H.ent_perm.size());
-  D.sdinv = m.get<double>(H.sdiag_src.size());
-  D.sdinv32 = m.get<float>(H.sdiag_src.size());
+  D.ssrc = m.upload(ssrc, st);
+  D.vperm = m.upload(vperm, st);
+  D.dsrc = m.upload(H.sdiag_src, st);
+  D.sstep = m.upload(sst, st);
+  D.srinfo = m.upload(ri, st);
+  D.srinfo32 = m.upload(ri32, st);
+  D.sval = m.get<double>(vperm.size());
+  D.sval32 = m.get<float>(vperm.size());
   D.rhs_s = m.get<double>(H.srow.size() * std::max(1, rmax));
   D.progress = m.get<unsigned long long>(H.ngroups);
   D.epoch = m.get<unsigned long long>(1);
@@ -250,6 +320,8 @@ int upload_schedule(stokes_problem* pb, const TrsvSchedHost& H, TrsvSchedDev& D,
   CK(hipMemsetAsync(D.done_count, 0, sizeof(unsigned int), st));
   CK(hipMemsetAsync(D.err, 0, sizeof(int), st));
   CK(launch_trsv_gather(D, pb->Lval, st));
+  // host vectors must outlive the asynchronous copies
+  CK(hipStreamSynchronize(st));
   return 0;
 }
 
@@ -409,8 +481,8 @@ int precond_velocity(stokes_problem* pb, int precond, Work& W, SchedPair* sp, co
   hipStream_t st = pb->stream;
   const int64_t n_u = pb->S.n_u;
   if (precond == STOKES_PC_IC0) {
-    CK(launch_trsv(sp->fwd, fp32, R, vin, W.y, nullptr, nullptr, skip, st));
-    CK(launch_trsv(sp->bwd, fp32, R, W.y, zout, vin, dot_out, skip, st));
+    CK(launch_trsv(sp->fwd, fp32, R, vin, W.y, nullptr, nullptr, skip, st, prof_take(pb, 1)));
+    CK(launch_trsv(sp->bwd, fp32, R, W.y, zout, vin, dot_out, skip, st, prof_take(pb, 2)));
     return 0;
   }
   if (precond == STOKES_PC_ICPCG) {
@@ -425,14 +497,16 @@ int precond_velocity(stokes_problem* pb, int precond, Work& W, SchedPair* sp, co
       for (int k = 0; k < 4; ++k) {
         CK(pcg_spmv<T>(R, n_u, pb->rowptr, pb->aend, pb->col, val, (const T*)W.pp, (T*)W.pq, s, st));
         CK(pcg_axpy<T>(R, n_u, (const T*)W.pp, (const T*)W.pq, zout, (T*)W.pr, s, ip, st));
-        CK(launch_trsv(sp->fwd, fp32, R, W.pr, W.y, nullptr, nullptr, s.alldone, st));
-        CK(launch_trsv(sp->bwd, fp32, R, W.y, W.pz, W.pr, s.rho + (1 - ip) * kRMax, s.alldone, st));
+        CK(launch_trsv(sp->fwd, fp32, R, W.pr, W.y, nullptr, nullptr, s.alldone, st, prof_take(pb, 1)));
+        CK(launch_trsv(sp->bwd, fp32, R, W.y, W.pz, W.pr, s.rho + (1 - ip) * kRMax, s.alldone, st,
+                       prof_take(pb, 2)));
         CK(pcg_pupdate<T>(R, n_u, (const T*)W.pz, (T*)W.pp, s, ip, st));
         ip = 1 - ip;
       }
       int done = 0;
       CK(hipMemcpyAsync(&done, s.alldone, sizeof(int), hipMemcpyDeviceToHost, st));
       CK(hipStreamSynchronize(st));
+      prof_flush(pb);
       if (done) break;
     }
     CK(dot<T, T>(R, 0, n_u, vin, zout, pb->partials, pb->counter, dot_out, st));
@@ -480,17 +554,30 @@ int minres_run(stokes_problem* pb, Work& W, int precond, double tol, int maxit, 
   for (;;) {
     for (int m = 0; m < pb->check_every; ++m, ++j) {
       const int p = (j - 1) & 1;
-      CK(mr_spmv<T>(R, n, pb->rowptr, pb->col, val, z[p], q, s, p, st));
-      CK(mr_lanczos<T>(R, n, n_u, q, v[p], v[1 - p], z[1 - p], pb->diagQ, diagA, two_nu, s, p, st));
+      {
+        PROF_BEGIN(0);
+        CK(mr_spmv<T>(R, n, pb->rowptr, pb->col, val, z[p], q, s, p, st));
+        PROF_END();
+      }
+      {
+        PROF_BEGIN(3);
+        CK(mr_lanczos<T>(R, n, n_u, q, v[p], v[1 - p], z[1 - p], pb->diagQ, diagA, two_nu, s, p, st));
+        PROF_END();
+      }
       rc = precond_velocity<T>(pb, precond, W, sp, v[1 - p], z[1 - p],
                                s.red + ((size_t)p * RED_KINDS + RED_G2U) * kRMax, s.alldone + p, s.st + p * kRMax,
                                nullptr);
       if (rc) return rc;
-      CK(mr_update<T>(R, n, z[p], w[p], w[1 - p], x, s, p, st));
+      {
+        PROF_BEGIN(4);
+        CK(mr_update<T>(R, n, z[p], w[p], w[1 - p], x, s, p, st));
+        PROF_END();
+      }
     }
     int done = 0;
     CK(hipMemcpyAsync(&done, s.alldone + ((j - 1) & 1), sizeof(int), hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
+    prof_flush(pb);
     if (done || j > maxit + pb->check_every + 1) break;
   }
   const int fp = (j - 1) & 1;
@@ -732,7 +819,7 @@ static int stokes_setup_impl(int n, int p, int dim, double nu, stokes_problem* p
   pb->Lval = m.get<double>(pb->nnzL);
   pb->flag = m.get<int>(4);
   pb->scratch = m.get<double>(128);
-  pb->partials = m.get<double>(2048 * 2 * kRMax + 64);
+  pb->partials = m.get<double>(size_t(kVecMaxBlocks) * 2 * kRMax + 64);
   pb->counter = m.get<unsigned int>(16);
   pb->mr.st = m.get<MinresState>(2 * kRMax);
   pb->mr.alldone = m.get<int>(2);
@@ -1066,6 +1153,26 @@ int stokes_levels(const stokes_problem* pb, int* fwd_levels, int* bwd_levels) {
   if (!pb || pb->scheds.empty()) return STOKES_EINVAL;
   if (fwd_levels) *fwd_levels = pb->scheds[0]->fwd.nlevels;
   if (bwd_levels) *bwd_levels = pb->scheds[0]->bwd.nlevels;
+  return 0;
+}
+
+int stokes_profile(stokes_problem* pb, int enable, double* ms, int64_t* counts) {
+  if (!pb) return STOKES_EINVAL;
+  CK(hipStreamSynchronize(pb->stream));
+  prof_flush(pb);
+  if (ms)
+    for (int k = 0; k < 5; ++k) ms[k] = pb->prof_ms[k];
+  if (counts)
+    for (int k = 0; k < 5; ++k) counts[k] = pb->prof_cnt[k];
+  if (enable == 1) {
+    for (int k = 0; k < 5; ++k) {
+      pb->prof_ms[k] = 0.0;
+      pb->prof_cnt[k] = 0;
+    }
+    pb->prof_on = true;
+  } else if (enable == 0) {
+    pb->prof_on = false;
+  }
   return 0;
 }
 

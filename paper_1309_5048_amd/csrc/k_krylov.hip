@@ -19,6 +19,124 @@
 namespace stk {
 
 // ---------------------------------------------------------------------------
+// Sparse row products.  A row is handled by kSG lanes (kVT / kSG rows per block pass);
+// each lane takes entries sub, sub + kSG, ... with U independent loads in flight, and the
+// group adds its lanes with DPP row operations (every lane of the group gets the sum).
+// Blocks take contiguous row ranges; when the grid is a multiple of 8 the ranges of the
+// blocks that one XCD runs (blocks are dispatched round robin over the 8 XCDs) are
+// adjacent, so the vector entries that an XCD gathers stay in its own L2.
+// ---------------------------------------------------------------------------
+constexpr int kSG = 16;
+constexpr int kSpmvMaxBlocks = 4096;
+static_assert(kSpmvMaxBlocks <= kVecMaxBlocks, "block partials are sized for kVecMaxBlocks");
+
+template <int R>
+constexpr int spmv_unroll() { return R == 1 ? 4 : (R <= 8 ? 2 : 1); }
+
+struct RowRange {
+  int64_t begin, end;
+};
+
+__device__ __forceinline__ RowRange block_rows(int64_t nrows, int rows_per_pass) {
+  const int nb = gridDim.x;
+  const int b = (nb % 8 == 0) ? (int)(blockIdx.x % 8) * (nb / 8) + (int)(blockIdx.x / 8) : (int)blockIdx.x;
+  const int64_t passes = (nrows + rows_per_pass - 1) / rows_per_pass;
+  const int64_t per = (passes + nb - 1) / nb;
+  RowRange r;
+  r.begin = std::min<int64_t>(nrows, (int64_t)b * per * rows_per_pass);
+  r.end = std::min<int64_t>(nrows, ((int64_t)b + 1) * per * rows_per_pass);
+  return r;
+}
+
+// Grid of the row kernels: at most kSpmvMaxBlocks blocks, a multiple of 8 when above 8.
+inline int spmv_blocks(int64_t nrows) {
+  const int64_t passes = std::max<int64_t>(1, (nrows + kVT / kSG - 1) / (kVT / kSG));
+  const int64_t per = (passes + kSpmvMaxBlocks - 1) / kSpmvMaxBlocks;
+  int64_t nb = (passes + per - 1) / per;
+  if (nb > 8) nb = (nb + 7) / 8 * 8;
+  return (int)std::min<int64_t>(nb, kSpmvMaxBlocks);
+}
+
+// R consecutive values (the R interleaved columns of one vector row) with wide loads.
+template <int R, typename T>
+__device__ __forceinline__ void load_cols(const T* __restrict__ p, T (&v)[R]) {
+  if constexpr (R % 2 == 0 && sizeof(T) == 8) {
+    const double2* q = reinterpret_cast<const double2*>(p);
+#pragma unroll
+    for (int c = 0; c < R / 2; ++c) {
+      const double2 t = q[c];
+      v[2 * c] = t.x;
+      v[2 * c + 1] = t.y;
+    }
+  } else if constexpr (R % 4 == 0 && sizeof(T) == 4) {
+    const float4* q = reinterpret_cast<const float4*>(p);
+#pragma unroll
+    for (int c = 0; c < R / 4; ++c) {
+      const float4 t = q[c];
+      v[4 * c] = t.x;
+      v[4 * c + 1] = t.y;
+      v[4 * c + 2] = t.z;
+      v[4 * c + 3] = t.w;
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < R; ++c) v[c] = p[c];
+  }
+}
+
+// acc[c] = sum over k in [kb, ke) of val[k] * x[col[k] * R + c], in every lane of the group.
+template <int R, typename Acc, typename T>
+__device__ __forceinline__ void row_dot(int32_t kb, int32_t ke, int sub, const int32_t* __restrict__ col,
+                                        const T* __restrict__ val, const T* __restrict__ x, Acc (&acc)[R]) {
+  constexpr int U = spmv_unroll<R>();
+#pragma unroll
+  for (int c = 0; c < R; ++c) acc[c] = Acc(0);
+  int32_t k = kb + sub;
+  for (; k + (U - 1) * kSG < ke; k += U * kSG) {
+    int32_t j[U];
+    T a[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      j[u] = col[k + u * kSG];
+      a[u] = val[k + u * kSG];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      T xv[R];
+      load_cols<R>(x + (size_t)j[u] * R, xv);
+#pragma unroll
+      for (int c = 0; c < R; ++c) acc[c] = fma((Acc)a[u], (Acc)xv[c], acc[c]);
+    }
+  }
+  for (; k < ke; k += kSG) {
+    T xv[R];
+    load_cols<R>(x + (size_t)col[k] * R, xv);
+    const Acc a = (Acc)val[k];
+#pragma unroll
+    for (int c = 0; c < R; ++c) acc[c] = fma(a, (Acc)xv[c], acc[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < R; ++c) acc[c] = group_sum<kSG>(acc[c]);
+}
+
+// Store R consecutive values with wide stores.
+template <int R, typename T>
+__device__ __forceinline__ void store_cols(T* __restrict__ p, const T (&v)[R]) {
+  if constexpr (R % 2 == 0 && sizeof(T) == 8) {
+    double2* q = reinterpret_cast<double2*>(p);
+#pragma unroll
+    for (int c = 0; c < R / 2; ++c) q[c] = double2{v[2 * c], v[2 * c + 1]};
+  } else if constexpr (R % 4 == 0 && sizeof(T) == 4) {
+    float4* q = reinterpret_cast<float4*>(p);
+#pragma unroll
+    for (int c = 0; c < R / 4; ++c) q[c] = float4{v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]};
+  } else {
+#pragma unroll
+    for (int c = 0; c < R; ++c) p[c] = v[c];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // MINRES initialisation: v_1 = b, v_0 = w_0 = w_1 = x = 0, z~_1 pressure (and Jacobi
 // velocity) part; gamma^2 partial sums of the pressure / velocity parts.
 // ---------------------------------------------------------------------------
@@ -96,7 +214,7 @@ __global__ void k_mr_init_state(MrScalars s, double tol, int maxit) {
 }
 
 // ---------------------------------------------------------------------------
-// q = Acal z~_j / gamma_j and delta partials (one wavefront per row, lanes over entries).
+// q = Acal z~_j / gamma_j and delta partials.
 // ---------------------------------------------------------------------------
 template <typename T, int R>
 __global__ __launch_bounds__(kVT) void k_mr_spmv(int64_t n, const int32_t* __restrict__ rowptr,
@@ -112,41 +230,23 @@ __global__ __launch_bounds__(kVT) void k_mr_spmv(int64_t n, const int32_t* __res
   double acc_d[R];
 #pragma unroll
   for (int c = 0; c < R; ++c) acc_d[c] = 0.0;
-  const int lane = threadIdx.x & 63;
-  const int64_t wave = (int64_t)blockIdx.x * (kVT / 64) + (threadIdx.x >> 6);
-  const int64_t nwaves = (int64_t)gridDim.x * (kVT / 64);
-  for (int64_t i = wave; i < n; i += nwaves) {
+  const int sub = threadIdx.x & (kSG - 1);
+  const RowRange rr = block_rows(n, kVT / kSG);
+  for (int64_t base = rr.begin; base < rr.end; base += kVT / kSG) {
+    const int64_t i = base + threadIdx.x / kSG;
+    const bool valid = i < rr.end;
+    const int32_t kb = valid ? rowptr[i] : 0, ke = valid ? rowptr[i + 1] : 0;
     T acc[R];
+    row_dot<R>(kb, ke, sub, col, val, z, acc);
+    if (valid && sub == 0) {  // lane 0 of the group finishes the R columns of row i
+      T qv[R], zv[R];
+      load_cols<R>(z + (size_t)i * R, zv);
 #pragma unroll
-    for (int c = 0; c < R; ++c) acc[c] = T(0);
-    for (int32_t k = rowptr[i] + lane; k < rowptr[i + 1]; k += 64) {
-      const T a = val[k];
-      const T* zp = z + (size_t)col[k] * R;
-#pragma unroll
-      for (int c = 0; c < R; ++c) acc[c] = fma(a, zp[c], acc[c]);
-    }
-#pragma unroll
-    for (int c = 0; c < R; ++c) {
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) acc[c] += __shfl_xor(acc[c], off, 64);
-    }
-    if (lane < R) {
-      // lane c finalises column c
-      T mine = acc[0];
-#pragma unroll
-      for (int c = 1; c < R; ++c)
-        if (lane == c) mine = acc[c];
-      double igc = ig[0];
-#pragma unroll
-      for (int c = 1; c < R; ++c)
-        if (lane == c) igc = ig[c];
-      const T qv = T((double)mine * igc);
-      q[(size_t)i * R + lane] = qv;
-      const double zv = (double)z[(size_t)i * R + lane];
-      double d = (double)qv * zv * igc;
-#pragma unroll
-      for (int c = 0; c < R; ++c)
-        if (lane == c) acc_d[c] += d;
+      for (int c = 0; c < R; ++c) {
+        qv[c] = T((double)acc[c] * ig[c]);
+        acc_d[c] += (double)qv[c] * (double)zv[c] * ig[c];
+      }
+      store_cols<R>(q + (size_t)i * R, qv);
     }
   }
   reduce_last<R>(acc_d, s.partials, s.counter, [&](int k, double v) { red_at(s, p, RED_DELTA)[k] = v; });
@@ -312,40 +412,31 @@ __global__ __launch_bounds__(kVT) void k_spmv_resid(int64_t nrows, const int32_t
   double acc_d[2 * R];
 #pragma unroll
   for (int c = 0; c < 2 * R; ++c) acc_d[c] = 0.0;
-  const int lane = threadIdx.x & 63;
-  const int64_t wave = (int64_t)blockIdx.x * (kVT / 64) + (threadIdx.x >> 6);
-  const int64_t nwaves = (int64_t)gridDim.x * (kVT / 64);
-  for (int64_t i = wave; i < nrows; i += nwaves) {
+  const int sub = threadIdx.x & (kSG - 1);
+  const RowRange rr = block_rows(nrows, kVT / kSG);
+  for (int64_t base = rr.begin; base < rr.end; base += kVT / kSG) {
+    const int64_t i = base + threadIdx.x / kSG;
+    const bool valid = i < rr.end;
+    const int32_t kb = valid ? rowptr[i] : 0;
+    const int32_t ke = valid ? (rowend ? rowend[i] : rowptr[i + 1]) : 0;
     double acc[R];
+    row_dot<R>(kb, ke, sub, col, val, xin, acc);
+    if (valid && sub == 0) {
+      T bv[R], yv[R];
+      if (bvec) {
+        load_cols<R>(bvec + (size_t)i * R, bv);
+      } else {
 #pragma unroll
-    for (int c = 0; c < R; ++c) acc[c] = 0.0;
-    const int32_t kend = rowend ? rowend[i] : rowptr[i + 1];
-    for (int32_t k = rowptr[i] + lane; k < kend; k += 64) {
-      const double a = (double)val[k];
-      const T* xp = xin + (size_t)col[k] * R;
+        for (int c = 0; c < R; ++c) bv[c] = T(0);
+      }
 #pragma unroll
-      for (int c = 0; c < R; ++c) acc[c] = fma(a, (double)xp[c], acc[c]);
-    }
-#pragma unroll
-    for (int c = 0; c < R; ++c) {
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) acc[c] += __shfl_xor(acc[c], off, 64);
-    }
-    if (lane < R) {
-      double mine = acc[0];
-#pragma unroll
-      for (int c = 1; c < R; ++c)
-        if (lane == c) mine = acc[c];
-      const size_t k = (size_t)i * R + lane;
-      double bv = bvec ? (double)bvec[k] : 0.0;
-      double yv = bvec ? bv - mine : mine;
-      y[k] = T(yv);
-#pragma unroll
-      for (int c = 0; c < R; ++c)
-        if (lane == c) {
-          acc_d[c] += yv * yv;
-          acc_d[R + c] += bv * bv;
-        }
+      for (int c = 0; c < R; ++c) {
+        const double y64 = bvec ? (double)bv[c] - acc[c] : acc[c];
+        yv[c] = T(y64);
+        acc_d[c] += y64 * y64;
+        acc_d[R + c] += (double)bv[c] * (double)bv[c];
+      }
+      store_cols<R>(y + (size_t)i * R, yv);
     }
   }
   if (out == nullptr) return;
@@ -472,35 +563,20 @@ __global__ __launch_bounds__(kVT) void k_pcg_spmv(int64_t n_u, const int32_t* __
   double acc_d[R];
 #pragma unroll
   for (int c = 0; c < R; ++c) acc_d[c] = 0.0;
-  const int lane = threadIdx.x & 63;
-  const int64_t wave = (int64_t)blockIdx.x * (kVT / 64) + (threadIdx.x >> 6);
-  const int64_t nwaves = (int64_t)gridDim.x * (kVT / 64);
-  for (int64_t i = wave; i < n_u; i += nwaves) {
+  const int sub = threadIdx.x & (kSG - 1);
+  const RowRange rr = block_rows(n_u, kVT / kSG);
+  for (int64_t base = rr.begin; base < rr.end; base += kVT / kSG) {
+    const int64_t i = base + threadIdx.x / kSG;
+    const bool valid = i < rr.end;
+    const int32_t kb = valid ? rowptr[i] : 0, ke = valid ? aend[i] : 0;
     T acc[R];
+    row_dot<R>(kb, ke, sub, col, val, pv, acc);
+    if (valid && sub == 0) {
+      T pw[R];
+      load_cols<R>(pv + (size_t)i * R, pw);
 #pragma unroll
-    for (int c = 0; c < R; ++c) acc[c] = T(0);
-    for (int32_t k = rowptr[i] + lane; k < aend[i]; k += 64) {
-      const T a = val[k];
-      const T* pp = pv + (size_t)col[k] * R;
-#pragma unroll
-      for (int c = 0; c < R; ++c) acc[c] = fma(a, pp[c], acc[c]);
-    }
-#pragma unroll
-    for (int c = 0; c < R; ++c) {
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) acc[c] += __shfl_xor(acc[c], off, 64);
-    }
-    if (lane < R) {
-      T mine = acc[0];
-#pragma unroll
-      for (int c = 1; c < R; ++c)
-        if (lane == c) mine = acc[c];
-      const size_t k = (size_t)i * R + lane;
-      q[k] = mine;
-      const double d = (double)mine * (double)pv[k];
-#pragma unroll
-      for (int c = 0; c < R; ++c)
-        if (lane == c) acc_d[c] += d;
+      for (int c = 0; c < R; ++c) acc_d[c] += (double)acc[c] * (double)pw[c];
+      store_cols<R>(q + (size_t)i * R, acc);
     }
   }
   reduce_last<R>(acc_d, s.partials, s.counter, [&](int k, double v) { s.pq[k] = v; });
@@ -600,7 +676,7 @@ hipError_t mr_init_state(int R, const MrScalars& s, double tol, int maxit, hipSt
 template <typename T>
 hipError_t mr_spmv(int R, int64_t n, const int32_t* rowptr, const int32_t* col, const T* val, const T* z, T* q,
                    const MrScalars& s, int p, hipStream_t st) {
-  const int nb = int(std::min<int64_t>(2048, std::max<int64_t>(1, (n + 3) / 4)));
+  const int nb = spmv_blocks(n);
   STK_R_SWITCH(R, hipLaunchKernelGGL((k_mr_spmv<T, RR>), dim3(nb), dim3(kVT), 0, st, n, rowptr, col, val, z, q, s, p));
   return hipGetLastError();
 }
@@ -625,7 +701,7 @@ template <typename T>
 hipError_t spmv_resid(int R, int64_t nrows, const int32_t* rowptr, const int32_t* rowend, const int32_t* col,
                       const T* val, const T* x, const T* b, T* y, double* partials, unsigned int* counter, double* out,
                       hipStream_t st) {
-  const int nb = int(std::min<int64_t>(2048, std::max<int64_t>(1, (nrows + 3) / 4)));
+  const int nb = spmv_blocks(nrows);
   STK_R_SWITCH(R, hipLaunchKernelGGL((k_spmv_resid<T, RR>), dim3(nb), dim3(kVT), 0, st, nrows, rowptr, rowend, col, val,
                                      x, b, y, partials, counter, out));
   return hipGetLastError();
@@ -695,7 +771,7 @@ hipError_t pcg_init2(int R, int64_t n_u, const T* z, T* pv, const PcgScalars& s,
 template <typename T>
 hipError_t pcg_spmv(int R, int64_t n_u, const int32_t* rowptr, const int32_t* aend, const int32_t* col, const T* val,
                     const T* pv, T* q, const PcgScalars& s, hipStream_t st) {
-  const int nb = int(std::min<int64_t>(2048, std::max<int64_t>(1, (n_u + 3) / 4)));
+  const int nb = spmv_blocks(n_u);
   STK_R_SWITCH(R, hipLaunchKernelGGL((k_pcg_spmv<T, RR>), dim3(nb), dim3(kVT), 0, st, n_u, rowptr, aend, col, val, pv, q,
                                      s));
   return hipGetLastError();

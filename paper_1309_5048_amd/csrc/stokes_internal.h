@@ -58,7 +58,6 @@ void build_lower_pattern(const Spaces& S, const SaddlePattern& P, LowerPattern& 
 constexpr int kTrsvG = 8;                  // lanes per row
 constexpr int kTrsvRPS = 64 / kTrsvG;      // rows per step (one compute wave)
 constexpr int kTrsvThreads = 192;          // compute wave + halo wave + writer wave
-constexpr int kTrsvRing = 16;              // output ring (steps) between compute and writer
 constexpr int kTrsvHaloLookahead = 16;     // steps before first use a halo slot is allocated
 constexpr int kLevelStride = 1 << 21;      // progress value = epoch * stride + level + 1
 
@@ -82,18 +81,42 @@ struct TrsvSchedHost {
   std::vector<int64_t> ent_perm;           // [nsteps*E*64] index in L values or -1 (pad)
 };
 
+// Device layout of a schedule.  Per step the compute wave reads, per lane, EP factor
+// values (EP = E rounded up to 4), ES 16-bit LDS slot ids (ES = E rounded up to 8) and
+// one 16-byte row record, all with vector loads.  The writer wave reads the global rows
+// (srow) and the step records.
+struct TrsvRow64 {
+  double dinv;   // reciprocal diagonal
+  int32_t slot;  // LDS slot of the result (0: not kept)
+  int32_t need;  // halo entries (prefix) staged before the step (same for the step's rows)
+};
+struct TrsvRow32 {
+  float dinv;
+  int32_t slot;
+  int32_t need;
+  int32_t pad;
+};
+struct TrsvStep {
+  int32_t level;    // dependency level of the step
+  int32_t publish;  // 1: publish progress after this step
+  int32_t need;     // halo entries (prefix) that must be staged
+  int32_t pad;
+};
+
 struct TrsvSchedDev {
-  int ngroups = 0, nsteps = 0, E = 0, nlevels = 0, nslots = 0, nrows = 0;
+  int ngroups = 0, nsteps = 0, E = 0, EP = 0, ES = 0, nlevels = 0, nslots = 0, nrows = 0;
   int32_t *grp_step_ptr = nullptr, *grp_halo_ptr = nullptr;
   int32_t *halo_row = nullptr, *halo_grp = nullptr, *halo_lvl = nullptr, *halo_slot = nullptr, *halo_free = nullptr;
-  int32_t *step_level = nullptr, *step_halo_need = nullptr, *step_publish = nullptr;
-  int32_t *srow = nullptr, *sslot = nullptr, *ent_src = nullptr;
-  int64_t *sdiag_src = nullptr, *ent_perm = nullptr;
-  double* ent_val = nullptr;   // factor values in schedule order
-  float* ent_val32 = nullptr;
-  double* sdinv = nullptr;     // reciprocal diagonals in schedule order
-  float* sdinv32 = nullptr;
-  void* rhs_s = nullptr;       // right-hand side gathered into schedule order (R_max doubles)
+  int32_t* srow = nullptr;         // [nsteps*RPS] global row or -1 (rhs gather, writer)
+  uint16_t* ssrc = nullptr;        // [nsteps][64][ES]
+  int64_t* vperm = nullptr;        // [nsteps][64][EP] index in L values or -1
+  int64_t* dsrc = nullptr;         // [nsteps*RPS] index of the diagonal or -1
+  TrsvStep* sstep = nullptr;       // [nsteps]
+  double* sval = nullptr;          // [nsteps][64][EP] factor values in schedule order
+  float* sval32 = nullptr;
+  TrsvRow64* srinfo = nullptr;     // [nsteps*RPS]
+  TrsvRow32* srinfo32 = nullptr;
+  void* rhs_s = nullptr;           // right-hand side gathered into schedule order (R_max doubles)
   unsigned long long* progress = nullptr;  // [ngroups]
   unsigned long long* epoch = nullptr;     // [1]
   unsigned int* done_count = nullptr;      // [1]
@@ -144,7 +167,7 @@ struct MrScalars {
   MinresState* st;   // [2][kRMax]
   int* alldone;      // [2]
   double* red;       // [2][RED_KINDS][kRMax]
-  double* partials;  // [maxblocks * 2 * kRMax]
+  double* partials;  // [kVecMaxBlocks * 2 * kRMax]
   unsigned int* counter;
 };
 
@@ -152,8 +175,9 @@ __device__ __forceinline__ double* red_at(const MrScalars& s, int p, int kind) {
   return s.red + ((size_t)p * RED_KINDS + kind) * kRMax;
 }
 
-// Block reduction of NV values per thread; the last block adds all partials in block
-// order and calls fin(k, value) for k < NV.  Returns nothing; thread 0 handles `fin`.
+// Block reduction of NV values per thread; the last block to finish (atomic ticket) adds
+// all block partials in a fixed order (thread t takes blocks t, t + kVT, ...; then a fixed
+// tree) and calls fin(k, value) for k < NV on threads k < NV.
 template <int NV, typename Fin>
 __device__ void reduce_last(double (&v)[NV], double* partials, unsigned int* counter, Fin fin) {
   __shared__ double sred[kVT / 64][NV];
@@ -180,20 +204,65 @@ __device__ void reduce_last(double (&v)[NV], double* partials, unsigned int* cou
     is_last = (prev == gridDim.x - 1);
   }
   __syncthreads();
-  if (is_last) {
-    __threadfence();
-    if (tid < NV) {
-      double x = 0.0;
-      for (unsigned int b = 0; b < gridDim.x; ++b) x += __hip_atomic_load(partials + (size_t)b * NV + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      fin(tid, x);
-    }
-    if (tid == 0) *counter = 0;
+  if (!is_last) return;
+  __threadfence();
+  double acc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+  for (unsigned int b = tid; b < gridDim.x; b += kVT)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] += partials[(size_t)b * NV + k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double x = acc[k];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (lane == 0) sred[wid][k] = x;
   }
+  __syncthreads();
+  if (tid < NV) {
+    double x = 0.0;
+#pragma unroll
+    for (int w = 0; w < kVT / 64; ++w) x += sred[w][tid];
+    fin(tid, x);
+  }
+  if (tid == 0) *counter = 0;
 }
 
+// Sum over aligned groups of SG lanes (SG = 8 or 16) with DPP row operations, on the
+// 32-bit halves of a double: xor 1 and xor 2 inside quads, mirror inside half rows, then
+// (SG = 16) mirror inside rows.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov64(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((long long)(unsigned)lo) | ((long long)hi << 32));
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov32(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov_any(double v) { return dpp_mov64<CTRL>(v); }
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov_any(float v) { return dpp_mov32<CTRL>(v); }
+
+template <int SG, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+  v += dpp_mov_any<0xB1>(v);
+  v += dpp_mov_any<0x4E>(v);
+  v += dpp_mov_any<0x141>(v);
+  if (SG == 16) v += dpp_mov_any<0x140>(v);
+  return v;
+}
+
+// Grid of the elementwise kernels: one item per thread up to kVecMaxBlocks blocks.
+constexpr int kVecMaxBlocks = 4096;
 inline int vec_blocks(int64_t nitems) {
-  int64_t b = (nitems + 4 * kVT - 1) / (4 * kVT);
-  return int(std::max<int64_t>(1, std::min<int64_t>(b, 1024)));
+  int64_t b = (nitems + kVT - 1) / kVT;
+  return int(std::max<int64_t>(1, std::min<int64_t>(b, kVecMaxBlocks)));
 }
 
 struct PcgScalars {
@@ -217,8 +286,12 @@ hipError_t assemble_load(const Spaces& S, double nu, int manufactured, int nmode
 hipError_t ic0_factor(int64_t n, int64_t nnzL, const int64_t* src, const int32_t* rowptr, const int32_t* col,
                       const double* Aval, double alpha, double* Lval, const int32_t* level_rows,
                       const std::vector<int32_t>& level_ptr, int* flag, hipStream_t st);
+// Optional events recorded on the stream right before/after the solve kernel itself.
+struct TrsvTiming {
+  hipEvent_t before = nullptr, after = nullptr;
+};
 hipError_t launch_trsv(const TrsvSchedDev& S, bool fp32, int R, const void* rhs, void* out, const void* dotv,
-                       double* dot_out, const int* skip, hipStream_t st);
+                       double* dot_out, const int* skip, hipStream_t st, const TrsvTiming* tm = nullptr);
 hipError_t launch_trsv_gather(const TrsvSchedDev& S, const double* Lval, hipStream_t st);
 size_t trsv_shmem_bytes(int nslots, bool fp32, int R);
 

@@ -86,6 +86,15 @@ class StokesProblem:
     def set_maxit(self, outer=0, inner=0):
         self._L.stokes_set_maxit(self._h, int(outer), int(inner))
 
+    def profile(self, enable=-1):
+        """Per-category kernel time (ms) and launch counts recorded with HIP events:
+        spmv, trsv_fwd, trsv_bwd, lanczos, update.  enable: 1 start/reset, 0 stop, -1 read."""
+        ms = (ctypes.c_double * 5)()
+        cnt = (ctypes.c_int64 * 5)()
+        self._check(self._L.stokes_profile(self._h, int(enable), ms, cnt), allow_nc=False)
+        names = ("spmv", "trsv_fwd", "trsv_bwd", "lanczos", "update")
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(names)}
+
     def levels(self):
         a, b = ctypes.c_int(), ctypes.c_int()
         self._check(self._L.stokes_levels(self._h, ctypes.byref(a), ctypes.byref(b)), allow_nc=False)
