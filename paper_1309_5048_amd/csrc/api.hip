@@ -257,35 +257,35 @@ void prof_flush(stokes_problem* pb) {
 int upload_schedule(stokes_problem* pb, const TrsvSchedHost& H, TrsvSchedDev& D, int rmax) {
   hipStream_t st = pb->stream;
   DevAlloc& m = pb->mem;
-  if (H.nslots >= 65536) return fail(pb, STOKES_EINVAL, "triangular-solve schedule needs more than 65535 LDS slots");
   D.ngroups = H.ngroups;
   D.nsteps = H.nsteps;
   D.E = H.E;
   D.EP = (H.E + 3) / 4 * 4;
-  D.ES = (D.EP + 7) / 8 * 8;
   D.nlevels = H.nlevels;
   D.nslots = H.nslots;
   D.nrows = int(pb->S.n_u);
   const size_t ns = size_t(H.nsteps);
-  // packed per-lane records: values (via a permutation into L) and 16-bit slot ids
+  // per-lane records: values (via a permutation into L) and 32-bit slot ids
   std::vector<int64_t> vperm(ns * 64 * D.EP, -1);
-  std::vector<uint16_t> ssrc(ns * 64 * D.ES, 0);
+  std::vector<uint32_t> ssrc(ns * 64 * D.EP, 0);
   for (size_t s = 0; s < ns; ++s)
     for (int e = 0; e < H.E; ++e)
       for (int l = 0; l < 64; ++l) {
         const size_t from = (s * H.E + e) * 64 + l;
         vperm[(s * 64 + l) * D.EP + e] = H.ent_perm[from];
-        ssrc[(s * 64 + l) * D.ES + e] = uint16_t(H.ent_src[from]);
+        ssrc[(s * 64 + l) * D.EP + e] = uint32_t(H.ent_src[from]);
       }
   std::vector<TrsvRow64> ri(ns * kTrsvRPS);
   std::vector<TrsvRow32> ri32(ns * kTrsvRPS);
   for (size_t k = 0; k < ns * kTrsvRPS; ++k) {
     const int32_t need = H.step_halo_need[k / kTrsvRPS];
+    // rows whose value no later step reads write to the dummy slot nslots
+    const int32_t slot = H.sslot[k] > 0 ? H.sslot[k] : H.nslots;
     ri[k].dinv = 0.0;
-    ri[k].slot = H.sslot[k];
+    ri[k].slot = slot;
     ri[k].need = need;
     ri32[k].dinv = 0.0f;
-    ri32[k].slot = H.sslot[k];
+    ri32[k].slot = slot;
     ri32[k].need = need;
     ri32[k].pad = 0;
   }
@@ -307,7 +307,8 @@ int upload_schedule(stokes_problem* pb, const TrsvSchedHost& H, TrsvSchedDev& D,
   D.srinfo32 = m.upload(ri32, st);
   D.sval = m.get<double>(vperm.size());
   D.sval32 = m.get<float>(vperm.size());
-  D.rhs_s = m.get<double>(H.srow.size() * std::max(1, rmax));
+  D.rhs_s = m.get<double>(H.srow.size() * 2 * std::max(1, rmax));
+  D.dummy = m.get<double>(64);
   D.progress = m.get<unsigned long long>(H.ngroups);
   D.epoch = m.get<unsigned long long>(1);
   D.done_count = m.get<unsigned int>(1);

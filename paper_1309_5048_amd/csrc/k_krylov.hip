@@ -371,7 +371,8 @@ __global__ __launch_bounds__(kVT) void k_mr_update(int64_t n, const T* __restric
     if (threadIdx.x < R) {
       const int c = threadIdx.x;
       MinresState st = s.st[p * kRMax + c];
-      const Givens g = G[c];
+      // same rotation as G[c] (recomputed: a register array cannot be indexed by thread)
+      const Givens g = givens_step(st, red_at(s, p, RED_DELTA)[c], red_at(s, p, RED_G2P)[c] + red_at(s, p, RED_G2U)[c]);
       if (g.live) {
         st.gamma_prev = st.gamma;
         st.gamma = g.gn;

@@ -57,7 +57,7 @@ void build_lower_pattern(const Spaces& S, const SaddlePattern& P, LowerPattern& 
 // ---------------------------------------------------------------------------
 constexpr int kTrsvG = 8;                  // lanes per row
 constexpr int kTrsvRPS = 64 / kTrsvG;      // rows per step (one compute wave)
-constexpr int kTrsvThreads = 192;          // compute wave + halo wave + writer wave
+constexpr int kTrsvThreads = 128;          // compute wavefront + halo wavefront
 constexpr int kTrsvHaloLookahead = 16;     // steps before first use a halo slot is allocated
 constexpr int kLevelStride = 1 << 21;      // progress value = epoch * stride + level + 1
 
@@ -82,12 +82,12 @@ struct TrsvSchedHost {
 };
 
 // Device layout of a schedule.  Per step the compute wave reads, per lane, EP factor
-// values (EP = E rounded up to 4), ES 16-bit LDS slot ids (ES = E rounded up to 8) and
-// one 16-byte row record, all with vector loads.  The writer wave reads the global rows
-// (srow) and the step records.
+// values (EP = E rounded up to 4), EP 32-bit LDS slot ids and one 16-byte row record,
+// all with vector loads, plus the global row (srow) and the per-solve right-hand side
+// and dot-vector entries in schedule order.
 struct TrsvRow64 {
   double dinv;   // reciprocal diagonal
-  int32_t slot;  // LDS slot of the result (0: not kept)
+  int32_t slot;  // LDS slot of the result (nslots, a dummy slot: not read later)
   int32_t need;  // halo entries (prefix) staged before the step (same for the step's rows)
 };
 struct TrsvRow32 {
@@ -104,11 +104,11 @@ struct TrsvStep {
 };
 
 struct TrsvSchedDev {
-  int ngroups = 0, nsteps = 0, E = 0, EP = 0, ES = 0, nlevels = 0, nslots = 0, nrows = 0;
+  int ngroups = 0, nsteps = 0, E = 0, EP = 0, nlevels = 0, nslots = 0, nrows = 0;
   int32_t *grp_step_ptr = nullptr, *grp_halo_ptr = nullptr;
   int32_t *halo_row = nullptr, *halo_grp = nullptr, *halo_lvl = nullptr, *halo_slot = nullptr, *halo_free = nullptr;
   int32_t* srow = nullptr;         // [nsteps*RPS] global row or -1 (rhs gather, writer)
-  uint16_t* ssrc = nullptr;        // [nsteps][64][ES]
+  uint32_t* ssrc = nullptr;        // [nsteps][64][EP] LDS slot ids
   int64_t* vperm = nullptr;        // [nsteps][64][EP] index in L values or -1
   int64_t* dsrc = nullptr;         // [nsteps*RPS] index of the diagonal or -1
   TrsvStep* sstep = nullptr;       // [nsteps]
@@ -116,7 +116,8 @@ struct TrsvSchedDev {
   float* sval32 = nullptr;
   TrsvRow64* srinfo = nullptr;     // [nsteps*RPS]
   TrsvRow32* srinfo32 = nullptr;
-  void* rhs_s = nullptr;           // right-hand side gathered into schedule order (R_max doubles)
+  void* rhs_s = nullptr;           // rhs and dot vector in schedule order ([row slot][2][R_max] doubles)
+  void* dummy = nullptr;           // target of the stores of padding rows (64 doubles)
   unsigned long long* progress = nullptr;  // [ngroups]
   unsigned long long* epoch = nullptr;     // [1]
   unsigned int* done_count = nullptr;      // [1]
@@ -175,11 +176,36 @@ __device__ __forceinline__ double* red_at(const MrScalars& s, int p, int kind) {
   return s.red + ((size_t)p * RED_KINDS + kind) * kRMax;
 }
 
-// Block reduction of NV values per thread; the last block to finish (atomic ticket) adds
-// all block partials in a fixed order (thread t takes blocks t, t + kVT, ...; then a fixed
-// tree) and calls fin(k, value) for k < NV on threads k < NV.
+// Device-scope (coherent across the XCDs' L2 caches) relaxed loads and stores of 64/32-bit
+// values, and a wait for this wave's outstanding vector memory operations (stores are
+// acknowledged once visible device-wide).  Used instead of agent-scope fences, which
+// write back or invalidate whole L2 caches.
+__device__ __forceinline__ void dev_store(double* p, double v) {
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), __builtin_bit_cast(unsigned long long, v),
+                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void dev_store(float* p, float v) {
+  __hip_atomic_store(reinterpret_cast<unsigned int*>(p), __builtin_bit_cast(unsigned int, v), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double dev_load(const double* p) {
+  return __builtin_bit_cast(double, __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p),
+                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ __forceinline__ float dev_load(const float* p) {
+  return __builtin_bit_cast(float, __hip_atomic_load(reinterpret_cast<const unsigned int*>(p), __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ __forceinline__ void wait_vm_stores() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Block reduction of NV values per thread; the last block to finish (ticket) adds all
+// block partials in a fixed order (thread t takes blocks t, t + kVT, ...; then a fixed
+// tree) and calls fin(k, value) for k < NV on threads k < NV.  Partials travel with
+// device-scope stores and loads; a block takes its ticket only after its partial stores
+// are acknowledged, so the last block sees every partial.
 template <int NV, typename Fin>
 __device__ void reduce_last(double (&v)[NV], double* partials, unsigned int* counter, Fin fin) {
+  static_assert(NV <= 64, "the partial stores and the ticket must come from one wavefront");
   __shared__ double sred[kVT / 64][NV];
   __shared__ int is_last;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -195,23 +221,21 @@ __device__ void reduce_last(double (&v)[NV], double* partials, unsigned int* cou
     double x = 0.0;
 #pragma unroll
     for (int w = 0; w < kVT / 64; ++w) x += sred[w][tid];
-    partials[(size_t)blockIdx.x * NV + tid] = x;
+    dev_store(partials + (size_t)blockIdx.x * NV + tid, x);
   }
-  __syncthreads();
   if (tid == 0) {
-    __threadfence();
-    const unsigned int prev = atomicAdd(counter, 1u);
+    wait_vm_stores();  // wavefront 0 holds all NV partial stores
+    const unsigned int prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     is_last = (prev == gridDim.x - 1);
   }
   __syncthreads();
   if (!is_last) return;
-  __threadfence();
   double acc[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) acc[k] = 0.0;
   for (unsigned int b = tid; b < gridDim.x; b += kVT)
 #pragma unroll
-    for (int k = 0; k < NV; ++k) acc[k] += partials[(size_t)b * NV + k];
+    for (int k = 0; k < NV; ++k) acc[k] += dev_load(partials + (size_t)b * NV + k);
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
@@ -227,7 +251,7 @@ __device__ void reduce_last(double (&v)[NV], double* partials, unsigned int* cou
     for (int w = 0; w < kVT / 64; ++w) x += sred[w][tid];
     fin(tid, x);
   }
-  if (tid == 0) *counter = 0;
+  if (tid == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Sum over aligned groups of SG lanes (SG = 8 or 16) with DPP row operations, on the
