@@ -209,6 +209,36 @@ class Oracle:
                          float(inner_tol), int(bool(fixed)), _p(info))
         return u, p, Info.from_array(info)
 
+    def solve_refined(self, f, tol=1e-8, maxit=10000, pc_A=PC_ICPCG, pc_Q=PQ_DIAG, inner_tol=1e-2, cycles=6):
+        """MINRES restarted on the true residual until ||b - Acal x||_{M^-1} <= tol ||b||_{M^-1}
+        with M the fixed block preconditioner blkdiag(IC(0), Diag(Q)/(2 nu)).  Used for the
+        inner-PCG velocity block, a nonlinear preconditioner whose MINRES estimate |eta|
+        measures the residual in a norm that changes between applications (Sec. 5: MINRES
+        minimises in the norm of a fixed SPD preconditioner).  Each cycle solves
+        Acal d = r to the remaining relative reduction (at most 0.5) and projects p."""
+        b0 = np.concatenate([_f64(f), np.zeros(self.n_p)])
+
+        def mnorm2(v):
+            z, _ = self.precond(v, pc_A=PC_IC0, pc_Q=pc_Q)
+            return float(v @ z)
+
+        bM = mnorm2(b0)
+        x = np.zeros(self.n)
+        b = b0.copy()
+        tol_k, iters, relM = tol, 0, np.inf
+        for _ in range(cycles):
+            d, inf = self.minres(b, tol=tol_k, maxit=maxit, pc_A=pc_A, pc_Q=pc_Q, inner_tol=inner_tol)
+            iters += inf["iters"]
+            x = x + d
+            x[self.n_u:] = self.project(x[self.n_u:])
+            r = b0 - self.matvec(x)
+            relM = np.sqrt(max(0.0, mnorm2(r)) / bM) if bM > 0 else 0.0
+            if relM <= tol:
+                break
+            b = r
+            tol_k = min(0.5, 0.5 * tol / relM)
+        return x[: self.n_u], x[self.n_u:], {"iters": iters, "relres_true_Minv": relM}
+
     def project(self, p):
         p = _f64(p).copy()
         self._L.or_project(self.h, _p(p))

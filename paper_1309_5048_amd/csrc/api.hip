@@ -145,6 +145,7 @@ struct Work {
   void *v[2] = {nullptr, nullptr}, *z[2] = {nullptr, nullptr}, *w[2] = {nullptr, nullptr};
   void *x = nullptr, *q = nullptr, *b = nullptr, *y = nullptr;
   void *pr = nullptr, *pp = nullptr, *pq = nullptr, *pz = nullptr;  // inner PCG
+  void *xr = nullptr, *br = nullptr;  // refinement: accumulated solution, original rhs (FP64)
 };
 
 }  // namespace
@@ -352,8 +353,9 @@ int max_rows_per_level(const stokes_problem* pb, const std::vector<int32_t>& gro
 // per group), reduced further while the LDS window does not fit R columns or the groups
 // cannot all be resident at once.
 int get_schedule(stokes_problem* pb, int R, bool fp32, SchedPair** out) {
+  (void)R;  // any width: the solve kernel splits wide batches into column chunks
   for (auto& sp : pb->scheds)
-    if ((fp32 ? sp->rmax32 : sp->rmax64) >= R) {
+    if ((fp32 ? sp->rmax32 : sp->rmax64) >= 1) {
       *out = sp.get();
       return 0;
     }
@@ -416,12 +418,14 @@ int get_schedule(stokes_problem* pb, int R, bool fp32, SchedPair** out) {
     CK(hipStreamSynchronize(pb->stream));
     pb->scheds.push_back(std::move(sp));
     SchedPair* last = pb->scheds.back().get();
-    if ((fp32 ? last->rmax32 : last->rmax64) >= R) {
+    // the first strip whose slots fit: wider batches than its rmax are solved in column
+    // chunks (fewer groups and crossings beat unchunked narrower strips)
+    if ((fp32 ? last->rmax32 : last->rmax64) >= 1) {
       *out = last;
       return 0;
     }
   }
-  return fail(pb, STOKES_EINVAL, "no triangular-solve schedule fits the LDS budget for this batch width");
+  return fail(pb, STOKES_EINVAL, "no triangular-solve schedule fits the LDS budget");
 }
 
 int get_work(stokes_problem* pb, int R, bool fp32, Work** out) {
@@ -664,7 +668,7 @@ int solve_core(stokes_problem* pb, Work& W64, int precond, int precision, double
   int iters_total[kRMax] = {0};
   int status[kRMax] = {0};
   double eta_rel[kRMax] = {0};
-  if (precision == STOKES_FP64) {
+  if (precision == STOKES_FP64 && precond != STOKES_PC_ICPCG) {
     int rc = minres_run<double>(pb, W64, precond, tol, pb->maxit_outer, ro);
     if (rc) return rc;
     for (int c = 0; c < R; ++c) {
@@ -674,6 +678,56 @@ int solve_core(stokes_problem* pb, Work& W64, int precond, int precision, double
     }
     int rc2 = project_pressure(pb, R, (double*)W64.x);
     if (rc2) return rc2;
+  } else if (precision == STOKES_FP64) {
+    // Inner IC(0)-CG to a relative tolerance is a nonlinear preconditioner: MINRES's |eta|
+    // then measures the residual in a norm that changes from one application to the next.
+    // Refine on the true residual (FP64, M = IC(0) norm) until it meets the tolerance.
+    if (W64.xr == nullptr) {
+      W64.xr = pb->mem.get<double>(size_t(n) * R);
+      W64.br = pb->mem.get<double>(size_t(n) * R);
+      if (pb->mem.err != hipSuccess) return fail_hip(pb, pb->mem.err, "refinement workspace", __LINE__);
+      for (auto& kv : pb->work)
+        if (kv.second.R == R && !kv.second.fp32) {
+          kv.second.xr = W64.xr;
+          kv.second.br = W64.br;
+        }
+    }
+    double* xacc = (double*)W64.xr;
+    double* b0 = (double*)W64.br;
+    double* b = (double*)W64.b;
+    hipLaunchKernelGGL(k_fill<double>, dim3(1024), dim3(256), 0, st, int64_t(n * R), xacc, 0.0);
+    CK(hipMemcpyAsync(b0, b, sizeof(double) * n * R, hipMemcpyDeviceToDevice, st));
+    double rel2[kRMax], relM[kRMax];
+    double tol_k = tol;
+    bool conv = false;
+    for (int ir = 0; ir < 6 && !conv; ++ir) {
+      int rc = minres_run<double>(pb, W64, precond, tol_k, pb->maxit_outer, ro);
+      if (rc) return rc;
+      for (int c = 0; c < R; ++c) {
+        iters_total[c] += ro.iters[c];
+        if (ro.status[c] < 0) status[c] = ro.status[c];
+      }
+      CK(accumulate<double>(R, int64_t(n * R), xacc, (const double*)W64.x, st));
+      rc = project_pressure(pb, R, xacc);
+      if (rc) return rc;
+      rc = true_residuals(pb, W64, precond, b0, xacc, rel2, relM);
+      if (rc) return rc;
+      double worst = 0.0;
+      conv = true;
+      for (int c = 0; c < R; ++c) {
+        conv &= (relM[c] <= tol);
+        worst = std::max(worst, relM[c]);
+      }
+      // next cycle solves Acal d = r (r left in W64.q) to the remaining relative reduction
+      CK(hipMemcpyAsync(b, W64.q, sizeof(double) * n * R, hipMemcpyDeviceToDevice, st));
+      tol_k = worst > 0.0 ? std::min(0.5, 0.5 * tol / worst) : tol;
+    }
+    CK(hipMemcpyAsync(W64.x, xacc, sizeof(double) * n * R, hipMemcpyDeviceToDevice, st));
+    CK(hipMemcpyAsync(b, b0, sizeof(double) * n * R, hipMemcpyDeviceToDevice, st));
+    for (int c = 0; c < R; ++c) {
+      if (status[c] >= 0) status[c] = relM[c] <= tol ? 0 : STOKES_NOT_CONVERGED;
+      eta_rel[c] = relM[c];
+    }
   } else {
     // Iterative refinement: FP64 residual, FP32 inner MINRES, FP64 accumulation.
     Work* W32 = nullptr;

@@ -40,6 +40,7 @@ struct TrsvArgs {
   int ngroups;
   int nslots;
   int nrows;
+  int ld;  // row stride of out (the full batch width; R columns are solved per launch)
 };
 
 // Output sentinel (signalling NaN) and its test, on the bit patterns.
@@ -298,7 +299,7 @@ __global__ __launch_bounds__(kTrsvThreads) __attribute__((amdgpu_waves_per_eu(1,
 #pragma unroll
           for (int c = 0; c < R; ++c) res[c] = (prd[d][c] - octet_sum(acc[c] + acc2[c])) * pri[d].dinv;
           const bool real = live && prow[d] >= 0;
-          T* gp = real ? out + (size_t)prow[d] * R : dummy;
+          T* gp = real ? out + (size_t)prow[d] * a.ld : dummy;
           if constexpr (R == 1) {
             dev_store(gp, res[0]);
           } else {
@@ -355,7 +356,7 @@ __global__ __launch_bounds__(kTrsvThreads) __attribute__((amdgpu_waves_per_eu(1,
       if (inb) {
 #pragma unroll
         for (int c = 0; c < R; ++c) {
-          v[c] = dev_load(out + (size_t)row * R + c);
+          v[c] = dev_load(out + (size_t)row * a.ld + c);
           ready = ready && !is_sentinel(v[c]);
         }
         ready = ready && lds_load(&ctr[CTR_COMPUTED]) >= fr;
@@ -414,12 +415,12 @@ __global__ __launch_bounds__(kTrsvThreads) __attribute__((amdgpu_waves_per_eu(1,
   }
 }
 
-// Per-solve gather into schedule order, rd_s[(step*RPS + r)*2R + c] = rhs[row*R + c] and
-// rd_s[... + R + c] = dotv[row*R + c] (0 without a dot vector), and the output rows reset
-// to the sentinel.
+// Per-solve gather into schedule order, rd_s[(step*RPS + r)*2R + c] = rhs[row*ld + c] and
+// rd_s[... + R + c] = dotv[row*ld + c] (0 without a dot vector), and the output rows reset
+// to the sentinel (R columns of a batch of width ld; the pointers carry the column offset).
 template <typename T, int R>
 __global__ void k_trsv_gather_rhs(int64_t nrow_slots, const int32_t* __restrict__ srow, const T* __restrict__ rhs,
-                                  const T* __restrict__ dotv, T* __restrict__ rd_s, T* __restrict__ out,
+                                  const T* __restrict__ dotv, int ld, T* __restrict__ rd_s, T* __restrict__ out,
                                   const int* __restrict__ skip) {
   if (skip != nullptr && *skip) return;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nrow_slots * R;
@@ -427,9 +428,9 @@ __global__ void k_trsv_gather_rhs(int64_t nrow_slots, const int32_t* __restrict_
     const int64_t k = t / R;
     const int c = int(t % R);
     const int row = srow[k];
-    rd_s[k * 2 * R + c] = row >= 0 ? rhs[(size_t)row * R + c] : T(0);
-    rd_s[k * 2 * R + R + c] = (row >= 0 && dotv != nullptr) ? dotv[(size_t)row * R + c] : T(0);
-    if (row >= 0) out[(size_t)row * R + c] = sentinel_value<T>();
+    rd_s[k * 2 * R + c] = row >= 0 ? rhs[(size_t)row * ld + c] : T(0);
+    rd_s[k * 2 * R + R + c] = (row >= 0 && dotv != nullptr) ? dotv[(size_t)row * ld + c] : T(0);
+    if (row >= 0) out[(size_t)row * ld + c] = sentinel_value<T>();
   }
 }
 
@@ -458,8 +459,8 @@ size_t trsv_shmem_bytes(int nslots, bool fp32, int R) {
 
 template <typename T, int R, int EP, int D>
 static hipError_t launch_trsv_t(const TrsvSchedDev& S, const T* sval, const typename RowRec<T>::type* srinfo,
-                                const T* rhs, T* out, const T* dotv, double* dot_out, const int* skip, hipStream_t st,
-                                const TrsvTiming* tm) {
+                                const T* rhs, T* out, const T* dotv, double* dot_out, int ld, const int* skip,
+                                hipStream_t st, const TrsvTiming* tm) {
   TrsvArgs a;
   a.grp_step_ptr = S.grp_step_ptr;
   a.grp_halo_ptr = S.grp_halo_ptr;
@@ -474,11 +475,12 @@ static hipError_t launch_trsv_t(const TrsvSchedDev& S, const T* sval, const type
   a.ngroups = S.ngroups;
   a.nslots = S.nslots;
   a.nrows = S.nrows;
+  a.ld = ld;
   T* rd_s = reinterpret_cast<T*>(S.rhs_s);
   T* dummy = reinterpret_cast<T*>(S.dummy);
   const int64_t nrow_slots = (int64_t)S.nsteps * kTrsvRPS;
-  hipLaunchKernelGGL((k_trsv_gather_rhs<T, R>), dim3(1024), dim3(256), 0, st, nrow_slots, S.srow, rhs, dotv, rd_s,
-                     out, skip);
+  hipLaunchKernelGGL((k_trsv_gather_rhs<T, R>), dim3(1024), dim3(256), 0, st, nrow_slots, S.srow, rhs, dotv, ld,
+                     rd_s, out, skip);
   const size_t shmem = trsv_shmem_t<T, R>(S.nslots);
   auto fn = k_trsv<T, R, EP, D>;
   hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
@@ -494,40 +496,61 @@ static hipError_t launch_trsv_t(const TrsvSchedDev& S, const T* sval, const type
 
 template <typename T, int R>
 static hipError_t launch_trsv_r(const TrsvSchedDev& S, const T* sval, const typename RowRec<T>::type* srinfo,
-                                const T* rhs, T* out, const T* dotv, double* dot_out, const int* skip, hipStream_t st,
-                                const TrsvTiming* tm) {
+                                const T* rhs, T* out, const T* dotv, double* dot_out, int ld, const int* skip,
+                                hipStream_t st, const TrsvTiming* tm) {
   switch (S.EP) {
     // prefetch depth D (steps in flight): for R = 1 as deep as the 63 outstanding vector
     // memory operations (about 7 to 10 per step) and the register file allow; with R
     // columns the per-step records are R times larger and D is small
-    case 4: return launch_trsv_t<T, R, 4, (R == 1 ? 9 : (R == 8 ? 3 : 2))>(S, sval, srinfo, rhs, out, dotv, dot_out, skip, st, tm);
-    case 8: return launch_trsv_t<T, R, 8, (R == 1 ? (sizeof(T) == 8 ? 7 : 8) : (R == 8 ? 3 : 2))>(S, sval, srinfo, rhs, out, dotv, dot_out, skip, st, tm);
-    case 12: return launch_trsv_t<T, R, 12, (R == 1 ? 4 : 2)>(S, sval, srinfo, rhs, out, dotv, dot_out, skip, st, tm);
-    case 16: return launch_trsv_t<T, R, 16, (R == 1 ? 3 : 2)>(S, sval, srinfo, rhs, out, dotv, dot_out, skip, st, tm);
+    case 4: return launch_trsv_t<T, R, 4, (R == 1 ? 9 : (R == 8 ? 3 : 2))>(S, sval, srinfo, rhs, out, dotv, dot_out, ld, skip, st, tm);
+    case 8: return launch_trsv_t<T, R, 8, (R == 1 ? (sizeof(T) == 8 ? 7 : 8) : (R == 8 ? 3 : 2))>(S, sval, srinfo, rhs, out, dotv, dot_out, ld, skip, st, tm);
+    case 12: return launch_trsv_t<T, R, 12, (R == 1 ? 4 : 2)>(S, sval, srinfo, rhs, out, dotv, dot_out, ld, skip, st, tm);
+    case 16: return launch_trsv_t<T, R, 16, (R == 1 ? 3 : 2)>(S, sval, srinfo, rhs, out, dotv, dot_out, ld, skip, st, tm);
   }
   return hipErrorInvalidValue;
 }
 
+// R columns in chunks of the widest width whose LDS slots fit (R, 8 or 1), one launch each.
+template <typename T>
+static hipError_t launch_trsv_p(const TrsvSchedDev& S, const T* sval, const typename RowRec<T>::type* srinfo, int R,
+                                const T* rhs, T* out, const T* dotv, double* dot_out, const int* skip, hipStream_t st,
+                                const TrsvTiming* tm) {
+  int dev = 0, lds_max = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  if (e != hipSuccess) return e;
+  int Rc = R;
+  while (Rc > 1 && (Rc > S.rmax || trsv_shmem_bytes(S.nslots, sizeof(T) == 4, Rc) > (size_t)lds_max))
+    Rc = Rc > 8 ? 8 : 1;
+  if (R % Rc != 0) return hipErrorInvalidValue;
+  for (int c0 = 0; c0 < R; c0 += Rc) {
+    // timing events: before the first chunk, after the last
+    TrsvTiming t;
+    if (tm != nullptr) {
+      t.before = c0 == 0 ? tm->before : nullptr;
+      t.after = c0 + Rc >= R ? tm->after : nullptr;
+    }
+    const T* dv = dotv ? dotv + c0 : nullptr;
+    double* dout = dot_out ? dot_out + c0 : nullptr;
+    switch (Rc) {
+      case 1: e = launch_trsv_r<T, 1>(S, sval, srinfo, rhs + c0, out + c0, dv, dout, R, skip, st, &t); break;
+      case 8: e = launch_trsv_r<T, 8>(S, sval, srinfo, rhs + c0, out + c0, dv, dout, R, skip, st, &t); break;
+      case 16: e = launch_trsv_r<T, 16>(S, sval, srinfo, rhs + c0, out + c0, dv, dout, R, skip, st, &t); break;
+      default: return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_trsv(const TrsvSchedDev& S, bool fp32, int R, const void* rhs, void* out, const void* dotv,
                        double* dot_out, const int* skip, hipStream_t st, const TrsvTiming* tm) {
-  if (fp32) {
-    const float* v = S.sval32;
-    const TrsvRow32* ri = S.srinfo32;
-    switch (R) {
-      case 1: return launch_trsv_r<float, 1>(S, v, ri, (const float*)rhs, (float*)out, (const float*)dotv, dot_out, skip, st, tm);
-      case 8: return launch_trsv_r<float, 8>(S, v, ri, (const float*)rhs, (float*)out, (const float*)dotv, dot_out, skip, st, tm);
-      case 16: return launch_trsv_r<float, 16>(S, v, ri, (const float*)rhs, (float*)out, (const float*)dotv, dot_out, skip, st, tm);
-    }
-  } else {
-    const double* v = S.sval;
-    const TrsvRow64* ri = S.srinfo;
-    switch (R) {
-      case 1: return launch_trsv_r<double, 1>(S, v, ri, (const double*)rhs, (double*)out, (const double*)dotv, dot_out, skip, st, tm);
-      case 8: return launch_trsv_r<double, 8>(S, v, ri, (const double*)rhs, (double*)out, (const double*)dotv, dot_out, skip, st, tm);
-      case 16: return launch_trsv_r<double, 16>(S, v, ri, (const double*)rhs, (double*)out, (const double*)dotv, dot_out, skip, st, tm);
-    }
-  }
-  return hipErrorInvalidValue;
+  if (fp32)
+    return launch_trsv_p<float>(S, S.sval32, S.srinfo32, R, (const float*)rhs, (float*)out, (const float*)dotv,
+                                dot_out, skip, st, tm);
+  return launch_trsv_p<double>(S, S.sval, S.srinfo, R, (const double*)rhs, (double*)out, (const double*)dotv, dot_out,
+                               skip, st, tm);
 }
 
 // Factor values into schedule order and reciprocal diagonals into the row records.

@@ -123,17 +123,25 @@ def test_minres_fixed_iterations(pair, pc):
     gp.set_maxit(20000, 200)
 
 
+def _oracle_solve(o, f, tol, pc):
+    """The oracle counterpart of the library's solve: plain MINRES, or for the inner-PCG
+    block (a nonlinear preconditioner) MINRES restarted on the true residual."""
+    if pc == PC_ICPCG:
+        return o.solve_refined(f, tol=tol)
+    return o.solve(f, tol=tol, pc_A=pc)
+
+
 @pytest.mark.parametrize("pc", [PC_IC0, PC_JACOBI, PC_ICPCG])
 def test_minres_converged(pair, pc):
     gp, o = pair
     f = o.load(1)
     u, p, info = gp.solve(_cuda(f), tol=1e-8, precond=pc)
-    uo, po, io = o.solve(f, tol=1e-8, pc_A=pc)
+    uo, po, io = _oracle_solve(o, f, 1e-8, pc)
     assert info["status"] == 0
     assert abs(info["iters"] - io["iters"]) <= _it_tol(o), (info["iters"], io["iters"])
-    assert info["relres_true_Minv"] <= 2e-8
+    assert info["relres_true_Minv"] <= 1e-8 if pc == PC_ICPCG else info["relres_true_Minv"] <= 2e-8
     u2, p2, info2 = gp.solve(_cuda(f), tol=1e-13, precond=pc)
-    uo2, po2, _ = o.solve(f, tol=1e-13, pc_A=pc)
+    uo2, po2, _ = _oracle_solve(o, f, 1e-13, pc)
     assert _rel(u2.cpu().numpy(), uo2) <= 1e-10
     assert _rel(p2.cpu().numpy(), po2) <= 1e-10
     # zero-mean pressure
