@@ -89,6 +89,9 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the variant comparisons")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=150)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="after the solves, run a plain elementwise copy of MIB MiB three times "
+                         "(reads and writes MIB MiB each): the reference for scaling memory counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this solver path is built and measured on a single "
@@ -243,6 +246,15 @@ def main():
             extra["c4_adjoint_8rhs"] = {"error": str(e)}
         out["variants"] = extra
 
+    if args.copy_probe > 0:
+        nbytes = args.copy_probe << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        sync()
+        out["copy_probe_bytes"] = nbytes
+        log("copy probe: 3 x %d bytes read and written" % nbytes)
     if not args.no_cpu:
         log("cpu baseline (oracle, 1 core)")
         out["cpu_baseline"] = cpu_baseline(N, kp, dim, iters, args.cpu_iters)

@@ -68,6 +68,8 @@ typedef struct {
   int32_t inner_iters_total; /* inner PCG iterations (ICPCG) summed over the solve        */
   int32_t status;            /* return code of this right-hand side                       */
   int32_t ic_shift_steps;    /* IC(0) diagonal-shift retries used at setup (0 = none)     */
+  int32_t refine_cycles;     /* MINRES runs on the true residual (1 unless MIXED or ICPCG) */
+  int32_t reserved;          /* zero                                                       */
   double relres_est;         /* |eta|/gamma_1 at exit (M^{-1}-norm estimate)              */
   double relres_true_2;      /* ||b - Acal x||_2 / ||b||_2, computed on the device          */
   double relres_true_Minv;   /* ||b - Acal x||_{M^-1} / ||b||_{M^-1} (IC(0)/Jacobi M)       */
@@ -110,6 +112,12 @@ int stokes_set_nu(stokes_problem* pb, double nu);
  * (defaults: outer 20000, inner 200).  Non-positive values keep the current setting. */
 int stokes_set_inner_tol(stokes_problem* pb, double rtol);
 int stokes_set_maxit(stokes_problem* pb, int outer, int inner);
+
+/* STOKES_MIXED refinement: relative residual reduction asked of the first FP32 inner MINRES
+ * (default 1e-4, must be < 1).  Later cycles ask for the reduction still missing to reach
+ * tol (with a factor 2 of margin), but never for more than rtol.  At most 30 cycles.
+ * Non-positive values keep the current setting. */
+int stokes_set_refine_tol(stokes_problem* pb, double rtol);
 
 /* Assemble nrhs load vectors [f]_i = (f, Phi_i) on the device (Gauss rule with k'+4
  * points per direction) into f_dev [nrhs][n_u]. */

@@ -21,6 +21,7 @@ FP64, MIXED = 0, 1
 # every exported entry point declared in include/stokes.h
 EXPORTS = (
     "stokes_setup", "stokes_sizes", "stokes_set_stream", "stokes_set_nu", "stokes_set_inner_tol",
+    "stokes_set_refine_tol",
     "stokes_set_maxit", "stokes_load", "stokes_solve", "stokes_solve_batched", "stokes_solve_precision",
     "stokes_solve_adjoint", "stokes_solve_adjoint_batched", "stokes_dnu_dot", "stokes_apply",
     "stokes_apply_precond", "stokes_export_csr", "stokes_export_pressure_mass", "stokes_levels",
@@ -30,7 +31,8 @@ EXPORTS = (
 
 class StokesInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("inner_iters_total", ctypes.c_int32), ("status", ctypes.c_int32),
-                ("ic_shift_steps", ctypes.c_int32), ("relres_est", ctypes.c_double),
+                ("ic_shift_steps", ctypes.c_int32), ("refine_cycles", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("relres_est", ctypes.c_double),
                 ("relres_true_2", ctypes.c_double), ("relres_true_Minv", ctypes.c_double),
                 ("setup_ms", ctypes.c_double), ("solve_ms", ctypes.c_double)]
 
@@ -63,6 +65,7 @@ def lib():
         "stokes_set_stream": (i32, [vp, vp]),
         "stokes_set_nu": (i32, [vp, dbl]),
         "stokes_set_inner_tol": (i32, [vp, dbl]),
+        "stokes_set_refine_tol": (i32, [vp, dbl]),
         "stokes_set_maxit": (i32, [vp, i32, i32]),
         "stokes_load": (i32, [vp, P(StokesForcing), i32, vp]),
         "stokes_solve": (i32, [vp, vp, vp, vp, dbl, i32, P(StokesInfo)]),

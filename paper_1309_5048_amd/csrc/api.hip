@@ -179,7 +179,7 @@ struct stokes_problem {
   unsigned int* counter = nullptr;
   std::map<int, Work> work;
   double inner_tol = 1e-2;
-  double mixed_inner_tol = 1e-4;
+  double refine_tol = 1e-4;
   int maxit_outer = 20000, maxit_inner = 200;
   int check_every = 8;
   double setup_ms = 0.0;
@@ -668,6 +668,7 @@ int solve_core(stokes_problem* pb, Work& W64, int precond, int precision, double
   int iters_total[kRMax] = {0};
   int status[kRMax] = {0};
   double eta_rel[kRMax] = {0};
+  int cycles = 1;
   if (precision == STOKES_FP64 && precond != STOKES_PC_ICPCG) {
     int rc = minres_run<double>(pb, W64, precond, tol, pb->maxit_outer, ro);
     if (rc) return rc;
@@ -700,9 +701,11 @@ int solve_core(stokes_problem* pb, Work& W64, int precond, int precision, double
     double rel2[kRMax], relM[kRMax];
     double tol_k = tol;
     bool conv = false;
+    cycles = 0;
     for (int ir = 0; ir < 6 && !conv; ++ir) {
       int rc = minres_run<double>(pb, W64, precond, tol_k, pb->maxit_outer, ro);
       if (rc) return rc;
+      ++cycles;
       for (int c = 0; c < R; ++c) {
         iters_total[c] += ro.iters[c];
         if (ro.status[c] < 0) status[c] = ro.status[c];
@@ -740,10 +743,15 @@ int solve_core(stokes_problem* pb, Work& W64, int precond, int precision, double
     CK(hipMemcpyAsync(r64, b64, sizeof(double) * n * R, hipMemcpyDeviceToDevice, st));
     double rel2[kRMax], relM[kRMax];
     bool conv = false;
+    // The first cycle asks the FP32 MINRES for refine_tol; later ones only for the reduction
+    // that remains (with a factor 2 of margin), never more than refine_tol per cycle.
+    double tol_k = pb->refine_tol;
+    cycles = 0;
     for (int ir = 0; ir < 30 && !conv; ++ir) {
       CK(convert<double, float>(int64_t(n * R), r64, (float*)W32->b, st));
-      rc = minres_run<float>(pb, *W32, precond, pb->mixed_inner_tol, pb->maxit_outer, ro);
+      rc = minres_run<float>(pb, *W32, precond, tol_k, pb->maxit_outer, ro);
       if (rc) return rc;
+      ++cycles;
       for (int c = 0; c < R; ++c) iters_total[c] += ro.iters[c];
       CK(accumulate<float>(R, int64_t(n * R), x64, (const float*)W32->x, st));
       rc = project_pressure(pb, R, x64);
@@ -753,7 +761,12 @@ int solve_core(stokes_problem* pb, Work& W64, int precond, int precision, double
       // refresh r64 = b - Acal x (true_residuals left it in W64.q)
       CK(hipMemcpyAsync(r64, W64.q, sizeof(double) * n * R, hipMemcpyDeviceToDevice, st));
       conv = true;
-      for (int c = 0; c < R; ++c) conv &= (relM[c] <= tol);
+      double worst = 0.0;
+      for (int c = 0; c < R; ++c) {
+        conv &= (relM[c] <= tol);
+        worst = std::max(worst, relM[c]);
+      }
+      tol_k = worst > 0.0 ? std::min(0.5, std::max(pb->refine_tol, 0.5 * tol / worst)) : pb->refine_tol;
     }
     for (int c = 0; c < R; ++c) {
       status[c] = relM[c] <= tol ? 0 : STOKES_NOT_CONVERGED;
@@ -773,6 +786,8 @@ int solve_core(stokes_problem* pb, Work& W64, int precond, int precision, double
       infos[c].relres_true_Minv = relM[c];
       infos[c].setup_ms = pb->setup_ms;
       infos[c].inner_iters_total = 0;
+      infos[c].refine_cycles = cycles;
+      infos[c].reserved = 0;
     }
     if (precond == STOKES_PC_ICPCG) {
       PcgState ps[kRMax];
@@ -975,6 +990,13 @@ int stokes_set_nu(stokes_problem* pb, double nu) {
 int stokes_set_inner_tol(stokes_problem* pb, double rtol) {
   if (!pb) return STOKES_EINVAL;
   if (rtol > 0.0) pb->inner_tol = rtol;
+  return 0;
+}
+
+int stokes_set_refine_tol(stokes_problem* pb, double rtol) {
+  if (!pb) return STOKES_EINVAL;
+  if (!(rtol < 1.0)) return fail(pb, STOKES_EINVAL, "refine_tol must be < 1");
+  if (rtol > 0.0) pb->refine_tol = rtol;
   return 0;
 }
 

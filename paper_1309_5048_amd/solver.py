@@ -83,6 +83,9 @@ class StokesProblem:
     def set_inner_tol(self, rtol):
         self._L.stokes_set_inner_tol(self._h, float(rtol))
 
+    def set_refine_tol(self, rtol):
+        self._check(self._L.stokes_set_refine_tol(self._h, float(rtol)), allow_nc=False)
+
     def set_maxit(self, outer=0, inner=0):
         self._L.stokes_set_maxit(self._h, int(outer), int(inner))
 
