@@ -178,7 +178,10 @@ def main():
             g2 = StokesProblem(512, 2, 2, 1.0)
             f2 = g2.load(True)[0]
             s64, i64 = timed_solves(g2, f2, 1, 1, tol=tol, precond=PC_IC0, precision=FP64)
+            log("c2 fp64 %.3f s, %d iterations" % (s64, i64[-1]["iters"]))
             s32, i32 = timed_solves(g2, f2, 1, 1, tol=tol, precond=PC_IC0, precision=MIXED)
+            log("c2 mixed %.3f s, %d iterations, %d refinement cycles" % (s32, i32[-1]["iters"],
+                                                                        i32[-1]["refine_cycles"]))
             u64, p64, _ = g2.solve(f2, tol=1e-13)
             um, pm, _ = g2.solve(f2, tol=tol, precision=MIXED)
             eu = float((um - u64).norm() / u64.norm())
@@ -200,6 +203,7 @@ def main():
             F3 = g3.load(True, forcing_modes(w3["seeds"], 3))
             g3.solve_batched(F3, tol=tol)
             sync()
+            log("c3 warm-up done")
             t = time.perf_counter()
             U3, P3, inf3 = g3.solve_batched(F3, tol=tol)
             sync()
@@ -232,6 +236,7 @@ def main():
             U4, P4 = stokes_solve(Fv, nu, g4, tol)
             sync()
             tf = time.perf_counter() - t
+            log("c4 forward %.3f s" % tf)
             loss = 0.5 * ((U4 - ut) ** 2).sum()
             t = time.perf_counter()
             loss.backward()

@@ -162,6 +162,8 @@ struct stokes_problem {
   int64_t nnz = 0, nnzL = 0;
   DevAlloc mem;  // everything owned by the problem
   int32_t *rowptr = nullptr, *col = nullptr, *aend = nullptr;
+  RowSplit rs_full, rs_A;  // row ranges of the row kernels: all rows / A part of velocity rows
+  std::vector<int32_t> split_full_h, split_A_h;  // host copies (kept alive for the async upload)
   double* val = nullptr;
   float* val32 = nullptr;
   double *diagQ = nullptr, *w = nullptr, *diagA = nullptr;
@@ -194,11 +196,17 @@ struct stokes_problem {
   size_t prof_used = 0;
   double prof_ms[5] = {0, 0, 0, 0, 0};
   int64_t prof_cnt[5] = {0, 0, 0, 0, 0};
+  // convergence polling: two pinned host flags and their completion events
+  int* hflag = nullptr;
+  hipEvent_t flag_ev[2] = {nullptr, nullptr};
   ~stokes_problem() {
     for (auto& t : prof_pool) {
       (void)hipEventDestroy(t.before);
       (void)hipEventDestroy(t.after);
     }
+    for (auto& e : flag_ev)
+      if (e) (void)hipEventDestroy(e);
+    if (hflag) (void)hipHostFree(hflag);
     mem.release();
   }
 };
@@ -237,16 +245,25 @@ const TrsvTiming* prof_take(stokes_problem* pb, int cat) {
   return &pb->prof_pool[pb->prof_used++];
 }
 
-// Accumulate the elapsed times of the recorded pairs (call after a stream sync).
+// Accumulate the elapsed times of the recorded pairs that have completed; pairs still in
+// flight stay in the pool for a later call.
 void prof_flush(stokes_problem* pb) {
+  size_t keep = 0;
   for (size_t k = 0; k < pb->prof_used; ++k) {
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, pb->prof_pool[k].before, pb->prof_pool[k].after) == hipSuccess) {
+    const hipError_t e = hipEventElapsedTime(&ms, pb->prof_pool[k].before, pb->prof_pool[k].after);
+    if (e == hipErrorNotReady) {
+      std::swap(pb->prof_pool[keep], pb->prof_pool[k]);
+      std::swap(pb->prof_cat[keep], pb->prof_cat[k]);
+      ++keep;
+      continue;
+    }
+    if (e == hipSuccess) {
       pb->prof_ms[pb->prof_cat[k]] += ms;
       pb->prof_cnt[pb->prof_cat[k]] += 1;
     }
   }
-  pb->prof_used = 0;
+  pb->prof_used = keep;
 }
 
 #define PROF_BEGIN(cat)                                   \
@@ -254,6 +271,109 @@ void prof_flush(stokes_problem* pb) {
   if (_pt) (void)hipEventRecord(_pt->before, pb->stream);
 #define PROF_END() \
   if (_pt) (void)hipEventRecord(_pt->after, pb->stream);
+
+// Single-column layout of a schedule (see TrsvFastDev).  Returns 0 and leaves F.ok false
+// when a group needs more than 8 entries per lane (the general kernel then serves R = 1).
+int build_fast_layout(stokes_problem* pb, const TrsvSchedHost& H, TrsvSchedDev& D) {
+  TrsvFastDev& F = D.fast;
+  hipStream_t st = pb->stream;
+  DevAlloc& m = pb->mem;
+  const int G = H.ngroups, RPS = kTrsvRPS, E = H.E;
+  if (int64_t(pb->S.n_u) * 8 >= (int64_t(1) << 31) || (int64_t)pb->nnzL >= (int64_t(1) << 31)) return 0;
+  std::vector<int32_t> gsp(G + 1, 0), gnp(G, 0), gep(G, 4);
+  std::vector<int64_t> gb64(G + 1, 0), gb32(G + 1, 0);
+  int64_t off64 = 0, off32 = 0;
+  for (int g = 0; g < G; ++g) {
+    const int s0 = H.grp_step_ptr[g], s1 = H.grp_step_ptr[g + 1];
+    int eg = 0;
+    for (int s = s0; s < s1; ++s)
+      for (int e = 0; e < E; ++e)
+        for (int l = 0; l < 64; ++l)
+          if (H.ent_perm[(size_t(s) * E + e) * 64 + l] >= 0) eg = std::max(eg, e + 1);
+    if (eg > 8) return 0;
+    gep[g] = eg <= 4 ? 4 : 8;
+    const int nreal = s1 - s0, dg = fast_depth(gep[g]);
+    gnp[g] = nreal > 0 ? (nreal + dg - 1) / dg * dg : 0;
+    const int alloc = nreal > 0 ? gnp[g] + dg : 0;
+    gsp[g + 1] = gsp[g] + alloc;
+    gb64[g] = off64;
+    gb32[g] = off32;
+    off64 += int64_t(alloc) * fast_block_bytes<double>(gep[g]);
+    off32 += int64_t(alloc) * fast_block_bytes<float>(gep[g]);
+  }
+  gb64[G] = off64;
+  gb32[G] = off32;
+  if (off64 >= (int64_t(1) << 31)) return 0;  // block offsets of a group must fit 32 bits
+  const int64_t T = gsp[G];
+  std::vector<unsigned char> b64(size_t(off64), 0), b32(size_t(off32), 0);
+  std::vector<int64_t> sv64(T), sv32(T);
+  std::vector<int32_t> sep(T), vperm(size_t(T) * 64 * 8, -1), dsrc(size_t(T) * RPS, -1), srow2(size_t(T) * RPS, 0);
+  for (int g = 0; g < G; ++g) {
+    const int s0 = H.grp_step_ptr[g], nreal = H.grp_step_ptr[g + 1] - s0, ep = gep[g];
+    const int sb64 = fast_block_bytes<double>(ep), sb32 = fast_block_bytes<float>(ep);
+    for (int j = 0; j < gsp[g + 1] - gsp[g]; ++j) {
+      const int64_t t = gsp[g] + j;
+      const int s = s0 + std::min(j, nreal - 1);
+      const bool repeat_step = j >= nreal;
+      unsigned char* p64 = b64.data() + gb64[g] + int64_t(j) * sb64;
+      unsigned char* p32 = b32.data() + gb32[g] + int64_t(j) * sb32;
+      sv64[t] = gb64[g] + int64_t(j) * sb64 + kFastHdr + 64 * ep * 4;
+      sv32[t] = gb32[g] + int64_t(j) * sb32 + kFastHdr + 64 * ep * 4;
+      sep[t] = ep;
+      const int32_t need = H.step_halo_need[s];
+      std::memcpy(p64 + RPS * 16, &need, 4);
+      std::memcpy(p32 + RPS * 16, &need, 4);
+      const int32_t row0 = H.srow[size_t(s) * RPS];
+      if (row0 < 0) return fail(pb, STOKES_EINVAL, "triangular-solve step without rows");
+      for (int rr = 0; rr < RPS; ++rr) {
+        const int32_t row = H.srow[size_t(s) * RPS + rr];
+        const int src = row >= 0 ? rr : 0;  // missing rows repeat row 0
+        const int32_t srow = H.srow[size_t(s) * RPS + src];
+        srow2[size_t(t) * RPS + rr] = (row >= 0 && !repeat_step) ? srow : ~srow;
+        dsrc[size_t(t) * RPS + rr] = int32_t(H.sdiag_src[size_t(s) * RPS + src]);
+        const int32_t slot = H.sslot[size_t(s) * RPS + src] > 0 ? H.sslot[size_t(s) * RPS + src] : H.nslots;
+        FastRec64 r64{0.0, int32_t(64 + slot * 8), int32_t(srow * 8)};
+        FastRec32 r32{0.0f, int32_t(64 + slot * 4), int32_t(srow * 4), 0};
+        std::memcpy(p64 + rr * 16, &r64, 16);
+        std::memcpy(p32 + rr * 16, &r32, 16);
+        for (int q = 0; q < kTrsvG; ++q) {
+          const int lane = rr * kTrsvG + q, lsrc = src * kTrsvG + q;
+          for (int e = 0; e < ep; ++e) {
+            int64_t vp = -1;
+            int32_t sl = 0;
+            if (e < E) {
+              vp = H.ent_perm[(size_t(s) * E + e) * 64 + lsrc];
+              sl = H.ent_src[(size_t(s) * E + e) * 64 + lsrc];
+            }
+            vperm[(size_t(t) * 64 + lane) * 8 + e] = int32_t(vp);
+            const uint32_t a64 = uint32_t(64 + sl * 8), a32 = uint32_t(64 + sl * 4);
+            std::memcpy(p64 + kFastHdr + (lane * ep + e) * 4, &a64, 4);
+            std::memcpy(p32 + kFastHdr + (lane * ep + e) * 4, &a32, 4);
+          }
+        }
+      }
+    }
+  }
+  F.nsteps = int(T);
+  F.grp_step_ptr = m.upload(gsp, st);
+  F.grp_npad = m.upload(gnp, st);
+  F.grp_ep = m.upload(gep, st);
+  F.grp_blk64 = m.upload(gb64, st);
+  F.grp_blk32 = m.upload(gb32, st);
+  F.blk64 = m.upload(b64, st);
+  F.blk32 = m.upload(b32, st);
+  F.step_val64 = m.upload(sv64, st);
+  F.step_val32 = m.upload(sv32, st);
+  F.step_ep = m.upload(sep, st);
+  F.vperm = m.upload(vperm, st);
+  F.dsrc = m.upload(dsrc, st);
+  F.srow2 = m.upload(srow2, st);
+  F.dyn = m.get<double>(size_t(T) * RPS * 2);
+  if (m.err != hipSuccess) return fail_hip(pb, m.err, "single-column schedule upload", __LINE__);
+  CK(hipStreamSynchronize(st));  // the host vectors must outlive the copies
+  F.ok = true;
+  return 0;
+}
 
 int upload_schedule(stokes_problem* pb, const TrsvSchedHost& H, TrsvSchedDev& D, int rmax) {
   hipStream_t st = pb->stream;
@@ -321,8 +441,10 @@ int upload_schedule(stokes_problem* pb, const TrsvSchedHost& H, TrsvSchedDev& D,
   CK(hipMemsetAsync(D.epoch, 0, sizeof(unsigned long long), st));
   CK(hipMemsetAsync(D.done_count, 0, sizeof(unsigned int), st));
   CK(hipMemsetAsync(D.err, 0, sizeof(int), st));
+  CK(hipStreamSynchronize(st));  // host vectors must outlive the asynchronous copies
+  int rc = build_fast_layout(pb, H, D);
+  if (rc) return rc;
   CK(launch_trsv_gather(D, pb->Lval, st));
-  // host vectors must outlive the asynchronous copies
   CK(hipStreamSynchronize(st));
   return 0;
 }
@@ -401,7 +523,7 @@ int get_schedule(stokes_problem* pb, int R, bool fp32, SchedPair** out) {
     sp->strip = strip;
     sp->rmax64 = fit_rmax(pb, nsl, false);
     sp->rmax32 = fit_rmax(pb, nsl, true);
-    // all groups of a cooperative launch must be resident together
+    // all groups of a solve must be resident together (they wait on each other)
     auto resident = [&](int r, bool f32) {
       if (r == 0) return 0;
       const size_t sh = trsv_shmem_bytes(nsl, f32, r);
@@ -500,7 +622,7 @@ int precond_velocity(stokes_problem* pb, int precond, Work& W, SchedPair* sp, co
     int ip = 0;
     for (int it = 0; it < pb->maxit_inner; it += 4) {
       for (int k = 0; k < 4; ++k) {
-        CK(pcg_spmv<T>(R, n_u, pb->rowptr, pb->aend, pb->col, val, (const T*)W.pp, (T*)W.pq, s, st));
+        CK(pcg_spmv<T>(R, pb->rs_A, pb->rowptr, pb->aend, pb->col, val, (const T*)W.pp, (T*)W.pq, s, st));
         CK(pcg_axpy<T>(R, n_u, (const T*)W.pp, (const T*)W.pq, zout, (T*)W.pr, s, ip, st));
         CK(launch_trsv(sp->fwd, fp32, R, W.pr, W.y, nullptr, nullptr, s.alldone, st, prof_take(pb, 1)));
         CK(launch_trsv(sp->bwd, fp32, R, W.y, W.pz, W.pr, s.rho + (1 - ip) * kRMax, s.alldone, st,
@@ -555,13 +677,20 @@ int minres_run(stokes_problem* pb, Work& W, int precond, double tol, int maxit, 
   int rc = precond_velocity<T>(pb, precond, W, sp, v[0], z[0], s.red + RED_G2U * kRMax, nullptr, nullptr, nullptr);
   if (rc) return rc;
   CK(mr_init_state(R, s, tol, maxit, st));
-  int j = 1;
+  if (pb->hflag == nullptr) {
+    CK(hipHostMalloc((void**)&pb->hflag, 2 * sizeof(int), hipHostMallocDefault));
+    for (auto& e : pb->flag_ev) CK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  // Iterations are enqueued in chunks of check_every.  After enqueueing chunk k the host
+  // waits for the done flag of chunk k-1 only, so the device always has a chunk queued;
+  // iterations after convergence return at once (device-side done flags).
+  int j = 1, chunk = 0;
   for (;;) {
     for (int m = 0; m < pb->check_every; ++m, ++j) {
       const int p = (j - 1) & 1;
       {
         PROF_BEGIN(0);
-        CK(mr_spmv<T>(R, n, pb->rowptr, pb->col, val, z[p], q, s, p, st));
+        CK(mr_spmv<T>(R, pb->rs_full, pb->rowptr, pb->col, val, z[p], q, s, p, st));
         PROF_END();
       }
       {
@@ -579,12 +708,20 @@ int minres_run(stokes_problem* pb, Work& W, int precond, double tol, int maxit, 
         PROF_END();
       }
     }
-    int done = 0;
-    CK(hipMemcpyAsync(&done, s.alldone + ((j - 1) & 1), sizeof(int), hipMemcpyDeviceToHost, st));
-    CK(hipStreamSynchronize(st));
-    prof_flush(pb);
-    if (done || j > maxit + pb->check_every + 1) break;
+    const int slot = chunk & 1;
+    CK(hipMemcpyAsync(pb->hflag + slot, s.alldone + ((j - 1) & 1), sizeof(int), hipMemcpyDeviceToHost, st));
+    CK(hipEventRecord(pb->flag_ev[slot], st));
+    const bool over = j > maxit + 2 * pb->check_every + 1;
+    if (chunk > 0 || over) {
+      const int ws = over ? slot : 1 - slot;
+      CK(hipEventSynchronize(pb->flag_ev[ws]));
+      prof_flush(pb);
+      if (pb->hflag[ws] || over) break;
+    }
+    ++chunk;
   }
+  CK(hipStreamSynchronize(st));
+  prof_flush(pb);
   const int fp = (j - 1) & 1;
   MinresState hs[kRMax];
   CK(hipMemcpyAsync(hs, s.st + fp * kRMax, sizeof(MinresState) * kRMax, hipMemcpyDeviceToHost, st));
@@ -622,7 +759,7 @@ int true_residuals(stokes_problem* pb, Work& W, int precond, const double* b, co
   const int64_t n_u = pb->S.n_u, n = n_u + pb->S.n_p;
   double* r = (double*)W.q;
   double* out = pb->scratch;  // [0..2R) norms, [2R..4R) r M r parts, [4R..6R) b M b parts
-  CK(spmv_resid<double>(R, n, pb->rowptr, nullptr, pb->col, pb->val, x, b, r, pb->partials, pb->counter, out, st));
+  CK(spmv_resid<double>(R, pb->rs_full, pb->rowptr, nullptr, pb->col, pb->val, x, b, r, pb->partials, pb->counter, out, st));
   const int pcl = (precond == STOKES_PC_JACOBI) ? STOKES_PC_JACOBI : STOKES_PC_IC0;
   for (int pass = 0; pass < 2; ++pass) {
     const double* vec = pass == 0 ? r : b;
@@ -878,6 +1015,16 @@ static int stokes_setup_impl(int n, int p, int dim, double nu, stokes_problem* p
   pb->rowptr = m.upload(pb->P.rowptr, st);
   pb->col = m.upload(pb->P.col, st);
   pb->aend = m.upload(pb->P.aend, st);
+  {
+    const int64_t n_all = pb->S.n_u + pb->S.n_p;
+    const int nbf = row_split_blocks(n_all, pb->num_cu), nba = row_split_blocks(pb->S.n_u, pb->num_cu);
+    pb->split_full_h = balanced_row_split(pb->P.rowptr, nullptr, n_all, nbf);
+    pb->split_A_h = balanced_row_split(pb->P.rowptr, &pb->P.aend, pb->S.n_u, nba);
+    pb->rs_full.nb = nbf;
+    pb->rs_full.split = m.upload(pb->split_full_h, st);
+    pb->rs_A.nb = nba;
+    pb->rs_A.split = m.upload(pb->split_A_h, st);
+  }
   pb->val = m.get<double>(pb->nnz);
   pb->val32 = m.get<float>(pb->nnz);
   pb->diagQ = m.get<double>(pb->S.n_p);
@@ -1153,7 +1300,7 @@ int stokes_dnu_dot(stokes_problem* pb, int nrhs, const double* lam_u, const doub
   hipStream_t st = pb->stream;
   const int64_t n_u = pb->S.n_u;
   for (int c = 0; c < nrhs; ++c) {
-    CK(spmv_resid<double>(1, n_u, pb->rowptr, pb->aend, pb->col, pb->val, u + size_t(c) * n_u, nullptr,
+    CK(spmv_resid<double>(1, pb->rs_A, pb->rowptr, pb->aend, pb->col, pb->val, u + size_t(c) * n_u, nullptr,
                           (double*)W->q, pb->partials, pb->counter, nullptr, st));
     CK(dot<double, double>(1, 0, n_u, lam_u + size_t(c) * n_u, (const double*)W->q, pb->partials, pb->counter,
                            pb->scratch + c, st));
@@ -1168,7 +1315,7 @@ int stokes_dnu_dot(stokes_problem* pb, int nrhs, const double* lam_u, const doub
 int stokes_apply(stokes_problem* pb, const double* x, double* y) {
   if (!pb || !x || !y) return fail(pb, STOKES_EINVAL, "bad arguments to stokes_apply");
   const int64_t n = pb->S.n_u + pb->S.n_p;
-  CK(spmv_resid<double>(1, n, pb->rowptr, nullptr, pb->col, pb->val, x, nullptr, y, pb->partials, pb->counter, nullptr,
+  CK(spmv_resid<double>(1, pb->rs_full, pb->rowptr, nullptr, pb->col, pb->val, x, nullptr, y, pb->partials, pb->counter, nullptr,
                         pb->stream));
   CK(hipStreamSynchronize(pb->stream));
   return 0;

@@ -463,3 +463,39 @@ void strip_groups(const Spaces& S, int strip, std::vector<int32_t>& group_of, in
 }
 
 }  // namespace stk
+
+// ---------------------------------------------------------------------------
+// Row ranges for the CSR row kernels, balanced by work: a row costs its entries plus a
+// fixed amount for the per-row loads and stores (kRowCost entries' worth).
+// ---------------------------------------------------------------------------
+namespace stk {
+
+int row_split_blocks(int64_t nrows, int num_cu) {
+  const int64_t cap = (int64_t)kSpmvBlocksPerCU * std::max(1, num_cu);
+  int64_t nb = std::max<int64_t>(1, std::min<int64_t>(cap, (nrows + 15) / 16));
+  nb = std::min<int64_t>(nb, kVecMaxBlocks);
+  if (nb > 8) nb = nb / 8 * 8;
+  return (int)nb;
+}
+
+std::vector<int32_t> balanced_row_split(const std::vector<int32_t>& rowptr, const std::vector<int32_t>* rowend,
+                                        int64_t nrows, int nb) {
+  constexpr int64_t kRowCost = 16;
+  auto len = [&](int64_t i) -> int64_t { return (rowend ? (*rowend)[i] : rowptr[i + 1]) - rowptr[i]; };
+  int64_t total = 0;
+  for (int64_t i = 0; i < nrows; ++i) total += len(i) + kRowCost;
+  std::vector<int32_t> split(nb + 1, 0);
+  int64_t i = 0, acc = 0;
+  for (int b = 1; b < nb; ++b) {
+    const int64_t target = (total * b) / nb;
+    while (i < nrows && acc + len(i) + kRowCost <= target) {
+      acc += len(i) + kRowCost;
+      ++i;
+    }
+    split[b] = (int32_t)i;
+  }
+  split[nb] = (int32_t)nrows;
+  return split;
+}
+
+}  // namespace stk

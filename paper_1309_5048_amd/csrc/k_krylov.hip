@@ -27,34 +27,24 @@ namespace stk {
 // adjacent, so the vector entries that an XCD gathers stay in its own L2.
 // ---------------------------------------------------------------------------
 constexpr int kSG = 16;
-constexpr int kSpmvMaxBlocks = 4096;
-static_assert(kSpmvMaxBlocks <= kVecMaxBlocks, "block partials are sized for kVecMaxBlocks");
-
 template <int R>
-constexpr int spmv_unroll() { return R == 1 ? 4 : (R <= 8 ? 2 : 1); }
+constexpr int spmv_unroll() { return R == 1 ? 8 : (R <= 8 ? 2 : 1); }
 
 struct RowRange {
   int64_t begin, end;
 };
 
-__device__ __forceinline__ RowRange block_rows(int64_t nrows, int rows_per_pass) {
+// Rows of this block: the contiguous range split[b], split[b+1] (entries balanced on the
+// host).  Blocks are dispatched round-robin over the 8 XCDs, so with a multiple of 8 blocks
+// b is chosen such that the blocks of one XCD own adjacent ranges (their vector gathers
+// then share that XCD's L2).
+__device__ __forceinline__ RowRange block_rows(const int32_t* __restrict__ split) {
   const int nb = gridDim.x;
   const int b = (nb % 8 == 0) ? (int)(blockIdx.x % 8) * (nb / 8) + (int)(blockIdx.x / 8) : (int)blockIdx.x;
-  const int64_t passes = (nrows + rows_per_pass - 1) / rows_per_pass;
-  const int64_t per = (passes + nb - 1) / nb;
   RowRange r;
-  r.begin = std::min<int64_t>(nrows, (int64_t)b * per * rows_per_pass);
-  r.end = std::min<int64_t>(nrows, ((int64_t)b + 1) * per * rows_per_pass);
+  r.begin = split[b];
+  r.end = split[b + 1];
   return r;
-}
-
-// Grid of the row kernels: at most kSpmvMaxBlocks blocks, a multiple of 8 when above 8.
-inline int spmv_blocks(int64_t nrows) {
-  const int64_t passes = std::max<int64_t>(1, (nrows + kVT / kSG - 1) / (kVT / kSG));
-  const int64_t per = (passes + kSpmvMaxBlocks - 1) / kSpmvMaxBlocks;
-  int64_t nb = (passes + per - 1) / per;
-  if (nb > 8) nb = (nb + 7) / 8 * 8;
-  return (int)std::min<int64_t>(nb, kSpmvMaxBlocks);
 }
 
 // R consecutive values (the R interleaved columns of one vector row) with wide loads.
@@ -85,35 +75,39 @@ __device__ __forceinline__ void load_cols(const T* __restrict__ p, T (&v)[R]) {
 }
 
 // acc[c] = sum over k in [kb, ke) of val[k] * x[col[k] * R + c], in every lane of the group.
+// Dot products of one CSR row (entries kb..ke-1) with the R columns of x, spread over the
+// kSG lanes of a row group and summed over them.  Entries are taken U*kSG at a time with
+// every load issued before the first use: the index and value loads of all U entries, then
+// the U vector gathers.  Lanes past the row end load the row's last entry again (a cache
+// hit) and add nothing.
 template <int R, typename Acc, typename T>
 __device__ __forceinline__ void row_dot(int32_t kb, int32_t ke, int sub, const int32_t* __restrict__ col,
                                         const T* __restrict__ val, const T* __restrict__ x, Acc (&acc)[R]) {
   constexpr int U = spmv_unroll<R>();
 #pragma unroll
   for (int c = 0; c < R; ++c) acc[c] = Acc(0);
-  int32_t k = kb + sub;
-  for (; k + (U - 1) * kSG < ke; k += U * kSG) {
+  for (int32_t k0 = kb + sub; k0 < ke; k0 += U * kSG) {
     int32_t j[U];
     T a[U];
+    bool ok[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      j[u] = col[k + u * kSG];
-      a[u] = val[k + u * kSG];
+      const int32_t k = k0 + u * kSG;
+      ok[u] = k < ke;
+      const int32_t kc = ok[u] ? k : ke - 1;
+      j[u] = col[kc];
+      a[u] = val[kc];
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       T xv[R];
       load_cols<R>(x + (size_t)j[u] * R, xv);
 #pragma unroll
-      for (int c = 0; c < R; ++c) acc[c] = fma((Acc)a[u], (Acc)xv[c], acc[c]);
+      for (int c = 0; c < R; ++c) {
+        const Acc t = fma((Acc)a[u], (Acc)xv[c], acc[c]);
+        acc[c] = ok[u] ? t : acc[c];
+      }
     }
-  }
-  for (; k < ke; k += kSG) {
-    T xv[R];
-    load_cols<R>(x + (size_t)col[k] * R, xv);
-    const Acc a = (Acc)val[k];
-#pragma unroll
-    for (int c = 0; c < R; ++c) acc[c] = fma(a, (Acc)xv[c], acc[c]);
   }
 #pragma unroll
   for (int c = 0; c < R; ++c) acc[c] = group_sum<kSG>(acc[c]);
@@ -217,7 +211,7 @@ __global__ void k_mr_init_state(MrScalars s, double tol, int maxit) {
 // q = Acal z~_j / gamma_j and delta partials.
 // ---------------------------------------------------------------------------
 template <typename T, int R>
-__global__ __launch_bounds__(kVT) void k_mr_spmv(int64_t n, const int32_t* __restrict__ rowptr,
+__global__ __launch_bounds__(kVT) void k_mr_spmv(const int32_t* __restrict__ split, const int32_t* __restrict__ rowptr,
                                                  const int32_t* __restrict__ col, const T* __restrict__ val,
                                                  const T* __restrict__ z, T* __restrict__ q, MrScalars s, int p) {
   if (s.alldone[p]) return;
@@ -231,7 +225,7 @@ __global__ __launch_bounds__(kVT) void k_mr_spmv(int64_t n, const int32_t* __res
 #pragma unroll
   for (int c = 0; c < R; ++c) acc_d[c] = 0.0;
   const int sub = threadIdx.x & (kSG - 1);
-  const RowRange rr = block_rows(n, kVT / kSG);
+  const RowRange rr = block_rows(split);
   for (int64_t base = rr.begin; base < rr.end; base += kVT / kSG) {
     const int64_t i = base + threadIdx.x / kSG;
     const bool valid = i < rr.end;
@@ -405,7 +399,7 @@ __global__ __launch_bounds__(kVT) void k_mr_update(int64_t n, const T* __restric
 // ---------------------------------------------------------------------------
 // y = Acal x (all rows) or, with bvec, y = b - Acal x; optional partial sums of y.y and b.b
 template <typename T, int R>
-__global__ __launch_bounds__(kVT) void k_spmv_resid(int64_t nrows, const int32_t* __restrict__ rowptr,
+__global__ __launch_bounds__(kVT) void k_spmv_resid(const int32_t* __restrict__ split, const int32_t* __restrict__ rowptr,
                                                     const int32_t* __restrict__ rowend, const int32_t* __restrict__ col,
                                                     const T* __restrict__ val, const T* __restrict__ xin,
                                                     const T* __restrict__ bvec, T* __restrict__ y, double* partials,
@@ -414,7 +408,7 @@ __global__ __launch_bounds__(kVT) void k_spmv_resid(int64_t nrows, const int32_t
 #pragma unroll
   for (int c = 0; c < 2 * R; ++c) acc_d[c] = 0.0;
   const int sub = threadIdx.x & (kSG - 1);
-  const RowRange rr = block_rows(nrows, kVT / kSG);
+  const RowRange rr = block_rows(split);
   for (int64_t base = rr.begin; base < rr.end; base += kVT / kSG) {
     const int64_t i = base + threadIdx.x / kSG;
     const bool valid = i < rr.end;
@@ -556,7 +550,7 @@ __global__ __launch_bounds__(kVT) void k_pcg_init2(int64_t n_u, const T* __restr
 
 // q = A p (velocity rows, A part of the saddle CSR) and p.q partials
 template <typename T, int R>
-__global__ __launch_bounds__(kVT) void k_pcg_spmv(int64_t n_u, const int32_t* __restrict__ rowptr,
+__global__ __launch_bounds__(kVT) void k_pcg_spmv(const int32_t* __restrict__ split, const int32_t* __restrict__ rowptr,
                                                   const int32_t* __restrict__ aend, const int32_t* __restrict__ col,
                                                   const T* __restrict__ val, const T* __restrict__ pv, T* __restrict__ q,
                                                   PcgScalars s) {
@@ -565,7 +559,7 @@ __global__ __launch_bounds__(kVT) void k_pcg_spmv(int64_t n_u, const int32_t* __
 #pragma unroll
   for (int c = 0; c < R; ++c) acc_d[c] = 0.0;
   const int sub = threadIdx.x & (kSG - 1);
-  const RowRange rr = block_rows(n_u, kVT / kSG);
+  const RowRange rr = block_rows(split);
   for (int64_t base = rr.begin; base < rr.end; base += kVT / kSG) {
     const int64_t i = base + threadIdx.x / kSG;
     const bool valid = i < rr.end;
@@ -675,10 +669,10 @@ hipError_t mr_init_state(int R, const MrScalars& s, double tol, int maxit, hipSt
 }
 
 template <typename T>
-hipError_t mr_spmv(int R, int64_t n, const int32_t* rowptr, const int32_t* col, const T* val, const T* z, T* q,
+hipError_t mr_spmv(int R, const RowSplit& rs, const int32_t* rowptr, const int32_t* col, const T* val, const T* z, T* q,
                    const MrScalars& s, int p, hipStream_t st) {
-  const int nb = spmv_blocks(n);
-  STK_R_SWITCH(R, hipLaunchKernelGGL((k_mr_spmv<T, RR>), dim3(nb), dim3(kVT), 0, st, n, rowptr, col, val, z, q, s, p));
+  STK_R_SWITCH(R, hipLaunchKernelGGL((k_mr_spmv<T, RR>), dim3(rs.nb), dim3(kVT), 0, st, rs.split, rowptr, col, val, z,
+                                     q, s, p));
   return hipGetLastError();
 }
 
@@ -699,12 +693,11 @@ hipError_t mr_update(int R, int64_t n, const T* z, const T* w, T* wprev_new, T* 
 }
 
 template <typename T>
-hipError_t spmv_resid(int R, int64_t nrows, const int32_t* rowptr, const int32_t* rowend, const int32_t* col,
+hipError_t spmv_resid(int R, const RowSplit& rs, const int32_t* rowptr, const int32_t* rowend, const int32_t* col,
                       const T* val, const T* x, const T* b, T* y, double* partials, unsigned int* counter, double* out,
                       hipStream_t st) {
-  const int nb = spmv_blocks(nrows);
-  STK_R_SWITCH(R, hipLaunchKernelGGL((k_spmv_resid<T, RR>), dim3(nb), dim3(kVT), 0, st, nrows, rowptr, rowend, col, val,
-                                     x, b, y, partials, counter, out));
+  STK_R_SWITCH(R, hipLaunchKernelGGL((k_spmv_resid<T, RR>), dim3(rs.nb), dim3(kVT), 0, st, rs.split, rowptr, rowend,
+                                     col, val, x, b, y, partials, counter, out));
   return hipGetLastError();
 }
 
@@ -770,11 +763,10 @@ hipError_t pcg_init2(int R, int64_t n_u, const T* z, T* pv, const PcgScalars& s,
 }
 
 template <typename T>
-hipError_t pcg_spmv(int R, int64_t n_u, const int32_t* rowptr, const int32_t* aend, const int32_t* col, const T* val,
-                    const T* pv, T* q, const PcgScalars& s, hipStream_t st) {
-  const int nb = spmv_blocks(n_u);
-  STK_R_SWITCH(R, hipLaunchKernelGGL((k_pcg_spmv<T, RR>), dim3(nb), dim3(kVT), 0, st, n_u, rowptr, aend, col, val, pv, q,
-                                     s));
+hipError_t pcg_spmv(int R, const RowSplit& rs, const int32_t* rowptr, const int32_t* aend, const int32_t* col,
+                    const T* val, const T* pv, T* q, const PcgScalars& s, hipStream_t st) {
+  STK_R_SWITCH(R, hipLaunchKernelGGL((k_pcg_spmv<T, RR>), dim3(rs.nb), dim3(kVT), 0, st, rs.split, rowptr, aend, col,
+                                     val, pv, q, s));
   return hipGetLastError();
 }
 
@@ -797,19 +789,19 @@ hipError_t pcg_pupdate(int R, int64_t n_u, const T* z, T* pv, const PcgScalars& 
 #define STK_INST(T)                                                                                                   \
   template hipError_t mr_init_vec<T>(int, int64_t, int64_t, const T*, T*, T*, T*, T*, T*, T*, const double*,         \
                                      const double*, double, const MrScalars&, hipStream_t);                          \
-  template hipError_t mr_spmv<T>(int, int64_t, const int32_t*, const int32_t*, const T*, const T*, T*,               \
+  template hipError_t mr_spmv<T>(int, const RowSplit&, const int32_t*, const int32_t*, const T*, const T*, T*,      \
                                  const MrScalars&, int, hipStream_t);                                               \
   template hipError_t mr_lanczos<T>(int, int64_t, int64_t, const T*, const T*, T*, T*, const double*, const double*,  \
                                     double, const MrScalars&, int, hipStream_t);                                     \
   template hipError_t mr_update<T>(int, int64_t, const T*, const T*, T*, T*, const MrScalars&, int, hipStream_t);    \
-  template hipError_t spmv_resid<T>(int, int64_t, const int32_t*, const int32_t*, const int32_t*, const T*, const T*, \
-                                    const T*, T*, double*, unsigned int*, double*, hipStream_t);                     \
+  template hipError_t spmv_resid<T>(int, const RowSplit&, const int32_t*, const int32_t*, const int32_t*, const T*,  \
+                                    const T*, const T*, T*, double*, unsigned int*, double*, hipStream_t);           \
   template hipError_t sub_mean<T>(int, int64_t, int64_t, T*, const double*, double, hipStream_t);                    \
   template hipError_t pcg_init<T>(int, int64_t, const T*, T*, T*, const PcgScalars&, const int*, hipStream_t);       \
   template hipError_t pcg_init2<T>(int, int64_t, const T*, T*, const PcgScalars&, double, int, const int*,           \
                                    const MinresState*, hipStream_t);                                                 \
-  template hipError_t pcg_spmv<T>(int, int64_t, const int32_t*, const int32_t*, const int32_t*, const T*, const T*,  \
-                                  T*, const PcgScalars&, hipStream_t);                                               \
+  template hipError_t pcg_spmv<T>(int, const RowSplit&, const int32_t*, const int32_t*, const int32_t*, const T*,    \
+                                  const T*, T*, const PcgScalars&, hipStream_t);                                     \
   template hipError_t pcg_axpy<T>(int, int64_t, const T*, const T*, T*, T*, const PcgScalars&, int, hipStream_t);    \
   template hipError_t pcg_pupdate<T>(int, int64_t, const T*, T*, const PcgScalars&, int, hipStream_t);
 STK_INST(double)

@@ -2,8 +2,8 @@
 // the latency-bound step of the velocity preconditioner (IC(0) of A, Sec. 6.4 of the
 // paper).
 //
-// One cooperative workgroup per group of rows (a spatial strip of one velocity
-// component).  Two wavefronts with separate jobs, synchronised through LDS counters:
+// One workgroup per group of rows (a spatial strip of one velocity component); all
+// groups are resident at once.  Two wavefronts with separate jobs, synchronised through LDS counters:
 //   wave 0 (compute): walks the group's steps (rows of one dependency level), gathers
 //          dependency values from LDS slots, reduces over kTrsvG lanes per row with DPP,
 //          keeps the result in its LDS slot and stores it to global memory (device
@@ -164,6 +164,64 @@ struct Vec16<float> {
   static constexpr int n = 4;
 };
 
+// Halo wavefront: entries are staged in order; lane j of a round watches entry pos + j.
+// An entry is ready when its R values are no longer the sentinel and the compute wave has
+// finished the steps that still read the slot's previous occupant.
+template <typename T, int R>
+__device__ __forceinline__ void halo_wave(const int32_t* __restrict__ grp_halo_ptr, const int32_t* __restrict__ halo_row,
+                                          const int32_t* __restrict__ halo_slot,
+                                          const int32_t* __restrict__ halo_free, int nrows, int nslots, int ld,
+                                          int* err, int g, int lane, int* ctr, T* xs, const T* out) {
+  const int h0 = grp_halo_ptr[g], h1 = grp_halo_ptr[g + 1];
+  const int nhalo = h1 - h0;
+  int pos = 0;
+  long spins = 0;
+  while (pos < nhalo) {
+    const int idx = pos + lane;
+    const bool valid = idx < nhalo;
+    int row = -1, slot = 0, fr = 0;
+    if (valid) {
+      row = halo_row[h0 + idx];
+      slot = halo_slot[h0 + idx];
+      fr = halo_free[h0 + idx];
+    }
+    const bool inb = valid && row >= 0 && row < nrows && slot > 0 && slot < nslots;
+    T v[R];
+    bool ready = true;
+    if (inb) {
+#pragma unroll
+      for (int c = 0; c < R; ++c) {
+        v[c] = dev_load(out + (size_t)row * ld + c);
+        ready = ready && !is_sentinel(v[c]);
+      }
+      ready = ready && lds_load(&ctr[CTR_COMPUTED]) >= fr;
+    }
+    const unsigned long long notready = __ballot(!ready);
+    int count = notready ? __ffsll((long long)notready) - 1 : 64;
+    count = min(count, nhalo - pos);
+    if (count == 0) {
+      ++spins;
+      if ((spins & 63) == 0 && (spins > (kSpinLimit >> 6) || err_set(err) || lds_load(&ctr[CTR_ERR]) != 0)) {
+        if (spins > (kSpinLimit >> 6)) raise_err(err);
+        if (lane == 0) {
+          lds_signal(&ctr[CTR_ERR], 1);
+          lds_signal(&ctr[CTR_HALO], nhalo);
+        }
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    if (lane < count && inb) {
+      T* xp = xs + (size_t)slot * R;
+#pragma unroll
+      for (int c = 0; c < R; ++c) xp[c] = v[c];
+    }
+    pos += count;
+    if (lane == 0) lds_signal(&ctr[CTR_HALO], pos);
+  }
+}
+
 template <typename T, int R, int EP, int D>
 __global__ __launch_bounds__(kTrsvThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_trsv(
     TrsvArgs a, const T* __restrict__ sval, const typename RowRec<T>::type* __restrict__ srinfo,
@@ -184,9 +242,6 @@ __global__ __launch_bounds__(kTrsvThreads) __attribute__((amdgpu_waves_per_eu(1,
   const int lane = tid & 63;
   const int s0 = a.grp_step_ptr[g], s1 = a.grp_step_ptr[g + 1];
   const int nsteps = s1 - s0;
-  const int h0 = a.grp_halo_ptr[g], h1 = a.grp_halo_ptr[g + 1];
-  const int nhalo = h1 - h0;
-
   if (tid < 16) ctr[tid] = 0;
   if (tid < R) xs[tid] = T(0);  // slot 0: the zero slot read by padding entries
   __syncthreads();
@@ -336,55 +391,8 @@ __global__ __launch_bounds__(kTrsvThreads) __attribute__((amdgpu_waves_per_eu(1,
     }
   } else {
     // ------------------------------- halo wave --------------------------------
-    // Entries are staged in order; lane j of a round watches entry pos + j.  An entry is
-    // ready when its R values are no longer the sentinel and the compute wave has
-    // finished the steps that still read the slot's previous occupant.
-    int pos = 0;
-    long spins = 0;
-    while (pos < nhalo) {
-      const int idx = pos + lane;
-      const bool valid = idx < nhalo;
-      int row = -1, slot = 0, fr = 0;
-      if (valid) {
-        row = a.halo_row[h0 + idx];
-        slot = a.halo_slot[h0 + idx];
-        fr = a.halo_free[h0 + idx];
-      }
-      const bool inb = valid && row >= 0 && row < a.nrows && slot > 0 && slot < a.nslots;
-      T v[R];
-      bool ready = true;
-      if (inb) {
-#pragma unroll
-        for (int c = 0; c < R; ++c) {
-          v[c] = dev_load(out + (size_t)row * a.ld + c);
-          ready = ready && !is_sentinel(v[c]);
-        }
-        ready = ready && lds_load(&ctr[CTR_COMPUTED]) >= fr;
-      }
-      const unsigned long long notready = __ballot(!ready);
-      int count = notready ? __ffsll((long long)notready) - 1 : 64;
-      count = min(count, nhalo - pos);
-      if (count == 0) {
-        ++spins;
-        if ((spins & 63) == 0 && (spins > (kSpinLimit >> 6) || err_set(a.err) || lds_load(&ctr[CTR_ERR]) != 0)) {
-          if (spins > (kSpinLimit >> 6)) raise_err(a.err);
-          if (lane == 0) {
-            lds_signal(&ctr[CTR_ERR], 1);
-            lds_signal(&ctr[CTR_HALO], nhalo);
-          }
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-        continue;
-      }
-      if (lane < count && inb) {
-        T* xp = xs + (size_t)slot * R;
-#pragma unroll
-        for (int c = 0; c < R; ++c) xp[c] = v[c];
-      }
-      pos += count;
-      if (lane == 0) lds_signal(&ctr[CTR_HALO], pos);
-    }
+    halo_wave<T, R>(a.grp_halo_ptr, a.halo_row, a.halo_slot, a.halo_free, a.nrows, a.nslots, a.ld, a.err, g, lane,
+                    ctr, xs, out);
   }
   __syncthreads();
   if (tid == 0 && lds_load(&ctr[CTR_ERR]) != 0) raise_err(a.err);
@@ -413,6 +421,330 @@ __global__ __launch_bounds__(kTrsvThreads) __attribute__((amdgpu_waves_per_eu(1,
       }
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Single-column solve on the per-group block layout (one right-hand side, contiguous
+// vectors).  Same protocol as k_trsv with R = 1; the compute wave's step is trimmed to
+// what the arithmetic needs: every record of a step is read relative to one scalar block
+// address (row records, step header, LDS byte addresses and factor values) plus the
+// per-solve {rhs, dot} pair, the gathers use the stored LDS byte addresses as they are,
+// padding rows and tail steps repeat real ones (no per-step branches), and a single wait
+// covers the step's gathers.
+// ---------------------------------------------------------------------------
+struct FastArgs {
+  const int32_t* grp_step_ptr;
+  const int32_t* grp_npad;
+  const int32_t* grp_ep;
+  const int64_t* grp_blk;
+  const unsigned char* blk;
+  const int32_t* grp_halo_ptr;
+  const int32_t* halo_row;
+  const int32_t* halo_slot;
+  const int32_t* halo_free;
+  unsigned int* done_count;
+  int* err;
+  double* partials;
+  int ngroups;
+  int nslots;
+  int nrows;
+};
+
+template <typename T>
+struct FastDyn {
+  T rhs, dot;
+};
+template <typename T>
+struct FastRec;
+template <>
+struct FastRec<double> {
+  using type = FastRec64;
+};
+template <>
+struct FastRec<float> {
+  using type = FastRec32;
+};
+
+// Buffer resources (raw, byte-addressed, bounds-checked against num_records) let every load
+// of a step take its per-step part from one scalar offset and its per-lane part from a
+// register computed once.
+constexpr int kBufferFlags = 0x00020000;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr int kStoreSc1 = 16;  // cache policy of device-scope stores (visible across the XCDs)
+constexpr int kWaitLgkm0 = 0xC07F;  // s_waitcnt lgkmcnt(0), no vmcnt / expcnt wait (gfx9 encoding)
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, (int)bytes, kBufferFlags);
+}
+
+// LDS access by byte address: dynamic shared memory starts at LDS address 0 in these
+// kernels (they declare no static shared memory; checked at kernel entry).
+template <typename T>
+__device__ __forceinline__ T lds_at(uint32_t addr) {
+  return *reinterpret_cast<const __attribute__((address_space(3))) T*>((size_t)addr);
+}
+template <typename T>
+__device__ __forceinline__ void lds_put(uint32_t addr, T v) {
+  *reinterpret_cast<__attribute__((address_space(3))) T*>((size_t)addr) = v;
+}
+
+// Group metadata loaded through vector loads is not known to be uniform: move it to
+// scalar registers (the buffer resources built from it must live there).
+__device__ __forceinline__ int uniform32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(v & 0xffffffff));
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+template <typename T>
+__device__ __forceinline__ T from_bits2(u32x2 b) {
+  return __builtin_bit_cast(T, b);
+}
+
+template <typename T, int EP, int D, bool kDot>
+__device__ __forceinline__ double fast_compute(const FastArgs& a, const FastDyn<T>* __restrict__ dyn,
+                                               T* __restrict__ out, unsigned char* smem, int g, int lane) {
+  using Rec = typename FastRec<T>::type;
+  constexpr int SB = fast_block_bytes<T>(EP);
+  constexpr int OFF_SLOT = kFastHdr;
+  constexpr int OFF_VAL = kFastHdr + 64 * EP * 4;
+  constexpr int NVL = EP * (int)sizeof(T) / 16;  // 16-byte loads of values per lane and step
+  constexpr int DYN = kTrsvRPS * (int)sizeof(FastDyn<T>);
+  int* ctr = reinterpret_cast<int*>(smem);
+  const int s0 = uniform32(a.grp_step_ptr[g]);
+  const int nalloc = uniform32(a.grp_step_ptr[g + 1]) - s0;
+  const int npad = uniform32(a.grp_npad[g]);
+  const int64_t b0 = uniform64(a.grp_blk[g]), b1 = uniform64(a.grp_blk[g + 1]);
+  const __amdgpu_buffer_rsrc_t rb = make_rsrc(a.blk + b0, (uint32_t)(b1 - b0));
+  const __amdgpu_buffer_rsrc_t rd = make_rsrc(dyn + (size_t)s0 * kTrsvRPS, (uint32_t)nalloc * DYN);
+  const __amdgpu_buffer_rsrc_t ro = make_rsrc(out, (uint32_t)a.nrows * (uint32_t)sizeof(T));
+  const int r = lane / kTrsvG;
+  const uint32_t o_rec = (uint32_t)r * 16u;
+  const uint32_t o_slot = (uint32_t)(OFF_SLOT + lane * EP * 4);
+  const uint32_t o_val = (uint32_t)(OFF_VAL + lane * EP * (int)sizeof(T));
+  const uint32_t o_dyn = (uint32_t)r * (uint32_t)sizeof(FastDyn<T>);
+  u32x4 pv[D][NVL];
+  u32x4 ps[D][EP / 4];
+  u32x4 prc[D];
+  unsigned pnd[D];
+  FastDyn<T> pdy[D];
+  auto load = [&](int d, int j) {
+    const int sb = j * SB, sd = j * DYN;
+#pragma unroll
+    for (int k = 0; k < NVL; ++k) pv[d][k] = __builtin_amdgcn_raw_buffer_load_b128(rb, o_val + 16 * k, sb, 0);
+#pragma unroll
+    for (int k = 0; k < EP / 4; ++k) ps[d][k] = __builtin_amdgcn_raw_buffer_load_b128(rb, o_slot + 16 * k, sb, 0);
+    prc[d] = __builtin_amdgcn_raw_buffer_load_b128(rb, o_rec, sb, 0);
+    pnd[d] = __builtin_amdgcn_raw_buffer_load_b32(rb, kTrsvRPS * 16, sb, 0);
+    if constexpr (sizeof(T) == 8) {
+      const u32x4 t = __builtin_amdgcn_raw_buffer_load_b128(rd, o_dyn, sd, 0);
+      pdy[d].rhs = from_bits2<T>(t.xy);
+      pdy[d].dot = from_bits2<T>(t.zw);
+    } else {
+      const u32x2 t = __builtin_amdgcn_raw_buffer_load_b64(rd, o_dyn, sd, 0);
+      const unsigned w0 = t.x, w1 = t.y;  // components copied out first (see below)
+      pdy[d].rhs = __builtin_bit_cast(T, w0);
+      pdy[d].dot = __builtin_bit_cast(T, w1);
+    }
+  };
+  double dacc = 0.0;
+  int halo_seen = 0;
+  if (npad > 0) {
+#pragma unroll
+    for (int d = 0; d + 1 < D; ++d) {
+      load(d, d);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    int j = 0;
+    do {
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const int jj = j + d;
+        const int need = __builtin_amdgcn_readfirstlane((int)pnd[d]);
+        if (need > halo_seen)
+          halo_seen = __builtin_amdgcn_readfirstlane(
+              lds_wait<false, false>(&ctr[CTR_HALO], need, &ctr[CTR_ERR], a.err));
+        T xv[EP];
+#pragma unroll
+        for (int e = 0; e < EP; ++e) xv[e] = lds_at<T>(ps[d][e / 4][e % 4]);
+        __builtin_amdgcn_sched_barrier(0);
+        load((d + D - 1) % D, jj + D - 1);
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_waitcnt(kWaitLgkm0);  // one wait for all gathers
+        __builtin_amdgcn_sched_barrier(0);
+        T acc = T(0), acc2 = T(0);
+#pragma unroll
+        for (int e = 0; e < EP; ++e) {
+          T v;
+          if constexpr (sizeof(T) == 8) {
+            const u32x4 w = pv[d][e / 2];
+            v = from_bits2<T>((e & 1) ? w.zw : w.xy);
+          } else {
+            // copy the component out first: clang's bit cast of a vector component
+            // expression reads component 0 whatever the index
+            const unsigned w = pv[d][e / 4][e % 4];
+            v = __builtin_bit_cast(T, w);
+          }
+          if (e & 1)
+            acc2 = fma(v, xv[e], acc2);
+          else
+            acc = fma(v, xv[e], acc);
+        }
+        const Rec rec = __builtin_bit_cast(Rec, prc[d]);
+        const T res = (pdy[d].rhs - octet_sum(acc + acc2)) * rec.dinv;
+        if constexpr (sizeof(T) == 8)
+          __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, res), ro, (uint32_t)rec.row_byte, 0,
+                                                kStoreSc1);
+        else
+          __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, res), ro, (uint32_t)rec.row_byte, 0,
+                                                kStoreSc1);
+        if (kDot) dacc = fma((double)res, (double)pdy[d].dot, dacc);
+        lds_put<T>((uint32_t)rec.slot_byte, res);
+        lds_signal(&ctr[CTR_COMPUTED], jj + 1);
+      }
+      j += D;
+    } while (j < npad);
+  }
+  return dacc;
+}
+
+template <typename T, bool kDot>
+__global__ __launch_bounds__(kTrsvThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_trsv_fast(
+    FastArgs a, const FastDyn<T>* __restrict__ dyn, T* __restrict__ out, double* __restrict__ dot_out,
+    const int* __restrict__ skip) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  if (skip != nullptr && *skip) return;
+  int* ctr = reinterpret_cast<int*>(smem);
+  T* xs = reinterpret_cast<T*>(smem + 64);
+  const int g = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int wid = tid >> 6;
+  const int lane = tid & 63;
+  if ((uint32_t)(size_t)(__attribute__((address_space(3))) void*)smem != 0u) {  // see lds_at
+    if (tid == 0) raise_err(a.err);
+    return;
+  }
+  if (tid < 16) ctr[tid] = 0;
+  if (tid == 0) xs[0] = T(0);  // slot 0: the zero slot read by padding entries
+  __syncthreads();
+  double dacc = 0.0;
+  if (wid == 0) {
+    if (uniform32(a.grp_ep[g]) == 4)
+      dacc = fast_compute<T, 4, fast_depth(4), kDot>(a, dyn, out, smem, g, lane);
+    else
+      dacc = fast_compute<T, 8, fast_depth(8), kDot>(a, dyn, out, smem, g, lane);
+  } else {
+    halo_wave<T, 1>(a.grp_halo_ptr, a.halo_row, a.halo_slot, a.halo_free, a.nrows, a.nslots, 1, a.err, g, lane, ctr,
+                    xs, out);
+  }
+  __syncthreads();
+  if (tid == 0 && lds_load(&ctr[CTR_ERR]) != 0) raise_err(a.err);
+  if (kDot && wid == 0) {
+    // every lane of an octet accumulated its row: the wave sum counts each row 8 times
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) dacc += __shfl_xor(dacc, off, 64);
+    dacc *= 1.0 / kTrsvG;
+    if (lane == 0) {
+      dev_store(a.partials + g, dacc);
+      wait_vm_stores();
+      const unsigned int prev = __hip_atomic_fetch_add(a.done_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (prev == (unsigned int)(a.ngroups - 1)) {
+        double v = 0.0;
+        for (int k = 0; k < a.ngroups; ++k) v += dev_load(a.partials + k);
+        dot_out[0] = v;
+        __hip_atomic_store(a.done_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+  }
+}
+
+// Per-solve {rhs, dot} pairs in the single-column step order (repeats carry dot = 0) and
+// the output rows reset to the sentinel.
+template <typename T>
+__global__ void k_fast_gather_dyn(int64_t nrow_slots, const int32_t* __restrict__ srow2, const T* __restrict__ rhs,
+                                  const T* __restrict__ dotv, FastDyn<T>* __restrict__ dyn, T* __restrict__ out,
+                                  const int* __restrict__ skip) {
+  if (skip != nullptr && *skip) return;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nrow_slots;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const int r2 = srow2[k];
+    const int row = r2 >= 0 ? r2 : ~r2;
+    FastDyn<T> v;
+    v.rhs = rhs[row];
+    v.dot = (r2 >= 0 && dotv != nullptr) ? dotv[row] : T(0);
+    dyn[k] = v;
+    if (r2 >= 0) out[row] = sentinel_value<T>();
+  }
+}
+
+// Factor values and reciprocal diagonals into the single-column blocks (both precisions):
+// one thread per (step, lane).
+__global__ void k_fast_gather_static(int64_t nsteps, const int64_t* __restrict__ step_val64,
+                                     const int64_t* __restrict__ step_val32, const int32_t* __restrict__ step_ep,
+                                     const int32_t* __restrict__ vperm, const int32_t* __restrict__ dsrc,
+                                     const double* __restrict__ Lval, unsigned char* __restrict__ blk64,
+                                     unsigned char* __restrict__ blk32) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nsteps * 64;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = t / 64;
+    const int lane = int(t % 64);
+    const int ep = step_ep[s];
+    double* v64 = reinterpret_cast<double*>(blk64 + step_val64[s]) + lane * ep;
+    float* v32 = reinterpret_cast<float*>(blk32 + step_val32[s]) + lane * ep;
+    for (int e = 0; e < ep; ++e) {
+      const int32_t p = vperm[(s * 64 + lane) * 8 + e];
+      const double v = p >= 0 ? Lval[p] : 0.0;
+      v64[e] = v;
+      v32[e] = (float)v;
+    }
+    if (lane < kTrsvRPS) {
+      const int32_t p = dsrc[s * kTrsvRPS + lane];
+      FastRec64* r64 = reinterpret_cast<FastRec64*>(blk64 + step_val64[s] - (kFastHdr + 64 * ep * 4)) + lane;
+      FastRec32* r32 = reinterpret_cast<FastRec32*>(blk32 + step_val32[s] - (kFastHdr + 64 * ep * 4)) + lane;
+      r64->dinv = p >= 0 ? 1.0 / Lval[p] : 0.0;
+      r32->dinv = p >= 0 ? 1.0f / (float)Lval[p] : 0.0f;
+    }
+  }
+}
+
+template <typename T, int R>
+size_t trsv_shmem_t(int nslots);
+
+template <typename T>
+static hipError_t launch_trsv_fast(const TrsvSchedDev& S, const T* rhs, T* out, const T* dotv, double* dot_out,
+                                   const int* skip, hipStream_t st, const TrsvTiming* tm) {
+  const TrsvFastDev& F = S.fast;
+  FastArgs a;
+  a.grp_step_ptr = F.grp_step_ptr;
+  a.grp_npad = F.grp_npad;
+  a.grp_ep = F.grp_ep;
+  a.grp_blk = sizeof(T) == 8 ? F.grp_blk64 : F.grp_blk32;
+  a.blk = sizeof(T) == 8 ? F.blk64 : F.blk32;
+  a.grp_halo_ptr = S.grp_halo_ptr;
+  a.halo_row = S.halo_row;
+  a.halo_slot = S.halo_slot;
+  a.halo_free = S.halo_free;
+  a.done_count = S.done_count;
+  a.err = S.err;
+  a.partials = S.partials;
+  a.ngroups = S.ngroups;
+  a.nslots = S.nslots;
+  a.nrows = S.nrows;
+  FastDyn<T>* dyn = reinterpret_cast<FastDyn<T>*>(F.dyn);
+  hipLaunchKernelGGL(k_fast_gather_dyn<T>, dim3(1024), dim3(256), 0, st, (int64_t)F.nsteps * kTrsvRPS, F.srow2, rhs,
+                     dotv, dyn, out, skip);
+  const size_t shmem = trsv_shmem_t<T, 1>(S.nslots);
+  const void* fn = dotv != nullptr ? (const void*)k_trsv_fast<T, true> : (const void*)k_trsv_fast<T, false>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+  if (e != hipSuccess) return e;
+  const FastDyn<T>* dync = dyn;
+  void* args[] = {&a, &dync, &out, &dot_out, &skip};
+  if (tm && tm->before) (void)hipEventRecord(tm->before, st);
+  e = hipLaunchKernel(fn, dim3(S.ngroups), dim3(kTrsvThreads), args, shmem, st);
+  if (tm && tm->after) (void)hipEventRecord(tm->after, st);
+  return e;
 }
 
 // Per-solve gather into schedule order, rd_s[(step*RPS + r)*2R + c] = rhs[row*ld + c] and
@@ -489,7 +821,10 @@ static hipError_t launch_trsv_t(const TrsvSchedDev& S, const T* sval, const type
   int with_dot = dotv != nullptr ? 1 : 0;
   void* args[] = {&a, &sval, &srinfo, &rd_sc, &out, &dummy, &with_dot, &dot_out, &skip};
   if (tm && tm->before) (void)hipEventRecord(tm->before, st);
-  e = hipLaunchCooperativeKernel((const void*)fn, dim3(S.ngroups), dim3(kTrsvThreads), args, (unsigned)shmem, st);
+  // An ordinary launch: the host has checked that every group fits on the chip at once,
+  // so all groups are dispatched together (a cooperative launch adds tens of microseconds
+  // of queue synchronisation around the kernel and is not needed for that).
+  e = hipLaunchKernel((const void*)fn, dim3(S.ngroups), dim3(kTrsvThreads), args, shmem, st);
   if (tm && tm->after) (void)hipEventRecord(tm->after, st);
   return e;
 }
@@ -546,6 +881,11 @@ static hipError_t launch_trsv_p(const TrsvSchedDev& S, const T* sval, const type
 
 hipError_t launch_trsv(const TrsvSchedDev& S, bool fp32, int R, const void* rhs, void* out, const void* dotv,
                        double* dot_out, const int* skip, hipStream_t st, const TrsvTiming* tm) {
+  if (R == 1 && S.fast.ok) {
+    if (fp32)
+      return launch_trsv_fast<float>(S, (const float*)rhs, (float*)out, (const float*)dotv, dot_out, skip, st, tm);
+    return launch_trsv_fast<double>(S, (const double*)rhs, (double*)out, (const double*)dotv, dot_out, skip, st, tm);
+  }
   if (fp32)
     return launch_trsv_p<float>(S, S.sval32, S.srinfo32, R, (const float*)rhs, (float*)out, (const float*)dotv,
                                 dot_out, skip, st, tm);
@@ -578,6 +918,9 @@ hipError_t launch_trsv_gather(const TrsvSchedDev& S, const double* Lval, hipStre
   const int64_t nd = (int64_t)S.nsteps * kTrsvRPS;
   hipLaunchKernelGGL(k_trsv_gather, dim3(1024), dim3(256), 0, st, S.vperm, ne, Lval, S.sval, S.sval32);
   hipLaunchKernelGGL(k_trsv_gather_dinv, dim3(256), dim3(256), 0, st, S.dsrc, nd, Lval, S.srinfo, S.srinfo32);
+  if (S.fast.ok)
+    hipLaunchKernelGGL(k_fast_gather_static, dim3(1024), dim3(256), 0, st, (int64_t)S.fast.nsteps, S.fast.step_val64,
+                       S.fast.step_val32, S.fast.step_ep, S.fast.vperm, S.fast.dsrc, Lval, S.fast.blk64, S.fast.blk32);
   return hipGetLastError();
 }
 

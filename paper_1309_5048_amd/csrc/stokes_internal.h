@@ -47,7 +47,7 @@ void build_lower_pattern(const Spaces& S, const SaddlePattern& P, LowerPattern& 
 
 // ---------------------------------------------------------------------------
 // Triangular-solve schedule (one direction).  Rows are split into groups (one
-// cooperative workgroup each).  Inside a group the rows are processed in
+// workgroup each, all resident together).  Inside a group the rows are processed in
 // dependency-level order in "steps" of at most kTrsvRPS rows of one level; the
 // dependencies of a row are spread over kTrsvG lanes, E per lane.  Every dependency
 // value is read from an LDS slot.  Slots are assigned by value lifetime (interval
@@ -103,6 +103,57 @@ struct TrsvStep {
   int32_t pad;
 };
 
+// Single-column layout of a schedule (the launch of one right-hand side with a contiguous
+// vector).  Each group has its own entries per lane, EP = 4 or 8 (the group's largest row
+// over kTrsvG lanes), and its steps are stored as one block each, read with a single
+// scalar base per step:
+//   [kTrsvRPS row records (16 bytes)][step header: halo prefix needed (16 bytes)]
+//   [64 lanes x EP LDS byte addresses (uint32)][64 lanes x EP factor values]
+// A row record holds the reciprocal diagonal, the LDS byte address of the row's result
+// slot and the row's byte offset in the output vector.  Steps with fewer than kTrsvRPS
+// rows repeat their first row (the same arithmetic on the same data, so the repeated
+// stores are identical), and every group is padded to a multiple of its prefetch depth
+// with repeats of its last step; repeats add nothing to the fused dot product.  The
+// per-solve right-hand side and dot-vector entries sit in a separate array of the same
+// step order.
+constexpr int kFastHdr = kTrsvRPS * 16 + 16;
+template <typename T>
+constexpr int fast_block_bytes(int ep) {
+  return kFastHdr + 64 * ep * (4 + (int)sizeof(T));
+}
+constexpr int fast_depth(int ep) { return ep == 4 ? 9 : 7; }  // register buffers of prefetched steps
+
+struct FastRec64 {
+  double dinv;
+  int32_t slot_byte;
+  int32_t row_byte;
+};
+struct FastRec32 {
+  float dinv;
+  int32_t slot_byte;
+  int32_t row_byte;
+  int32_t pad;
+};
+
+struct TrsvFastDev {
+  bool ok = false;
+  int nsteps = 0;                  // allocated steps (with padding and prefetch tail)
+  int32_t* grp_step_ptr = nullptr; // [ngroups+1] allocated step ranges
+  int32_t* grp_npad = nullptr;     // [ngroups] executed steps (multiple of the group's depth)
+  int32_t* grp_ep = nullptr;       // [ngroups] 4 or 8
+  int64_t* grp_blk64 = nullptr;    // [ngroups+1] byte offset of the group's first block
+  int64_t* grp_blk32 = nullptr;
+  unsigned char* blk64 = nullptr;
+  unsigned char* blk32 = nullptr;
+  int64_t* step_val64 = nullptr;   // [nsteps] byte offset of each step's values (FP64 blocks)
+  int64_t* step_val32 = nullptr;
+  int32_t* step_ep = nullptr;      // [nsteps]
+  int32_t* vperm = nullptr;        // [nsteps][64][8] index in L values or -1
+  int32_t* dsrc = nullptr;         // [nsteps * RPS] index of the diagonal in L values
+  int32_t* srow2 = nullptr;        // [nsteps * RPS] row, or ~row for a repeat
+  void* dyn = nullptr;             // [nsteps * RPS] {rhs, dot} (16 bytes)
+};
+
 struct TrsvSchedDev {
   int ngroups = 0, nsteps = 0, E = 0, EP = 0, nlevels = 0, nslots = 0, nrows = 0;
   int32_t *grp_step_ptr = nullptr, *grp_halo_ptr = nullptr;
@@ -124,6 +175,7 @@ struct TrsvSchedDev {
   int* err = nullptr;                      // [1] spin-limit flag
   double* partials = nullptr;              // [ngroups * 16]
   int rmax = 0;                            // widest R the LDS budget allows
+  TrsvFastDev fast;                        // single-column layout (fast.ok)
 };
 
 // dir = +1 forward (L y = r), -1 backward (L^T z = y).  group_of[i] gives the group
@@ -319,12 +371,23 @@ hipError_t launch_trsv(const TrsvSchedDev& S, bool fp32, int R, const void* rhs,
 hipError_t launch_trsv_gather(const TrsvSchedDev& S, const double* Lval, hipStream_t st);
 size_t trsv_shmem_bytes(int nslots, bool fp32, int R);
 
+// Row ranges of the CSR row kernels: block b owns rows split[b] .. split[b+1]-1 (device
+// array of nb+1 entries), ranges balanced by entries on the host.
+struct RowSplit {
+  const int32_t* split = nullptr;
+  int nb = 0;
+};
+constexpr int kSpmvBlocksPerCU = 8;
+std::vector<int32_t> balanced_row_split(const std::vector<int32_t>& rowptr, const std::vector<int32_t>* rowend,
+                                        int64_t nrows, int nb);
+int row_split_blocks(int64_t nrows, int num_cu);
+
 template <typename T>
 hipError_t mr_init_vec(int R, int64_t n, int64_t n_u, const T* b, T* v1, T* v0, T* w1, T* w0, T* x, T* z1,
                        const double* diagQ, const double* diagA, double two_nu, const MrScalars& s, hipStream_t st);
 hipError_t mr_init_state(int R, const MrScalars& s, double tol, int maxit, hipStream_t st);
 template <typename T>
-hipError_t mr_spmv(int R, int64_t n, const int32_t* rowptr, const int32_t* col, const T* val, const T* z, T* q,
+hipError_t mr_spmv(int R, const RowSplit& rs, const int32_t* rowptr, const int32_t* col, const T* val, const T* z, T* q,
                    const MrScalars& s, int p, hipStream_t st);
 template <typename T>
 hipError_t mr_lanczos(int R, int64_t n, int64_t n_u, const T* q, const T* v, T* vprev_next, T* znext, const double* diagQ,
@@ -333,7 +396,7 @@ template <typename T>
 hipError_t mr_update(int R, int64_t n, const T* z, const T* w, T* wprev_new, T* x, const MrScalars& s, int p,
                      hipStream_t st);
 template <typename T>
-hipError_t spmv_resid(int R, int64_t nrows, const int32_t* rowptr, const int32_t* rowend, const int32_t* col,
+hipError_t spmv_resid(int R, const RowSplit& rs, const int32_t* rowptr, const int32_t* rowend, const int32_t* col,
                       const T* val, const T* x, const T* b, T* y, double* partials, unsigned int* counter, double* out,
                       hipStream_t st);
 template <typename Ta, typename Tb>
@@ -357,8 +420,8 @@ template <typename T>
 hipError_t pcg_init2(int R, int64_t n_u, const T* z, T* pv, const PcgScalars& s, double rtol, int maxit,
                      const int* outer_done, const MinresState* outer_st, hipStream_t st);
 template <typename T>
-hipError_t pcg_spmv(int R, int64_t n_u, const int32_t* rowptr, const int32_t* aend, const int32_t* col, const T* val,
-                    const T* pv, T* q, const PcgScalars& s, hipStream_t st);
+hipError_t pcg_spmv(int R, const RowSplit& rs, const int32_t* rowptr, const int32_t* aend, const int32_t* col,
+                    const T* val, const T* pv, T* q, const PcgScalars& s, hipStream_t st);
 template <typename T>
 hipError_t pcg_axpy(int R, int64_t n_u, const T* pv, const T* q, T* x, T* r, const PcgScalars& s, int ip,
                     hipStream_t st);

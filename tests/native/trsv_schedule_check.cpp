@@ -227,4 +227,20 @@ int hc_schedule_check(int N, int kp, int dim, int strip, int seed, double* stats
   return 0;
 }
 
+// Row ranges of the CSR row kernels for the saddle pattern (which = 0: all rows,
+// 1: A part of the velocity rows) on num_cu CUs.  Call with null split to get nb.
+int hc_row_split(int N, int kp, int dim, int which, int num_cu, int* nb, int32_t* split) {
+  Spaces S = make_spaces(N, kp, dim);
+  SaddlePattern P;
+  std::string err;
+  if (build_saddle_pattern(S, P, err) != 0) return -1;
+  const int64_t nrows = which == 0 ? S.n_u + S.n_p : S.n_u;
+  *nb = row_split_blocks(nrows, num_cu);
+  if (split) {
+    const std::vector<int32_t> v = balanced_row_split(P.rowptr, which == 0 ? nullptr : &P.aend, nrows, *nb);
+    for (size_t i = 0; i < v.size(); ++i) split[i] = v[i];
+  }
+  return 0;
+}
+
 }  // extern "C"

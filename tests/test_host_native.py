@@ -30,6 +30,7 @@ def hostcheck(tmp_path_factory):
     L = ctypes.CDLL(out)
     L.hc_pattern.argtypes = [ctypes.c_int] * 3 + [ctypes.c_void_p] * 6
     L.hc_schedule_check.argtypes = [ctypes.c_int] * 5 + [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int]
+    L.hc_row_split.argtypes = [ctypes.c_int] * 5 + [ctypes.c_void_p] * 2
     return L
 
 
@@ -95,3 +96,23 @@ def test_trsv_schedule_headline_sizes(hostcheck):
         assert rc == 0, msg.value.decode()
         assert int(st[0]) == lev
         assert st[7] < 1e-12 and st[8] < 1e-10
+
+
+@pytest.mark.parametrize("N,kp,dim", [(1, 1, 2), (3, 2, 2), (16, 1, 2), (64, 2, 2), (256, 2, 2), (6, 1, 3), (16, 3, 3)])
+def test_row_split(hostcheck, N, kp, dim):
+    """The row ranges of the SpMV kernels cover every row once, in order, within the block
+    limits, and balance the work (entries + 16 per row) to within one row of the mean."""
+    nu, np_, rp, col, aend = _hc_pattern(hostcheck, N, kp, dim)
+    for which, nrows in ((0, nu + np_), (1, nu)):
+        for cus in (1, 256):
+            nb = ctypes.c_int()
+            assert hostcheck.hc_row_split(N, kp, dim, which, cus, ctypes.byref(nb), None) == 0
+            nb = nb.value
+            assert 1 <= nb <= min(4096, 8 * cus) and (nb <= 8 or nb % 8 == 0)
+            split = np.zeros(nb + 1, np.int32)
+            hostcheck.hc_row_split(N, kp, dim, which, cus, ctypes.byref(ctypes.c_int()), split.ctypes.data)
+            assert split[0] == 0 and split[-1] == nrows and np.all(np.diff(split) >= 0)
+            end = rp[1:nrows + 1] if which == 0 else aend
+            cost = (end - rp[:nrows]) + 16
+            work = np.add.reduceat(np.append(cost, 0), split[:-1])[:nb] * (np.diff(split) > 0)
+            assert work.max() <= cost.sum() / nb + 2 * cost.max()
