@@ -27,9 +27,6 @@ namespace stk {
 // adjacent, so the vector entries that an XCD gathers stay in its own L2.
 // ---------------------------------------------------------------------------
 constexpr int kSG = 16;
-template <int R>
-constexpr int spmv_unroll() { return R == 1 ? 8 : (R <= 8 ? 2 : 1); }
-
 struct RowRange {
   int64_t begin, end;
 };
@@ -75,42 +72,121 @@ __device__ __forceinline__ void load_cols(const T* __restrict__ p, T (&v)[R]) {
 }
 
 // acc[c] = sum over k in [kb, ke) of val[k] * x[col[k] * R + c], in every lane of the group.
-// Dot products of one CSR row (entries kb..ke-1) with the R columns of x, spread over the
-// kSG lanes of a row group and summed over them.  Entries are taken U*kSG at a time with
-// every load issued before the first use: the index and value loads of all U entries, then
-// the U vector gathers.  Lanes past the row end load the row's last entry again (a cache
-// hit) and add nothing.
-template <int R, typename Acc, typename T>
-__device__ __forceinline__ void row_dot(int32_t kb, int32_t ke, int sub, const int32_t* __restrict__ col,
-                                        const T* __restrict__ val, const T* __restrict__ x, Acc (&acc)[R]) {
-  constexpr int U = spmv_unroll<R>();
+// Rows per lane group and entries per lane in the first chunk of a pass: with one column,
+// two rows per group and 4 entries per lane (index, value and vector loads of both rows in
+// flight at once); with R columns one row and fewer entries (register budget).
+template <int R>
+constexpr int spmv_rows_per_group() { return R == 1 ? 2 : 1; }
+template <int R>
+constexpr int spmv_chunk() { return R == 1 ? 4 : (R <= 8 ? 2 : 1); }
+constexpr int kStageRows = 512;  // rows whose entry ranges a block stages in LDS at a time
+
+// Entries [k0, k0 + U*kSG) of one row (lane sub takes k0 + sub + u*kSG), accumulated into
+// acc with every load of the chunk issued before the first use.  Lanes past the row end
+// load the row's last entry again (a cache hit) and add nothing.
+template <int R, int U, typename Acc, typename T>
+__device__ __forceinline__ void row_chunk(int32_t k0, int32_t ke, const int32_t* __restrict__ col,
+                                          const T* __restrict__ val, const T* __restrict__ x, Acc (&acc)[R]) {
+  int32_t j[U];
+  T a[U];
+  bool ok[U];
 #pragma unroll
-  for (int c = 0; c < R; ++c) acc[c] = Acc(0);
-  for (int32_t k0 = kb + sub; k0 < ke; k0 += U * kSG) {
-    int32_t j[U];
-    T a[U];
-    bool ok[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int32_t k = k0 + u * kSG;
-      ok[u] = k < ke;
-      const int32_t kc = ok[u] ? k : ke - 1;
-      j[u] = col[kc];
-      a[u] = val[kc];
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      T xv[R];
-      load_cols<R>(x + (size_t)j[u] * R, xv);
-#pragma unroll
-      for (int c = 0; c < R; ++c) {
-        const Acc t = fma((Acc)a[u], (Acc)xv[c], acc[c]);
-        acc[c] = ok[u] ? t : acc[c];
-      }
-    }
+  for (int u = 0; u < U; ++u) {
+    const int32_t k = k0 + u * kSG;
+    ok[u] = k < ke;
+    const int32_t kc = ok[u] ? k : ke - 1;
+    j[u] = col[kc];
+    a[u] = val[kc];
   }
 #pragma unroll
-  for (int c = 0; c < R; ++c) acc[c] = group_sum<kSG>(acc[c]);
+  for (int u = 0; u < U; ++u) {
+    T xv[R];
+    load_cols<R>(x + (size_t)j[u] * R, xv);
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+      const Acc t = fma((Acc)a[u], (Acc)xv[c], acc[c]);
+      acc[c] = ok[u] ? t : acc[c];
+    }
+  }
+}
+
+// All rows of this block (entries rowptr[i] .. rowend[i]-1, or rowptr[i+1]-1 without
+// rowend), kSG lanes per row and spmv_rows_per_group rows per lane group.  The rows' entry
+// ranges are staged in LDS kStageRows at a time; the first chunk of every row of a pass is
+// loaded together (one row chunk for each of the group's rows), longer rows continue row
+// by row.  fin(i, acc) runs on lane 0 of the row's lane group with the row's sums.
+template <int R, typename Acc, typename T, typename Fin>
+__device__ __forceinline__ void csr_rows(const int32_t* __restrict__ split, const int32_t* __restrict__ rowptr,
+                                         const int32_t* __restrict__ rowend, const int32_t* __restrict__ col,
+                                         const T* __restrict__ val, const T* __restrict__ x, Fin fin) {
+  constexpr int RPG = spmv_rows_per_group<R>();
+  constexpr int U = spmv_chunk<R>();
+  constexpr int G = kVT / kSG;
+  __shared__ int32_t s_kb[kStageRows], s_ke[kStageRows];
+  const int sub = threadIdx.x & (kSG - 1);
+  const int grp = threadIdx.x / kSG;
+  const RowRange rr = block_rows(split);
+  for (int64_t c0 = rr.begin; c0 < rr.end; c0 += kStageRows) {
+    const int nrow = (int)min<int64_t>(kStageRows, rr.end - c0);
+    for (int t = threadIdx.x; t < nrow; t += kVT) {
+      s_kb[t] = rowptr[c0 + t];
+      s_ke[t] = rowend ? rowend[c0 + t] : rowptr[c0 + t + 1];
+    }
+    __syncthreads();
+    for (int base = 0; base < nrow; base += G * RPG) {
+      int32_t kb[RPG], ke[RPG];
+      Acc acc[RPG][R];
+#pragma unroll
+      for (int q = 0; q < RPG; ++q) {
+        const int t = base + q * G + grp;
+        kb[q] = t < nrow ? s_kb[t] : 0;
+        ke[q] = t < nrow ? s_ke[t] : 0;
+#pragma unroll
+        for (int c = 0; c < R; ++c) acc[q][c] = Acc(0);
+      }
+      // first chunk of every row of the pass, all loads in flight together
+      {
+        int32_t j[RPG][U];
+        T a[RPG][U];
+        bool ok[RPG][U];
+#pragma unroll
+        for (int q = 0; q < RPG; ++q)
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int32_t k = kb[q] + sub + u * kSG;
+            ok[q][u] = k < ke[q];
+            // (entry 0 for an empty or absent row: a valid address whose value is not added)
+            const int32_t kc = ok[q][u] ? k : (ke[q] > kb[q] ? ke[q] - 1 : 0);
+            j[q][u] = col[kc];
+            a[q][u] = val[kc];
+          }
+#pragma unroll
+        for (int q = 0; q < RPG; ++q)
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            T xv[R];
+            load_cols<R>(x + (size_t)j[q][u] * R, xv);
+#pragma unroll
+            for (int c = 0; c < R; ++c) {
+              const Acc t = fma((Acc)a[q][u], (Acc)xv[c], acc[q][c]);
+              acc[q][c] = ok[q][u] ? t : acc[q][c];
+            }
+          }
+      }
+      // the rest of longer rows
+#pragma unroll
+      for (int q = 0; q < RPG; ++q)
+        for (int32_t k0 = kb[q] + sub + U * kSG; k0 < ke[q]; k0 += U * kSG) row_chunk<R, U>(k0, ke[q], col, val, x, acc[q]);
+#pragma unroll
+      for (int q = 0; q < RPG; ++q) {
+#pragma unroll
+        for (int c = 0; c < R; ++c) acc[q][c] = group_sum<kSG>(acc[q][c]);
+        const int t = base + q * G + grp;
+        if (t < nrow && sub == 0) fin(c0 + t, acc[q]);
+      }
+    }
+    __syncthreads();
+  }
 }
 
 // Store R consecutive values with wide stores.
@@ -224,25 +300,16 @@ __global__ __launch_bounds__(kVT) void k_mr_spmv(const int32_t* __restrict__ spl
   double acc_d[R];
 #pragma unroll
   for (int c = 0; c < R; ++c) acc_d[c] = 0.0;
-  const int sub = threadIdx.x & (kSG - 1);
-  const RowRange rr = block_rows(split);
-  for (int64_t base = rr.begin; base < rr.end; base += kVT / kSG) {
-    const int64_t i = base + threadIdx.x / kSG;
-    const bool valid = i < rr.end;
-    const int32_t kb = valid ? rowptr[i] : 0, ke = valid ? rowptr[i + 1] : 0;
-    T acc[R];
-    row_dot<R>(kb, ke, sub, col, val, z, acc);
-    if (valid && sub == 0) {  // lane 0 of the group finishes the R columns of row i
-      T qv[R], zv[R];
-      load_cols<R>(z + (size_t)i * R, zv);
+  csr_rows<R, T>(split, rowptr, nullptr, col, val, z, [&](int64_t i, T (&acc)[R]) {
+    T qv[R], zv[R];
+    load_cols<R>(z + (size_t)i * R, zv);
 #pragma unroll
-      for (int c = 0; c < R; ++c) {
-        qv[c] = T((double)acc[c] * ig[c]);
-        acc_d[c] += (double)qv[c] * (double)zv[c] * ig[c];
-      }
-      store_cols<R>(q + (size_t)i * R, qv);
+    for (int c = 0; c < R; ++c) {
+      qv[c] = T((double)acc[c] * ig[c]);
+      acc_d[c] += (double)qv[c] * (double)zv[c] * ig[c];
     }
-  }
+    store_cols<R>(q + (size_t)i * R, qv);
+  });
   reduce_last<R>(acc_d, s.partials, s.counter, [&](int k, double v) { red_at(s, p, RED_DELTA)[k] = v; });
 }
 
@@ -407,33 +474,23 @@ __global__ __launch_bounds__(kVT) void k_spmv_resid(const int32_t* __restrict__ 
   double acc_d[2 * R];
 #pragma unroll
   for (int c = 0; c < 2 * R; ++c) acc_d[c] = 0.0;
-  const int sub = threadIdx.x & (kSG - 1);
-  const RowRange rr = block_rows(split);
-  for (int64_t base = rr.begin; base < rr.end; base += kVT / kSG) {
-    const int64_t i = base + threadIdx.x / kSG;
-    const bool valid = i < rr.end;
-    const int32_t kb = valid ? rowptr[i] : 0;
-    const int32_t ke = valid ? (rowend ? rowend[i] : rowptr[i + 1]) : 0;
-    double acc[R];
-    row_dot<R>(kb, ke, sub, col, val, xin, acc);
-    if (valid && sub == 0) {
-      T bv[R], yv[R];
-      if (bvec) {
-        load_cols<R>(bvec + (size_t)i * R, bv);
-      } else {
+  csr_rows<R, double>(split, rowptr, rowend, col, val, xin, [&](int64_t i, double (&acc)[R]) {
+    T bv[R], yv[R];
+    if (bvec) {
+      load_cols<R>(bvec + (size_t)i * R, bv);
+    } else {
 #pragma unroll
-        for (int c = 0; c < R; ++c) bv[c] = T(0);
-      }
-#pragma unroll
-      for (int c = 0; c < R; ++c) {
-        const double y64 = bvec ? (double)bv[c] - acc[c] : acc[c];
-        yv[c] = T(y64);
-        acc_d[c] += y64 * y64;
-        acc_d[R + c] += (double)bv[c] * (double)bv[c];
-      }
-      store_cols<R>(y + (size_t)i * R, yv);
+      for (int c = 0; c < R; ++c) bv[c] = T(0);
     }
-  }
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+      const double y64 = bvec ? (double)bv[c] - acc[c] : acc[c];
+      yv[c] = T(y64);
+      acc_d[c] += y64 * y64;
+      acc_d[R + c] += (double)bv[c] * (double)bv[c];
+    }
+    store_cols<R>(y + (size_t)i * R, yv);
+  });
   if (out == nullptr) return;
   reduce_last<2 * R>(acc_d, partials, counter, [&](int k, double v) { out[k] = v; });
 }
@@ -558,22 +615,13 @@ __global__ __launch_bounds__(kVT) void k_pcg_spmv(const int32_t* __restrict__ sp
   double acc_d[R];
 #pragma unroll
   for (int c = 0; c < R; ++c) acc_d[c] = 0.0;
-  const int sub = threadIdx.x & (kSG - 1);
-  const RowRange rr = block_rows(split);
-  for (int64_t base = rr.begin; base < rr.end; base += kVT / kSG) {
-    const int64_t i = base + threadIdx.x / kSG;
-    const bool valid = i < rr.end;
-    const int32_t kb = valid ? rowptr[i] : 0, ke = valid ? aend[i] : 0;
-    T acc[R];
-    row_dot<R>(kb, ke, sub, col, val, pv, acc);
-    if (valid && sub == 0) {
-      T pw[R];
-      load_cols<R>(pv + (size_t)i * R, pw);
+  csr_rows<R, T>(split, rowptr, aend, col, val, pv, [&](int64_t i, T (&acc)[R]) {
+    T pw[R];
+    load_cols<R>(pv + (size_t)i * R, pw);
 #pragma unroll
-      for (int c = 0; c < R; ++c) acc_d[c] += (double)acc[c] * (double)pw[c];
-      store_cols<R>(q + (size_t)i * R, acc);
-    }
-  }
+    for (int c = 0; c < R; ++c) acc_d[c] += (double)acc[c] * (double)pw[c];
+    store_cols<R>(q + (size_t)i * R, acc);
+  });
   reduce_last<R>(acc_d, s.partials, s.counter, [&](int k, double v) { s.pq[k] = v; });
 }
 
