@@ -42,6 +42,27 @@ def spmv_bytes(nnz, n, R=1, wbytes=8):
     return (wbytes + 4) * nnz + 4 * (n + 1) + 2 * wbytes * n * R
 
 
+def measured_traffic():
+    """HBM bytes per launch of the triangular solve and the saddle product, from the committed
+    rocprofv3 counter summary, while the kernel sources are the ones it was measured on."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "trsv_spmv_c1_2d_k2_n256_traffic.md")
+    try:
+        txt = open(path).read()
+    except OSError:
+        return {}
+    m = re.search(r"traffic_source_sha256: ([0-9a-f]+)", txt)
+    t = re.search(r"traffic_bytes_per_launch: trsv=(\d+) spmv=(\d+)", txt)
+    h = hashlib.sha256()
+    for src in ("k_trsv.hip", "k_krylov.hip"):
+        with open(os.path.join(ROOT, "paper_1309_5048_amd", "csrc", src), "rb") as fh:
+            h.update(fh.read())
+    if not m or not t or m.group(1) != h.hexdigest():
+        return {}
+    return {"trsv_fwd": int(t.group(1)), "trsv_bwd": int(t.group(1)), "spmv": int(t.group(2))}
+
+
 def sync():
     import torch
     torch.cuda.synchronize()
@@ -130,6 +151,8 @@ def main():
     iters = infos[-1]["iters"]
     log("solve %.4f s, %d iterations, relres %.2e" % (sec, iters, infos[-1]["relres_true_Minv"]))
 
+    traffic = measured_traffic()
+
     def roof(name, bytes_per_launch):
         ms, cnt = prof[name]
         if cnt == 0:
@@ -137,7 +160,7 @@ def main():
         avg_s = ms / cnt / 1e3
         gbs = bytes_per_launch / avg_s / 1e9
         return {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(gbs / HBM_PEAK_GBS, 5), "traffic": None, "kernel": name,
+                "frac": round(gbs / HBM_PEAK_GBS, 5), "traffic": traffic.get(name), "kernel": name,
                 "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_bytes_per_launch": int(bytes_per_launch),
                 "launches": int(cnt)}
 
