@@ -23,7 +23,7 @@ _SRC = os.path.join(_HERE, "stokes_oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 PC_IC0, PC_ICPCG, PC_JACOBI, PC_EXACT, PC_JPCG = 0, 1, 2, 3, 4
-PQ_DIAG, PQ_EXACT = 0, 1
+PQ_DIAG, PQ_EXACT, PQ_JPCG = 0, 1, 2
 
 
 def build(force=False):
@@ -211,15 +211,19 @@ class Oracle:
 
     def solve_refined(self, f, tol=1e-8, maxit=10000, pc_A=PC_ICPCG, pc_Q=PQ_DIAG, inner_tol=1e-2, cycles=6):
         """MINRES restarted on the true residual until ||b - Acal x||_{M^-1} <= tol ||b||_{M^-1}
-        with M the fixed block preconditioner blkdiag(IC(0), Diag(Q)/(2 nu)).  Used for the
-        inner-PCG velocity block, a nonlinear preconditioner whose MINRES estimate |eta|
-        measures the residual in a norm that changes between applications (Sec. 5: MINRES
-        minimises in the norm of a fixed SPD preconditioner).  Each cycle solves
-        Acal d = r to the remaining relative reduction (at most 0.5) and projects p."""
+        with M the fixed block preconditioner that the inner solves approximate:
+        blkdiag(IC(0), Diag(Q)/(2 nu)) for IC(0)-PCG on A, blkdiag(Diag(A), Diag(Q)/(2 nu))
+        for Jacobi-PCG on A (and on Q).  Used for inner-PCG blocks, nonlinear preconditioners
+        whose MINRES estimate |eta| measures the residual in a norm that changes between
+        applications (Sec. 5: MINRES minimises in the norm of a fixed SPD preconditioner).
+        Each cycle solves Acal d = r to the remaining relative reduction (at most 0.5) and
+        projects p."""
         b0 = np.concatenate([_f64(f), np.zeros(self.n_p)])
+        lin_A = PC_JACOBI if pc_A in (PC_JACOBI, PC_JPCG) else PC_IC0
+        lin_Q = PQ_DIAG if pc_Q in (PQ_DIAG, PQ_JPCG) else pc_Q
 
         def mnorm2(v):
-            z, _ = self.precond(v, pc_A=PC_IC0, pc_Q=pc_Q)
+            z, _ = self.precond(v, pc_A=lin_A, pc_Q=lin_Q)
             return float(v @ z)
 
         bM = mnorm2(b0)

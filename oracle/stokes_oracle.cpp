@@ -929,7 +929,7 @@ void dense_chol_solve(const std::vector<double>& l, int64_t n, const double* r, 
 }
 
 enum { PCA_IC0 = 0, PCA_ICPCG = 1, PCA_JACOBI = 2, PCA_EXACT = 3, PCA_JPCG = 4 };
-enum { PCQ_DIAG = 0, PCQ_EXACT = 1 };
+enum { PCQ_DIAG = 0, PCQ_EXACT = 1, PCQ_JPCG = 2 };
 
 // Inner PCG on A (Sec. 6.4): x0 = 0, stop when ||r||_2 <= rtol ||b||_2, tested after
 // each update; preconditioner IC(0) (PCA_ICPCG) or Jacobi (PCA_JPCG).
@@ -970,8 +970,44 @@ int pcg_A(const Problem& P, int which, const double* b, double* x, double rtol, 
   return it;
 }
 
+// Inner PCG on the pressure mass matrix Q with the Jacobi preconditioner Diag(Q): the
+// pressure half of the PCG(A,Q) variant (Sec. 5.1: both blocks solved by Jacobi-PCG).
+// x0 = 0, stop when ||r||_2 <= rtol ||b||_2, tested after each update.
+int pcg_Q(const Problem& P, const double* b, double* x, double rtol, int maxit) {
+  int64_t n = P.np_dofs;
+  std::vector<double> r(b, b + n), z(n), p(n), q(n);
+  std::fill(x, x + n, 0.0);
+  double bnorm = std::sqrt(dot(b, b, n));
+  if (bnorm == 0.0) return 0;
+  for (int64_t i = 0; i < n; ++i) z[i] = r[i] / P.diagQ[i];
+  p = z;
+  double rho = dot(r.data(), z.data(), n);
+  int it = 0;
+  while (it < maxit) {
+    for (int64_t i = 0; i < n; ++i) {
+      double acc = 0.0;
+      for (int64_t k = P.Q_ptr[i]; k < P.Q_ptr[i + 1]; ++k) acc += P.Q_val[k] * p[P.Q_col[k]];
+      q[i] = acc;
+    }
+    double alpha = rho / dot(p.data(), q.data(), n);
+    for (int64_t i = 0; i < n; ++i) {
+      x[i] += alpha * p[i];
+      r[i] -= alpha * q[i];
+    }
+    ++it;
+    if (std::sqrt(dot(r.data(), r.data(), n)) <= rtol * bnorm) break;
+    for (int64_t i = 0; i < n; ++i) z[i] = r[i] / P.diagQ[i];
+    double rho_new = dot(r.data(), z.data(), n);
+    double beta = rho_new / rho;
+    rho = rho_new;
+    for (int64_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+  }
+  return it;
+}
+
 // Block-diagonal preconditioner M = blkdiag(M_A, M_Q) applied to r: z = M^{-1} r (eq.
-// general_precond_M).  M_Q = Diag(Q)/(2 nu) or Q/(2 nu) (exact).
+// general_precond_M).  M_Q = Diag(Q)/(2 nu), Q/(2 nu) (exact), or Q/(2 nu) approximated by
+// Jacobi-PCG on Q (PCQ_JPCG; its iterations are added to the inner count).
 int apply_precond(const Problem& P, int pcA, int pcQ, double inner_tol, const double* r, double* z) {
   int64_t nu = P.nu_dofs, np = P.np_dofs;
   int inner = 0;
@@ -994,6 +1030,9 @@ int apply_precond(const Problem& P, int pcA, int pcQ, double inner_tol, const do
   }
   if (pcQ == PCQ_DIAG) {
     for (int64_t k = 0; k < np; ++k) z[nu + k] = 2.0 * P.nu * r[nu + k] / P.diagQ[k];
+  } else if (pcQ == PCQ_JPCG) {
+    inner += pcg_Q(P, r + nu, z + nu, inner_tol, 200);
+    for (int64_t k = 0; k < np; ++k) z[nu + k] *= 2.0 * P.nu;
   } else {
     dense_chol_solve(P.cholQ, np, r + nu, z + nu);
     for (int64_t k = 0; k < np; ++k) z[nu + k] *= 2.0 * P.nu;
@@ -1103,8 +1142,9 @@ void true_residuals(const Problem& P, const double* b, const double* x, int pcA,
   saddle_matvec(P, x, r.data());
   for (int64_t i = 0; i < n; ++i) r[i] = b[i] - r[i];
   int lin = (pcA == PCA_ICPCG) ? PCA_IC0 : (pcA == PCA_JPCG ? PCA_JACOBI : pcA);
-  apply_precond(P, lin, pcQ, 0.0, r.data(), z.data());
-  apply_precond(P, lin, pcQ, 0.0, b, zb.data());
+  int linq = pcQ == PCQ_JPCG ? PCQ_DIAG : pcQ;
+  apply_precond(P, lin, linq, 0.0, r.data(), z.data());
+  apply_precond(P, lin, linq, 0.0, b, zb.data());
   double bb = dot(b, b, n), bm = dot(b, zb.data(), n);
   *rel2 = bb > 0 ? std::sqrt(dot(r.data(), r.data(), n) / bb) : 0.0;
   *relM = bm > 0 ? std::sqrt(std::max(0.0, dot(r.data(), z.data(), n)) / bm) : 0.0;
