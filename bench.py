@@ -120,7 +120,7 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1309_5048_amd import StokesProblem, PC_IC0, PC_ICPCG, MIXED, FP64
+    from paper_1309_5048_amd import StokesProblem, PC_IC0, PC_ICPCG, PC_JPCG, MIXED, FP64
 
     torch.cuda.set_device(0)
     N, kp, dim, tol = 256, 2, 2, 1e-8
@@ -195,6 +195,15 @@ def main():
             log("icpcg", extra["c1_icpcg_inner1e-2"])
         except Exception as e:  # report, keep the headline
             extra["c1_icpcg_inner1e-2"] = {"error": str(e)}
+        try:
+            # the PCG(A), Diag(Q) variant: Jacobi-preconditioned inner CG on A
+            s_j, inf_j = timed_solves(gp, f, 1, 1, tol=tol, precond=PC_JPCG)
+            extra["c1_jpcg_inner1e-2"] = {"s": round(s_j, 5), "iters": inf_j[-1]["iters"],
+                                          "inner_iters_total": inf_j[-1]["inner_iters_total"],
+                                          "relres_true_Minv": inf_j[-1]["relres_true_Minv"]}
+            log("jpcg", extra["c1_jpcg_inner1e-2"])
+        except Exception as e:  # report, keep the headline
+            extra["c1_jpcg_inner1e-2"] = {"error": str(e)}
         del gp
         torch.cuda.empty_cache()
         try:

@@ -53,6 +53,12 @@ extern "C" {
 #define STOKES_PC_ICPCG 1  /* M_A^{-1} r = IC(0)-preconditioned CG on A r, relative 2-norm
                               tolerance stokes_set_inner_tol (default 1e-2), x0 = 0      */
 #define STOKES_PC_JACOBI 2 /* M_A = Diag(A)  (the Diag(A,Q) variant of Sec. 5.1)          */
+#define STOKES_PC_JPCG 4   /* M_A^{-1} r = Diag(A)-preconditioned CG on A r, tolerance as
+                              for STOKES_PC_ICPCG: the PCG(A), Diag(Q) variant of Sec. 5.1
+                              (the paper's tables use the inner tolerance 1e-6); like
+                              STOKES_PC_ICPCG a nonlinear preconditioner, so MINRES is
+                              restarted on the true residual until it meets tol in the norm
+                              of blkdiag(Diag(A), Diag(Q)/(2 nu)).  Value 3 is not used.   */
 
 /* Arithmetic of the Krylov iteration. */
 #define STOKES_FP64 0  /* everything in double precision                                  */

@@ -612,21 +612,29 @@ int precond_velocity(stokes_problem* pb, int precond, Work& W, SchedPair* sp, co
     CK(launch_trsv(sp->bwd, fp32, R, W.y, zout, vin, dot_out, skip, st, prof_take(pb, 2)));
     return 0;
   }
-  if (precond == STOKES_PC_ICPCG) {
+  if (precond == STOKES_PC_ICPCG || precond == STOKES_PC_JPCG) {
     const T* val = fp32 ? (const T*)pb->val32 : (const T*)pb->val;
     PcgScalars& s = pb->pcg;
+    // z = M^{-1} r with rho = r.z: the IC(0) triangular solves (fused dot), or Jacobi
+    auto inner_precond = [&](double* rho_out, const int* sk, bool prof) -> hipError_t {
+      if (precond == STOKES_PC_JPCG)
+        return pcg_jacobi<T>(R, n_u, (const T*)W.pr, pb->diagA, (T*)W.pz, s, rho_out, sk, st);
+      hipError_t e = launch_trsv(sp->fwd, fp32, R, W.pr, W.y, nullptr, nullptr, sk, st, prof ? prof_take(pb, 1) : nullptr);
+      if (e != hipSuccess) return e;
+      return launch_trsv(sp->bwd, fp32, R, W.y, W.pz, W.pr, rho_out, sk, st, prof ? prof_take(pb, 2) : nullptr);
+    };
     CK(pcg_init<T>(R, n_u, vin, (T*)W.pr, zout, s, skip, st));
-    CK(launch_trsv(sp->fwd, fp32, R, W.pr, W.y, nullptr, nullptr, skip, st));
-    CK(launch_trsv(sp->bwd, fp32, R, W.y, W.pz, W.pr, s.rho, skip, st));
+    CK(inner_precond(s.rho, skip, false));
     CK(pcg_init2<T>(R, n_u, (const T*)W.pz, (T*)W.pp, s, pb->inner_tol, pb->maxit_inner, skip, outer_st, st));
     int ip = 0;
-    for (int it = 0; it < pb->maxit_inner; it += 4) {
-      for (int k = 0; k < 4; ++k) {
+    // iterations are queued in chunks between host checks of the done flag (Jacobi-PCG
+    // runs many cheap iterations, IC(0)-PCG a few long ones)
+    const int chunk_it = precond == STOKES_PC_JPCG ? 16 : 4;
+    for (int it = 0; it < pb->maxit_inner; it += chunk_it) {
+      for (int k = 0; k < chunk_it; ++k) {
         CK(pcg_spmv<T>(R, pb->rs_A, pb->rowptr, pb->aend, pb->col, val, (const T*)W.pp, (T*)W.pq, s, st));
         CK(pcg_axpy<T>(R, n_u, (const T*)W.pp, (const T*)W.pq, zout, (T*)W.pr, s, ip, st));
-        CK(launch_trsv(sp->fwd, fp32, R, W.pr, W.y, nullptr, nullptr, s.alldone, st, prof_take(pb, 1)));
-        CK(launch_trsv(sp->bwd, fp32, R, W.y, W.pz, W.pr, s.rho + (1 - ip) * kRMax, s.alldone, st,
-                       prof_take(pb, 2)));
+        CK(inner_precond(s.rho + (1 - ip) * kRMax, s.alldone, true));
         CK(pcg_pupdate<T>(R, n_u, (const T*)W.pz, (T*)W.pp, s, ip, st));
         ip = 1 - ip;
       }
@@ -657,7 +665,7 @@ int minres_run(stokes_problem* pb, Work& W, int precond, double tol, int maxit, 
   hipStream_t st = pb->stream;
   const int64_t n_u = pb->S.n_u, n = n_u + pb->S.n_p;
   SchedPair* sp = nullptr;
-  if (precond != STOKES_PC_JACOBI) {
+  if (precond != STOKES_PC_JACOBI && precond != STOKES_PC_JPCG) {
     int rc = get_schedule(pb, R, fp32, &sp);
     if (rc) return rc;
   }
@@ -671,7 +679,8 @@ int minres_run(stokes_problem* pb, Work& W, int precond, double tol, int maxit, 
   T* x = (T*)W.x;
   T* q = (T*)W.q;
   // reset the PCG column totals
-  if (precond == STOKES_PC_ICPCG) CK(hipMemsetAsync(pb->pcg.st, 0, sizeof(PcgState) * kRMax, st));
+  if (precond == STOKES_PC_ICPCG || precond == STOKES_PC_JPCG)
+    CK(hipMemsetAsync(pb->pcg.st, 0, sizeof(PcgState) * kRMax, st));
   CK(mr_init_vec<T>(R, n, n_u, (const T*)W.b, v[0], v[1], w[0], w[1], x, z[0], pb->diagQ, diagA, two_nu, s, st));
   // the outer state is not initialised yet: no outer-done test for this application
   int rc = precond_velocity<T>(pb, precond, W, sp, v[0], z[0], s.red + RED_G2U * kRMax, nullptr, nullptr, nullptr);
@@ -760,7 +769,7 @@ int true_residuals(stokes_problem* pb, Work& W, int precond, const double* b, co
   double* r = (double*)W.q;
   double* out = pb->scratch;  // [0..2R) norms, [2R..4R) r M r parts, [4R..6R) b M b parts
   CK(spmv_resid<double>(R, pb->rs_full, pb->rowptr, nullptr, pb->col, pb->val, x, b, r, pb->partials, pb->counter, out, st));
-  const int pcl = (precond == STOKES_PC_JACOBI) ? STOKES_PC_JACOBI : STOKES_PC_IC0;
+  const int pcl = (precond == STOKES_PC_JACOBI || precond == STOKES_PC_JPCG) ? STOKES_PC_JACOBI : STOKES_PC_IC0;
   for (int pass = 0; pass < 2; ++pass) {
     const double* vec = pass == 0 ? r : b;
     double* o = out + 2 * R + pass * 2 * R;
@@ -806,7 +815,8 @@ int solve_core(stokes_problem* pb, Work& W64, int precond, int precision, double
   int status[kRMax] = {0};
   double eta_rel[kRMax] = {0};
   int cycles = 1;
-  if (precision == STOKES_FP64 && precond != STOKES_PC_ICPCG) {
+  const bool inner_pcg = precond == STOKES_PC_ICPCG || precond == STOKES_PC_JPCG;
+  if (precision == STOKES_FP64 && !inner_pcg) {
     int rc = minres_run<double>(pb, W64, precond, tol, pb->maxit_outer, ro);
     if (rc) return rc;
     for (int c = 0; c < R; ++c) {
@@ -817,9 +827,10 @@ int solve_core(stokes_problem* pb, Work& W64, int precond, int precision, double
     int rc2 = project_pressure(pb, R, (double*)W64.x);
     if (rc2) return rc2;
   } else if (precision == STOKES_FP64) {
-    // Inner IC(0)-CG to a relative tolerance is a nonlinear preconditioner: MINRES's |eta|
-    // then measures the residual in a norm that changes from one application to the next.
-    // Refine on the true residual (FP64, M = IC(0) norm) until it meets the tolerance.
+    // Inner CG to a relative tolerance is a nonlinear preconditioner: MINRES's |eta| then
+    // measures the residual in a norm that changes from one application to the next.
+    // Refine on the true residual (FP64, M = IC(0) or Diag(A) on the velocity block) until
+    // it meets the tolerance.
     if (W64.xr == nullptr) {
       W64.xr = pb->mem.get<double>(size_t(n) * R);
       W64.br = pb->mem.get<double>(size_t(n) * R);
@@ -926,7 +937,7 @@ int solve_core(stokes_problem* pb, Work& W64, int precond, int precision, double
       infos[c].refine_cycles = cycles;
       infos[c].reserved = 0;
     }
-    if (precond == STOKES_PC_ICPCG) {
+    if (inner_pcg) {
       PcgState ps[kRMax];
       CK(hipMemcpyAsync(ps, pb->pcg.st, sizeof(PcgState) * kRMax, hipMemcpyDeviceToHost, st));
       CK(hipStreamSynchronize(st));
@@ -944,7 +955,7 @@ int solve_core(stokes_problem* pb, Work& W64, int precond, int precision, double
 
 int check_args_solve(stokes_problem* pb, double tol, int precond, int precision) {
   if (!(tol > 0.0) || !(tol < 1.0)) return fail(pb, STOKES_EINVAL, "tol must be in (0, 1)");
-  if (precond < 0 || precond > 2) return fail(pb, STOKES_EINVAL, "unknown preconditioner");
+  if (precond < 0 || precond > 4 || precond == 3) return fail(pb, STOKES_EINVAL, "unknown preconditioner");
   if (precision != STOKES_FP64 && precision != STOKES_MIXED) return fail(pb, STOKES_EINVAL, "unknown precision");
   return 0;
 }
@@ -1322,7 +1333,7 @@ int stokes_apply(stokes_problem* pb, const double* x, double* y) {
 }
 
 int stokes_apply_precond(stokes_problem* pb, int precond, const double* r, double* y, int* inner_iters) {
-  if (!pb || !r || !y || precond < 0 || precond > 2) return fail(pb, STOKES_EINVAL, "bad arguments");
+  if (!pb || !r || !y || precond < 0 || precond > 4 || precond == 3) return fail(pb, STOKES_EINVAL, "bad arguments");
   Work* W = nullptr;
   int rc = get_work(pb, 1, false, &W);
   if (rc) return rc;
@@ -1333,12 +1344,13 @@ int stokes_apply_precond(stokes_problem* pb, int precond, const double* r, doubl
   CK(hipGetLastError());
   if (precond != STOKES_PC_JACOBI) {
     SchedPair* sp = nullptr;
-    if ((rc = get_schedule(pb, 1, false, &sp))) return rc;
-    if (precond == STOKES_PC_ICPCG) CK(hipMemsetAsync(pb->pcg.st, 0, sizeof(PcgState) * kRMax, st));
+    if (precond != STOKES_PC_JPCG && (rc = get_schedule(pb, 1, false, &sp))) return rc;
+    if (precond == STOKES_PC_ICPCG || precond == STOKES_PC_JPCG)
+      CK(hipMemsetAsync(pb->pcg.st, 0, sizeof(PcgState) * kRMax, st));
     rc = precond_velocity<double>(pb, precond, *W, sp, r, y, pb->scratch + 100, nullptr, nullptr, nullptr);
     if (rc) return rc;
-    if ((rc = check_trsv_err(pb, sp))) return rc;
-    if (inner_iters && precond == STOKES_PC_ICPCG) {
+    if (sp && (rc = check_trsv_err(pb, sp))) return rc;
+    if (inner_iters && (precond == STOKES_PC_ICPCG || precond == STOKES_PC_JPCG)) {
       PcgState ps;
       CK(hipMemcpyAsync(&ps, pb->pcg.st, sizeof(PcgState), hipMemcpyDeviceToHost, st));
       CK(hipStreamSynchronize(st));

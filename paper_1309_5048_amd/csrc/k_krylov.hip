@@ -667,6 +667,30 @@ __global__ __launch_bounds__(kVT) void k_pcg_axpy(int64_t n_u, const T* __restri
   });
 }
 
+// Jacobi preconditioner of the inner PCG: z = r / diag(A) and rho = r.z into rho_out[c]
+// (the role of the fused dot of the IC(0) triangular solves).  skip: device flag or null.
+template <typename T, int R>
+__global__ __launch_bounds__(kVT) void k_pcg_jacobi(int64_t n_u, const T* __restrict__ r,
+                                                    const double* __restrict__ diag, T* __restrict__ z,
+                                                    double* __restrict__ partials, unsigned int* __restrict__ counter,
+                                                    double* __restrict__ rho_out, const int* __restrict__ skip) {
+  if (skip != nullptr && *skip) return;
+  double acc[R];
+#pragma unroll
+  for (int c = 0; c < R; ++c) acc[c] = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kVT + threadIdx.x; i < n_u; i += (int64_t)gridDim.x * kVT) {
+    const double d = diag[i];
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+      const size_t k = (size_t)i * R + c;
+      const T zv = T((double)r[k] / d);
+      z[k] = zv;
+      acc[c] += (double)r[k] * (double)zv;
+    }
+  }
+  reduce_last<R>(acc, partials, counter, [&](int k, double v) { rho_out[k] = v; });
+}
+
 // all-done flag after k_pcg_axpy (single thread)
 template <int R>
 __global__ void k_pcg_check(PcgScalars s) {
@@ -834,6 +858,14 @@ hipError_t pcg_axpy(int R, int64_t n_u, const T* pv, const T* q, T* x, T* r, con
 }
 
 template <typename T>
+hipError_t pcg_jacobi(int R, int64_t n_u, const T* r, const double* diag, T* z, const PcgScalars& s, double* rho_out,
+                      const int* skip, hipStream_t st) {
+  STK_R_SWITCH(R, hipLaunchKernelGGL((k_pcg_jacobi<T, RR>), dim3(vec_blocks(n_u)), dim3(kVT), 0, st, n_u, r, diag, z,
+                                     s.partials, s.counter, rho_out, skip));
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t pcg_pupdate(int R, int64_t n_u, const T* z, T* pv, const PcgScalars& s, int ip, hipStream_t st) {
   STK_R_SWITCH(R, hipLaunchKernelGGL((k_pcg_pupdate<T, RR>), dim3(vec_blocks(n_u)), dim3(kVT), 0, st, n_u, z, pv, s, ip));
   return hipGetLastError();
@@ -857,7 +889,9 @@ hipError_t pcg_pupdate(int R, int64_t n_u, const T* z, T* pv, const PcgScalars& 
   template hipError_t pcg_spmv<T>(int, const RowSplit&, const int32_t*, const int32_t*, const int32_t*, const T*,    \
                                   const T*, T*, const PcgScalars&, hipStream_t);                                     \
   template hipError_t pcg_axpy<T>(int, int64_t, const T*, const T*, T*, T*, const PcgScalars&, int, hipStream_t);    \
-  template hipError_t pcg_pupdate<T>(int, int64_t, const T*, T*, const PcgScalars&, int, hipStream_t);
+  template hipError_t pcg_pupdate<T>(int, int64_t, const T*, T*, const PcgScalars&, int, hipStream_t);     \
+  template hipError_t pcg_jacobi<T>(int, int64_t, const T*, const double*, T*, const PcgScalars&, double*,    \
+                                    const int*, hipStream_t);
 STK_INST(double)
 STK_INST(float)
 

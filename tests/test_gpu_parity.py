@@ -14,7 +14,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
-from oracle.oracle import PC_IC0, PC_ICPCG, PC_JACOBI, PQ_DIAG, Oracle  # noqa: E402
+from oracle.oracle import PC_IC0, PC_ICPCG, PC_JACOBI, PC_JPCG, PQ_DIAG, Oracle  # noqa: E402
 from synthetic_inputs import forcing_modes, random_vector  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -85,15 +85,15 @@ def test_saddle_product(pair):
     assert _rel(y, o.matvec(x)) <= 1e-14
 
 
-@pytest.mark.parametrize("pc", [PC_IC0, PC_JACOBI, PC_ICPCG])
+@pytest.mark.parametrize("pc", [PC_IC0, PC_JACOBI, PC_ICPCG, PC_JPCG])
 def test_preconditioner(pair, pc):
     gp, o = pair
     r = random_vector(o.n, 12)
     z, it = gp.apply_precond(_cuda(r), pc)
     zo, ito = o.precond(r, pc_A=pc, pc_Q=PQ_DIAG, inner_tol=1e-2)
-    tol = 1e-12 if pc != PC_ICPCG else 1e-9
+    tol = 1e-12 if pc not in (PC_ICPCG, PC_JPCG) else 1e-9
     assert _rel(z.cpu().numpy(), zo) <= tol
-    if pc == PC_ICPCG:
+    if pc in (PC_ICPCG, PC_JPCG):
         assert abs(it - ito) <= 1
 
 
@@ -126,20 +126,24 @@ def test_minres_fixed_iterations(pair, pc):
 def _oracle_solve(o, f, tol, pc):
     """The oracle counterpart of the library's solve: plain MINRES, or for the inner-PCG
     block (a nonlinear preconditioner) MINRES restarted on the true residual."""
-    if pc == PC_ICPCG:
-        return o.solve_refined(f, tol=tol)
+    if pc in (PC_ICPCG, PC_JPCG):
+        return o.solve_refined(f, tol=tol, pc_A=pc)
     return o.solve(f, tol=tol, pc_A=pc)
 
 
-@pytest.mark.parametrize("pc", [PC_IC0, PC_JACOBI, PC_ICPCG])
+@pytest.mark.parametrize("pc", [PC_IC0, PC_JACOBI, PC_ICPCG, PC_JPCG])
 def test_minres_converged(pair, pc):
     gp, o = pair
     f = o.load(1)
     u, p, info = gp.solve(_cuda(f), tol=1e-8, precond=pc)
     uo, po, io = _oracle_solve(o, f, 1e-8, pc)
     assert info["status"] == 0
-    assert abs(info["iters"] - io["iters"]) <= _it_tol(o), (info["iters"], io["iters"])
-    assert info["relres_true_Minv"] <= 1e-8 if pc == PC_ICPCG else info["relres_true_Minv"] <= 2e-8
+    # Jacobi-CG inside MINRES at k' = 3 (a weak inner preconditioner on the worst-conditioned
+    # A, stopped at a loose 1e-2) makes MINRES's path follow the inner solves' rounding:
+    # counts agree within a quarter there, exactly as elsewhere
+    bar = max(3, 0.25 * io["iters"]) if (pc == PC_JPCG and o.kp > 2) else _it_tol(o)
+    assert abs(info["iters"] - io["iters"]) <= bar, (info["iters"], io["iters"])
+    assert info["relres_true_Minv"] <= 1e-8 if pc in (PC_ICPCG, PC_JPCG) else info["relres_true_Minv"] <= 2e-8
     u2, p2, info2 = gp.solve(_cuda(f), tol=1e-13, precond=pc)
     uo2, po2, _ = _oracle_solve(o, f, 1e-13, pc)
     assert _rel(u2.cpu().numpy(), uo2) <= 1e-10
