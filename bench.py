@@ -120,7 +120,7 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1309_5048_amd import StokesProblem, PC_IC0, PC_ICPCG, PC_JPCG, MIXED, FP64
+    from paper_1309_5048_amd import StokesProblem, PC_IC0, PC_ICPCG, PC_JPCG, PC_PCGAQ, MIXED, FP64
 
     torch.cuda.set_device(0)
     N, kp, dim, tol = 256, 2, 2, 1e-8
@@ -204,6 +204,15 @@ def main():
             log("jpcg", extra["c1_jpcg_inner1e-2"])
         except Exception as e:  # report, keep the headline
             extra["c1_jpcg_inner1e-2"] = {"error": str(e)}
+        try:
+            # PCG(A,Q): Jacobi-preconditioned inner CG on both blocks
+            s_q, inf_q = timed_solves(gp, f, 1, 1, tol=tol, precond=PC_PCGAQ)
+            extra["c1_pcgAQ_inner1e-2"] = {"s": round(s_q, 5), "iters": inf_q[-1]["iters"],
+                                           "inner_iters_total": inf_q[-1]["inner_iters_total"],
+                                           "relres_true_Minv": inf_q[-1]["relres_true_Minv"]}
+            log("pcgAQ", extra["c1_pcgAQ_inner1e-2"])
+        except Exception as e:  # report, keep the headline
+            extra["c1_pcgAQ_inner1e-2"] = {"error": str(e)}
         del gp
         torch.cuda.empty_cache()
         try:

@@ -59,6 +59,9 @@ extern "C" {
                               STOKES_PC_ICPCG a nonlinear preconditioner, so MINRES is
                               restarted on the true residual until it meets tol in the norm
                               of blkdiag(Diag(A), Diag(Q)/(2 nu)).  Value 3 is not used.   */
+#define STOKES_PC_PCGAQ 5  /* PCG(A,Q) of Sec. 5.1: STOKES_PC_JPCG on the velocity block and
+                              M_Q^{-1} r = 2 nu x, x from Diag(Q)-preconditioned CG on
+                              Q x = r (same tolerance); restarted like STOKES_PC_JPCG       */
 
 /* Arithmetic of the Krylov iteration. */
 #define STOKES_FP64 0  /* everything in double precision                                  */

@@ -145,6 +145,7 @@ struct Work {
   void *v[2] = {nullptr, nullptr}, *z[2] = {nullptr, nullptr}, *w[2] = {nullptr, nullptr};
   void *x = nullptr, *q = nullptr, *b = nullptr, *y = nullptr;
   void *pr = nullptr, *pp = nullptr, *pq = nullptr, *pz = nullptr;  // inner PCG
+  void *qr = nullptr, *qp = nullptr, *qq = nullptr, *qz = nullptr;  // pressure-block PCG
   void *xr = nullptr, *br = nullptr;  // refinement: accumulated solution, original rhs (FP64)
 };
 
@@ -176,6 +177,13 @@ struct stokes_problem {
   std::vector<std::unique_ptr<SchedPair>> scheds;
   MrScalars mr;
   PcgScalars pcg;
+  // pressure-block CG (PCG(A,Q)): Q in CSR, its row ranges, FP32 values, scalars
+  int32_t *Qrowptr = nullptr, *Qcol = nullptr;
+  double* Qval = nullptr;
+  float* Qval32 = nullptr;
+  RowSplit rs_Q;
+  std::vector<int32_t> Qrowptr_h, split_Q_h;
+  PcgScalars pcgQ;
   double* scratch = nullptr;  // [64] small host-visible results
   double* partials = nullptr;
   unsigned int* counter = nullptr;
@@ -578,6 +586,11 @@ int get_work(stokes_problem* pb, int R, bool fp32, Work** out) {
   W.pp = get(nu);
   W.pq = get(nu);
   W.pz = get(nu);
+  const size_t np = size_t(pb->S.n_p) * R;
+  W.qr = get(np);
+  W.qp = get(np);
+  W.qq = get(np);
+  W.qz = get(np);
   if (pb->mem.err != hipSuccess) return fail_hip(pb, pb->mem.err, "workspace allocation", __LINE__);
   pb->work[key] = W;
   *out = &pb->work[key];
@@ -612,12 +625,13 @@ int precond_velocity(stokes_problem* pb, int precond, Work& W, SchedPair* sp, co
     CK(launch_trsv(sp->bwd, fp32, R, W.y, zout, vin, dot_out, skip, st, prof_take(pb, 2)));
     return 0;
   }
-  if (precond == STOKES_PC_ICPCG || precond == STOKES_PC_JPCG) {
+  const bool jacobi_cg = precond == STOKES_PC_JPCG || precond == STOKES_PC_PCGAQ;
+  if (precond == STOKES_PC_ICPCG || jacobi_cg) {
     const T* val = fp32 ? (const T*)pb->val32 : (const T*)pb->val;
     PcgScalars& s = pb->pcg;
     // z = M^{-1} r with rho = r.z: the IC(0) triangular solves (fused dot), or Jacobi
     auto inner_precond = [&](double* rho_out, const int* sk, bool prof) -> hipError_t {
-      if (precond == STOKES_PC_JPCG)
+      if (jacobi_cg)
         return pcg_jacobi<T>(R, n_u, (const T*)W.pr, pb->diagA, (T*)W.pz, s, rho_out, sk, st);
       hipError_t e = launch_trsv(sp->fwd, fp32, R, W.pr, W.y, nullptr, nullptr, sk, st, prof ? prof_take(pb, 1) : nullptr);
       if (e != hipSuccess) return e;
@@ -629,7 +643,7 @@ int precond_velocity(stokes_problem* pb, int precond, Work& W, SchedPair* sp, co
     int ip = 0;
     // iterations are queued in chunks between host checks of the done flag (Jacobi-PCG
     // runs many cheap iterations, IC(0)-PCG a few long ones)
-    const int chunk_it = precond == STOKES_PC_JPCG ? 16 : 4;
+    const int chunk_it = jacobi_cg ? 16 : 4;
     for (int it = 0; it < pb->maxit_inner; it += chunk_it) {
       for (int k = 0; k < chunk_it; ++k) {
         CK(pcg_spmv<T>(R, pb->rs_A, pb->rowptr, pb->aend, pb->col, val, (const T*)W.pp, (T*)W.pq, s, st));
@@ -651,6 +665,86 @@ int precond_velocity(stokes_problem* pb, int precond, Work& W, SchedPair* sp, co
   return 0;  // Jacobi: handled inside the vector kernels
 }
 
+// Q in CSR (pattern of overlapping pressure supports, values by quadrature) and the
+// pressure-block CG scalars, built on first use.
+int ensure_pressure_cg(stokes_problem* pb) {
+  if (pb->Qval != nullptr) return 0;
+  const Spaces& S = pb->S;
+  const int nlo = S.nlo, kp = S.kp, dim = S.dim;
+  const int64_t np = S.n_p;
+  std::vector<int32_t>& rp = pb->Qrowptr_h;
+  std::vector<int32_t> cl;
+  rp.assign(size_t(np) + 1, 0);
+  for (int64_t r = 0; r < np; ++r) {
+    int i[3] = {int(r % nlo), dim > 1 ? int((r / nlo) % nlo) : 0, dim > 2 ? int(r / (int64_t(nlo) * nlo)) : 0};
+    int lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = d < dim ? std::max(0, i[d] - kp) : 0;
+      hi[d] = d < dim ? std::min(nlo - 1, i[d] + kp) : 0;
+    }
+    for (int j2 = lo[2]; j2 <= hi[2]; ++j2)
+      for (int j1 = lo[1]; j1 <= hi[1]; ++j1)
+        for (int j0 = lo[0]; j0 <= hi[0]; ++j0) cl.push_back(int32_t(j0 + int64_t(nlo) * (j1 + int64_t(nlo) * j2)));
+    rp[size_t(r) + 1] = int32_t(cl.size());
+  }
+  DevAlloc& m = pb->mem;
+  hipStream_t st = pb->stream;
+  pb->Qrowptr = m.upload(rp, st);
+  pb->Qcol = m.upload(cl, st);
+  pb->Qval = m.get<double>(cl.size());
+  pb->Qval32 = m.get<float>(cl.size());
+  pb->rs_Q.nb = row_split_blocks(np, pb->num_cu);
+  pb->split_Q_h = balanced_row_split(rp, nullptr, np, pb->rs_Q.nb);
+  pb->rs_Q.split = m.upload(pb->split_Q_h, st);
+  pb->pcgQ.st = m.get<PcgState>(kRMax);
+  pb->pcgQ.alldone = m.get<int>(1);
+  pb->pcgQ.rho = m.get<double>(2 * kRMax);
+  pb->pcgQ.pq = m.get<double>(kRMax);
+  pb->pcgQ.rr = m.get<double>(kRMax);
+  pb->pcgQ.partials = pb->partials;
+  pb->pcgQ.counter = pb->counter + 2;
+  if (m.err != hipSuccess) return fail_hip(pb, m.err, "pressure-block CG allocation", __LINE__);
+  CK(hipMemsetAsync(pb->pcgQ.st, 0, kRMax * sizeof(PcgState), st));
+  CK(assemble_Q(S, pb->Qrowptr, pb->Qcol, pb->Qval, st));
+  CK(convert<double, float>(int64_t(cl.size()), pb->Qval, pb->Qval32, st));
+  CK(hipStreamSynchronize(st));  // the host vectors must outlive the copies
+  return 0;
+}
+
+// Pressure block of the PCG(A,Q) preconditioner: zout_p = 2 nu Q^{-1} vin_p by
+// Diag(Q)-preconditioned CG (x0 = 0, relative tolerance inner_tol), and the dot
+// v_p . z_p into dot_out[R].  vin_p / zout_p point at the pressure rows (row n_u).
+template <typename T>
+int precond_pressure(stokes_problem* pb, Work& W, const T* vin_p, T* zout_p, double* dot_out, const int* skip,
+                     const MinresState* outer_st) {
+  const int R = W.R;
+  const bool fp32 = W.fp32;
+  hipStream_t st = pb->stream;
+  const int64_t n_p = pb->S.n_p;
+  const T* qval = fp32 ? (const T*)pb->Qval32 : (const T*)pb->Qval;
+  PcgScalars& s = pb->pcgQ;
+  CK(pcg_init<T>(R, n_p, vin_p, (T*)W.qr, zout_p, s, skip, st));
+  CK(pcg_jacobi<T>(R, n_p, (const T*)W.qr, pb->diagQ, (T*)W.qz, s, s.rho, skip, st));
+  CK(pcg_init2<T>(R, n_p, (const T*)W.qz, (T*)W.qp, s, pb->inner_tol, pb->maxit_inner, skip, outer_st, st));
+  int ip = 0;
+  for (int it = 0; it < pb->maxit_inner; it += 16) {
+    for (int k = 0; k < 16; ++k) {
+      CK(pcg_spmv<T>(R, pb->rs_Q, pb->Qrowptr, nullptr, pb->Qcol, qval, (const T*)W.qp, (T*)W.qq, s, st));
+      CK(pcg_axpy<T>(R, n_p, (const T*)W.qp, (const T*)W.qq, zout_p, (T*)W.qr, s, ip, st));
+      CK(pcg_jacobi<T>(R, n_p, (const T*)W.qr, pb->diagQ, (T*)W.qz, s, s.rho + (1 - ip) * kRMax, s.alldone, st));
+      CK(pcg_pupdate<T>(R, n_p, (const T*)W.qz, (T*)W.qp, s, ip, st));
+      ip = 1 - ip;
+    }
+    int done = 0;
+    CK(hipMemcpyAsync(&done, s.alldone, sizeof(int), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    if (done) break;
+  }
+  CK(scale_skip<T>(n_p * R, zout_p, 2.0 * pb->nu, skip, st));
+  CK(dot<T, T>(R, 0, n_p, vin_p, zout_p, pb->partials, pb->counter, dot_out, st));
+  return 0;
+}
+
 struct RunOut {
   int iters[kRMax];
   int status[kRMax];
@@ -665,9 +759,15 @@ int minres_run(stokes_problem* pb, Work& W, int precond, double tol, int maxit, 
   hipStream_t st = pb->stream;
   const int64_t n_u = pb->S.n_u, n = n_u + pb->S.n_p;
   SchedPair* sp = nullptr;
-  if (precond != STOKES_PC_JACOBI && precond != STOKES_PC_JPCG) {
+  if (precond != STOKES_PC_JACOBI && precond != STOKES_PC_JPCG && precond != STOKES_PC_PCGAQ) {
     int rc = get_schedule(pb, R, fp32, &sp);
     if (rc) return rc;
+  }
+  const bool pcg_q = precond == STOKES_PC_PCGAQ;
+  if (pcg_q) {
+    int rc = ensure_pressure_cg(pb);
+    if (rc) return rc;
+    CK(hipMemsetAsync(pb->pcgQ.st, 0, sizeof(PcgState) * kRMax, st));
   }
   const T* val = fp32 ? (const T*)pb->val32 : (const T*)pb->val;
   const double* diagA = precond == STOKES_PC_JACOBI ? pb->diagA : nullptr;
@@ -679,12 +779,16 @@ int minres_run(stokes_problem* pb, Work& W, int precond, double tol, int maxit, 
   T* x = (T*)W.x;
   T* q = (T*)W.q;
   // reset the PCG column totals
-  if (precond == STOKES_PC_ICPCG || precond == STOKES_PC_JPCG)
+  if (precond == STOKES_PC_ICPCG || precond == STOKES_PC_JPCG || pcg_q)
     CK(hipMemsetAsync(pb->pcg.st, 0, sizeof(PcgState) * kRMax, st));
   CK(mr_init_vec<T>(R, n, n_u, (const T*)W.b, v[0], v[1], w[0], w[1], x, z[0], pb->diagQ, diagA, two_nu, s, st));
   // the outer state is not initialised yet: no outer-done test for this application
   int rc = precond_velocity<T>(pb, precond, W, sp, v[0], z[0], s.red + RED_G2U * kRMax, nullptr, nullptr, nullptr);
   if (rc) return rc;
+  if (pcg_q) {  // the pressure block replaces the Diag(Q) part the vector kernel wrote
+    rc = precond_pressure<T>(pb, W, v[0] + n_u * R, z[0] + n_u * R, s.red + RED_G2P * kRMax, nullptr, nullptr);
+    if (rc) return rc;
+  }
   CK(mr_init_state(R, s, tol, maxit, st));
   if (pb->hflag == nullptr) {
     CK(hipHostMalloc((void**)&pb->hflag, 2 * sizeof(int), hipHostMallocDefault));
@@ -711,6 +815,11 @@ int minres_run(stokes_problem* pb, Work& W, int precond, double tol, int maxit, 
                                s.red + ((size_t)p * RED_KINDS + RED_G2U) * kRMax, s.alldone + p, s.st + p * kRMax,
                                nullptr);
       if (rc) return rc;
+      if (pcg_q) {
+        rc = precond_pressure<T>(pb, W, v[1 - p] + n_u * R, z[1 - p] + n_u * R,
+                                 s.red + ((size_t)p * RED_KINDS + RED_G2P) * kRMax, s.alldone + p, s.st + p * kRMax);
+        if (rc) return rc;
+      }
       {
         PROF_BEGIN(4);
         CK(mr_update<T>(R, n, z[p], w[p], w[1 - p], x, s, p, st));
@@ -769,7 +878,9 @@ int true_residuals(stokes_problem* pb, Work& W, int precond, const double* b, co
   double* r = (double*)W.q;
   double* out = pb->scratch;  // [0..2R) norms, [2R..4R) r M r parts, [4R..6R) b M b parts
   CK(spmv_resid<double>(R, pb->rs_full, pb->rowptr, nullptr, pb->col, pb->val, x, b, r, pb->partials, pb->counter, out, st));
-  const int pcl = (precond == STOKES_PC_JACOBI || precond == STOKES_PC_JPCG) ? STOKES_PC_JACOBI : STOKES_PC_IC0;
+  const int pcl = (precond == STOKES_PC_JACOBI || precond == STOKES_PC_JPCG || precond == STOKES_PC_PCGAQ)
+                      ? STOKES_PC_JACOBI
+                      : STOKES_PC_IC0;
   for (int pass = 0; pass < 2; ++pass) {
     const double* vec = pass == 0 ? r : b;
     double* o = out + 2 * R + pass * 2 * R;
@@ -815,7 +926,7 @@ int solve_core(stokes_problem* pb, Work& W64, int precond, int precision, double
   int status[kRMax] = {0};
   double eta_rel[kRMax] = {0};
   int cycles = 1;
-  const bool inner_pcg = precond == STOKES_PC_ICPCG || precond == STOKES_PC_JPCG;
+  const bool inner_pcg = precond == STOKES_PC_ICPCG || precond == STOKES_PC_JPCG || precond == STOKES_PC_PCGAQ;
   if (precision == STOKES_FP64 && !inner_pcg) {
     int rc = minres_run<double>(pb, W64, precond, tol, pb->maxit_outer, ro);
     if (rc) return rc;
@@ -938,10 +1049,13 @@ int solve_core(stokes_problem* pb, Work& W64, int precond, int precision, double
       infos[c].reserved = 0;
     }
     if (inner_pcg) {
-      PcgState ps[kRMax];
+      PcgState ps[kRMax], pq[kRMax];
       CK(hipMemcpyAsync(ps, pb->pcg.st, sizeof(PcgState) * kRMax, hipMemcpyDeviceToHost, st));
+      if (precond == STOKES_PC_PCGAQ)
+        CK(hipMemcpyAsync(pq, pb->pcgQ.st, sizeof(PcgState) * kRMax, hipMemcpyDeviceToHost, st));
       CK(hipStreamSynchronize(st));
-      for (int c = 0; c < nrhs; ++c) infos[c].inner_iters_total = ps[c].total;
+      for (int c = 0; c < nrhs; ++c)
+        infos[c].inner_iters_total = ps[c].total + (precond == STOKES_PC_PCGAQ ? pq[c].total : 0);
     }
   }
   int worst = 0;
@@ -955,7 +1069,7 @@ int solve_core(stokes_problem* pb, Work& W64, int precond, int precision, double
 
 int check_args_solve(stokes_problem* pb, double tol, int precond, int precision) {
   if (!(tol > 0.0) || !(tol < 1.0)) return fail(pb, STOKES_EINVAL, "tol must be in (0, 1)");
-  if (precond < 0 || precond > 4 || precond == 3) return fail(pb, STOKES_EINVAL, "unknown preconditioner");
+  if (precond < 0 || precond > 5 || precond == 3) return fail(pb, STOKES_EINVAL, "unknown preconditioner");
   if (precision != STOKES_FP64 && precision != STOKES_MIXED) return fail(pb, STOKES_EINVAL, "unknown precision");
   return 0;
 }
@@ -1333,7 +1447,7 @@ int stokes_apply(stokes_problem* pb, const double* x, double* y) {
 }
 
 int stokes_apply_precond(stokes_problem* pb, int precond, const double* r, double* y, int* inner_iters) {
-  if (!pb || !r || !y || precond < 0 || precond > 4 || precond == 3) return fail(pb, STOKES_EINVAL, "bad arguments");
+  if (!pb || !r || !y || precond < 0 || precond > 5 || precond == 3) return fail(pb, STOKES_EINVAL, "bad arguments");
   Work* W = nullptr;
   int rc = get_work(pb, 1, false, &W);
   if (rc) return rc;
@@ -1344,17 +1458,28 @@ int stokes_apply_precond(stokes_problem* pb, int precond, const double* r, doubl
   CK(hipGetLastError());
   if (precond != STOKES_PC_JACOBI) {
     SchedPair* sp = nullptr;
-    if (precond != STOKES_PC_JPCG && (rc = get_schedule(pb, 1, false, &sp))) return rc;
-    if (precond == STOKES_PC_ICPCG || precond == STOKES_PC_JPCG)
-      CK(hipMemsetAsync(pb->pcg.st, 0, sizeof(PcgState) * kRMax, st));
+    const bool jac = precond == STOKES_PC_JPCG || precond == STOKES_PC_PCGAQ;
+    if (!jac && (rc = get_schedule(pb, 1, false, &sp))) return rc;
+    if (precond != STOKES_PC_IC0) CK(hipMemsetAsync(pb->pcg.st, 0, sizeof(PcgState) * kRMax, st));
     rc = precond_velocity<double>(pb, precond, *W, sp, r, y, pb->scratch + 100, nullptr, nullptr, nullptr);
     if (rc) return rc;
     if (sp && (rc = check_trsv_err(pb, sp))) return rc;
-    if (inner_iters && (precond == STOKES_PC_ICPCG || precond == STOKES_PC_JPCG)) {
+    int qtotal = 0;
+    if (precond == STOKES_PC_PCGAQ) {
+      if ((rc = ensure_pressure_cg(pb))) return rc;
+      CK(hipMemsetAsync(pb->pcgQ.st, 0, sizeof(PcgState) * kRMax, st));
+      rc = precond_pressure<double>(pb, *W, r + n_u, y + n_u, pb->scratch + 101, nullptr, nullptr);
+      if (rc) return rc;
+      PcgState pq;
+      CK(hipMemcpyAsync(&pq, pb->pcgQ.st, sizeof(PcgState), hipMemcpyDeviceToHost, st));
+      CK(hipStreamSynchronize(st));
+      qtotal = pq.total;
+    }
+    if (inner_iters && precond != STOKES_PC_IC0) {
       PcgState ps;
       CK(hipMemcpyAsync(&ps, pb->pcg.st, sizeof(PcgState), hipMemcpyDeviceToHost, st));
       CK(hipStreamSynchronize(st));
-      *inner_iters = ps.total;
+      *inner_iters = ps.total + qtotal;
     }
   }
   CK(hipStreamSynchronize(st));

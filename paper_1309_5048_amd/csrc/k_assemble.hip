@@ -339,6 +339,48 @@ __global__ void k_pressure_mass(AsmArgs a, double* __restrict__ diagQ, double* _
   w[k] = s1;
 }
 
+// Q_kl = int phi_k phi_l over the elements the two supports share; one wavefront per row,
+// lanes over the row's entries (the pressure mass matrix, for the pressure-block CG).
+__device__ double q_entry(const AsmArgs& a, int64_t k, int64_t l) {
+  Fun fk, fl;
+  decode_dof(a, a.n_u + k, fk);
+  decode_dof(a, a.n_u + l, fl);
+  int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = max(fk.elo[d], fl.elo[d]);
+    hi[d] = min(fk.ehi[d], fl.ehi[d]);
+    if (lo[d] > hi[d]) return 0.0;
+  }
+  const double h = 1.0 / a.N;
+  double vol = 1.0;
+  for (int d = 0; d < a.dim; ++d) vol *= h;
+  const int nq2 = a.dim == 3 ? a.nq : 1;
+  double s = 0.0;
+  int e[3], q[3];
+  for (e[2] = lo[2]; e[2] <= hi[2]; ++e[2])
+    for (e[1] = lo[1]; e[1] <= hi[1]; ++e[1])
+      for (e[0] = lo[0]; e[0] <= hi[0]; ++e[0])
+        for (q[2] = 0; q[2] < nq2; ++q[2])
+          for (q[1] = 0; q[1] < a.nq; ++q[1])
+            for (q[0] = 0; q[0] < a.nq; ++q[0]) {
+              double wt = vol;
+              for (int d = 0; d < a.dim; ++d) wt *= a.wq[q[d]];
+              double Bk, Bl, G[3];
+              eval_fun(a, fk, e, q, &Bk, G);
+              eval_fun(a, fl, e, q, &Bl, G);
+              s += wt * Bk * Bl;
+            }
+  return s;
+}
+
+__global__ void k_assemble_Q(AsmArgs a, int64_t nrows, const int32_t* __restrict__ rowptr,
+                             const int32_t* __restrict__ col, double* __restrict__ val) {
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  const int lane = threadIdx.x & 63;
+  if (row >= nrows) return;
+  for (int32_t k = rowptr[row] + lane; k < rowptr[row + 1]; k += 64) val[k] = q_entry(a, row, col[k]);
+}
+
 // ---------------------------------------------------------------------------
 // Load vector.  Forcing: manufactured (curl of x^2(1-x)^2 y^2(1-y)^2 in 2D, curl of
 // (g,g,g) with g = phi(x)phi(y)phi(z) in 3D, pressure prod cos(pi x_d), f = -nu Lap u +
@@ -514,6 +556,24 @@ hipError_t assemble_saddle(const Spaces& S, double nu, double cpen, const int32_
   hipLaunchKernelGGL(k_assemble_saddle, dim3(unsigned((n + rows_per_block - 1) / rows_per_block)), dim3(256), 0, st,
                      a, n, rowptr, col, val);
   hipLaunchKernelGGL(k_pressure_mass, dim3(unsigned((S.n_p + 255) / 256)), dim3(256), 0, st, a, diagQ, w);
+  e = hipGetLastError();
+  hipError_t e2 = hipStreamSynchronize(st);
+  free_tables(T);
+  return e != hipSuccess ? e : e2;
+}
+
+hipError_t assemble_Q(const Spaces& S, const int32_t* rowptr, const int32_t* col, double* val, hipStream_t st) {
+  Tables T;
+  const int nq = S.kp + 2;
+  hipError_t e = build_tables(S, nq, T, st);
+  if (e != hipSuccess) {
+    free_tables(T);
+    return e;
+  }
+  AsmArgs a = make_args(S, 1.0, 0.0, nq, T);
+  const int rows_per_block = 4;
+  hipLaunchKernelGGL(k_assemble_Q, dim3(unsigned((S.n_p + rows_per_block - 1) / rows_per_block)), dim3(256), 0, st, a,
+                     S.n_p, rowptr, col, val);
   e = hipGetLastError();
   hipError_t e2 = hipStreamSynchronize(st);
   free_tables(T);

@@ -819,6 +819,22 @@ hipError_t accumulate(int R, int64_t nR, double* x, const Td* d, hipStream_t st)
   return hipGetLastError();
 }
 
+// a *= s unless *skip (device flag or null)
+template <typename T>
+__global__ void k_scale_skip(int64_t n, T* __restrict__ a, double s, const int* __restrict__ skip) {
+  if (skip != nullptr && *skip) return;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = T((double)a[i] * s);
+}
+
+template <typename T>
+hipError_t scale_skip(int64_t n, T* a, double s, const int* skip, hipStream_t st) {
+  hipLaunchKernelGGL(k_scale_skip<T>, dim3(1024), dim3(256), 0, st, n, a, s, skip);
+  return hipGetLastError();
+}
+template hipError_t scale_skip<double>(int64_t, double*, double, const int*, hipStream_t);
+template hipError_t scale_skip<float>(int64_t, float*, double, const int*, hipStream_t);
+
 hipError_t scale(int64_t n, double* a, double s, hipStream_t st) {
   hipLaunchKernelGGL(k_scale, dim3(1024), dim3(256), 0, st, n, a, s);
   return hipGetLastError();

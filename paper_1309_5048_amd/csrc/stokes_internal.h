@@ -357,6 +357,8 @@ struct PcgScalars {
 // ---------------------------------------------------------------------------
 hipError_t assemble_saddle(const Spaces& S, double nu, double cpen, const int32_t* rowptr, const int32_t* col,
                            double* val, double* diagQ, double* w, hipStream_t st);
+// Pressure mass matrix Q (CSR pattern given, values computed).
+hipError_t assemble_Q(const Spaces& S, const int32_t* rowptr, const int32_t* col, double* val, hipStream_t st);
 hipError_t assemble_load(const Spaces& S, double nu, int manufactured, int nmodes, int nrhs, const double* amp_d,
                          const int32_t* wave_d, const double* phase_d, double* f, hipStream_t st);
 hipError_t ic0_factor(int64_t n, int64_t nnzL, const int64_t* src, const int32_t* rowptr, const int32_t* col,
@@ -413,6 +415,8 @@ hipError_t convert(int64_t n, const Ts* a, Td* b, hipStream_t st);
 template <typename Td>
 hipError_t accumulate(int R, int64_t nR, double* x, const Td* d, hipStream_t st);
 hipError_t scale(int64_t n, double* a, double s, hipStream_t st);
+template <typename T>
+hipError_t scale_skip(int64_t n, T* a, double s, const int* skip, hipStream_t st);
 template <typename T>
 hipError_t pcg_init(int R, int64_t n_u, const T* b, T* r, T* x, const PcgScalars& s, const int* outer_done,
                     hipStream_t st);
