@@ -54,8 +54,7 @@ def lib():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise ImportError("libstokes.so not built: run `python -m paper_1309_5048_amd.build` "
-                          "(or __graft_entry__.build())")
+        raise ImportError("libstokes.so not built: run `python -m paper_1309_5048_amd.build`")
     L = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
     P = ctypes.POINTER
