@@ -229,10 +229,11 @@ class Oracle:
         bM = mnorm2(b0)
         x = np.zeros(self.n)
         b = b0.copy()
-        tol_k, iters, relM = tol, 0, np.inf
+        tol_k, iters, inner, relM = tol, 0, 0, np.inf
         for _ in range(cycles):
             d, inf = self.minres(b, tol=tol_k, maxit=maxit, pc_A=pc_A, pc_Q=pc_Q, inner_tol=inner_tol)
             iters += inf["iters"]
+            inner += inf["inner_total"]
             x = x + d
             x[self.n_u:] = self.project(x[self.n_u:])
             r = b0 - self.matvec(x)
@@ -241,7 +242,7 @@ class Oracle:
                 break
             b = r
             tol_k = min(0.5, 0.5 * tol / relM)
-        return x[: self.n_u], x[self.n_u:], {"iters": iters, "relres_true_Minv": relM}
+        return x[: self.n_u], x[self.n_u:], {"iters": iters, "inner_total": inner, "relres_true_Minv": relM}
 
     def project(self, p):
         p = _f64(p).copy()

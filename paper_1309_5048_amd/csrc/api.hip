@@ -184,6 +184,9 @@ struct stokes_problem {
   RowSplit rs_Q;
   std::vector<int32_t> Qrowptr_h, split_Q_h;
   PcgScalars pcgQ;
+  // inner CG iterations the last application needed (velocity, pressure): the first chunk
+  // queued before the host reads the done flag
+  int pcg_expect = 4, pcgq_expect = 4;
   double* scratch = nullptr;  // [64] small host-visible results
   double* partials = nullptr;
   unsigned int* counter = nullptr;
@@ -611,6 +614,22 @@ int check_trsv_err(stokes_problem* pb, const SchedPair* sp) {
   return 0;
 }
 
+// Inner CG state after a queued chunk: *done = all columns finished; once they have, the
+// largest iteration count of this application goes to *expect.  Returns nonzero on error.
+int pcg_done(stokes_problem* pb, const PcgScalars& s, int R, int* done, int* expect) {
+  PcgState ps[kRMax];
+  CK(hipMemcpyAsync(ps, s.st, sizeof(PcgState) * R, hipMemcpyDeviceToHost, pb->stream));
+  CK(hipStreamSynchronize(pb->stream));
+  int nd = 0, mx = 0;
+  for (int c = 0; c < R; ++c) {
+    nd += ps[c].done ? 1 : 0;
+    mx = std::max(mx, ps[c].iter);
+  }
+  *done = nd == R;
+  if (*done && mx > 0) *expect = mx;
+  return 0;
+}
+
 // Velocity block of the preconditioner: zout_u = M_A^{-1} vin_u, and the dot v_u . z_u
 // into dot_out[R].  skip: device flag (all columns done) or null.
 template <typename T>
@@ -641,20 +660,23 @@ int precond_velocity(stokes_problem* pb, int precond, Work& W, SchedPair* sp, co
     CK(inner_precond(s.rho, skip, false));
     CK(pcg_init2<T>(R, n_u, (const T*)W.pz, (T*)W.pp, s, pb->inner_tol, pb->maxit_inner, skip, outer_st, st));
     int ip = 0;
-    // iterations are queued in chunks between host checks of the done flag (Jacobi-PCG
-    // runs many cheap iterations, IC(0)-PCG a few long ones)
-    const int chunk_it = jacobi_cg ? 16 : 4;
-    for (int it = 0; it < pb->maxit_inner; it += chunk_it) {
+    // Iterations are queued in chunks between host reads of the done flag: first as many as
+    // the last application needed, then 4 at a time (iterations after convergence return
+    // at once on the device flag).
+    int queued = 0;
+    while (queued < pb->maxit_inner) {
+      const int chunk_it = std::min(pb->maxit_inner - queued, queued == 0 ? std::max(1, pb->pcg_expect) : 4);
+      queued += chunk_it;
       for (int k = 0; k < chunk_it; ++k) {
-        CK(pcg_spmv<T>(R, pb->rs_A, pb->rowptr, pb->aend, pb->col, val, (const T*)W.pp, (T*)W.pq, s, st));
+        CK(pcg_spmv<T>(R, pb->rs_A, pb->rowptr, pb->aend, pb->col, val, (const T*)W.pp, (T*)W.pq, s,
+                       precond == STOKES_PC_ICPCG, st));
         CK(pcg_axpy<T>(R, n_u, (const T*)W.pp, (const T*)W.pq, zout, (T*)W.pr, s, ip, st));
         CK(inner_precond(s.rho + (1 - ip) * kRMax, s.alldone, true));
         CK(pcg_pupdate<T>(R, n_u, (const T*)W.pz, (T*)W.pp, s, ip, st));
         ip = 1 - ip;
       }
       int done = 0;
-      CK(hipMemcpyAsync(&done, s.alldone, sizeof(int), hipMemcpyDeviceToHost, st));
-      CK(hipStreamSynchronize(st));
+      if (int e = pcg_done(pb, s, R, &done, &pb->pcg_expect)) return e;
       prof_flush(pb);
       if (done) break;
     }
@@ -727,17 +749,19 @@ int precond_pressure(stokes_problem* pb, Work& W, const T* vin_p, T* zout_p, dou
   CK(pcg_jacobi<T>(R, n_p, (const T*)W.qr, pb->diagQ, (T*)W.qz, s, s.rho, skip, st));
   CK(pcg_init2<T>(R, n_p, (const T*)W.qz, (T*)W.qp, s, pb->inner_tol, pb->maxit_inner, skip, outer_st, st));
   int ip = 0;
-  for (int it = 0; it < pb->maxit_inner; it += 16) {
-    for (int k = 0; k < 16; ++k) {
-      CK(pcg_spmv<T>(R, pb->rs_Q, pb->Qrowptr, nullptr, pb->Qcol, qval, (const T*)W.qp, (T*)W.qq, s, st));
+  int queued = 0;
+  while (queued < pb->maxit_inner) {
+    const int chunk_it = std::min(pb->maxit_inner - queued, queued == 0 ? std::max(1, pb->pcgq_expect) : 4);
+    queued += chunk_it;
+    for (int k = 0; k < chunk_it; ++k) {
+      CK(pcg_spmv<T>(R, pb->rs_Q, pb->Qrowptr, nullptr, pb->Qcol, qval, (const T*)W.qp, (T*)W.qq, s, false, st));
       CK(pcg_axpy<T>(R, n_p, (const T*)W.qp, (const T*)W.qq, zout_p, (T*)W.qr, s, ip, st));
       CK(pcg_jacobi<T>(R, n_p, (const T*)W.qr, pb->diagQ, (T*)W.qz, s, s.rho + (1 - ip) * kRMax, s.alldone, st));
       CK(pcg_pupdate<T>(R, n_p, (const T*)W.qz, (T*)W.qp, s, ip, st));
       ip = 1 - ip;
     }
     int done = 0;
-    CK(hipMemcpyAsync(&done, s.alldone, sizeof(int), hipMemcpyDeviceToHost, st));
-    CK(hipStreamSynchronize(st));
+    if (int e = pcg_done(pb, s, R, &done, &pb->pcgq_expect)) return e;
     if (done) break;
   }
   CK(scale_skip<T>(n_p * R, zout_p, 2.0 * pb->nu, skip, st));
@@ -767,7 +791,6 @@ int minres_run(stokes_problem* pb, Work& W, int precond, double tol, int maxit, 
   if (pcg_q) {
     int rc = ensure_pressure_cg(pb);
     if (rc) return rc;
-    CK(hipMemsetAsync(pb->pcgQ.st, 0, sizeof(PcgState) * kRMax, st));
   }
   const T* val = fp32 ? (const T*)pb->val32 : (const T*)pb->val;
   const double* diagA = precond == STOKES_PC_JACOBI ? pb->diagA : nullptr;
@@ -778,9 +801,6 @@ int minres_run(stokes_problem* pb, Work& W, int precond, double tol, int maxit, 
   T* w[2] = {(T*)W.w[0], (T*)W.w[1]};
   T* x = (T*)W.x;
   T* q = (T*)W.q;
-  // reset the PCG column totals
-  if (precond == STOKES_PC_ICPCG || precond == STOKES_PC_JPCG || pcg_q)
-    CK(hipMemsetAsync(pb->pcg.st, 0, sizeof(PcgState) * kRMax, st));
   CK(mr_init_vec<T>(R, n, n_u, (const T*)W.b, v[0], v[1], w[0], w[1], x, z[0], pb->diagQ, diagA, two_nu, s, st));
   // the outer state is not initialised yet: no outer-done test for this application
   int rc = precond_velocity<T>(pb, precond, W, sp, v[0], z[0], s.red + RED_G2U * kRMax, nullptr, nullptr, nullptr);
@@ -927,6 +947,15 @@ int solve_core(stokes_problem* pb, Work& W64, int precond, int precision, double
   double eta_rel[kRMax] = {0};
   int cycles = 1;
   const bool inner_pcg = precond == STOKES_PC_ICPCG || precond == STOKES_PC_JPCG || precond == STOKES_PC_PCGAQ;
+  // inner CG totals count over every refinement cycle of this solve
+  if (inner_pcg) {
+    CK(hipMemsetAsync(pb->pcg.st, 0, sizeof(PcgState) * kRMax, st));
+    if (precond == STOKES_PC_PCGAQ) {
+      int rc = ensure_pressure_cg(pb);
+      if (rc) return rc;
+      CK(hipMemsetAsync(pb->pcgQ.st, 0, sizeof(PcgState) * kRMax, st));
+    }
+  }
   if (precision == STOKES_FP64 && !inner_pcg) {
     int rc = minres_run<double>(pb, W64, precond, tol, pb->maxit_outer, ro);
     if (rc) return rc;

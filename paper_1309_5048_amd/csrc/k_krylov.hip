@@ -85,12 +85,21 @@ constexpr int kStageRows = 512;  // rows whose entry ranges a block stages in LD
 // acc with every load of the chunk issued before the first use.  Lanes past the row end
 // load the row's last entry again and add nothing.
 //
-// Matrix entries are read with non-temporal loads: each product streams them once, and
-// ordinary loads would let them (about 210 MB for the 2D N = 256, k' = 2 system) evict the
-// triangular-solve schedules from the last-level cache between products.  Measured in a
-// MINRES-IC(0) solve of that system: 412 -> 311 us per triangular solve, 62 -> 72 us per
-// product.
-template <int R, int U, typename Acc, typename T>
+// The saddle product reads matrix entries with non-temporal loads: each product streams
+// them once, and ordinary loads would let them (about 210 MB for the 2D N = 256, k' = 2
+// system) evict the triangular-solve schedules from the last-level cache between products.
+// Measured in a MINRES-IC(0) solve of that system: 412 -> 311 us per triangular solve,
+// 62 -> 72 us per product.  The inner CG's product over the A rows takes either policy
+// (NT): non-temporal beside the IC(0) schedules, ordinary where the A entries are the
+// loop's whole working set and stay cached between its iterations.
+// Matrix entry load: non-temporal (NT) or ordinary.
+template <bool NT, typename T>
+__device__ __forceinline__ T ld_entry(const T* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+
+template <int R, int U, bool NT, typename Acc, typename T>
 __device__ __forceinline__ void row_chunk(int32_t k0, int32_t ke, const int32_t* __restrict__ col,
                                           const T* __restrict__ val, const T* __restrict__ x, Acc (&acc)[R]) {
   int32_t j[U];
@@ -101,8 +110,8 @@ __device__ __forceinline__ void row_chunk(int32_t k0, int32_t ke, const int32_t*
     const int32_t k = k0 + u * kSG;
     ok[u] = k < ke;
     const int32_t kc = ok[u] ? k : ke - 1;
-    j[u] = __builtin_nontemporal_load(col + kc);
-    a[u] = __builtin_nontemporal_load(val + kc);
+    j[u] = ld_entry<NT>(col + kc);
+    a[u] = ld_entry<NT>(val + kc);
   }
 #pragma unroll
   for (int u = 0; u < U; ++u) {
@@ -121,7 +130,7 @@ __device__ __forceinline__ void row_chunk(int32_t k0, int32_t ke, const int32_t*
 // ranges are staged in LDS kStageRows at a time; the first chunk of every row of a pass is
 // loaded together (one row chunk for each of the group's rows), longer rows continue row
 // by row.  fin(i, acc) runs on lane 0 of the row's lane group with the row's sums.
-template <int R, typename Acc, typename T, typename Fin>
+template <int R, bool NT, typename Acc, typename T, typename Fin>
 __device__ __forceinline__ void csr_rows(const int32_t* __restrict__ split, const int32_t* __restrict__ rowptr,
                                          const int32_t* __restrict__ rowend, const int32_t* __restrict__ col,
                                          const T* __restrict__ val, const T* __restrict__ x, Fin fin) {
@@ -163,8 +172,8 @@ __device__ __forceinline__ void csr_rows(const int32_t* __restrict__ split, cons
             ok[q][u] = k < ke[q];
             // (entry 0 for an empty or absent row: a valid address whose value is not added)
             const int32_t kc = ok[q][u] ? k : (ke[q] > kb[q] ? ke[q] - 1 : 0);
-            j[q][u] = __builtin_nontemporal_load(col + kc);
-            a[q][u] = __builtin_nontemporal_load(val + kc);
+            j[q][u] = ld_entry<NT>(col + kc);
+            a[q][u] = ld_entry<NT>(val + kc);
           }
 #pragma unroll
         for (int q = 0; q < RPG; ++q)
@@ -182,7 +191,7 @@ __device__ __forceinline__ void csr_rows(const int32_t* __restrict__ split, cons
       // the rest of longer rows
 #pragma unroll
       for (int q = 0; q < RPG; ++q)
-        for (int32_t k0 = kb[q] + sub + U * kSG; k0 < ke[q]; k0 += U * kSG) row_chunk<R, U>(k0, ke[q], col, val, x, acc[q]);
+        for (int32_t k0 = kb[q] + sub + U * kSG; k0 < ke[q]; k0 += U * kSG) row_chunk<R, U, NT>(k0, ke[q], col, val, x, acc[q]);
 #pragma unroll
       for (int q = 0; q < RPG; ++q) {
 #pragma unroll
@@ -306,7 +315,7 @@ __global__ __launch_bounds__(kVT) void k_mr_spmv(const int32_t* __restrict__ spl
   double acc_d[R];
 #pragma unroll
   for (int c = 0; c < R; ++c) acc_d[c] = 0.0;
-  csr_rows<R, T>(split, rowptr, nullptr, col, val, z, [&](int64_t i, T (&acc)[R]) {
+  csr_rows<R, true, T>(split, rowptr, nullptr, col, val, z, [&](int64_t i, T (&acc)[R]) {
     T qv[R], zv[R];
     load_cols<R>(z + (size_t)i * R, zv);
 #pragma unroll
@@ -480,7 +489,7 @@ __global__ __launch_bounds__(kVT) void k_spmv_resid(const int32_t* __restrict__ 
   double acc_d[2 * R];
 #pragma unroll
   for (int c = 0; c < 2 * R; ++c) acc_d[c] = 0.0;
-  csr_rows<R, double>(split, rowptr, rowend, col, val, xin, [&](int64_t i, double (&acc)[R]) {
+  csr_rows<R, true, double>(split, rowptr, rowend, col, val, xin, [&](int64_t i, double (&acc)[R]) {
     T bv[R], yv[R];
     if (bvec) {
       load_cols<R>(bvec + (size_t)i * R, bv);
@@ -612,7 +621,7 @@ __global__ __launch_bounds__(kVT) void k_pcg_init2(int64_t n_u, const T* __restr
 }
 
 // q = A p (velocity rows, A part of the saddle CSR) and p.q partials
-template <typename T, int R>
+template <typename T, int R, bool NT>
 __global__ __launch_bounds__(kVT) void k_pcg_spmv(const int32_t* __restrict__ split, const int32_t* __restrict__ rowptr,
                                                   const int32_t* __restrict__ aend, const int32_t* __restrict__ col,
                                                   const T* __restrict__ val, const T* __restrict__ pv, T* __restrict__ q,
@@ -621,7 +630,7 @@ __global__ __launch_bounds__(kVT) void k_pcg_spmv(const int32_t* __restrict__ sp
   double acc_d[R];
 #pragma unroll
   for (int c = 0; c < R; ++c) acc_d[c] = 0.0;
-  csr_rows<R, T>(split, rowptr, aend, col, val, pv, [&](int64_t i, T (&acc)[R]) {
+  csr_rows<R, NT, T>(split, rowptr, aend, col, val, pv, [&](int64_t i, T (&acc)[R]) {
     T pw[R];
     load_cols<R>(pv + (size_t)i * R, pw);
 #pragma unroll
@@ -656,7 +665,7 @@ __global__ __launch_bounds__(kVT) void k_pcg_axpy(int64_t n_u, const T* __restri
       r[k] = T(rn);
       acc[c] += rn * rn;
     }
-  reduce_last<R>(acc, s.partials, s.counter, [&](int c, double v) {
+  const bool last = reduce_last<R>(acc, s.partials, s.counter, [&](int c, double v) {
     PcgState& st = s.st[c];
     if (!st.done) {
       st.rr = v;
@@ -665,6 +674,14 @@ __global__ __launch_bounds__(kVT) void k_pcg_axpy(int64_t n_u, const T* __restri
       if (v <= st.rtol2 * st.bnorm2 || st.iter >= st.maxit) st.done = 1;
     }
   });
+  if (last) {  // the all-done flag, in the block that finished the reduction
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int nd = 0;
+      for (int c = 0; c < R; ++c) nd += s.st[c].done;
+      *s.alldone = (nd == R);
+    }
+  }
 }
 
 // Jacobi preconditioner of the inner PCG: z = r / diag(A) and rho = r.z into rho_out[c]
@@ -689,16 +706,6 @@ __global__ __launch_bounds__(kVT) void k_pcg_jacobi(int64_t n_u, const T* __rest
     }
   }
   reduce_last<R>(acc, partials, counter, [&](int k, double v) { rho_out[k] = v; });
-}
-
-// all-done flag after k_pcg_axpy (single thread)
-template <int R>
-__global__ void k_pcg_check(PcgScalars s) {
-  if (threadIdx.x == 0) {
-    int nd = 0;
-    for (int c = 0; c < R; ++c) nd += s.st[c].done;
-    *s.alldone = (nd == R);
-  }
 }
 
 // beta = rho_new/rho; p = z + beta p  (rho_new in rho[1-ip])
@@ -858,9 +865,14 @@ hipError_t pcg_init2(int R, int64_t n_u, const T* z, T* pv, const PcgScalars& s,
 
 template <typename T>
 hipError_t pcg_spmv(int R, const RowSplit& rs, const int32_t* rowptr, const int32_t* aend, const int32_t* col,
-                    const T* val, const T* pv, T* q, const PcgScalars& s, hipStream_t st) {
-  STK_R_SWITCH(R, hipLaunchKernelGGL((k_pcg_spmv<T, RR>), dim3(rs.nb), dim3(kVT), 0, st, rs.split, rowptr, aend, col,
-                                     val, pv, q, s));
+                    const T* val, const T* pv, T* q, const PcgScalars& s, bool stream_entries, hipStream_t st) {
+  if (stream_entries) {
+    STK_R_SWITCH(R, hipLaunchKernelGGL((k_pcg_spmv<T, RR, true>), dim3(rs.nb), dim3(kVT), 0, st, rs.split, rowptr,
+                                       aend, col, val, pv, q, s));
+  } else {
+    STK_R_SWITCH(R, hipLaunchKernelGGL((k_pcg_spmv<T, RR, false>), dim3(rs.nb), dim3(kVT), 0, st, rs.split, rowptr,
+                                       aend, col, val, pv, q, s));
+  }
   return hipGetLastError();
 }
 
@@ -868,8 +880,7 @@ template <typename T>
 hipError_t pcg_axpy(int R, int64_t n_u, const T* pv, const T* q, T* x, T* r, const PcgScalars& s, int ip,
                     hipStream_t st) {
   STK_R_SWITCH(R, hipLaunchKernelGGL((k_pcg_axpy<T, RR>), dim3(vec_blocks(n_u)), dim3(kVT), 0, st, n_u, pv, q, x, r, s,
-                                     ip);
-               hipLaunchKernelGGL((k_pcg_check<RR>), dim3(1), dim3(64), 0, st, s));
+                                     ip));
   return hipGetLastError();
 }
 
@@ -903,7 +914,7 @@ hipError_t pcg_pupdate(int R, int64_t n_u, const T* z, T* pv, const PcgScalars& 
   template hipError_t pcg_init2<T>(int, int64_t, const T*, T*, const PcgScalars&, double, int, const int*,           \
                                    const MinresState*, hipStream_t);                                                 \
   template hipError_t pcg_spmv<T>(int, const RowSplit&, const int32_t*, const int32_t*, const int32_t*, const T*,    \
-                                  const T*, T*, const PcgScalars&, hipStream_t);                                     \
+                                  const T*, T*, const PcgScalars&, bool, hipStream_t);                               \
   template hipError_t pcg_axpy<T>(int, int64_t, const T*, const T*, T*, T*, const PcgScalars&, int, hipStream_t);    \
   template hipError_t pcg_pupdate<T>(int, int64_t, const T*, T*, const PcgScalars&, int, hipStream_t);     \
   template hipError_t pcg_jacobi<T>(int, int64_t, const T*, const double*, T*, const PcgScalars&, double*,    \

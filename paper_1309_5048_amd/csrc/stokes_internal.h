@@ -252,11 +252,11 @@ __device__ __forceinline__ void wait_vm_stores() { asm volatile("s_waitcnt vmcnt
 
 // Block reduction of NV values per thread; the last block to finish (ticket) adds all
 // block partials in a fixed order (thread t takes blocks t, t + kVT, ...; then a fixed
-// tree) and calls fin(k, value) for k < NV on threads k < NV.  Partials travel with
+// tree) and calls fin(k, value) for k < NV on threads k < NV; returns true in that block.  Partials travel with
 // device-scope stores and loads; a block takes its ticket only after its partial stores
 // are acknowledged, so the last block sees every partial.
 template <int NV, typename Fin>
-__device__ void reduce_last(double (&v)[NV], double* partials, unsigned int* counter, Fin fin) {
+__device__ bool reduce_last(double (&v)[NV], double* partials, unsigned int* counter, Fin fin) {
   static_assert(NV <= 64, "the partial stores and the ticket must come from one wavefront");
   __shared__ double sred[kVT / 64][NV];
   __shared__ int is_last;
@@ -281,7 +281,7 @@ __device__ void reduce_last(double (&v)[NV], double* partials, unsigned int* cou
     is_last = (prev == gridDim.x - 1);
   }
   __syncthreads();
-  if (!is_last) return;
+  if (!is_last) return false;
   double acc[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) acc[k] = 0.0;
@@ -304,6 +304,7 @@ __device__ void reduce_last(double (&v)[NV], double* partials, unsigned int* cou
     fin(tid, x);
   }
   if (tid == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return true;  // this block ran fin
 }
 
 // Sum over aligned groups of SG lanes (SG = 8 or 16) with DPP row operations, on the
@@ -425,7 +426,7 @@ hipError_t pcg_init2(int R, int64_t n_u, const T* z, T* pv, const PcgScalars& s,
                      const int* outer_done, const MinresState* outer_st, hipStream_t st);
 template <typename T>
 hipError_t pcg_spmv(int R, const RowSplit& rs, const int32_t* rowptr, const int32_t* aend, const int32_t* col,
-                    const T* val, const T* pv, T* q, const PcgScalars& s, hipStream_t st);
+                    const T* val, const T* pv, T* q, const PcgScalars& s, bool stream_entries, hipStream_t st);
 template <typename T>
 hipError_t pcg_axpy(int R, int64_t n_u, const T* pv, const T* q, T* x, T* r, const PcgScalars& s, int ip,
                     hipStream_t st);

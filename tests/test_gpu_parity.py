@@ -131,6 +131,15 @@ def _oracle_solve(o, f, tol, pc):
     return o.solve(f, tol=tol, pc_A=pc)
 
 
+def _check_inner_total(info, io, frac):
+    """Inner CG total of a refined solve against the oracle's: the per-application counts
+    agree within 2 and the outer counts within `frac`, so the totals agree within that
+    fraction plus 2 per outer iteration."""
+    gi, oi = info["inner_iters_total"], io["inner_total"]
+    assert oi > 0
+    assert abs(gi - oi) <= frac * oi + 2 * max(info["iters"], io["iters"]) + 2, (gi, oi)
+
+
 @pytest.mark.parametrize("pc", [PC_IC0, PC_JACOBI, PC_ICPCG, PC_JPCG])
 def test_minres_converged(pair, pc):
     gp, o = pair
@@ -143,6 +152,9 @@ def test_minres_converged(pair, pc):
     # counts agree within a quarter there, exactly as elsewhere
     bar = max(3, 0.25 * io["iters"]) if (pc == PC_JPCG and o.kp > 2) else _it_tol(o)
     assert abs(info["iters"] - io["iters"]) <= bar, (info["iters"], io["iters"])
+    if pc in (PC_ICPCG, PC_JPCG):
+        # inner CG iterations summed over every refinement cycle, as the oracle counts them
+        _check_inner_total(info, io, bar / max(1, io["iters"]))
     assert info["relres_true_Minv"] <= 1e-8 if pc in (PC_ICPCG, PC_JPCG) else info["relres_true_Minv"] <= 2e-8
     u2, p2, info2 = gp.solve(_cuda(f), tol=1e-13, precond=pc)
     uo2, po2, _ = _oracle_solve(o, f, 1e-13, pc)
@@ -182,6 +194,7 @@ def test_pcg_AQ(pair):
     assert info["status"] == 0 and info["relres_true_Minv"] <= 1e-8
     bar = max(3, 0.25 * io["iters"]) if o.kp > 2 else _it_tol(o)
     assert abs(info["iters"] - io["iters"]) <= bar, (info["iters"], io["iters"])
+    _check_inner_total(info, io, bar / max(1, io["iters"]))
     u2, p2, _ = gp.solve(_cuda(f), tol=1e-13, precond=PC_PCGAQ)
     uo2, po2, _ = o.solve_refined(f, tol=1e-13, pc_A=PC_JPCG, pc_Q=PQ_JPCG)
     assert _rel(u2.cpu().numpy(), uo2) <= 1e-10
