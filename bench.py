@@ -120,7 +120,7 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1309_5048_amd import StokesProblem, PC_IC0, PC_ICPCG, PC_JPCG, PC_PCGAQ, MIXED, FP64
+    from paper_1309_5048_amd import StokesProblem, PC_IC0, PC_ICPCG, PC_IDEAL, PC_JPCG, PC_PCGAQ, MIXED, FP64
 
     torch.cuda.set_device(0)
     N, kp, dim, tol = 256, 2, 2, 1e-8
@@ -213,6 +213,15 @@ def main():
             log("pcgAQ", extra["c1_pcgAQ_inner1e-2"])
         except Exception as e:  # report, keep the headline
             extra["c1_pcgAQ_inner1e-2"] = {"error": str(e)}
+        try:
+            # Ideal(A,Q): both blocks solved by inner CG to the fixed relative residual 1e-12
+            s_i, inf_i = timed_solves(gp, f, 1, 1, tol=tol, precond=PC_IDEAL)
+            extra["c1_ideal"] = {"s": round(s_i, 5), "iters": inf_i[-1]["iters"],
+                                 "inner_iters_total": inf_i[-1]["inner_iters_total"],
+                                 "relres_true_Minv": inf_i[-1]["relres_true_Minv"]}
+            log("ideal", extra["c1_ideal"])
+        except Exception as e:  # report, keep the headline
+            extra["c1_ideal"] = {"error": str(e)}
         del gp
         torch.cuda.empty_cache()
         try:

@@ -48,7 +48,7 @@ extern "C" {
 #define STOKES_EHIP (-3)
 #define STOKES_EBREAKDOWN (-4)
 
-/* Velocity-block preconditioner M_A; the pressure block is always Diag(Q)/(2 nu). */
+/* Block preconditioner M = blkdiag(M_A, M_Q).  M_Q = Diag(Q)/(2 nu) unless stated. */
 #define STOKES_PC_IC0 0    /* M_A = L L^T, IC(0) of A in natural order (Sec. 6.4)          */
 #define STOKES_PC_ICPCG 1  /* M_A^{-1} r = IC(0)-preconditioned CG on A r, relative 2-norm
                               tolerance stokes_set_inner_tol (default 1e-2), x0 = 0      */
@@ -58,10 +58,18 @@ extern "C" {
                               (the paper's tables use the inner tolerance 1e-6); like
                               STOKES_PC_ICPCG a nonlinear preconditioner, so MINRES is
                               restarted on the true residual until it meets tol in the norm
-                              of blkdiag(Diag(A), Diag(Q)/(2 nu)).  Value 3 is not used.   */
+                              of blkdiag(Diag(A), Diag(Q)/(2 nu)).                          */
 #define STOKES_PC_PCGAQ 5  /* PCG(A,Q) of Sec. 5.1: STOKES_PC_JPCG on the velocity block and
                               M_Q^{-1} r = 2 nu x, x from Diag(Q)-preconditioned CG on
                               Q x = r (same tolerance); restarted like STOKES_PC_JPCG       */
+#define STOKES_PC_IDEAL 3  /* Ideal(A,Q) of Sec. 5.1, M = blkdiag(A, Q/(2 nu)): each block
+                              solved by Diag-preconditioned CG to the fixed relative residual
+                              1e-12 (at most 100000 iterations; stokes_set_inner_tol and
+                              stokes_set_maxit do not apply), so MINRES runs once, without
+                              restarts, on a preconditioner fixed up to rounding.  Iterative
+                              block solves stand in for the paper's direct ones.  FP64 only
+                              (STOKES_MIXED: STOKES_EINVAL); relres_true_Minv is measured
+                              in the blkdiag(Diag(A), Diag(Q)/(2 nu)) norm.                */
 
 /* Arithmetic of the Krylov iteration. */
 #define STOKES_FP64 0  /* everything in double precision                                  */
@@ -74,10 +82,11 @@ typedef struct stokes_problem stokes_problem; /* opaque: owns all device matrice
 
 typedef struct {
   int32_t iters;             /* MINRES iterations (summed over refinement steps if MIXED) */
-  int32_t inner_iters_total; /* inner PCG iterations (ICPCG) summed over the solve        */
+  int32_t inner_iters_total; /* inner CG iterations (both blocks) summed over the solve    */
   int32_t status;            /* return code of this right-hand side                       */
   int32_t ic_shift_steps;    /* IC(0) diagonal-shift retries used at setup (0 = none)     */
-  int32_t refine_cycles;     /* MINRES runs on the true residual (1 unless MIXED or ICPCG) */
+  int32_t refine_cycles;     /* MINRES runs on the true residual (1 unless MIXED or an
+                                inner-CG preconditioner other than STOKES_PC_IDEAL)         */
   int32_t reserved;          /* zero                                                       */
   double relres_est;         /* |eta|/gamma_1 at exit (M^{-1}-norm estimate)              */
   double relres_true_2;      /* ||b - Acal x||_2 / ||b||_2, computed on the device          */
@@ -167,8 +176,8 @@ int stokes_dnu_dot(stokes_problem* pb, int nrhs, const double* lam_u, const doub
 /* Products with the assembled operators, for checks: y = Acal x (x, y [n_u + n_p]). */
 int stokes_apply(stokes_problem* pb, const double* x, double* y);
 
-/* y = M^{-1} r with the chosen velocity preconditioner (r, y [n_u + n_p]); *inner_iters
- * receives the PCG iteration count for STOKES_PC_ICPCG (may be NULL). */
+/* y = M^{-1} r with the chosen block preconditioner (r, y [n_u + n_p]); *inner_iters
+ * receives the inner CG iteration count of both blocks (0 without inner CG; may be NULL). */
 int stokes_apply_precond(stokes_problem* pb, int precond, const double* r, double* y, int* inner_iters);
 
 /* Copy the assembled matrices to HOST buffers (for checks).  which: 0 = saddle Acal

@@ -184,9 +184,10 @@ struct stokes_problem {
   RowSplit rs_Q;
   std::vector<int32_t> Qrowptr_h, split_Q_h;
   PcgScalars pcgQ;
-  // inner CG iterations the last application needed (velocity, pressure): the first chunk
-  // queued before the host reads the done flag
-  int pcg_expect = 4, pcgq_expect = 4;
+  // inner CG iterations the last application needed, per velocity preconditioner and for
+  // the pressure block (PCG(A,Q), Ideal(A,Q)): the first chunk queued before the host
+  // reads the done flag
+  int pcg_expect[6] = {4, 4, 4, 4, 4, 4}, pcgq_expect[2] = {4, 4};
   double* scratch = nullptr;  // [64] small host-visible results
   double* partials = nullptr;
   unsigned int* counter = nullptr;
@@ -614,6 +615,12 @@ int check_trsv_err(stokes_problem* pb, const SchedPair* sp) {
   return 0;
 }
 
+// Ideal(A,Q) (Sec. 5.1, exact block solves) is realised by Diag-preconditioned CG on A and
+// on Q run to this relative residual, far below the outer tolerances the solver accepts,
+// so that MINRES sees the fixed preconditioner blkdiag(A, Q/(2 nu)) up to rounding.
+constexpr double kIdealTol = 1e-12;
+constexpr int kIdealMaxit = 100000;
+
 // Inner CG state after a queued chunk: *done = all columns finished; once they have, the
 // largest iteration count of this application goes to *expect.  Returns nonzero on error.
 int pcg_done(stokes_problem* pb, const PcgScalars& s, int R, int* done, int* expect) {
@@ -644,8 +651,12 @@ int precond_velocity(stokes_problem* pb, int precond, Work& W, SchedPair* sp, co
     CK(launch_trsv(sp->bwd, fp32, R, W.y, zout, vin, dot_out, skip, st, prof_take(pb, 2)));
     return 0;
   }
-  const bool jacobi_cg = precond == STOKES_PC_JPCG || precond == STOKES_PC_PCGAQ;
+  const bool jacobi_cg = precond == STOKES_PC_JPCG || precond == STOKES_PC_PCGAQ || precond == STOKES_PC_IDEAL;
   if (precond == STOKES_PC_ICPCG || jacobi_cg) {
+    const bool ideal = precond == STOKES_PC_IDEAL;
+    const double rtol_in = ideal ? kIdealTol : pb->inner_tol;
+    const int maxit_in = ideal ? kIdealMaxit : pb->maxit_inner;
+    int& expect = pb->pcg_expect[precond];
     const T* val = fp32 ? (const T*)pb->val32 : (const T*)pb->val;
     PcgScalars& s = pb->pcg;
     // z = M^{-1} r with rho = r.z: the IC(0) triangular solves (fused dot), or Jacobi
@@ -658,14 +669,14 @@ int precond_velocity(stokes_problem* pb, int precond, Work& W, SchedPair* sp, co
     };
     CK(pcg_init<T>(R, n_u, vin, (T*)W.pr, zout, s, skip, st));
     CK(inner_precond(s.rho, skip, false));
-    CK(pcg_init2<T>(R, n_u, (const T*)W.pz, (T*)W.pp, s, pb->inner_tol, pb->maxit_inner, skip, outer_st, st));
+    CK(pcg_init2<T>(R, n_u, (const T*)W.pz, (T*)W.pp, s, rtol_in, maxit_in, skip, outer_st, st));
     int ip = 0;
     // Iterations are queued in chunks between host reads of the done flag: first as many as
     // the last application needed, then 4 at a time (iterations after convergence return
     // at once on the device flag).
     int queued = 0;
-    while (queued < pb->maxit_inner) {
-      const int chunk_it = std::min(pb->maxit_inner - queued, queued == 0 ? std::max(1, pb->pcg_expect) : 4);
+    while (queued < maxit_in) {
+      const int chunk_it = std::min(maxit_in - queued, queued == 0 ? std::max(1, expect) : 4);
       queued += chunk_it;
       for (int k = 0; k < chunk_it; ++k) {
         CK(pcg_spmv<T>(R, pb->rs_A, pb->rowptr, pb->aend, pb->col, val, (const T*)W.pp, (T*)W.pq, s,
@@ -676,7 +687,7 @@ int precond_velocity(stokes_problem* pb, int precond, Work& W, SchedPair* sp, co
         ip = 1 - ip;
       }
       int done = 0;
-      if (int e = pcg_done(pb, s, R, &done, &pb->pcg_expect)) return e;
+      if (int e = pcg_done(pb, s, R, &done, &expect)) return e;
       prof_flush(pb);
       if (done) break;
     }
@@ -733,12 +744,13 @@ int ensure_pressure_cg(stokes_problem* pb) {
   return 0;
 }
 
-// Pressure block of the PCG(A,Q) preconditioner: zout_p = 2 nu Q^{-1} vin_p by
-// Diag(Q)-preconditioned CG (x0 = 0, relative tolerance inner_tol), and the dot
-// v_p . z_p into dot_out[R].  vin_p / zout_p point at the pressure rows (row n_u).
+// Pressure block of the PCG(A,Q) and Ideal(A,Q) preconditioners: zout_p = 2 nu Q^{-1} vin_p
+// by Diag(Q)-preconditioned CG (x0 = 0, relative tolerance inner_tol, or kIdealTol for
+// Ideal(A,Q)), and the dot v_p . z_p into dot_out[R].  vin_p / zout_p point at the pressure
+// rows (row n_u).
 template <typename T>
-int precond_pressure(stokes_problem* pb, Work& W, const T* vin_p, T* zout_p, double* dot_out, const int* skip,
-                     const MinresState* outer_st) {
+int precond_pressure(stokes_problem* pb, Work& W, bool ideal, const T* vin_p, T* zout_p, double* dot_out,
+                     const int* skip, const MinresState* outer_st) {
   const int R = W.R;
   const bool fp32 = W.fp32;
   hipStream_t st = pb->stream;
@@ -747,11 +759,14 @@ int precond_pressure(stokes_problem* pb, Work& W, const T* vin_p, T* zout_p, dou
   PcgScalars& s = pb->pcgQ;
   CK(pcg_init<T>(R, n_p, vin_p, (T*)W.qr, zout_p, s, skip, st));
   CK(pcg_jacobi<T>(R, n_p, (const T*)W.qr, pb->diagQ, (T*)W.qz, s, s.rho, skip, st));
-  CK(pcg_init2<T>(R, n_p, (const T*)W.qz, (T*)W.qp, s, pb->inner_tol, pb->maxit_inner, skip, outer_st, st));
+  const double rtol_in = ideal ? kIdealTol : pb->inner_tol;
+  const int maxit_in = ideal ? kIdealMaxit : pb->maxit_inner;
+  int& expect = pb->pcgq_expect[ideal ? 1 : 0];
+  CK(pcg_init2<T>(R, n_p, (const T*)W.qz, (T*)W.qp, s, rtol_in, maxit_in, skip, outer_st, st));
   int ip = 0;
   int queued = 0;
-  while (queued < pb->maxit_inner) {
-    const int chunk_it = std::min(pb->maxit_inner - queued, queued == 0 ? std::max(1, pb->pcgq_expect) : 4);
+  while (queued < maxit_in) {
+    const int chunk_it = std::min(maxit_in - queued, queued == 0 ? std::max(1, expect) : 4);
     queued += chunk_it;
     for (int k = 0; k < chunk_it; ++k) {
       CK(pcg_spmv<T>(R, pb->rs_Q, pb->Qrowptr, nullptr, pb->Qcol, qval, (const T*)W.qp, (T*)W.qq, s, false, st));
@@ -761,7 +776,7 @@ int precond_pressure(stokes_problem* pb, Work& W, const T* vin_p, T* zout_p, dou
       ip = 1 - ip;
     }
     int done = 0;
-    if (int e = pcg_done(pb, s, R, &done, &pb->pcgq_expect)) return e;
+    if (int e = pcg_done(pb, s, R, &done, &expect)) return e;
     if (done) break;
   }
   CK(scale_skip<T>(n_p * R, zout_p, 2.0 * pb->nu, skip, st));
@@ -783,11 +798,12 @@ int minres_run(stokes_problem* pb, Work& W, int precond, double tol, int maxit, 
   hipStream_t st = pb->stream;
   const int64_t n_u = pb->S.n_u, n = n_u + pb->S.n_p;
   SchedPair* sp = nullptr;
-  if (precond != STOKES_PC_JACOBI && precond != STOKES_PC_JPCG && precond != STOKES_PC_PCGAQ) {
+  if (precond == STOKES_PC_IC0 || precond == STOKES_PC_ICPCG) {
     int rc = get_schedule(pb, R, fp32, &sp);
     if (rc) return rc;
   }
-  const bool pcg_q = precond == STOKES_PC_PCGAQ;
+  const bool pcg_q = precond == STOKES_PC_PCGAQ || precond == STOKES_PC_IDEAL;
+  const bool ideal = precond == STOKES_PC_IDEAL;
   if (pcg_q) {
     int rc = ensure_pressure_cg(pb);
     if (rc) return rc;
@@ -806,7 +822,7 @@ int minres_run(stokes_problem* pb, Work& W, int precond, double tol, int maxit, 
   int rc = precond_velocity<T>(pb, precond, W, sp, v[0], z[0], s.red + RED_G2U * kRMax, nullptr, nullptr, nullptr);
   if (rc) return rc;
   if (pcg_q) {  // the pressure block replaces the Diag(Q) part the vector kernel wrote
-    rc = precond_pressure<T>(pb, W, v[0] + n_u * R, z[0] + n_u * R, s.red + RED_G2P * kRMax, nullptr, nullptr);
+    rc = precond_pressure<T>(pb, W, ideal, v[0] + n_u * R, z[0] + n_u * R, s.red + RED_G2P * kRMax, nullptr, nullptr);
     if (rc) return rc;
   }
   CK(mr_init_state(R, s, tol, maxit, st));
@@ -836,7 +852,7 @@ int minres_run(stokes_problem* pb, Work& W, int precond, double tol, int maxit, 
                                nullptr);
       if (rc) return rc;
       if (pcg_q) {
-        rc = precond_pressure<T>(pb, W, v[1 - p] + n_u * R, z[1 - p] + n_u * R,
+        rc = precond_pressure<T>(pb, W, ideal, v[1 - p] + n_u * R, z[1 - p] + n_u * R,
                                  s.red + ((size_t)p * RED_KINDS + RED_G2P) * kRMax, s.alldone + p, s.st + p * kRMax);
         if (rc) return rc;
       }
@@ -898,7 +914,8 @@ int true_residuals(stokes_problem* pb, Work& W, int precond, const double* b, co
   double* r = (double*)W.q;
   double* out = pb->scratch;  // [0..2R) norms, [2R..4R) r M r parts, [4R..6R) b M b parts
   CK(spmv_resid<double>(R, pb->rs_full, pb->rowptr, nullptr, pb->col, pb->val, x, b, r, pb->partials, pb->counter, out, st));
-  const int pcl = (precond == STOKES_PC_JACOBI || precond == STOKES_PC_JPCG || precond == STOKES_PC_PCGAQ)
+  const int pcl = (precond == STOKES_PC_JACOBI || precond == STOKES_PC_JPCG || precond == STOKES_PC_PCGAQ ||
+                   precond == STOKES_PC_IDEAL)
                       ? STOKES_PC_JACOBI
                       : STOKES_PC_IC0;
   for (int pass = 0; pass < 2; ++pass) {
@@ -947,10 +964,13 @@ int solve_core(stokes_problem* pb, Work& W64, int precond, int precision, double
   double eta_rel[kRMax] = {0};
   int cycles = 1;
   const bool inner_pcg = precond == STOKES_PC_ICPCG || precond == STOKES_PC_JPCG || precond == STOKES_PC_PCGAQ;
+  // Ideal(A,Q): a fixed preconditioner up to rounding, one MINRES run (no restarts)
+  const bool pcg_q = precond == STOKES_PC_PCGAQ || precond == STOKES_PC_IDEAL;
+  const bool counts_inner = inner_pcg || precond == STOKES_PC_IDEAL;
   // inner CG totals count over every refinement cycle of this solve
-  if (inner_pcg) {
+  if (counts_inner) {
     CK(hipMemsetAsync(pb->pcg.st, 0, sizeof(PcgState) * kRMax, st));
-    if (precond == STOKES_PC_PCGAQ) {
+    if (pcg_q) {
       int rc = ensure_pressure_cg(pb);
       if (rc) return rc;
       CK(hipMemsetAsync(pb->pcgQ.st, 0, sizeof(PcgState) * kRMax, st));
@@ -1077,14 +1097,12 @@ int solve_core(stokes_problem* pb, Work& W64, int precond, int precision, double
       infos[c].refine_cycles = cycles;
       infos[c].reserved = 0;
     }
-    if (inner_pcg) {
+    if (counts_inner) {
       PcgState ps[kRMax], pq[kRMax];
       CK(hipMemcpyAsync(ps, pb->pcg.st, sizeof(PcgState) * kRMax, hipMemcpyDeviceToHost, st));
-      if (precond == STOKES_PC_PCGAQ)
-        CK(hipMemcpyAsync(pq, pb->pcgQ.st, sizeof(PcgState) * kRMax, hipMemcpyDeviceToHost, st));
+      if (pcg_q) CK(hipMemcpyAsync(pq, pb->pcgQ.st, sizeof(PcgState) * kRMax, hipMemcpyDeviceToHost, st));
       CK(hipStreamSynchronize(st));
-      for (int c = 0; c < nrhs; ++c)
-        infos[c].inner_iters_total = ps[c].total + (precond == STOKES_PC_PCGAQ ? pq[c].total : 0);
+      for (int c = 0; c < nrhs; ++c) infos[c].inner_iters_total = ps[c].total + (pcg_q ? pq[c].total : 0);
     }
   }
   int worst = 0;
@@ -1098,8 +1116,10 @@ int solve_core(stokes_problem* pb, Work& W64, int precond, int precision, double
 
 int check_args_solve(stokes_problem* pb, double tol, int precond, int precision) {
   if (!(tol > 0.0) || !(tol < 1.0)) return fail(pb, STOKES_EINVAL, "tol must be in (0, 1)");
-  if (precond < 0 || precond > 5 || precond == 3) return fail(pb, STOKES_EINVAL, "unknown preconditioner");
+  if (precond < 0 || precond > 5) return fail(pb, STOKES_EINVAL, "unknown preconditioner");
   if (precision != STOKES_FP64 && precision != STOKES_MIXED) return fail(pb, STOKES_EINVAL, "unknown precision");
+  if (precond == STOKES_PC_IDEAL && precision != STOKES_FP64)
+    return fail(pb, STOKES_EINVAL, "STOKES_PC_IDEAL needs STOKES_FP64 (its inner tolerance is below FP32 rounding)");
   return 0;
 }
 
@@ -1476,7 +1496,8 @@ int stokes_apply(stokes_problem* pb, const double* x, double* y) {
 }
 
 int stokes_apply_precond(stokes_problem* pb, int precond, const double* r, double* y, int* inner_iters) {
-  if (!pb || !r || !y || precond < 0 || precond > 5 || precond == 3) return fail(pb, STOKES_EINVAL, "bad arguments");
+  if (!pb || !r || !y || precond < 0 || precond > 5) return fail(pb, STOKES_EINVAL, "bad arguments");
+  if (inner_iters) *inner_iters = 0;
   Work* W = nullptr;
   int rc = get_work(pb, 1, false, &W);
   if (rc) return rc;
@@ -1487,17 +1508,19 @@ int stokes_apply_precond(stokes_problem* pb, int precond, const double* r, doubl
   CK(hipGetLastError());
   if (precond != STOKES_PC_JACOBI) {
     SchedPair* sp = nullptr;
-    const bool jac = precond == STOKES_PC_JPCG || precond == STOKES_PC_PCGAQ;
+    const bool pq_cg = precond == STOKES_PC_PCGAQ || precond == STOKES_PC_IDEAL;
+    const bool jac = precond == STOKES_PC_JPCG || pq_cg;
     if (!jac && (rc = get_schedule(pb, 1, false, &sp))) return rc;
     if (precond != STOKES_PC_IC0) CK(hipMemsetAsync(pb->pcg.st, 0, sizeof(PcgState) * kRMax, st));
     rc = precond_velocity<double>(pb, precond, *W, sp, r, y, pb->scratch + 100, nullptr, nullptr, nullptr);
     if (rc) return rc;
     if (sp && (rc = check_trsv_err(pb, sp))) return rc;
     int qtotal = 0;
-    if (precond == STOKES_PC_PCGAQ) {
+    if (pq_cg) {
       if ((rc = ensure_pressure_cg(pb))) return rc;
       CK(hipMemsetAsync(pb->pcgQ.st, 0, sizeof(PcgState) * kRMax, st));
-      rc = precond_pressure<double>(pb, *W, r + n_u, y + n_u, pb->scratch + 101, nullptr, nullptr);
+      rc = precond_pressure<double>(pb, *W, precond == STOKES_PC_IDEAL, r + n_u, y + n_u, pb->scratch + 101, nullptr,
+                                    nullptr);
       if (rc) return rc;
       PcgState pq;
       CK(hipMemcpyAsync(&pq, pb->pcgQ.st, sizeof(PcgState), hipMemcpyDeviceToHost, st));

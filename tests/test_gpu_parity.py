@@ -14,7 +14,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
-from oracle.oracle import PC_IC0, PC_ICPCG, PC_JACOBI, PC_JPCG, PQ_DIAG, PQ_JPCG, Oracle  # noqa: E402
+from oracle.oracle import PC_EXACT, PC_IC0, PC_ICPCG, PC_JACOBI, PC_JPCG, PQ_DIAG, PQ_EXACT, PQ_JPCG, Oracle  # noqa: E402
 from synthetic_inputs import forcing_modes, random_vector  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -199,6 +199,34 @@ def test_pcg_AQ(pair):
     uo2, po2, _ = o.solve_refined(f, tol=1e-13, pc_A=PC_JPCG, pc_Q=PQ_JPCG)
     assert _rel(u2.cpu().numpy(), uo2) <= 1e-10
     assert _rel(p2.cpu().numpy(), po2) <= 1e-10
+
+
+def test_ideal_AQ(pair):
+    """Ideal(A,Q) (library code 3: Diag-CG on both blocks to the fixed relative residual
+    1e-12) against the oracle's exact block solves (dense Cholesky of A and of Q, Sec. 5.1):
+    one application, then plain MINRES with the same stop count and solution.  The oracle's
+    exact-solve counts are pinned to the paper's Ideal(A,Q) column (Sec. 6.2 table)."""
+    from paper_1309_5048_amd import MIXED, PC_IDEAL
+    gp, o = pair
+    r = random_vector(o.n, 17)
+    z, it = gp.apply_precond(_cuda(r), PC_IDEAL)
+    zo, _ = o.precond(r, pc_A=PC_EXACT, pc_Q=PQ_EXACT)
+    assert it > 0
+    # CG stopped at relative residual 1e-12: error <= cond(block) * 1e-12 (cond <= ~1e4 here)
+    assert _rel(z.cpu().numpy(), zo) <= 1e-8
+    f = o.load(1)
+    u, p, info = gp.solve(_cuda(f), tol=1e-8, precond=PC_IDEAL)
+    uo, po, io = o.solve(f, tol=1e-8, pc_A=PC_EXACT, pc_Q=PQ_EXACT)
+    assert info["status"] == 0 and info["refine_cycles"] == 1 and info["inner_iters_total"] > 0
+    assert abs(info["iters"] - io["iters"]) <= _it_tol(o), (info["iters"], io["iters"])
+    u2, p2, info2 = gp.solve(_cuda(f), tol=1e-11, precond=PC_IDEAL)
+    uo2, po2, _ = o.solve(f, tol=1e-11, pc_A=PC_EXACT, pc_Q=PQ_EXACT)
+    assert info2["status"] == 0
+    assert _rel(u2.cpu().numpy(), uo2) <= 1e-8
+    assert _rel(p2.cpu().numpy(), po2) <= 1e-8
+    # FP32 cannot reach the inner tolerance: rejected
+    with pytest.raises(RuntimeError):
+        gp.solve(_cuda(f), tol=1e-8, precond=PC_IDEAL, precision=MIXED)
 
 
 @pytest.mark.parametrize("nrhs", [3, 8, 16])
