@@ -120,7 +120,7 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1309_5048_amd import StokesProblem, PC_IC0, PC_ICPCG, PC_IDEAL, PC_JPCG, PC_PCGAQ, MIXED, FP64
+    from paper_1309_5048_amd import StokesProblem, PC_IC0, PC_ICPCG, PC_IDEAL, PC_IDEAL_A, PC_JPCG, PC_PCGAQ, MIXED, FP64
 
     torch.cuda.set_device(0)
     N, kp, dim, tol = 256, 2, 2, 1e-8
@@ -222,6 +222,15 @@ def main():
             log("ideal", extra["c1_ideal"])
         except Exception as e:  # report, keep the headline
             extra["c1_ideal"] = {"error": str(e)}
+        try:
+            # Ideal(A) + Diag(Q): the velocity block as in Ideal(A,Q), Diag(Q) on the pressure
+            s_ia, inf_ia = timed_solves(gp, f, 1, 1, tol=tol, precond=PC_IDEAL_A)
+            extra["c1_ideal_A_diagQ"] = {"s": round(s_ia, 5), "iters": inf_ia[-1]["iters"],
+                                         "inner_iters_total": inf_ia[-1]["inner_iters_total"],
+                                         "relres_true_Minv": inf_ia[-1]["relres_true_Minv"]}
+            log("ideal_A_diagQ", extra["c1_ideal_A_diagQ"])
+        except Exception as e:  # report, keep the headline
+            extra["c1_ideal_A_diagQ"] = {"error": str(e)}
         del gp
         torch.cuda.empty_cache()
         try:

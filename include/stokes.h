@@ -70,6 +70,9 @@ extern "C" {
                               block solves stand in for the paper's direct ones.  FP64 only
                               (STOKES_MIXED: STOKES_EINVAL); relres_true_Minv is measured
                               in the blkdiag(Diag(A), Diag(Q)/(2 nu)) norm.                */
+#define STOKES_PC_IDEAL_A 6 /* Ideal(A) + Diag(Q) of Sec. 5.1, M = blkdiag(A, Diag(Q)/(2 nu)):
+                              the velocity block as for STOKES_PC_IDEAL, the pressure block
+                              by its diagonal; one MINRES run; FP64 only                   */
 
 /* Arithmetic of the Krylov iteration. */
 #define STOKES_FP64 0  /* everything in double precision                                  */

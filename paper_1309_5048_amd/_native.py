@@ -15,7 +15,7 @@ STOKES_ENOMEM = -2
 STOKES_EHIP = -3
 STOKES_EBREAKDOWN = -4
 
-PC_IC0, PC_ICPCG, PC_JACOBI, PC_IDEAL, PC_JPCG, PC_PCGAQ = 0, 1, 2, 3, 4, 5
+PC_IC0, PC_ICPCG, PC_JACOBI, PC_IDEAL, PC_JPCG, PC_PCGAQ, PC_IDEAL_A = 0, 1, 2, 3, 4, 5, 6
 FP64, MIXED = 0, 1
 
 # every exported entry point declared in include/stokes.h

@@ -187,7 +187,7 @@ struct stokes_problem {
   // inner CG iterations the last application needed, per velocity preconditioner and for
   // the pressure block (PCG(A,Q), Ideal(A,Q)): the first chunk queued before the host
   // reads the done flag
-  int pcg_expect[6] = {4, 4, 4, 4, 4, 4}, pcgq_expect[2] = {4, 4};
+  int pcg_expect[7] = {4, 4, 4, 4, 4, 4, 4}, pcgq_expect[2] = {4, 4};
   double* scratch = nullptr;  // [64] small host-visible results
   double* partials = nullptr;
   unsigned int* counter = nullptr;
@@ -651,9 +651,9 @@ int precond_velocity(stokes_problem* pb, int precond, Work& W, SchedPair* sp, co
     CK(launch_trsv(sp->bwd, fp32, R, W.y, zout, vin, dot_out, skip, st, prof_take(pb, 2)));
     return 0;
   }
-  const bool jacobi_cg = precond == STOKES_PC_JPCG || precond == STOKES_PC_PCGAQ || precond == STOKES_PC_IDEAL;
+  const bool ideal = precond == STOKES_PC_IDEAL || precond == STOKES_PC_IDEAL_A;
+  const bool jacobi_cg = precond == STOKES_PC_JPCG || precond == STOKES_PC_PCGAQ || ideal;
   if (precond == STOKES_PC_ICPCG || jacobi_cg) {
-    const bool ideal = precond == STOKES_PC_IDEAL;
     const double rtol_in = ideal ? kIdealTol : pb->inner_tol;
     const int maxit_in = ideal ? kIdealMaxit : pb->maxit_inner;
     int& expect = pb->pcg_expect[precond];
@@ -681,8 +681,13 @@ int precond_velocity(stokes_problem* pb, int precond, Work& W, SchedPair* sp, co
       for (int k = 0; k < chunk_it; ++k) {
         CK(pcg_spmv<T>(R, pb->rs_A, pb->rowptr, pb->aend, pb->col, val, (const T*)W.pp, (T*)W.pq, s,
                        precond == STOKES_PC_ICPCG, st));
-        CK(pcg_axpy<T>(R, n_u, (const T*)W.pp, (const T*)W.pq, zout, (T*)W.pr, s, ip, st));
-        CK(inner_precond(s.rho + (1 - ip) * kRMax, s.alldone, true));
+        if (jacobi_cg) {
+          CK(pcg_axpy_jacobi<T>(R, n_u, (const T*)W.pp, (const T*)W.pq, pb->diagA, zout, (T*)W.pr, (T*)W.pz, s, ip,
+                                st));
+        } else {
+          CK(pcg_axpy<T>(R, n_u, (const T*)W.pp, (const T*)W.pq, zout, (T*)W.pr, s, ip, st));
+          CK(inner_precond(s.rho + (1 - ip) * kRMax, s.alldone, true));
+        }
         CK(pcg_pupdate<T>(R, n_u, (const T*)W.pz, (T*)W.pp, s, ip, st));
         ip = 1 - ip;
       }
@@ -770,8 +775,8 @@ int precond_pressure(stokes_problem* pb, Work& W, bool ideal, const T* vin_p, T*
     queued += chunk_it;
     for (int k = 0; k < chunk_it; ++k) {
       CK(pcg_spmv<T>(R, pb->rs_Q, pb->Qrowptr, nullptr, pb->Qcol, qval, (const T*)W.qp, (T*)W.qq, s, false, st));
-      CK(pcg_axpy<T>(R, n_p, (const T*)W.qp, (const T*)W.qq, zout_p, (T*)W.qr, s, ip, st));
-      CK(pcg_jacobi<T>(R, n_p, (const T*)W.qr, pb->diagQ, (T*)W.qz, s, s.rho + (1 - ip) * kRMax, s.alldone, st));
+      CK(pcg_axpy_jacobi<T>(R, n_p, (const T*)W.qp, (const T*)W.qq, pb->diagQ, zout_p, (T*)W.qr, (T*)W.qz, s, ip,
+                            st));
       CK(pcg_pupdate<T>(R, n_p, (const T*)W.qz, (T*)W.qp, s, ip, st));
       ip = 1 - ip;
     }
@@ -915,7 +920,7 @@ int true_residuals(stokes_problem* pb, Work& W, int precond, const double* b, co
   double* out = pb->scratch;  // [0..2R) norms, [2R..4R) r M r parts, [4R..6R) b M b parts
   CK(spmv_resid<double>(R, pb->rs_full, pb->rowptr, nullptr, pb->col, pb->val, x, b, r, pb->partials, pb->counter, out, st));
   const int pcl = (precond == STOKES_PC_JACOBI || precond == STOKES_PC_JPCG || precond == STOKES_PC_PCGAQ ||
-                   precond == STOKES_PC_IDEAL)
+                   precond == STOKES_PC_IDEAL || precond == STOKES_PC_IDEAL_A)
                       ? STOKES_PC_JACOBI
                       : STOKES_PC_IC0;
   for (int pass = 0; pass < 2; ++pass) {
@@ -964,9 +969,10 @@ int solve_core(stokes_problem* pb, Work& W64, int precond, int precision, double
   double eta_rel[kRMax] = {0};
   int cycles = 1;
   const bool inner_pcg = precond == STOKES_PC_ICPCG || precond == STOKES_PC_JPCG || precond == STOKES_PC_PCGAQ;
-  // Ideal(A,Q): a fixed preconditioner up to rounding, one MINRES run (no restarts)
+  // Ideal(A,Q), Ideal(A) + Diag(Q): fixed preconditioners up to rounding, one MINRES run
+  // (no restarts)
   const bool pcg_q = precond == STOKES_PC_PCGAQ || precond == STOKES_PC_IDEAL;
-  const bool counts_inner = inner_pcg || precond == STOKES_PC_IDEAL;
+  const bool counts_inner = inner_pcg || precond == STOKES_PC_IDEAL || precond == STOKES_PC_IDEAL_A;
   // inner CG totals count over every refinement cycle of this solve
   if (counts_inner) {
     CK(hipMemsetAsync(pb->pcg.st, 0, sizeof(PcgState) * kRMax, st));
@@ -1116,10 +1122,10 @@ int solve_core(stokes_problem* pb, Work& W64, int precond, int precision, double
 
 int check_args_solve(stokes_problem* pb, double tol, int precond, int precision) {
   if (!(tol > 0.0) || !(tol < 1.0)) return fail(pb, STOKES_EINVAL, "tol must be in (0, 1)");
-  if (precond < 0 || precond > 5) return fail(pb, STOKES_EINVAL, "unknown preconditioner");
+  if (precond < 0 || precond > 6) return fail(pb, STOKES_EINVAL, "unknown preconditioner");
   if (precision != STOKES_FP64 && precision != STOKES_MIXED) return fail(pb, STOKES_EINVAL, "unknown precision");
-  if (precond == STOKES_PC_IDEAL && precision != STOKES_FP64)
-    return fail(pb, STOKES_EINVAL, "STOKES_PC_IDEAL needs STOKES_FP64 (its inner tolerance is below FP32 rounding)");
+  if ((precond == STOKES_PC_IDEAL || precond == STOKES_PC_IDEAL_A) && precision != STOKES_FP64)
+    return fail(pb, STOKES_EINVAL, "the Ideal preconditioners need STOKES_FP64 (their inner tolerance is below FP32 rounding)");
   return 0;
 }
 
@@ -1496,7 +1502,7 @@ int stokes_apply(stokes_problem* pb, const double* x, double* y) {
 }
 
 int stokes_apply_precond(stokes_problem* pb, int precond, const double* r, double* y, int* inner_iters) {
-  if (!pb || !r || !y || precond < 0 || precond > 5) return fail(pb, STOKES_EINVAL, "bad arguments");
+  if (!pb || !r || !y || precond < 0 || precond > 6) return fail(pb, STOKES_EINVAL, "bad arguments");
   if (inner_iters) *inner_iters = 0;
   Work* W = nullptr;
   int rc = get_work(pb, 1, false, &W);
@@ -1509,7 +1515,7 @@ int stokes_apply_precond(stokes_problem* pb, int precond, const double* r, doubl
   if (precond != STOKES_PC_JACOBI) {
     SchedPair* sp = nullptr;
     const bool pq_cg = precond == STOKES_PC_PCGAQ || precond == STOKES_PC_IDEAL;
-    const bool jac = precond == STOKES_PC_JPCG || pq_cg;
+    const bool jac = precond == STOKES_PC_JPCG || precond == STOKES_PC_IDEAL_A || pq_cg;
     if (!jac && (rc = get_schedule(pb, 1, false, &sp))) return rc;
     if (precond != STOKES_PC_IC0) CK(hipMemsetAsync(pb->pcg.st, 0, sizeof(PcgState) * kRMax, st));
     rc = precond_velocity<double>(pb, precond, *W, sp, r, y, pb->scratch + 100, nullptr, nullptr, nullptr);

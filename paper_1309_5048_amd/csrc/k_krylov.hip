@@ -684,6 +684,64 @@ __global__ __launch_bounds__(kVT) void k_pcg_axpy(int64_t n_u, const T* __restri
   }
 }
 
+// The CG update and the Jacobi step in one pass, for Diag-preconditioned CG: as k_pcg_axpy,
+// then z = r / diag and rho = r.z into rho[1 - ip] for the live columns, both reductions
+// in one (2R values).  Columns already done keep x, r and z.
+template <typename T, int R>
+__global__ __launch_bounds__(kVT) void k_pcg_axpy_jacobi(int64_t n, const T* __restrict__ pv,
+                                                         const T* __restrict__ q, const double* __restrict__ diag,
+                                                         T* __restrict__ x, T* __restrict__ r, T* __restrict__ z,
+                                                         PcgScalars s, int ip) {
+  if (*s.alldone) return;
+  double al[R];
+  bool live[R];
+#pragma unroll
+  for (int c = 0; c < R; ++c) {
+    live[c] = !s.st[c].done;
+    al[c] = live[c] ? s.rho[ip * kRMax + c] / s.pq[c] : 0.0;
+  }
+  double acc[2 * R];
+#pragma unroll
+  for (int c = 0; c < 2 * R; ++c) acc[c] = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kVT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVT) {
+    const double d = diag[i];
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+      if (!live[c]) continue;
+      const size_t k = (size_t)i * R + c;
+      x[k] = T((double)x[k] + al[c] * (double)pv[k]);
+      const double rn = (double)r[k] - al[c] * (double)q[k];
+      const T rt = T(rn);
+      r[k] = rt;
+      acc[c] += rn * rn;
+      const T zv = T((double)rt / d);
+      z[k] = zv;
+      acc[R + c] += (double)rt * (double)zv;
+    }
+  }
+  const bool last = reduce_last<2 * R>(acc, s.partials, s.counter, [&](int k, double v) {
+    if (k >= R) {
+      s.rho[(1 - ip) * kRMax + (k - R)] = v;
+      return;
+    }
+    PcgState& st = s.st[k];
+    if (!st.done) {
+      st.rr = v;
+      st.iter += 1;
+      st.total += 1;
+      if (v <= st.rtol2 * st.bnorm2 || st.iter >= st.maxit) st.done = 1;
+    }
+  });
+  if (last) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int nd = 0;
+      for (int c = 0; c < R; ++c) nd += s.st[c].done;
+      *s.alldone = (nd == R);
+    }
+  }
+}
+
 // Jacobi preconditioner of the inner PCG: z = r / diag(A) and rho = r.z into rho_out[c]
 // (the role of the fused dot of the IC(0) triangular solves).  skip: device flag or null.
 template <typename T, int R>
@@ -877,6 +935,14 @@ hipError_t pcg_spmv(int R, const RowSplit& rs, const int32_t* rowptr, const int3
 }
 
 template <typename T>
+hipError_t pcg_axpy_jacobi(int R, int64_t n, const T* pv, const T* q, const double* diag, T* x, T* r, T* z,
+                           const PcgScalars& s, int ip, hipStream_t st) {
+  STK_R_SWITCH(R, hipLaunchKernelGGL((k_pcg_axpy_jacobi<T, RR>), dim3(vec_blocks(n)), dim3(kVT), 0, st, n, pv, q, diag,
+                                     x, r, z, s, ip));
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t pcg_axpy(int R, int64_t n_u, const T* pv, const T* q, T* x, T* r, const PcgScalars& s, int ip,
                     hipStream_t st) {
   STK_R_SWITCH(R, hipLaunchKernelGGL((k_pcg_axpy<T, RR>), dim3(vec_blocks(n_u)), dim3(kVT), 0, st, n_u, pv, q, x, r, s,
@@ -916,6 +982,8 @@ hipError_t pcg_pupdate(int R, int64_t n_u, const T* z, T* pv, const PcgScalars& 
   template hipError_t pcg_spmv<T>(int, const RowSplit&, const int32_t*, const int32_t*, const int32_t*, const T*,    \
                                   const T*, T*, const PcgScalars&, bool, hipStream_t);                               \
   template hipError_t pcg_axpy<T>(int, int64_t, const T*, const T*, T*, T*, const PcgScalars&, int, hipStream_t);    \
+  template hipError_t pcg_axpy_jacobi<T>(int, int64_t, const T*, const T*, const double*, T*, T*, T*,                \
+                                         const PcgScalars&, int, hipStream_t);                                       \
   template hipError_t pcg_pupdate<T>(int, int64_t, const T*, T*, const PcgScalars&, int, hipStream_t);     \
   template hipError_t pcg_jacobi<T>(int, int64_t, const T*, const double*, T*, const PcgScalars&, double*,    \
                                     const int*, hipStream_t);

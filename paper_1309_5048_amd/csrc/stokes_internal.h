@@ -431,6 +431,9 @@ template <typename T>
 hipError_t pcg_axpy(int R, int64_t n_u, const T* pv, const T* q, T* x, T* r, const PcgScalars& s, int ip,
                     hipStream_t st);
 template <typename T>
+hipError_t pcg_axpy_jacobi(int R, int64_t n, const T* pv, const T* q, const double* diag, T* x, T* r, T* z,
+                           const PcgScalars& s, int ip, hipStream_t st);
+template <typename T>
 hipError_t pcg_pupdate(int R, int64_t n_u, const T* z, T* pv, const PcgScalars& s, int ip, hipStream_t st);
 template <typename T>
 hipError_t pcg_jacobi(int R, int64_t n_u, const T* r, const double* diag, T* z, const PcgScalars& s, double* rho_out,

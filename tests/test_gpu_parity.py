@@ -229,6 +229,38 @@ def test_ideal_AQ(pair):
         gp.solve(_cuda(f), tol=1e-8, precond=PC_IDEAL, precision=MIXED)
 
 
+def test_ideal_A_diagQ(pair):
+    """Ideal(A) + Diag(Q) (library code 6: Diag-CG on A to 1e-12, Diag(Q) on the pressure)
+    against the oracle's dense Cholesky of A with Diag(Q) (Sec. 5.1), whose stop counts are
+    pinned to the paper's Ideal(A) + Diag(Q) column (Sec. 6.2 table)."""
+    from paper_1309_5048_amd import MIXED, PC_IDEAL_A
+    gp, o = pair
+    r = random_vector(o.n, 19)
+    z, it = gp.apply_precond(_cuda(r), PC_IDEAL_A)
+    zo, _ = o.precond(r, pc_A=PC_EXACT, pc_Q=PQ_DIAG)
+    assert it > 0
+    assert _rel(z.cpu().numpy(), zo) <= 1e-8
+    f = o.load(1)
+    u, p, info = gp.solve(_cuda(f), tol=1e-8, precond=PC_IDEAL_A)
+    uo, po, io = o.solve(f, tol=1e-8, pc_A=PC_EXACT, pc_Q=PQ_DIAG)
+    assert info["status"] == 0 and info["refine_cycles"] == 1
+    # the same algorithm in the oracle (Diag(A)-CG to 1e-12 inside one MINRES run)
+    _, _, ij = o.solve(f, tol=1e-8, pc_A=PC_JPCG, pc_Q=PQ_DIAG, inner_tol=1e-12)
+    assert abs(info["iters"] - ij["iters"]) <= _it_tol(o), (info["iters"], ij["iters"])
+    # and the exact solves: at k' = 3 Diag(Q) is a poor pressure block (gamma_Q ~ 0.012,
+    # Sec. 6.4) and the inner solves' 1e-12 residuals alone move the stop (N = 5: 25 exact,
+    # 29 with the oracle's own converged CG, 27 at 1e-14)
+    bar = _it_tol(o) if o.kp <= 2 else max(3, 0.2 * io["iters"])
+    assert abs(info["iters"] - io["iters"]) <= bar, (info["iters"], io["iters"])
+    u2, p2, info2 = gp.solve(_cuda(f), tol=1e-11, precond=PC_IDEAL_A)
+    uo2, po2, _ = o.solve(f, tol=1e-11, pc_A=PC_EXACT, pc_Q=PQ_DIAG)
+    assert info2["status"] == 0
+    assert _rel(u2.cpu().numpy(), uo2) <= 1e-8
+    assert _rel(p2.cpu().numpy(), po2) <= 1e-8
+    with pytest.raises(RuntimeError):
+        gp.solve(_cuda(f), tol=1e-8, precond=PC_IDEAL_A, precision=MIXED)
+
+
 @pytest.mark.parametrize("nrhs", [3, 8, 16])
 def test_batched(pair, nrhs):
     gp, o = pair
@@ -300,6 +332,9 @@ def test_edge_cases():
         gp.solve(_cuda(Oracle(6, 2).load(1)), tol=2.0)
     with pytest.raises(StokesError):
         StokesProblem(4, 5, 2, 1.0)
+    for pc in (-1, 7):  # preconditioner codes outside 0..6
+        with pytest.raises(StokesError):
+            gp.solve(_cuda(Oracle(6, 2).load(1)), tol=1e-8, precond=pc)
     gp.set_maxit(2, 0)
     u, p, info = gp.solve(_cuda(Oracle(6, 2).load(1)), tol=1e-8)
     assert info["status"] == 1 and info["iters"] == 2
