@@ -70,6 +70,8 @@ def lib():
         L.or_dnu_dot.argtypes = [vp, vp, vp]
         L.or_eval.argtypes = [vp, vp, vp, i64, vp, vp]
         L.or_errors.argtypes = [vp, i32, vp, vp, vp]
+        L.or_load_cavity.restype = i32
+        L.or_load_cavity.argtypes = [vp, i32, vp]
         _lib = L
     return _lib
 
@@ -166,6 +168,15 @@ class Oracle:
         R, M = amp.shape[0], amp.shape[2]
         f = np.zeros((R, self.n_u))
         self._L.or_load(self.h, int(problem), R, M, _p(amp), _p(wave), _p(phase), _p(f))
+        return f
+
+    def load_cavity(self, kind=0):
+        """2D load vector with tangential boundary data through the Nitsche form l_h
+        (eq. nitsche_rhs): kind 0 the lid-driven cavity (Sec. 6.4), kind 1 the verification
+        flow u = curl(x(1-x)y(1-y)), p = 0."""
+        f = np.zeros(self.n_u)
+        if self._L.or_load_cavity(self.h, int(kind), _p(f)) != 0:
+            raise ValueError("cavity load: 2D only, kind 0 or 1")
         return f
 
     def matvec(self, x):

@@ -775,6 +775,100 @@ void load_vector(const Problem& P, int problem, int nmodes, const double* amp, c
 }
 
 // ---------------------------------------------------------------------------
+// Load vector with non-homogeneous tangential boundary data (2D), Sec. 4: the
+// Nitsche linear form of eq. nitsche_rhs added to the volume load,
+//   f_i = (f, Phi_i) + sum_F int_F 2 nu ( -((sym grad Phi_i) n) . g + (C_pen/h_F) g . Phi_i ) dS.
+//   kind 0: lid-driven cavity (Sec. 6.4): f = 0, g = (1, 0) on the side y = 1, g = 0 elsewhere.
+//   kind 1: a verification flow with u = curl psi, psi = x(1-x)y(1-y), i.e.
+//           u = (x(1-x)(1-2y), -(1-2x)y(1-y)), p = 0, f = -nu Lap u = (2nu(1-2y), -2nu(1-2x)),
+//           g = u on every side (tangential there, u.n = 0).  u lies in the velocity space for
+//           every k' >= 1, so a consistent discretisation returns it exactly.
+// Volume and faces use k'+2 Gauss points per direction (exact: the integrands are polynomials
+// of degree at most k'+3 per direction).
+// ---------------------------------------------------------------------------
+static void cavity_data(int kind, double nu, const double* x, int fdir, int side, double* f, double* g) {
+  f[0] = f[1] = f[2] = 0.0;
+  g[0] = g[1] = g[2] = 0.0;
+  if (kind == 0) {
+    if (fdir == 1 && side == 1) g[0] = 1.0;
+    return;
+  }
+  f[0] = 2.0 * nu * (1.0 - 2.0 * x[1]);
+  f[1] = -2.0 * nu * (1.0 - 2.0 * x[0]);
+  g[0] = x[0] * (1.0 - x[0]) * (1.0 - 2.0 * x[1]);
+  g[1] = -(1.0 - 2.0 * x[0]) * x[1] * (1.0 - x[1]);
+}
+
+void cavity_load(const Problem& P, int kind, double* fout) {
+  std::fill(fout, fout + P.nu_dofs, 0.0);
+  const int nq = P.kp + 2;
+  std::vector<double> xq, wq;
+  gauss_legendre01(nq, xq, wq);
+  Tab1D tabs[3][2];
+  std::vector<VelEval> ve;
+  int e[3] = {0, 0, 0};
+  for (e[1] = 0; e[1] < P.N; ++e[1])
+    for (e[0] = 0; e[0] < P.N; ++e[0]) {
+      // volume part (f, Phi_i)
+      if (kind == 1) {
+        build_tabs_for_element(P, e, xq, tabs);
+        int q[3] = {0, 0, 0};
+        for (q[1] = 0; q[1] < nq; ++q[1])
+          for (q[0] = 0; q[0] < nq; ++q[0]) {
+            double x[3] = {(e[0] + xq[q[0]]) * P.h, (e[1] + xq[q[1]]) * P.h, 0.0};
+            const double wt = P.h * P.h * wq[q[0]] * wq[q[1]];
+            double f[3], g[3];
+            cavity_data(kind, P.nu, x, -1, -1, f, g);
+            tensor_eval_velocity(P, e, tabs, q, ve);
+            for (const VelEval& v : ve) fout[v.g] += wt * (f[0] * v.val[0] + f[1] * v.val[1]);
+          }
+      }
+      // boundary sides of this element: l_h(Phi_i)
+      for (int fdir = 0; fdir < 2; ++fdir)
+        for (int side = 0; side < 2; ++side) {
+          if ((side == 0 && e[fdir] != 0) || (side == 1 && e[fdir] != P.N - 1)) continue;
+          double nrm[3] = {0, 0, 0};
+          nrm[fdir] = side == 0 ? -1.0 : 1.0;
+          const int t = 1 - fdir;  // tangential direction
+          Tab1D ftabs[3][2];
+          std::vector<double> xs_t(nq);
+          for (int qq = 0; qq < nq; ++qq) xs_t[qq] = (e[t] + xq[qq]) * P.h;
+          std::vector<double> xs_n(1, side == 0 ? 0.0 : 1.0);
+          for (int dir = 0; dir < 2; ++dir) {
+            const std::vector<double>& xs = dir == fdir ? xs_n : xs_t;
+            eval_on_element(P.sp_lo, e[dir], xs, ftabs[dir][0].v, ftabs[dir][0].d);
+            ftabs[dir][0].nloc = P.sp_lo.deg + 1;
+            eval_on_element(P.sp_hi, e[dir], xs, ftabs[dir][1].v, ftabs[dir][1].d);
+            ftabs[dir][1].nloc = P.sp_hi.deg + 1;
+          }
+          for (int qq = 0; qq < nq; ++qq) {
+            int qf[3] = {0, 0, 0};
+            qf[t] = qq;
+            double x[3] = {0, 0, 0};
+            x[t] = xs_t[qq];
+            x[fdir] = xs_n[0];
+            const double wt = P.h * wq[qq];
+            double f[3], g[3];
+            cavity_data(kind, P.nu, x, fdir, side, f, g);
+            tensor_eval_velocity(P, e, ftabs, qf, ve);
+            for (const VelEval& v : ve) {
+              double eps[3][3];
+              sym_grad(v, eps);
+              double epsn_g = 0.0, g_v = 0.0;
+              for (int a = 0; a < 3; ++a) {
+                double en = 0.0;
+                for (int b = 0; b < 3; ++b) en += eps[a][b] * nrm[b];
+                epsn_g += en * g[a];
+                g_v += g[a] * v.val[a];
+              }
+              fout[v.g] += wt * 2.0 * P.nu * (-epsn_g + (P.cpen / P.h) * g_v);
+            }
+          }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Sparse kernels on the assembled matrices (plain loops).
 // ---------------------------------------------------------------------------
 // Saddle-point product [A B^T; B 0] [u; p].
@@ -1276,6 +1370,15 @@ void or_load(void* h, int problem, int nrhs, int nmodes, const double* amp, cons
     const double* ph = phase ? phase + int64_t(r) * P->dim * nmodes : nullptr;
     load_vector(*P, problem, a ? nmodes : 0, a, k, ph, f + int64_t(r) * P->nu_dofs);
   }
+}
+
+// Cavity-type load vector (2D; kind 0 lid, 1 verification flow).  Returns -1 for 3D or an
+// unknown kind.
+int or_load_cavity(void* h, int kind, double* f) {
+  Problem* P = static_cast<Problem*>(h);
+  if (P->dim != 2 || kind < 0 || kind > 1) return -1;
+  cavity_load(*P, kind, f);
+  return 0;
 }
 
 void or_matvec(void* h, const double* x, double* y) { saddle_matvec(*static_cast<Problem*>(h), x, y); }

@@ -530,3 +530,57 @@ def test_ic0_breakdown_reports_error():
     if np.linalg.eigvalsh(A)[0] < 0:
         rc, shift = o.ic0()
         assert rc == -4 or shift > 0
+
+
+# ---------------------------------------------------------------------------
+# Tangential boundary data through the Nitsche form l_h (eq. nitsche_rhs, Sec. 4).
+# Consistency: a flow that lies in the discrete space (u = curl(x(1-x)y(1-y)), p = 0,
+# tangential on the boundary) is returned exactly.  The lid-driven cavity (Sec. 6.4):
+# mirror symmetry about x = 1/2, zero net flux through x = 1/2 (the discrete velocity is
+# divergence free), lid velocity close to 1, and l_h supported on the lid's functions.
+# ---------------------------------------------------------------------------
+def _verification_flow(pts):
+    x, y = pts[:, 0], pts[:, 1]
+    return np.stack([x * (1 - x) * (1 - 2 * y), -(1 - 2 * x) * y * (1 - y)], 1)
+
+
+@pytest.mark.parametrize("N,kp,nu", [(6, 1, 1.0), (5, 2, 0.3), (4, 3, 1.0), (1, 2, 1.0)])
+def test_cavity_load_reproduces_discrete_flow(N, kp, nu):
+    o = Oracle(N, kp, nu=nu)
+    f = o.load_cavity(1)
+    pts = np.random.default_rng(3).uniform(0, 1, (40, 2))
+    for pa in (PC_EXACT, PC_IC0):
+        u, p, info = o.solve(f, tol=1e-14, pc_A=pa)
+        v = o.evaluate(u, p, pts)
+        assert np.abs(v[:, :2] - _verification_flow(pts)).max() <= 1e-11, pa
+        assert np.abs(v[:, 3]).max() <= 1e-10
+
+
+def test_cavity_lid_properties():
+    o = Oracle(16, 2)
+    f = o.load_cavity(0)
+    u, p, info = o.solve(f, tol=1e-12)
+    rng = np.random.default_rng(4)
+    P1 = rng.uniform(0, 1, (20, 2))
+    P2 = P1.copy()
+    P2[:, 0] = 1 - P1[:, 0]
+    a, b = o.evaluate(u, p, P1), o.evaluate(u, p, P2)
+    assert np.abs(a[:, 0] - b[:, 0]).max() <= 1e-10
+    assert np.abs(a[:, 1] + b[:, 1]).max() <= 1e-10
+    # net flux through x = 1/2: Gauss rule per element, exact for the piecewise polynomial
+    xg, wg = np.polynomial.legendre.leggauss(6)
+    ys = np.concatenate([(e + (xg + 1) / 2) / 16 for e in range(16)])
+    ws = np.concatenate([wg / 2 / 16 for e in range(16)])
+    ux = o.evaluate(u, p, np.stack([np.full_like(ys, 0.5), ys], 1))[:, 0]
+    assert abs(ws @ ux) <= 1e-10
+    top = o.evaluate(u, p, np.stack([np.linspace(0.2, 0.8, 7), np.ones(7)], 1))[:, 0]
+    assert np.abs(top - 1).max() <= 0.05
+    # l_h acts only on functions whose support meets y = 1: the last k'+1 rows (y index) of
+    # the first component, which has N + k' - 1 functions in x (degree k'+1, both end
+    # functions removed) and N + k' in y, x fastest
+    nx = o.N + o.kp - 1
+    fx = f[: o.n_u // 2].reshape(o.N + o.kp, nx)
+    assert np.abs(fx[: -(o.kp + 1)]).max() == 0.0 and np.abs(fx[-1]).max() > 0
+    assert np.abs(f[o.n_u // 2:]).max() <= 1e-14 * np.abs(f).max()
+    with pytest.raises(ValueError):
+        Oracle(2, 1, dim=3).load_cavity(0)
