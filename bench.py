@@ -120,7 +120,7 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1309_5048_amd import StokesProblem, PC_IC0, PC_ICPCG, PC_IDEAL, PC_IDEAL_A, PC_JPCG, PC_PCGAQ, MIXED, FP64
+    from paper_1309_5048_amd import StokesProblem, PC_IC0, PC_ICPCG, PC_IDEAL, PC_IDEAL_A, PC_JPCG, PC_PCGAQ, MIXED, FP64, CAVITY_LID
 
     torch.cuda.set_device(0)
     N, kp, dim, tol = 256, 2, 2, 1e-8
@@ -231,6 +231,17 @@ def main():
             log("ideal_A_diagQ", extra["c1_ideal_A_diagQ"])
         except Exception as e:  # report, keep the headline
             extra["c1_ideal_A_diagQ"] = {"error": str(e)}
+        try:
+            # the lid-driven cavity on the C1 mesh: load through the Nitsche form l_h
+            fc = gp.load_cavity(CAVITY_LID)
+            s_c0, inf_c0 = timed_solves(gp, fc, 1, 1, tol=tol, precond=PC_IC0)
+            s_cq, inf_cq = timed_solves(gp, fc, 1, 1, tol=tol, precond=PC_PCGAQ)
+            extra["c1_cavity"] = {"ic0_s": round(s_c0, 5), "ic0_iters": inf_c0[-1]["iters"],
+                                  "pcgAQ_s": round(s_cq, 5), "pcgAQ_iters": inf_cq[-1]["iters"],
+                                  "pcgAQ_inner_iters_total": inf_cq[-1]["inner_iters_total"]}
+            log("cavity", extra["c1_cavity"])
+        except Exception as e:  # report, keep the headline
+            extra["c1_cavity"] = {"error": str(e)}
         del gp
         torch.cuda.empty_cache()
         try:

@@ -144,6 +144,20 @@ int stokes_set_refine_tol(stokes_problem* pb, double rtol);
  * points per direction) into f_dev [nrhs][n_u]. */
 int stokes_load(stokes_problem* pb, const stokes_forcing* spec, int nrhs, double* f_dev);
 
+/* Load vector with tangential boundary data imposed weakly (2D only):
+ * f_i = (f, Phi_i) + l_h(Phi_i), l_h the Nitsche form of eq. nitsche_rhs (Sec. 4),
+ * l_h(v) = sum_F int_F 2 nu ( -((sym grad v) n).g + (C_pen/h_F) g.v ) dS, Gauss rule with
+ * k'+2 points per direction (exact for these data).  f_dev [n_u] (device) is overwritten.
+ *   STOKES_CAVITY_LID:    the lid-driven cavity of Sec. 6.4: f = 0, g = (1, 0) on y = 1,
+ *                         g = 0 on the other sides.
+ *   STOKES_CAVITY_VERIFY: u = (x(1-x)(1-2y), -(1-2x)y(1-y)) (= curl of x(1-x)y(1-y)), p = 0,
+ *                         f = -nu Lap u, g = u on every side.  u lies in the discrete space
+ *                         for every k', so the solve returns it up to the solver tolerance.
+ * Uses the current viscosity (stokes_set_nu).  3D or another kind: STOKES_EINVAL. */
+#define STOKES_CAVITY_LID 0
+#define STOKES_CAVITY_VERIFY 1
+int stokes_load_cavity(stokes_problem* pb, int kind, double* f_dev);
+
 /* Solve [A B^T; B 0][u; p] = [f; 0] from x0 = 0: f [n_u] in, u [n_u] and pr [n_p] out
  * (pr has zero mean, w.pr = 0).  tol: relative M^{-1}-norm residual (e.g. 1e-8).
  * precond: STOKES_PC_*.  info may be NULL. */

@@ -1360,6 +1360,16 @@ int stokes_load(stokes_problem* pb, const stokes_forcing* spec, int nrhs, double
   return 0;
 }
 
+int stokes_load_cavity(stokes_problem* pb, int kind, double* f_dev) {
+  if (!pb || !f_dev) return fail(pb, STOKES_EINVAL, "bad arguments to stokes_load_cavity");
+  if (pb->S.dim != 2) return fail(pb, STOKES_EINVAL, "stokes_load_cavity: 2D problems only");
+  if (kind != STOKES_CAVITY_LID && kind != STOKES_CAVITY_VERIFY)
+    return fail(pb, STOKES_EINVAL, "stokes_load_cavity: unknown kind");
+  hipError_t e = assemble_load_cavity(pb->S, pb->nu, pb->cpen, kind, f_dev, pb->stream);
+  if (e != hipSuccess) return fail_hip(pb, e, "assemble_load_cavity", __LINE__);
+  return 0;
+}
+
 int stokes_solve_batched(stokes_problem* pb, int nrhs, const double* F, double* U, double* P, double tol, int precond,
                          int precision, stokes_info* infos) {
   if (!pb) return STOKES_EINVAL;

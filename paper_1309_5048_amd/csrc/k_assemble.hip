@@ -483,6 +483,76 @@ __global__ void k_load_vector(AsmArgs a, ModeArgs m, double* __restrict__ f) {
   f[(size_t)r * a.n_u + i] = sum;
 }
 
+// Tangential boundary data of the 2D cavity-type problems: volume force f and boundary
+// velocity g at x (on the side with normal direction fd, side 0: coordinate 0, 1:
+// coordinate 1).  kind 0: lid-driven cavity (Sec. 6.4), f = 0, g = (1, 0) on y = 1.
+// kind 1: u = curl(x(1-x)y(1-y)) = (x(1-x)(1-2y), -(1-2x)y(1-y)), p = 0, f = -nu Lap u,
+// g = u, a flow that lies in the discrete velocity space for every k' >= 1.
+__device__ void cavity_fg(int kind, double nu, const double* x, int fd, int side, double* f, double* g) {
+  f[0] = f[1] = 0.0;
+  g[0] = g[1] = 0.0;
+  if (kind == 0) {
+    if (fd == 1 && side == 1) g[0] = 1.0;
+    return;
+  }
+  f[0] = 2.0 * nu * (1.0 - 2.0 * x[1]);
+  f[1] = -2.0 * nu * (1.0 - 2.0 * x[0]);
+  g[0] = x[0] * (1.0 - x[0]) * (1.0 - 2.0 * x[1]);
+  g[1] = -(1.0 - 2.0 * x[0]) * x[1] * (1.0 - x[1]);
+}
+
+// f_i = (f, Phi_i) + l_h(Phi_i) with the Nitsche form of eq. nitsche_rhs,
+//   l_h(v) = sum_F int_F 2 nu ( -((sym grad v) n) . g + (C_pen/h_F) g . v ) dS,
+// for Phi_i = B e_c: ((sym grad Phi_i) n) . g = (g_c dB/dn + (n.g) dB/dx_c) / 2.
+// One thread per velocity function (2D), quadrature over the elements and boundary sides
+// of its support (k'+2 points per direction, table points nq / nq+1 at the element ends).
+__global__ void k_load_cavity(AsmArgs a, int kind, const double* __restrict__ xq, double* __restrict__ f) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n_u) return;
+  Fun fi;
+  decode_dof(a, i, fi);
+  const int c = fi.comp;
+  const double h = 1.0 / a.N;
+  const int nq = a.nq;
+  double sum = 0.0;
+  int e[3] = {0, 0, 0}, q[3] = {0, 0, 0};
+  if (kind == 1) {
+    for (e[1] = fi.elo[1]; e[1] <= fi.ehi[1]; ++e[1])
+      for (e[0] = fi.elo[0]; e[0] <= fi.ehi[0]; ++e[0])
+        for (q[1] = 0; q[1] < nq; ++q[1])
+          for (q[0] = 0; q[0] < nq; ++q[0]) {
+            const double x[2] = {(e[0] + xq[q[0]]) * h, (e[1] + xq[q[1]]) * h};
+            double fv[2], gv[2], B, G[3] = {0, 0, 0};
+            cavity_fg(kind, a.nu, x, -1, -1, fv, gv);
+            eval_fun(a, fi, e, q, &B, G);
+            sum += h * h * a.wq[q[0]] * a.wq[q[1]] * fv[c] * B;
+          }
+  }
+  const double pen = a.cpen / h;
+  for (int fd = 0; fd < 2; ++fd)
+    for (int side = 0; side < 2; ++side) {
+      const int eb = side == 0 ? 0 : a.N - 1;
+      if (fi.elo[fd] > eb || fi.ehi[fd] < eb) continue;
+      const double sgn = side == 0 ? -1.0 : 1.0;
+      const int t = 1 - fd;
+      e[fd] = eb;
+      q[fd] = side == 0 ? nq : nq + 1;
+      for (e[t] = fi.elo[t]; e[t] <= fi.ehi[t]; ++e[t])
+        for (int qq = 0; qq < nq; ++qq) {
+          q[t] = qq;
+          double x[2];
+          x[t] = (e[t] + xq[qq]) * h;
+          x[fd] = side == 0 ? 0.0 : 1.0;
+          double fv[2], gv[2], B, G[3] = {0, 0, 0};
+          cavity_fg(kind, a.nu, x, fd, side, fv, gv);
+          eval_fun(a, fi, e, q, &B, G);
+          const double epsn_g = 0.5 * (gv[c] * sgn * G[fd] + sgn * gv[fd] * G[c]);
+          sum += h * a.wq[qq] * 2.0 * a.nu * (-epsn_g + pen * gv[c] * B);
+        }
+    }
+  f[i] = sum;
+}
+
 // ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
@@ -600,6 +670,22 @@ hipError_t assemble_load(const Spaces& S, double nu, int manufactured, int nmode
   m.xq = T.xq;
   const int64_t nt = S.n_u * nrhs;
   hipLaunchKernelGGL(k_load_vector, dim3(unsigned((nt + 127) / 128)), dim3(128), 0, st, a, m, f);
+  e = hipGetLastError();
+  hipError_t e2 = hipStreamSynchronize(st);
+  free_tables(T);
+  return e != hipSuccess ? e : e2;
+}
+
+hipError_t assemble_load_cavity(const Spaces& S, double nu, double cpen, int kind, double* f, hipStream_t st) {
+  Tables T;
+  const int nq = S.kp + 2;
+  hipError_t e = build_tables(S, nq, T, st);
+  if (e != hipSuccess) {
+    free_tables(T);
+    return e;
+  }
+  AsmArgs a = make_args(S, nu, cpen, nq, T);
+  hipLaunchKernelGGL(k_load_cavity, dim3(unsigned((S.n_u + 127) / 128)), dim3(128), 0, st, a, kind, T.xq, f);
   e = hipGetLastError();
   hipError_t e2 = hipStreamSynchronize(st);
   free_tables(T);

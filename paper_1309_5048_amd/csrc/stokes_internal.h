@@ -360,6 +360,7 @@ hipError_t assemble_saddle(const Spaces& S, double nu, double cpen, const int32_
                            double* val, double* diagQ, double* w, hipStream_t st);
 // Pressure mass matrix Q (CSR pattern given, values computed).
 hipError_t assemble_Q(const Spaces& S, const int32_t* rowptr, const int32_t* col, double* val, hipStream_t st);
+hipError_t assemble_load_cavity(const Spaces& S, double nu, double cpen, int kind, double* f, hipStream_t st);
 hipError_t assemble_load(const Spaces& S, double nu, int manufactured, int nmodes, int nrhs, const double* amp_d,
                          const int32_t* wave_d, const double* phase_d, double* f, hipStream_t st);
 hipError_t ic0_factor(int64_t n, int64_t nnzL, const int64_t* src, const int32_t* rowptr, const int32_t* col,

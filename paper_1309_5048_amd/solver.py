@@ -125,6 +125,14 @@ class StokesProblem:
         del keep
         return f
 
+    def load_cavity(self, kind=N.CAVITY_LID):
+        """2D load vector [n_u] with tangential boundary data through the Nitsche form l_h:
+        CAVITY_LID (lid-driven cavity) or CAVITY_VERIFY (a flow in the discrete space)."""
+        f = self.empty(self.n_u)
+        self._stream()
+        self._check(self._L.stokes_load_cavity(self._h, int(kind), _ptr(f)), allow_nc=False)
+        return f
+
     # -- solves -------------------------------------------------------------
     def solve(self, f, tol=1e-8, precond=N.PC_IC0, precision=N.FP64, out=None):
         """u [n_u], p [n_p] (zero mean), info dict."""

@@ -261,6 +261,38 @@ def test_ideal_A_diagQ(pair):
         gp.solve(_cuda(f), tol=1e-8, precond=PC_IDEAL_A, precision=MIXED)
 
 
+def test_cavity_load(pair):
+    """Load vectors with tangential boundary data through l_h (eq. nitsche_rhs): the
+    lid-driven cavity (Sec. 6.4) and the verification flow, against the oracle (pinned by
+    consistency and the lid's symmetry); the device solve returns the verification flow."""
+    from paper_1309_5048_amd import CAVITY_LID, CAVITY_VERIFY, StokesError
+    gp, o = pair
+    if o.dim == 3:
+        with pytest.raises(StokesError):
+            gp.load_cavity(CAVITY_LID)
+        return
+    for kind in (CAVITY_LID, CAVITY_VERIFY):
+        f = gp.load_cavity(kind).cpu().numpy()
+        fo = o.load_cavity(kind)
+        assert _rel(f, fo) <= 1e-13, kind
+    with pytest.raises(StokesError):
+        gp.load_cavity(2)
+    f = gp.load_cavity(CAVITY_VERIFY)
+    u, p, info = gp.solve(f, tol=1e-13)
+    pts = np.random.default_rng(6).uniform(0, 1, (30, 2))
+    v = o.evaluate(u.cpu().numpy(), p.cpu().numpy(), pts)
+    x, y = pts[:, 0], pts[:, 1]
+    ue = np.stack([x * (1 - x) * (1 - 2 * y), -(1 - 2 * x) * y * (1 - y)], 1)
+    # exact up to the solver tolerance (a wrong boundary term moves u by O(h^k) or more)
+    assert np.abs(v[:, :2] - ue).max() <= 1e-9
+    assert np.abs(v[:, 3]).max() <= 1e-8
+    f = gp.load_cavity(CAVITY_LID)
+    u, p, info = gp.solve(f, tol=1e-13)
+    uo, po, _ = o.solve(f.cpu().numpy(), tol=1e-13)
+    assert _rel(u.cpu().numpy(), uo) <= 1e-10
+    assert _rel(p.cpu().numpy(), po) <= 1e-10
+
+
 @pytest.mark.parametrize("nrhs", [3, 8, 16])
 def test_batched(pair, nrhs):
     gp, o = pair

@@ -584,3 +584,29 @@ def test_cavity_lid_properties():
     assert np.abs(f[o.n_u // 2:]).max() <= 1e-14 * np.abs(f).max()
     with pytest.raises(ValueError):
         Oracle(2, 1, dim=3).load_cavity(0)
+
+
+@pytest.mark.slow
+def test_iteration_counts_cavity_k2(paper):
+    """The paper's cavity counts (Sec. 6.4 table, k' = 2, tol 1e-12 on the true 2-norm relative
+    residual, inner PCG 1e-6) for the five preconditioners, with the lid load through l_h.
+    Ideal(A,Q) within 2 and Diag(A,Q) within 3 %; the Diag(Q) variants, whose slow pressure
+    convergence (gamma_Q ~ 0.058) makes the count sensitive to the discretisation's details
+    (the paper adds corner functions), within 12 %; the PCG variants from h = 1/16 (on the
+    coarsest mesh those functions weigh most, and the paper's PCG(A,Q) count of 48 at h = 1/8
+    stands apart from its own column of 37s), PCG(A,Q) within 2."""
+    ref = paper["iters_cavity_k2"]
+    for i, inv_h in enumerate(ref["inv_h"][:3]):
+        o = Oracle(inv_h, 2)
+        b = np.concatenate([o.load_cavity(0), np.zeros(o.n_p)])
+        K = o.saddle()
+        for key, pa, pq, tol_in, bar in (("ideal_A_Q", PC_EXACT, PQ_EXACT, 0, 2), ("diag_A_Q", PC_JACOBI, PQ_DIAG, 0, 0.03),
+                                         ("ideal_A_diagQ", PC_EXACT, PQ_DIAG, 0, 0.12),
+                                         ("pcg_A_diagQ", PC_JPCG, PQ_DIAG, 1e-6, 0.12), ("pcg_A_Q", PC_JPCG, PQ_JPCG, 1e-6, 2)):
+            if key.startswith("pcg") and inv_h == 8:
+                continue
+            x, info, xh = o.minres(b, tol=1e-14, maxit=1500, pc_A=pa, pc_Q=pq, inner_tol=tol_in, x_history=True)
+            r2 = np.linalg.norm(b - (K @ xh.T).T, axis=1) / np.linalg.norm(b)
+            j2 = int(np.argmax(r2 <= 1e-12)) + 1
+            lim = bar if bar >= 1 else bar * ref[key][i]
+            assert abs(j2 - ref[key][i]) <= lim, (inv_h, key, j2, ref[key][i])
