@@ -211,6 +211,9 @@ struct stokes_problem {
   // convergence polling: two pinned host flags and their completion events
   int* hflag = nullptr;
   hipEvent_t flag_ev[2] = {nullptr, nullptr};
+  // the same for the inner CG loops
+  int* pcg_hflag = nullptr;
+  hipEvent_t pcg_ev[2] = {nullptr, nullptr};
   ~stokes_problem() {
     for (auto& t : prof_pool) {
       (void)hipEventDestroy(t.before);
@@ -219,6 +222,9 @@ struct stokes_problem {
     for (auto& e : flag_ev)
       if (e) (void)hipEventDestroy(e);
     if (hflag) (void)hipHostFree(hflag);
+    for (auto& e : pcg_ev)
+      if (e) (void)hipEventDestroy(e);
+    if (pcg_hflag) (void)hipHostFree(pcg_hflag);
     mem.release();
   }
 };
@@ -621,19 +627,41 @@ int check_trsv_err(stokes_problem* pb, const SchedPair* sp) {
 constexpr double kIdealTol = 1e-12;
 constexpr int kIdealMaxit = 100000;
 
-// Inner CG state after a queued chunk: *done = all columns finished; once they have, the
-// largest iteration count of this application goes to *expect.  Returns nonzero on error.
-int pcg_done(stokes_problem* pb, const PcgScalars& s, int R, int* done, int* expect) {
-  PcgState ps[kRMax];
-  CK(hipMemcpyAsync(ps, s.st, sizeof(PcgState) * R, hipMemcpyDeviceToHost, pb->stream));
-  CK(hipStreamSynchronize(pb->stream));
-  int nd = 0, mx = 0;
-  for (int c = 0; c < R; ++c) {
-    nd += ps[c].done ? 1 : 0;
-    mx = std::max(mx, ps[c].iter);
+// Queue inner CG iterations (iter() queues one) until the device all-done flag is set or
+// maxit are queued: a first chunk of 4 fewer than the previous application needed, then
+// chunks of 4.  The flag written after chunk c is read while chunk c+1 is already queued,
+// so the device does not wait for the host; at most one chunk runs after convergence, its
+// launches returning at once.  *expect receives this application's largest count.
+template <typename Iter>
+int pcg_run(stokes_problem* pb, const PcgScalars& s, int R, int maxit, int* expect, Iter iter) {
+  hipStream_t st = pb->stream;
+  if (pb->pcg_hflag == nullptr) {
+    CK(hipHostMalloc((void**)&pb->pcg_hflag, 2 * sizeof(int), hipHostMallocDefault));
+    for (auto& e : pb->pcg_ev) CK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   }
-  *done = nd == R;
-  if (*done && mx > 0) *expect = mx;
+  int queued = 0, chunk = 0;
+  bool done = false;
+  while (queued < maxit && !done) {
+    const int n = std::min(maxit - queued, chunk == 0 ? std::max(1, *expect - 4) : 4);
+    for (int k = 0; k < n; ++k) CK(iter());
+    queued += n;
+    const int slot = chunk & 1;
+    CK(hipMemcpyAsync(pb->pcg_hflag + slot, s.alldone, sizeof(int), hipMemcpyDeviceToHost, st));
+    CK(hipEventRecord(pb->pcg_ev[slot], st));
+    if (chunk > 0) {
+      CK(hipEventSynchronize(pb->pcg_ev[1 - slot]));
+      done = pb->pcg_hflag[1 - slot] != 0;
+      prof_flush(pb);
+    }
+    ++chunk;
+  }
+  PcgState ps[kRMax];
+  CK(hipMemcpyAsync(ps, s.st, sizeof(PcgState) * R, hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  int mx = 0;
+  for (int c = 0; c < R; ++c) mx = std::max(mx, ps[c].iter);
+  if (mx > 0) *expect = mx;
+  prof_flush(pb);
   return 0;
 }
 
@@ -671,31 +699,21 @@ int precond_velocity(stokes_problem* pb, int precond, Work& W, SchedPair* sp, co
     CK(inner_precond(s.rho, skip, false));
     CK(pcg_init2<T>(R, n_u, (const T*)W.pz, (T*)W.pp, s, rtol_in, maxit_in, skip, outer_st, st));
     int ip = 0;
-    // Iterations are queued in chunks between host reads of the done flag: first as many as
-    // the last application needed, then 4 at a time (iterations after convergence return
-    // at once on the device flag).
-    int queued = 0;
-    while (queued < maxit_in) {
-      const int chunk_it = std::min(maxit_in - queued, queued == 0 ? std::max(1, expect) : 4);
-      queued += chunk_it;
-      for (int k = 0; k < chunk_it; ++k) {
-        CK(pcg_spmv<T>(R, pb->rs_A, pb->rowptr, pb->aend, pb->col, val, (const T*)W.pp, (T*)W.pq, s,
-                       precond == STOKES_PC_ICPCG, st));
-        if (jacobi_cg) {
-          CK(pcg_axpy_jacobi<T>(R, n_u, (const T*)W.pp, (const T*)W.pq, pb->diagA, zout, (T*)W.pr, (T*)W.pz, s, ip,
-                                st));
-        } else {
-          CK(pcg_axpy<T>(R, n_u, (const T*)W.pp, (const T*)W.pq, zout, (T*)W.pr, s, ip, st));
-          CK(inner_precond(s.rho + (1 - ip) * kRMax, s.alldone, true));
-        }
-        CK(pcg_pupdate<T>(R, n_u, (const T*)W.pz, (T*)W.pp, s, ip, st));
-        ip = 1 - ip;
+    auto iter = [&]() -> hipError_t {
+      hipError_t e = pcg_spmv<T>(R, pb->rs_A, pb->rowptr, pb->aend, pb->col, val, (const T*)W.pp, (T*)W.pq, s,
+                                 precond == STOKES_PC_ICPCG, st);
+      if (e == hipSuccess && jacobi_cg)
+        e = pcg_axpy_jacobi<T>(R, n_u, (const T*)W.pp, (const T*)W.pq, pb->diagA, zout, (T*)W.pr, (T*)W.pz, s, ip,
+                               st);
+      if (e == hipSuccess && !jacobi_cg) {
+        e = pcg_axpy<T>(R, n_u, (const T*)W.pp, (const T*)W.pq, zout, (T*)W.pr, s, ip, st);
+        if (e == hipSuccess) e = inner_precond(s.rho + (1 - ip) * kRMax, s.alldone, true);
       }
-      int done = 0;
-      if (int e = pcg_done(pb, s, R, &done, &expect)) return e;
-      prof_flush(pb);
-      if (done) break;
-    }
+      if (e == hipSuccess) e = pcg_pupdate<T>(R, n_u, (const T*)W.pz, (T*)W.pp, s, ip, st);
+      ip = 1 - ip;
+      return e;
+    };
+    if (int e = pcg_run(pb, s, R, maxit_in, &expect, iter)) return e;
     CK(dot<T, T>(R, 0, n_u, vin, zout, pb->partials, pb->counter, dot_out, st));
     (void)inner_total;
     return 0;
@@ -769,21 +787,15 @@ int precond_pressure(stokes_problem* pb, Work& W, bool ideal, const T* vin_p, T*
   int& expect = pb->pcgq_expect[ideal ? 1 : 0];
   CK(pcg_init2<T>(R, n_p, (const T*)W.qz, (T*)W.qp, s, rtol_in, maxit_in, skip, outer_st, st));
   int ip = 0;
-  int queued = 0;
-  while (queued < maxit_in) {
-    const int chunk_it = std::min(maxit_in - queued, queued == 0 ? std::max(1, expect) : 4);
-    queued += chunk_it;
-    for (int k = 0; k < chunk_it; ++k) {
-      CK(pcg_spmv<T>(R, pb->rs_Q, pb->Qrowptr, nullptr, pb->Qcol, qval, (const T*)W.qp, (T*)W.qq, s, false, st));
-      CK(pcg_axpy_jacobi<T>(R, n_p, (const T*)W.qp, (const T*)W.qq, pb->diagQ, zout_p, (T*)W.qr, (T*)W.qz, s, ip,
-                            st));
-      CK(pcg_pupdate<T>(R, n_p, (const T*)W.qz, (T*)W.qp, s, ip, st));
-      ip = 1 - ip;
-    }
-    int done = 0;
-    if (int e = pcg_done(pb, s, R, &done, &expect)) return e;
-    if (done) break;
-  }
+  auto iter = [&]() -> hipError_t {
+    hipError_t e = pcg_spmv<T>(R, pb->rs_Q, pb->Qrowptr, nullptr, pb->Qcol, qval, (const T*)W.qp, (T*)W.qq, s, false, st);
+    if (e == hipSuccess)
+      e = pcg_axpy_jacobi<T>(R, n_p, (const T*)W.qp, (const T*)W.qq, pb->diagQ, zout_p, (T*)W.qr, (T*)W.qz, s, ip, st);
+    if (e == hipSuccess) e = pcg_pupdate<T>(R, n_p, (const T*)W.qz, (T*)W.qp, s, ip, st);
+    ip = 1 - ip;
+    return e;
+  };
+  if (int e = pcg_run(pb, s, R, maxit_in, &expect, iter)) return e;
   CK(scale_skip<T>(n_p * R, zout_p, 2.0 * pb->nu, skip, st));
   CK(dot<T, T>(R, 0, n_p, vin_p, zout_p, pb->partials, pb->counter, dot_out, st));
   return 0;
