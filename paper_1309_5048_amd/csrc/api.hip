@@ -749,7 +749,7 @@ int ensure_pressure_cg(stokes_problem* pb) {
   pb->Qcol = m.upload(cl, st);
   pb->Qval = m.get<double>(cl.size());
   pb->Qval32 = m.get<float>(cl.size());
-  pb->rs_Q.nb = row_split_blocks(np, pb->num_cu);
+  pb->rs_Q.nb = row_split_blocks(np, pb->num_cu, kPcgSpmvBlocksPerCU);
   pb->split_Q_h = balanced_row_split(rp, nullptr, np, pb->rs_Q.nb);
   pb->rs_Q.split = m.upload(pb->split_Q_h, st);
   pb->pcgQ.st = m.get<PcgState>(kRMax);
@@ -1209,7 +1209,8 @@ static int stokes_setup_impl(int n, int p, int dim, double nu, stokes_problem* p
   pb->aend = m.upload(pb->P.aend, st);
   {
     const int64_t n_all = pb->S.n_u + pb->S.n_p;
-    const int nbf = row_split_blocks(n_all, pb->num_cu), nba = row_split_blocks(pb->S.n_u, pb->num_cu);
+    const int nbf = row_split_blocks(n_all, pb->num_cu);
+    const int nba = row_split_blocks(pb->S.n_u, pb->num_cu, kPcgSpmvBlocksPerCU);
     pb->split_full_h = balanced_row_split(pb->P.rowptr, nullptr, n_all, nbf);
     pb->split_A_h = balanced_row_split(pb->P.rowptr, &pb->P.aend, pb->S.n_u, nba);
     pb->rs_full.nb = nbf;

@@ -470,8 +470,8 @@ void strip_groups(const Spaces& S, int strip, std::vector<int32_t>& group_of, in
 // ---------------------------------------------------------------------------
 namespace stk {
 
-int row_split_blocks(int64_t nrows, int num_cu) {
-  const int64_t cap = (int64_t)kSpmvBlocksPerCU * std::max(1, num_cu);
+int row_split_blocks(int64_t nrows, int num_cu, int per_cu) {
+  const int64_t cap = (int64_t)std::max(1, per_cu) * std::max(1, num_cu);
   int64_t nb = std::max<int64_t>(1, std::min<int64_t>(cap, (nrows + 15) / 16));
   nb = std::min<int64_t>(nb, kVecMaxBlocks);
   if (nb > 8) nb = nb / 8 * 8;

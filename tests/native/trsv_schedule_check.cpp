@@ -235,7 +235,7 @@ int hc_row_split(int N, int kp, int dim, int which, int num_cu, int* nb, int32_t
   std::string err;
   if (build_saddle_pattern(S, P, err) != 0) return -1;
   const int64_t nrows = which == 0 ? S.n_u + S.n_p : S.n_u;
-  *nb = row_split_blocks(nrows, num_cu);
+  *nb = which == 0 ? row_split_blocks(nrows, num_cu) : row_split_blocks(nrows, num_cu, kPcgSpmvBlocksPerCU);
   if (split) {
     const std::vector<int32_t> v = balanced_row_split(P.rowptr, which == 0 ? nullptr : &P.aend, nrows, *nb);
     for (size_t i = 0; i < v.size(); ++i) split[i] = v[i];
