@@ -15,8 +15,10 @@
  *   Solver (Sec. 5): preconditioned MINRES with M = blkdiag(M_A, M_Q) (eq.
  *     general_precond_M), M_Q = Diag(Q)/(2 nu) (the scaled mass matrix Q_nu of Sec. 5.1
  *     replaced by its diagonal), M_A = IC(0) of A (Sec. 6.4), IC(0)-PCG on A (Sec. 6.4,
- *     relaxed inner tolerance) or Diag(A).  Stop when the preconditioned residual
- *     estimate |eta_j| <= tol * ||b||_{M^-1} (Sec. 5, M^{-1}-norm of the residual).
+ *     relaxed inner tolerance) or Diag(A); and the other variants of Sec. 5.1 (inner
+ *     Diag-CG on A and on Q, Ideal blocks by converged CG; STOKES_PC_*).  Stop when the
+ *     preconditioned residual estimate |eta_j| <= tol * ||b||_{M^-1} (Sec. 5, M^{-1}-norm
+ *     of the residual).
  *
  * Conventions
  *   - Every vector pointer is a DEVICE pointer to contiguous doubles (the caller owns it;
@@ -129,8 +131,10 @@ int stokes_set_stream(stokes_problem* pb, void* hip_stream);
  * (A ~ nu, L ~ sqrt(nu)), M_Q = Diag(Q)/(2 nu). */
 int stokes_set_nu(stokes_problem* pb, double nu);
 
-/* Inner PCG relative tolerance for STOKES_PC_ICPCG (default 1e-2) and iteration limits
- * (defaults: outer 20000, inner 200).  Non-positive values keep the current setting. */
+/* Inner CG relative tolerance of STOKES_PC_ICPCG, STOKES_PC_JPCG and STOKES_PC_PCGAQ
+ * (default 1e-2) and iteration limits (defaults: outer 20000, inner 200 per block and
+ * application).  The Ideal preconditioners use their own fixed values.  Non-positive values
+ * keep the current setting. */
 int stokes_set_inner_tol(stokes_problem* pb, double rtol);
 int stokes_set_maxit(stokes_problem* pb, int outer, int inner);
 
