@@ -1,7 +1,8 @@
 """GPU checks at the benchmark's full sizes, through the same entry points and launch
 configuration the benchmark times:
 
-  C1  2D, N = 256, k' = 2 (n_u 132,612, n_p 66,564), FP64, IC(0) and inner IC(0)-CG blocks
+  C1  2D, N = 256, k' = 2 (n_u 132,612, n_p 66,564), FP64, IC(0) and inner IC(0)-CG blocks;
+      the lid-driven cavity load on that mesh with the inner Diag-CG variants
   C4  the C1 mesh with 8 adjoint right-hand sides
   C3  3D, N = 32, k' = 1, 16 right-hand sides in one batched solve
   C2  2D, N = 512, k' = 2, mixed FP32/FP64 refinement
@@ -21,7 +22,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
-from oracle.oracle import PC_IC0, PC_ICPCG, PQ_DIAG, Oracle  # noqa: E402
+from oracle.oracle import PC_IC0, PC_ICPCG, PC_JACOBI, PQ_DIAG, Oracle  # noqa: E402
 from synthetic_inputs import WORKLOADS, forcing_modes, random_vector  # noqa: E402
 
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
@@ -126,6 +127,39 @@ def test_c1_converged(c1, pc):
     assert rel <= bar, rel
     assert abs(rel - info["relres_true_Minv"]) <= 1e-6 * rel
     assert _zero_mean(gp, x[o.n_u:])
+
+
+def _relres_Minv_jacobi(o, b, x):
+    """The same with the Jacobi block M = blkdiag(Diag(A), Diag(Q)/(2 nu)), the fixed
+    preconditioner that the inner Diag-CG variants approximate."""
+    r = b - o.matvec(x)
+    zr, _ = o.precond(r, pc_A=PC_JACOBI, pc_Q=PQ_DIAG)
+    zb, _ = o.precond(b, pc_A=PC_JACOBI, pc_Q=PQ_DIAG)
+    return np.sqrt(max(0.0, r @ zr) / (b @ zb))
+
+
+def test_c1_cavity_pcg_AQ(c1):
+    """The lid-driven cavity on the C1 mesh: the device load (Nitsche form l_h) against the
+    oracle's at every entry, then PCG(A,Q) (inner Diag-CG on A and Q to 1e-2, refined on the
+    true residual) and the other variants with inner CG: the oracle-formed residual in the
+    Jacobi-block norm meets tol."""
+    from paper_1309_5048_amd import CAVITY_LID, PC_JPCG, PC_PCGAQ
+    gp, o, w = c1
+    print("[case] c1 cavity load", flush=True)
+    f = gp.load_cavity(CAVITY_LID)
+    fo = o.load_cavity(0)
+    assert _rel(f.cpu().numpy(), fo) <= 1e-13
+    b = np.concatenate([fo, np.zeros(o.n_p)])
+    gp.set_inner_tol(1e-2)
+    for pc in (PC_PCGAQ, PC_JPCG):
+        print("[case] c1 cavity solve, precond %d" % pc, flush=True)
+        u, p, info = gp.solve(f, tol=w["tol"], precond=pc)
+        assert info["status"] == 0
+        x = np.concatenate([u.cpu().numpy(), p.cpu().numpy()])
+        rel = _relres_Minv_jacobi(o, b, x)
+        assert rel <= w["tol"] * (1 + 1e-6), rel
+        assert abs(rel - info["relres_true_Minv"]) <= 1e-6 * rel
+        assert _zero_mean(gp, x[o.n_u:])
 
 
 def test_c4_adjoint_residuals(c1):
