@@ -293,6 +293,33 @@ def test_cavity_load(pair):
     assert _rel(p.cpu().numpy(), po) <= 1e-10
 
 
+@pytest.mark.parametrize("pc,nrhs", [("icpcg", 3), ("jpcg", 3), ("pcgAQ", 3), ("pcgAQ", 16), ("ideal", 3)])
+def test_batched_inner_cg(pair, pc, nrhs):
+    """Batched solves (R = 8 or 16 interleaved columns) with the inner-CG preconditioners:
+    every column converges and matches the oracle's single-column solve (refined MINRES
+    for the inner-CG blocks, exact block solves for Ideal(A,Q))."""
+    from paper_1309_5048_amd import PC_IDEAL, PC_PCGAQ
+    gp, o = pair
+    code = {"icpcg": PC_ICPCG, "jpcg": PC_JPCG, "pcgAQ": PC_PCGAQ, "ideal": PC_IDEAL}[pc]
+    modes = forcing_modes(list(range(4000, 4000 + nrhs)), o.dim)
+    F = o.load(1, modes)
+    tol = 1e-11 if pc == "ideal" else 1e-13
+    U, P, infos = gp.solve_batched(_cuda(F), tol=tol, precond=code)
+    for r in range(nrhs):
+        assert infos[r]["status"] == 0, (r, infos[r])
+        assert infos[r]["inner_iters_total"] > 0
+        if pc == "ideal":
+            uo, po, _ = o.solve(F[r], tol=tol, pc_A=PC_EXACT, pc_Q=PQ_EXACT)
+            bar = 1e-8
+        else:
+            pa = PC_ICPCG if pc == "icpcg" else PC_JPCG
+            pq = PQ_JPCG if pc == "pcgAQ" else PQ_DIAG
+            uo, po, _ = o.solve_refined(F[r], tol=tol, pc_A=pa, pc_Q=pq)
+            bar = 1e-10
+        assert _rel(U[r].cpu().numpy(), uo) <= bar, (r, _rel(U[r].cpu().numpy(), uo))
+        assert _rel(P[r].cpu().numpy(), po) <= bar, (r, _rel(P[r].cpu().numpy(), po))
+
+
 @pytest.mark.parametrize("nrhs", [3, 8, 16])
 def test_batched(pair, nrhs):
     gp, o = pair
