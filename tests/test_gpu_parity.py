@@ -368,6 +368,29 @@ def test_adjoint(pair):
     assert abs(d - o.dnu_dot(lu, u)) <= 1e-12 * abs(o.dnu_dot(lu, u))
 
 
+@pytest.mark.parametrize("pc", ["pcgAQ", "ideal"])
+def test_adjoint_inner_cg(pair, pc):
+    """The adjoint solve with an inner-CG preconditioner: PCG(A,Q) (refined MINRES) reaches
+    the oracle's IC(0) adjoint at tol 1e-13; Ideal(A,Q) (one MINRES run) matches the oracle's
+    adjoint with exact block solves."""
+    from paper_1309_5048_amd import PC_IDEAL, PC_PCGAQ
+    gp, o = pair
+    g_u = random_vector(o.n_u, 7)
+    g_p = random_vector(o.n_p, 8)
+    tol = 1e-13 if pc == "pcgAQ" else 1e-11
+    lam, infos = gp.solve_adjoint(_cuda(np.concatenate([g_u, g_p])), tol=tol,
+                                  precond=PC_PCGAQ if pc == "pcgAQ" else PC_IDEAL)
+    assert infos[0]["status"] == 0 and infos[0]["inner_iters_total"] > 0
+    if pc == "pcgAQ":
+        lu, lp, _ = o.adjoint(g_u, g_p, tol=1e-13)
+    else:  # the same method in the oracle: exact block solves, one MINRES run
+        lu, lp, _ = o.adjoint(g_u, g_p, tol=tol, pc_A=PC_EXACT, pc_Q=PQ_EXACT)
+    lam = lam.cpu().numpy()
+    bar = 1e-9 if pc == "pcgAQ" else 1e-8
+    assert _rel(lam[:o.n_u], lu) <= bar
+    assert _rel(lam[o.n_u:], lp) <= bar
+
+
 # ---------------------------------------------------------------------------
 # Degenerate inputs and error paths
 # ---------------------------------------------------------------------------
