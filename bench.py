@@ -283,6 +283,16 @@ def main():
                                               "mixed_rel_err_p": ep,
                                               "mixed_relres_true_Minv": i32[-1]["relres_true_Minv"]}
             log("c2", extra["c2_n512_mixed_vs_fp64"])
+            # PCG(A,Q) at N = 512: the inner Diag-CG products are bandwidth-bound, so the mixed
+            # mode (FP32 inner MINRES and inner CG) pays there
+            g2.set_inner_tol(1e-2)
+            q64, j64 = timed_solves(g2, f2, 1, 1, tol=tol, precond=PC_PCGAQ, precision=FP64)
+            q32, j32 = timed_solves(g2, f2, 1, 1, tol=tol, precond=PC_PCGAQ, precision=MIXED)
+            extra["c2_n512_pcgAQ_mixed_vs_fp64"] = {
+                "fp64_s": round(q64, 5), "fp64_iters": j64[-1]["iters"], "mixed_s": round(q32, 5),
+                "mixed_iters": j32[-1]["iters"], "mixed_refine_cycles": j32[-1]["refine_cycles"],
+                "speedup": round(q64 / q32, 3), "mixed_relres_true_Minv": j32[-1]["relres_true_Minv"]}
+            log("c2 pcgAQ", extra["c2_n512_pcgAQ_mixed_vs_fp64"])
             del g2
             torch.cuda.empty_cache()
         except Exception as e:
