@@ -337,6 +337,26 @@ def test_batched(pair, nrhs):
         assert _rel(P2[r].cpu().numpy(), po) <= 1e-10
 
 
+@pytest.mark.parametrize("pc", ["jpcg", "pcgAQ"])
+def test_mixed_precision_inner_cg(pair, pc):
+    """The mixed mode with the inner Diag-CG preconditioners (FP32 inner MINRES and inner CG,
+    FP64 true residual): converged in the Jacobi-block norm, and refined to 1e-11 the
+    solution matches the FP64 oracle to 1e-8."""
+    from paper_1309_5048_amd import MIXED, PC_PCGAQ
+    gp, o = pair
+    code = PC_PCGAQ if pc == "pcgAQ" else PC_JPCG
+    f = o.load(1)
+    gp.set_inner_tol(1e-2)
+    u, p, info = gp.solve(_cuda(f), tol=1e-8, precond=code, precision=MIXED)
+    assert info["status"] == 0 and info["relres_true_Minv"] <= 1e-8
+    assert info["inner_iters_total"] > 0
+    u, p, info = gp.solve(_cuda(f), tol=1e-11, precond=code, precision=MIXED)
+    assert info["status"] == 0 and info["relres_true_Minv"] <= 1e-11
+    uo, po, _ = o.solve(f, tol=1e-13)
+    assert _rel(u.cpu().numpy(), uo) <= 1e-8
+    assert _rel(p.cpu().numpy(), po) <= 1e-8
+
+
 def test_mixed_precision(pair):
     from paper_1309_5048_amd import MIXED
     gp, o = pair
