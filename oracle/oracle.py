@@ -7,7 +7,8 @@ no code with the HIP path.
 Preconditioner codes (block-diagonal M = blkdiag(M_A, M_Q), paper Sec. 5.1):
   pc_A: 0 IC(0), 1 IC(0)-PCG (inner, relative 2-norm tolerance), 2 Jacobi,
         3 exact (dense Cholesky, small meshes only), 4 Jacobi-PCG
-  pc_Q: 0 Diag(Q)/(2 nu), 1 exact Q/(2 nu) (dense Cholesky)
+  pc_Q: 0 Diag(Q)/(2 nu), 1 exact Q/(2 nu) (dense Cholesky), 2 Jacobi-PCG on Q,
+        3 IC(0) of Q applied once, 4 IC(0)-PCG on Q
 Forcing problems: 0 none, 1 manufactured curl solution with p = prod cos(pi x),
   2 the paper's square-domain solution (Sec. 6.2, divergence-free sign),
   3 pure gradient forcing f = grad(sin(2 pi x) cos(pi y) [cos(pi z)]).
@@ -23,7 +24,7 @@ _SRC = os.path.join(_HERE, "stokes_oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 PC_IC0, PC_ICPCG, PC_JACOBI, PC_EXACT, PC_JPCG = 0, 1, 2, 3, 4
-PQ_DIAG, PQ_EXACT, PQ_JPCG = 0, 1, 2
+PQ_DIAG, PQ_EXACT, PQ_JPCG, PQ_IC0, PQ_ICPCG = 0, 1, 2, 3, 4
 
 
 def build(force=False):
@@ -55,6 +56,9 @@ def lib():
         L.or_get_diagQ_w.argtypes = [vp, vp, vp]
         L.or_ic0.restype = i32
         L.or_ic0.argtypes = [vp, P(i32)]
+        L.or_ic0_q.restype = i32
+        L.or_ic0_q.argtypes = [vp]
+        L.or_set_sum_order.argtypes = [i32]
         L.or_load.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp]
         L.or_matvec.argtypes = [vp, vp, vp]
         L.or_precond.restype = i32
@@ -120,13 +124,16 @@ class Oracle:
             self.h = None
 
     # -- matrices -----------------------------------------------------------
+    _WHICH = {"A": 0, "B": 1, "Q": 2, "L": 3, "LQ": 4}
+
     def nnz(self, which):
-        return int(self._L.or_nnz(self.h, {"A": 0, "B": 1, "Q": 2, "L": 3}[which]))
+        return int(self._L.or_nnz(self.h, self._WHICH[which]))
 
     def csr(self, which):
-        """(indptr int64, indices int32, data float64) of A, B, Q or L."""
-        w = {"A": 0, "B": 1, "Q": 2, "L": 3}[which]
-        rows = {"A": self.n_u, "B": self.n_p, "Q": self.n_p, "L": self.n_u}[which]
+        """(indptr int64, indices int32, data float64) of A, B, Q, L (IC(0) of A) or LQ (IC(0)
+        of Q)."""
+        w = self._WHICH[which]
+        rows = {"A": self.n_u, "B": self.n_p, "Q": self.n_p, "L": self.n_u, "LQ": self.n_p}[which]
         nnz = self.nnz(which)
         ptr = np.zeros(rows + 1, np.int64)
         col = np.zeros(nnz, np.int32)
@@ -137,8 +144,8 @@ class Oracle:
     def scipy(self, which):
         import scipy.sparse as sp
         ptr, col, val = self.csr(which)
-        rows = {"A": self.n_u, "B": self.n_p, "Q": self.n_p, "L": self.n_u}[which]
-        cols = {"A": self.n_u, "B": self.n_u, "Q": self.n_p, "L": self.n_u}[which]
+        rows = {"A": self.n_u, "B": self.n_p, "Q": self.n_p, "L": self.n_u, "LQ": self.n_p}[which]
+        cols = {"A": self.n_u, "B": self.n_u, "Q": self.n_p, "L": self.n_u, "LQ": self.n_p}[which]
         return sp.csr_matrix((val, col, ptr), shape=(rows, cols))
 
     def saddle(self):
@@ -156,6 +163,16 @@ class Oracle:
         s = ctypes.c_int(0)
         rc = self._L.or_ic0(self.h, ctypes.byref(s))
         return rc, s.value
+
+    def ic0_q(self):
+        """IC(0) factor of the pressure mass matrix Q (0, or -4 on breakdown)."""
+        return int(self._L.or_ic0_q(self.h))
+
+    @staticmethod
+    def set_sum_order(reverse):
+        """Sum the oracle's inner products forward (False, default) or in reverse (True):
+        the same mathematics with another rounding, for sensitivity checks."""
+        lib().or_set_sum_order(int(bool(reverse)))
 
     # -- vectors ------------------------------------------------------------
     def load(self, problem=1, modes=None):
@@ -231,7 +248,7 @@ class Oracle:
         projects p."""
         b0 = np.concatenate([_f64(f), np.zeros(self.n_p)])
         lin_A = PC_JACOBI if pc_A in (PC_JACOBI, PC_JPCG) else PC_IC0
-        lin_Q = PQ_DIAG if pc_Q in (PQ_DIAG, PQ_JPCG) else pc_Q
+        lin_Q = {PQ_JPCG: PQ_DIAG, PQ_ICPCG: PQ_IC0}.get(pc_Q, pc_Q)
 
         def mnorm2(v):
             z, _ = self.precond(v, pc_A=lin_A, pc_Q=lin_Q)

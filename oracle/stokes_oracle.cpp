@@ -175,6 +175,12 @@ struct Problem {
   std::vector<int32_t> L_col;
   std::vector<double> L_val;
 
+  // IC(0) factor of Q, the same layout.
+  bool have_LQ = false;
+  std::vector<int64_t> LQ_ptr;
+  std::vector<int32_t> LQ_col;
+  std::vector<double> LQ_val;
+
   // Dense Cholesky factors for the "ideal" preconditioner blocks (small meshes only).
   bool have_dense_A = false, have_dense_Q = false;
   std::vector<double> cholA, cholQ;
@@ -900,64 +906,78 @@ void A_matvec(const Problem& P, const double* x, double* y) {
   }
 }
 
+// Summation order of the inner products: forward (the default) or, for checks of the
+// method's sensitivity to rounding, reversed.  The mathematical result is the same.
+int g_sum_reverse = 0;
+
 double dot(const double* a, const double* b, int64_t n) {
   double s = 0;
+  if (g_sum_reverse) {
+    for (int64_t i = n - 1; i >= 0; --i) s += a[i] * b[i];
+    return s;
+  }
   for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
   return s;
 }
 
 // ---------------------------------------------------------------------------
-// IC(0) (Sec. 6.4): L L^T ~ A with pattern(L) = pattern(tril A), computed row by row
-// in natural order:
-//   L_ij = (A_ij - sum_{k<j} L_ik L_jk) / L_jj      for j < i in the pattern
-//   L_ii = sqrt(A_ii - sum_{k<i} L_ik^2)
-// where the sums run over k present in both rows.  A non-positive radicand restarts
-// the factorisation on A + alpha diag(A) with alpha = 1e-3, 1e-2, 1e-1.
+// IC(0) (Sec. 6.4: incomplete Cholesky with zero fill-in of A, and of Q): L L^T ~ M with
+// pattern(L) = pattern(tril M), computed row by row in natural order:
+//   L_ij = (M_ij - sum_{k<j} L_ik L_jk) / L_jj      for j < i in the pattern
+//   L_ii = sqrt(M_ii - sum_{k<i} L_ik^2)
+// where the sums run over k present in both rows.  Returns false on a non-positive
+// radicand.  alpha adds alpha * M_ii to the diagonal (the shift retry of A's factor).
 // ---------------------------------------------------------------------------
-bool ic0_try(Problem& P, double alpha) {
-  int64_t n = P.nu_dofs;
-  P.L_ptr.assign(1, 0);
-  P.L_col.clear();
-  P.L_val.clear();
+bool ic0_factor_csr(const std::vector<int64_t>& M_ptr, const std::vector<int32_t>& M_col,
+                    const std::vector<double>& M_val, int64_t n, double alpha, std::vector<int64_t>& L_ptr,
+                    std::vector<int32_t>& L_col, std::vector<double>& L_val) {
+  L_ptr.assign(1, 0);
+  L_col.clear();
+  L_val.clear();
   for (int64_t i = 0; i < n; ++i) {
-    for (int64_t k = P.A_ptr[i]; k < P.A_ptr[i + 1]; ++k) {
-      if (P.A_col[k] > i) break;
-      P.L_col.push_back(P.A_col[k]);
-      double v = P.A_val[k];
-      if (P.A_col[k] == i) v += alpha * P.A_val[k];
-      P.L_val.push_back(v);
+    for (int64_t k = M_ptr[i]; k < M_ptr[i + 1]; ++k) {
+      if (M_col[k] > i) break;
+      L_col.push_back(M_col[k]);
+      double v = M_val[k];
+      if (M_col[k] == i) v += alpha * M_val[k];
+      L_val.push_back(v);
     }
-    P.L_ptr.push_back(int64_t(P.L_col.size()));
+    L_ptr.push_back(int64_t(L_col.size()));
   }
   for (int64_t i = 0; i < n; ++i) {
-    int64_t rb = P.L_ptr[i], re = P.L_ptr[i + 1];  // row i, last entry is the diagonal
+    int64_t rb = L_ptr[i], re = L_ptr[i + 1];  // row i, last entry is the diagonal
     for (int64_t m = rb; m < re - 1; ++m) {
-      int64_t j = P.L_col[m];
-      int64_t jb = P.L_ptr[j], je = P.L_ptr[j + 1];
-      double s = P.L_val[m];
+      int64_t j = L_col[m];
+      int64_t jb = L_ptr[j], je = L_ptr[j + 1];
+      double s = L_val[m];
       // sum over k < j present in both rows i and j
       int64_t a = rb, b = jb;
       while (a < m && b < je - 1) {
-        if (P.L_col[a] == P.L_col[b]) {
-          s -= P.L_val[a] * P.L_val[b];
+        if (L_col[a] == L_col[b]) {
+          s -= L_val[a] * L_val[b];
           ++a;
           ++b;
-        } else if (P.L_col[a] < P.L_col[b]) {
+        } else if (L_col[a] < L_col[b]) {
           ++a;
         } else {
           ++b;
         }
       }
-      P.L_val[m] = s / P.L_val[je - 1];
+      L_val[m] = s / L_val[je - 1];
     }
-    double d = P.L_val[re - 1];
-    for (int64_t m = rb; m < re - 1; ++m) d -= P.L_val[m] * P.L_val[m];
+    double d = L_val[re - 1];
+    for (int64_t m = rb; m < re - 1; ++m) d -= L_val[m] * L_val[m];
     if (!(d > 0.0)) return false;
-    P.L_val[re - 1] = std::sqrt(d);
+    L_val[re - 1] = std::sqrt(d);
   }
   return true;
 }
 
+bool ic0_try(Problem& P, double alpha) {
+  return ic0_factor_csr(P.A_ptr, P.A_col, P.A_val, P.nu_dofs, alpha, P.L_ptr, P.L_col, P.L_val);
+}
+
+// IC(0) of A with the diagonal-shift retries alpha = 1e-3, 1e-2, 1e-1 on breakdown.
 int ic0(Problem& P) {
   const double alphas[4] = {0.0, 1e-3, 1e-2, 1e-1};
   for (int s = 0; s < 4; ++s) {
@@ -972,23 +992,34 @@ int ic0(Problem& P) {
   return -4;
 }
 
-// z = (L L^T)^{-1} r: forward substitution, then backward substitution with L^T
-// done column-wise from the rows of L.
-void ic0_apply(const Problem& P, const double* r, double* z) {
-  int64_t n = P.nu_dofs;
+// IC(0) of the pressure mass matrix Q (Sec. 6.4 factors both blocks).  Q is SPD; no shift.
+int ic0_Q(Problem& P) {
+  if (!ic0_factor_csr(P.Q_ptr, P.Q_col, P.Q_val, P.np_dofs, 0.0, P.LQ_ptr, P.LQ_col, P.LQ_val)) return -4;
+  P.have_LQ = true;
+  return 0;
+}
+
+// z = (L L^T)^{-1} r: forward substitution, then backward substitution with L^T done
+// column-wise from the rows of L.
+void ic0_solve_csr(const std::vector<int64_t>& L_ptr, const std::vector<int32_t>& L_col,
+                   const std::vector<double>& L_val, int64_t n, const double* r, double* z) {
   std::vector<double> y(n);
   for (int64_t i = 0; i < n; ++i) {
     double s = r[i];
-    int64_t re = P.L_ptr[i + 1];
-    for (int64_t m = P.L_ptr[i]; m < re - 1; ++m) s -= P.L_val[m] * y[P.L_col[m]];
-    y[i] = s / P.L_val[re - 1];
+    int64_t re = L_ptr[i + 1];
+    for (int64_t m = L_ptr[i]; m < re - 1; ++m) s -= L_val[m] * y[L_col[m]];
+    y[i] = s / L_val[re - 1];
   }
   for (int64_t i = n - 1; i >= 0; --i) {
-    int64_t re = P.L_ptr[i + 1];
-    double zi = y[i] / P.L_val[re - 1];
+    int64_t re = L_ptr[i + 1];
+    double zi = y[i] / L_val[re - 1];
     z[i] = zi;
-    for (int64_t m = P.L_ptr[i]; m < re - 1; ++m) y[P.L_col[m]] -= P.L_val[m] * zi;
+    for (int64_t m = L_ptr[i]; m < re - 1; ++m) y[L_col[m]] -= L_val[m] * zi;
   }
+}
+
+void ic0_apply(const Problem& P, const double* r, double* z) {
+  ic0_solve_csr(P.L_ptr, P.L_col, P.L_val, P.nu_dofs, r, z);
 }
 
 // Dense Cholesky (row-major, lower) for the ideal preconditioner blocks.
@@ -1023,7 +1054,7 @@ void dense_chol_solve(const std::vector<double>& l, int64_t n, const double* r, 
 }
 
 enum { PCA_IC0 = 0, PCA_ICPCG = 1, PCA_JACOBI = 2, PCA_EXACT = 3, PCA_JPCG = 4 };
-enum { PCQ_DIAG = 0, PCQ_EXACT = 1, PCQ_JPCG = 2 };
+enum { PCQ_DIAG = 0, PCQ_EXACT = 1, PCQ_JPCG = 2, PCQ_IC0 = 3, PCQ_ICPCG = 4 };
 
 // Inner PCG on A (Sec. 6.4): x0 = 0, stop when ||r||_2 <= rtol ||b||_2, tested after
 // each update; preconditioner IC(0) (PCA_ICPCG) or Jacobi (PCA_JPCG).
@@ -1064,16 +1095,24 @@ int pcg_A(const Problem& P, int which, const double* b, double* x, double rtol, 
   return it;
 }
 
-// Inner PCG on the pressure mass matrix Q with the Jacobi preconditioner Diag(Q): the
-// pressure half of the PCG(A,Q) variant (Sec. 5.1: both blocks solved by Jacobi-PCG).
-// x0 = 0, stop when ||r||_2 <= rtol ||b||_2, tested after each update.
-int pcg_Q(const Problem& P, const double* b, double* x, double rtol, int maxit) {
+// Inner PCG on the pressure mass matrix Q, preconditioned by Diag(Q) (PCQ_JPCG: the
+// pressure half of the PCG(A,Q) variant, Sec. 5.1) or by IC(0) of Q (PCQ_ICPCG: the
+// pressure half of IC(0)-PCG(A,Q), Sec. 6.4).  x0 = 0, stop when ||r||_2 <= rtol ||b||_2,
+// tested after each update.
+int pcg_Q(const Problem& P, int which, const double* b, double* x, double rtol, int maxit) {
   int64_t n = P.np_dofs;
   std::vector<double> r(b, b + n), z(n), p(n), q(n);
   std::fill(x, x + n, 0.0);
   double bnorm = std::sqrt(dot(b, b, n));
   if (bnorm == 0.0) return 0;
-  for (int64_t i = 0; i < n; ++i) z[i] = r[i] / P.diagQ[i];
+  auto prec = [&](const double* in, double* out) {
+    if (which == PCQ_ICPCG) {
+      ic0_solve_csr(P.LQ_ptr, P.LQ_col, P.LQ_val, n, in, out);
+    } else {
+      for (int64_t i = 0; i < n; ++i) out[i] = in[i] / P.diagQ[i];
+    }
+  };
+  prec(r.data(), z.data());
   p = z;
   double rho = dot(r.data(), z.data(), n);
   int it = 0;
@@ -1090,7 +1129,7 @@ int pcg_Q(const Problem& P, const double* b, double* x, double rtol, int maxit) 
     }
     ++it;
     if (std::sqrt(dot(r.data(), r.data(), n)) <= rtol * bnorm) break;
-    for (int64_t i = 0; i < n; ++i) z[i] = r[i] / P.diagQ[i];
+    prec(r.data(), z.data());
     double rho_new = dot(r.data(), z.data(), n);
     double beta = rho_new / rho;
     rho = rho_new;
@@ -1100,8 +1139,10 @@ int pcg_Q(const Problem& P, const double* b, double* x, double rtol, int maxit) 
 }
 
 // Block-diagonal preconditioner M = blkdiag(M_A, M_Q) applied to r: z = M^{-1} r (eq.
-// general_precond_M).  M_Q = Diag(Q)/(2 nu), Q/(2 nu) (exact), or Q/(2 nu) approximated by
-// Jacobi-PCG on Q (PCQ_JPCG; its iterations are added to the inner count).
+// general_precond_M).  M_Q = Diag(Q)/(2 nu), Q/(2 nu) (exact), L_Q L_Q^T/(2 nu) with
+// L_Q the IC(0) factor of Q (PCQ_IC0), or Q/(2 nu) approximated by PCG on Q with the Jacobi
+// (PCQ_JPCG) or IC(0) (PCQ_ICPCG) preconditioner; PCG iterations on Q are added to the
+// inner count.
 int apply_precond(const Problem& P, int pcA, int pcQ, double inner_tol, const double* r, double* z) {
   int64_t nu = P.nu_dofs, np = P.np_dofs;
   int inner = 0;
@@ -1124,8 +1165,11 @@ int apply_precond(const Problem& P, int pcA, int pcQ, double inner_tol, const do
   }
   if (pcQ == PCQ_DIAG) {
     for (int64_t k = 0; k < np; ++k) z[nu + k] = 2.0 * P.nu * r[nu + k] / P.diagQ[k];
-  } else if (pcQ == PCQ_JPCG) {
-    inner += pcg_Q(P, r + nu, z + nu, inner_tol, 200);
+  } else if (pcQ == PCQ_JPCG || pcQ == PCQ_ICPCG) {
+    inner += pcg_Q(P, pcQ, r + nu, z + nu, inner_tol, 200);
+    for (int64_t k = 0; k < np; ++k) z[nu + k] *= 2.0 * P.nu;
+  } else if (pcQ == PCQ_IC0) {
+    ic0_solve_csr(P.LQ_ptr, P.LQ_col, P.LQ_val, np, r + nu, z + nu);
     for (int64_t k = 0; k < np; ++k) z[nu + k] *= 2.0 * P.nu;
   } else {
     dense_chol_solve(P.cholQ, np, r + nu, z + nu);
@@ -1236,7 +1280,7 @@ void true_residuals(const Problem& P, const double* b, const double* x, int pcA,
   saddle_matvec(P, x, r.data());
   for (int64_t i = 0; i < n; ++i) r[i] = b[i] - r[i];
   int lin = (pcA == PCA_ICPCG) ? PCA_IC0 : (pcA == PCA_JPCG ? PCA_JACOBI : pcA);
-  int linq = pcQ == PCQ_JPCG ? PCQ_DIAG : pcQ;
+  int linq = pcQ == PCQ_JPCG ? PCQ_DIAG : (pcQ == PCQ_ICPCG ? PCQ_IC0 : pcQ);
   apply_precond(P, lin, linq, 0.0, r.data(), z.data());
   apply_precond(P, lin, linq, 0.0, b, zb.data());
   double bb = dot(b, b, n), bm = dot(b, zb.data(), n);
@@ -1247,6 +1291,9 @@ void true_residuals(const Problem& P, const double* b, const double* x, int pcA,
 bool prepare_precond(Problem& P, int pcA, int pcQ) {
   if ((pcA == PCA_IC0 || pcA == PCA_ICPCG) && !P.have_L) {
     if (ic0(P) != 0) return false;
+  }
+  if ((pcQ == PCQ_IC0 || pcQ == PCQ_ICPCG) && !P.have_LQ) {
+    if (ic0_Q(P) != 0) return false;
   }
   if (pcA == PCA_EXACT && !P.have_dense_A) {
     int64_t n = P.nu_dofs;
@@ -1317,7 +1364,7 @@ void or_sizes(void* h, int64_t* n_u, int64_t* n_p) {
   *n_p = P->np_dofs;
 }
 
-// which: 0 = A, 1 = B, 2 = Q, 3 = L (after or_ic0)
+// which: 0 = A, 1 = B, 2 = Q, 3 = L (after or_ic0), 4 = L_Q (after or_ic0_q)
 int64_t or_nnz(void* h, int which) {
   Problem* P = static_cast<Problem*>(h);
   switch (which) {
@@ -1325,6 +1372,7 @@ int64_t or_nnz(void* h, int which) {
     case 1: return int64_t(P->B_col.size());
     case 2: return int64_t(P->Q_col.size());
     case 3: return int64_t(P->L_col.size());
+    case 4: return int64_t(P->LQ_col.size());
   }
   return -1;
 }
@@ -1339,6 +1387,7 @@ void or_get_csr(void* h, int which, int64_t* ptr, int32_t* col, double* val) {
     case 1: pp = &P->B_ptr; cc = &P->B_col; vv = &P->B_val; break;
     case 2: pp = &P->Q_ptr; cc = &P->Q_col; vv = &P->Q_val; break;
     case 3: pp = &P->L_ptr; cc = &P->L_col; vv = &P->L_val; break;
+    case 4: pp = &P->LQ_ptr; cc = &P->LQ_col; vv = &P->LQ_val; break;
     default: return;
   }
   if (ptr) std::memcpy(ptr, pp->data(), pp->size() * sizeof(int64_t));
@@ -1358,6 +1407,15 @@ int or_ic0(void* h, int* shift_steps) {
   if (shift_steps) *shift_steps = P->ic_shift_steps;
   return rc;
 }
+
+// IC(0) factor of Q (0, or -4 on a non-positive pivot).
+int or_ic0_q(void* h) {
+  Problem* P = static_cast<Problem*>(h);
+  return P->have_LQ ? 0 : ic0_Q(*P);
+}
+
+// Inner products summed forward (0, the default) or in reverse order (1).
+void or_set_sum_order(int reverse) { g_sum_reverse = reverse ? 1 : 0; }
 
 // Load vector(s).  problem: 0 none, 1 manufactured (default), 2 paper square, 3 gradient.
 // amp [nrhs][dim][nmodes], wave [nrhs][nmodes][dim], phase [nrhs][dim][nmodes]; f [nrhs][n_u].

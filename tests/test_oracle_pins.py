@@ -610,3 +610,144 @@ def test_iteration_counts_cavity_k2(paper):
             j2 = int(np.argmax(r2 <= 1e-12)) + 1
             lim = bar if bar >= 1 else bar * ref[key][i]
             assert abs(j2 - ref[key][i]) <= lim, (inv_h, key, j2, ref[key][i])
+
+
+# ---------------------------------------------------------------------------
+# IC(0) of the pressure mass matrix Q (Sec. 6.4, the IC(0)-PCG(A,Q) preconditioner).
+# On the identity map Q is the Kronecker product of banded 1D mass matrices, whose exact
+# Cholesky factor is the Kronecker product of the 1D banded factors: its pattern lies
+# inside pattern(tril Q) in the lexicographic order, so IC(0) in natural order IS the exact
+# Cholesky factor (zero fill-in loses nothing).  That is the paper's observation that
+# PCG(Q) with the IC(0) preconditioner converges in one iteration at every mesh size and
+# tolerance.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kp,inv_hs", [(2, [8, 16, 32, 64, 128, 256]), (3, [8, 16, 32, 64, 128, 256])])
+def test_ic0_Q_nnz_matches_paper(paper, kp, inv_hs):
+    tab = paper["nnz_ic_k%d" % kp]
+    for inv_h in inv_hs:
+        ref = _tab_row(tab, inv_h)
+        o = Oracle(inv_h, kp, pattern_only=True)
+        assert (o.nnz("Q") + o.n_p) // 2 == ref["nnz_ICQ"]
+    o = Oracle(8, kp)
+    assert o.ic0_q() == 0 and o.nnz("LQ") == _tab_row(tab, 8)["nnz_ICQ"]
+
+
+@pytest.mark.parametrize("N,kp,dim", [(6, 1, 2), (8, 2, 2), (5, 3, 2), (3, 1, 3)])
+def test_ic0_Q_is_exact_cholesky(N, kp, dim):
+    import scipy.sparse.linalg as sla
+    from oracle.oracle import PQ_IC0, PQ_ICPCG
+    o = Oracle(N, kp, dim)
+    assert o.ic0_q() == 0
+    Q = o.scipy("Q").toarray()
+    Lc = sl.cholesky(Q, lower=True)
+    LQ = o.scipy("LQ").toarray()
+    assert np.abs(LQ - Lc).max() <= 1e-13 * np.abs(Lc).max()
+    r = np.random.default_rng(3).standard_normal(o.n)
+    ref = sla.spsolve(o.scipy("Q").tocsc(), r[o.n_u:]) * 2.0 * o.nu
+    z, _ = o.precond(r, pc_A=PC_IC0, pc_Q=PQ_IC0)
+    assert np.linalg.norm(z[o.n_u:] - ref) <= 1e-12 * np.linalg.norm(ref)
+    for tol_in in (1e-3, 1e-6):  # one inner iteration on Q, as the paper reports
+        z, it = o.precond(r, pc_A=PC_IC0, pc_Q=PQ_ICPCG, inner_tol=tol_in)
+        assert it == 1
+        assert np.linalg.norm(z[o.n_u:] - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+@pytest.mark.slow
+def test_iteration_counts_ic_pcg_cavity_k2(paper):
+    """IC(0)-PCG(A,Q) on the lid-driven cavity (Sec. 6.4 table, k' = 2, outer tol 1e-12 on
+    the true 2-norm relative residual): outer counts within 2 and mean inner PCG(A) counts
+    within 15 % of the paper's at both inner tolerances, one inner iteration on Q.  The
+    paper reorders with RCM before IC(0); the oracle keeps the natural order, so the inner
+    counts are compared loosely.  Their growth per halving of h (P16: 1.6-1.9x in the
+    paper) is checked on its own."""
+    from oracle.oracle import PQ_ICPCG
+    ref = paper["iters_ic_pcg_cavity_k2"]
+    means = {1e-3: [], 1e-6: []}
+    for i, inv_h in enumerate(ref["inv_h"][:3]):
+        o = Oracle(inv_h, 2)
+        b = np.concatenate([o.load_cavity(0), np.zeros(o.n_p)])
+        K = o.saddle()
+        for tol_in, key in ((1e-3, "tol1e-3"), (1e-6, "tol1e-6")):
+            x, info, xh = o.minres(b, tol=1e-14, maxit=300, pc_A=PC_ICPCG, pc_Q=PQ_ICPCG, inner_tol=tol_in,
+                                   x_history=True)
+            r2 = np.linalg.norm(b - (K @ xh.T).T, axis=1) / np.linalg.norm(b)
+            j2 = int(np.argmax(r2 <= 1e-12)) + 1
+            assert abs(j2 - ref[key + "_outer"][i]) <= 2, (inv_h, tol_in, j2)
+            # inner counts over the j2 + 1 preconditioner applications of that run
+            _, i2 = o.minres(b, maxit=j2, pc_A=PC_ICPCG, pc_Q=PQ_ICPCG, inner_tol=tol_in, fixed=True)
+            apps = j2 + 1
+            mean_A = (i2["inner_total"] - apps) / apps  # one Q iteration per application
+            assert abs(mean_A / ref[key + "_inner_A"][i] - 1.0) <= 0.15, (inv_h, tol_in, mean_A)
+            means[tol_in].append(mean_A)
+    for tol_in, m in means.items():
+        for a, b in zip(m, m[1:]):
+            assert 1.4 <= b / a <= 2.1, (tol_in, m)
+
+
+# ---------------------------------------------------------------------------
+# Stop counts under rounding.  MINRES on this saddle system reduces |eta| in pairs of
+# almost equal steps; where tol falls on such a pair, a rounding-level change alone moves
+# the stop by two.  The oracle shows it by itself: summing its inner products in reverse
+# order (the same mathematics) moves some 3D k'=1 and 2D k'=3 stops by exactly two, and
+# none in 2D for k' <= 2.  This is the reading behind the stop-count bar of the GPU tests.
+# ---------------------------------------------------------------------------
+def test_stop_counts_move_by_two_under_rounding():
+    from synthetic_inputs import forcing_modes
+    moved = {}
+    try:
+        for (N, kp, dim) in [(16, 1, 2), (12, 2, 2), (5, 3, 2), (4, 1, 3)]:
+            o = Oracle(N, kp, dim)
+            o.ic0()
+            F = [o.load(1)] + list(o.load(1, forcing_modes(list(range(1000, 1006)), dim)))
+            d = []
+            for f in F:
+                b = np.concatenate([f, np.zeros(o.n_p)])
+                Oracle.set_sum_order(False)
+                _, i0 = o.minres(b, tol=1e-8)
+                Oracle.set_sum_order(True)
+                _, i1 = o.minres(b, tol=1e-8)
+                d.append(i1["iters"] - i0["iters"])
+            moved[(N, kp, dim)] = d
+    finally:
+        Oracle.set_sum_order(False)
+    assert all(x == 0 for x in moved[(16, 1, 2)] + moved[(12, 2, 2)]), moved
+    for key in ((5, 3, 2), (4, 1, 3)):
+        assert any(x != 0 for x in moved[key]), moved
+        assert all(abs(x) <= 2 for x in moved[key]), moved
+
+
+# ---------------------------------------------------------------------------
+# The restarted inner-PCG solve (oracle `solve_refined`, reading A20).  With a tight inner
+# tolerance the inner PCG solves the velocity block exactly up to rounding, so one cycle
+# suffices and the result is the plain MINRES solve with inner PCG, which in turn is MINRES
+# with the exact block (dense Cholesky of A); at the loose tolerance its final residual,
+# formed and measured with scipy from the oracle's matrices and IC(0) factor alone, meets
+# tol in the norm of the fixed preconditioner.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("pc_A", [PC_ICPCG, PC_JPCG])
+def test_solve_refined(pc_A):
+    import scipy.sparse.linalg as sla
+    o = Oracle(10, 2)
+    o.ic0()
+    f = o.load(1)
+    u0, p0, i0 = o.solve(f, tol=1e-10, pc_A=PC_EXACT)
+    u1, p1, i1 = o.solve_refined(f, tol=1e-10, pc_A=pc_A, inner_tol=1e-13)
+    _, _, ip = o.solve(f, tol=1e-10, pc_A=pc_A, inner_tol=1e-13)
+    assert i1["iters"] == ip["iters"]  # one cycle: the plain MINRES run with inner PCG
+    assert abs(i1["iters"] - i0["iters"]) <= 1
+    assert np.linalg.norm(u1 - u0) <= 1e-8 * np.linalg.norm(u0)
+    assert np.linalg.norm(p1 - p0) <= 1e-8 * np.linalg.norm(p0)
+    tol = 1e-8
+    u, p, info = o.solve_refined(f, tol=tol, pc_A=pc_A, inner_tol=1e-2)
+    K = o.saddle()
+    b = np.concatenate([f, np.zeros(o.n_p)])
+    r = b - K @ np.concatenate([u, p])
+    dQ, _ = o.diagQ_w()
+
+    def minv(v):
+        zu = (sla.spsolve_triangular(o.scipy("L").T.tocsr(), sla.spsolve_triangular(o.scipy("L"), v[:o.n_u]),
+                                     lower=False) if pc_A == PC_ICPCG else v[:o.n_u] / o.scipy("A").diagonal())
+        return np.concatenate([zu, 2.0 * o.nu * v[o.n_u:] / dQ])
+    relM = np.sqrt((r @ minv(r)) / (b @ minv(b)))
+    assert relM <= tol * (1 + 1e-9), relM
+    assert abs(relM - info["relres_true_Minv"]) <= 1e-6 * relM
