@@ -57,13 +57,13 @@ extern "C" {
 #define STOKES_PC_JACOBI 2 /* M_A = Diag(A)  (the Diag(A,Q) variant of Sec. 5.1)          */
 #define STOKES_PC_JPCG 4   /* M_A^{-1} r = Diag(A)-preconditioned CG on A r, tolerance as
                               for STOKES_PC_ICPCG: the PCG(A), Diag(Q) variant of Sec. 5.1
-                              (the paper's tables use the inner tolerance 1e-6); like
-                              STOKES_PC_ICPCG a nonlinear preconditioner, so MINRES is
-                              restarted on the true residual until it meets tol in the norm
-                              of blkdiag(Diag(A), Diag(Q)/(2 nu)).                          */
+                              (the paper's tables use the inner tolerance 1e-6)             */
 #define STOKES_PC_PCGAQ 5  /* PCG(A,Q) of Sec. 5.1: STOKES_PC_JPCG on the velocity block and
                               M_Q^{-1} r = 2 nu x, x from Diag(Q)-preconditioned CG on
-                              Q x = r (same tolerance); restarted like STOKES_PC_JPCG       */
+                              Q x = r (same tolerance)                                     */
+/* STOKES_PC_ICPCG, STOKES_PC_JPCG and STOKES_PC_PCGAQ change with their input: by default
+ * MINRES runs once with them and stops on its own estimate, as in Sec. 5.1;
+ * stokes_set_restarts selects restarts on the true residual instead.                  */
 #define STOKES_PC_IDEAL 3  /* Ideal(A,Q) of Sec. 5.1, M = blkdiag(A, Q/(2 nu)): each block
                               solved by Diag-preconditioned CG to the fixed relative residual
                               1e-12 (at most 100000 iterations; stokes_set_inner_tol and
@@ -90,8 +90,8 @@ typedef struct {
   int32_t inner_iters_total; /* inner CG iterations (both blocks) summed over the solve    */
   int32_t status;            /* return code of this right-hand side                       */
   int32_t ic_shift_steps;    /* IC(0) diagonal-shift retries used at setup (0 = none)     */
-  int32_t refine_cycles;     /* MINRES runs on the true residual (1 unless MIXED or an
-                                inner-CG preconditioner other than STOKES_PC_IDEAL)         */
+  int32_t refine_cycles;     /* MINRES runs on the true residual (1 unless MIXED, or an
+                                inner-CG preconditioner with stokes_set_restarts > 0)      */
   int32_t reserved;          /* zero                                                       */
   double relres_est;         /* |eta|/gamma_1 at exit (M^{-1}-norm estimate)              */
   double relres_true_2;      /* ||b - Acal x||_2 / ||b||_2, computed on the device          */
@@ -137,6 +137,21 @@ int stokes_set_nu(stokes_problem* pb, double nu);
  * keep the current setting. */
 int stokes_set_inner_tol(stokes_problem* pb, double rtol);
 int stokes_set_maxit(stokes_problem* pb, int outer, int inner);
+
+/* Outer method of the inner-CG preconditioners (STOKES_PC_ICPCG, STOKES_PC_JPCG,
+ * STOKES_PC_PCGAQ) in STOKES_FP64.  Inner CG stopped at a relative tolerance is a nonlinear
+ * preconditioner, while MINRES (Sec. 5) is built on a fixed SPD one, so its estimate |eta|
+ * measures the residual in a norm that changes between applications.
+ *   max_cycles = 0 (default): the paper's method (Sec. 5.1, Sec. 6.2/6.4 tables): one MINRES
+ *     run, stopped when |eta_j| <= tol * gamma_1; relres_true_Minv then reports where the
+ *     true residual landed.
+ *   max_cycles in 1..30: MINRES restarted from the FP64 true residual until
+ *     ||b - Acal x||_{M^-1} <= tol ||b||_{M^-1} for the fixed block preconditioner the inner
+ *     solves approximate (M_A = IC(0) for STOKES_PC_ICPCG, Diag(A) otherwise; M_Q =
+ *     Diag(Q)/(2 nu)), each cycle asking for the remaining reduction (at most 0.5), at most
+ *     max_cycles cycles; status STOKES_NOT_CONVERGED if that norm still misses tol.
+ * Other values: STOKES_EINVAL. */
+int stokes_set_restarts(stokes_problem* pb, int max_cycles);
 
 /* STOKES_MIXED refinement: relative residual reduction asked of the first FP32 inner MINRES
  * (default 1e-4, must be < 1).  Later cycles ask for the reduction still missing to reach

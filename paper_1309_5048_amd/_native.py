@@ -23,7 +23,7 @@ CAVITY_LID, CAVITY_VERIFY = 0, 1
 EXPORTS = (
     "stokes_setup", "stokes_sizes", "stokes_set_stream", "stokes_set_nu", "stokes_set_inner_tol",
     "stokes_set_refine_tol",
-    "stokes_set_maxit", "stokes_load", "stokes_load_cavity", "stokes_solve", "stokes_solve_batched", "stokes_solve_precision",
+    "stokes_set_maxit", "stokes_set_restarts", "stokes_load", "stokes_load_cavity", "stokes_solve", "stokes_solve_batched", "stokes_solve_precision",
     "stokes_solve_adjoint", "stokes_solve_adjoint_batched", "stokes_dnu_dot", "stokes_apply",
     "stokes_apply_precond", "stokes_export_csr", "stokes_export_pressure_mass", "stokes_levels",
     "stokes_profile", "stokes_last_error", "stokes_destroy",
@@ -67,6 +67,7 @@ def lib():
         "stokes_set_inner_tol": (i32, [vp, dbl]),
         "stokes_set_refine_tol": (i32, [vp, dbl]),
         "stokes_set_maxit": (i32, [vp, i32, i32]),
+        "stokes_set_restarts": (i32, [vp, i32]),
         "stokes_load": (i32, [vp, P(StokesForcing), i32, vp]),
         "stokes_load_cavity": (i32, [vp, i32, vp]),
         "stokes_solve": (i32, [vp, vp, vp, vp, dbl, i32, P(StokesInfo)]),

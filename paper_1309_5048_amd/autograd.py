@@ -9,6 +9,15 @@ the paper), so the adjoint reuses MINRES with the same preconditioner:
 import torch
 
 from . import _native as N
+from .solver import StokesError
+
+
+def _require_converged(infos, what):
+    """A gradient built on an unconverged solve is wrong by more than the tolerance: raise."""
+    for r, info in enumerate(infos):
+        if info["status"] != 0:
+            raise StokesError(N.STOKES_NOT_CONVERGED if info["status"] > 0 else info["status"],
+                              "%s of right-hand side %d did not converge (status %d)" % (what, r, info["status"]))
 
 
 class StokesSolve(torch.autograd.Function):
@@ -18,6 +27,7 @@ class StokesSolve(torch.autograd.Function):
         if abs(nu_val - problem.nu) > 0.0:
             problem.set_nu(nu_val)
         U, P, infos = problem.solve_batched(F.detach().contiguous(), tol=tol, precond=precond)
+        _require_converged(infos, "forward solve")
         ctx.problem, ctx.tol, ctx.precond = problem, tol, precond
         ctx.save_for_backward(U)
         ctx.infos = infos
@@ -33,7 +43,8 @@ class StokesSolve(torch.autograd.Function):
         if gP is None:
             gP = torch.zeros(R, problem.n_p, dtype=U.dtype, device=U.device)
         G = torch.cat([gU.reshape(R, problem.n_u), gP.reshape(R, problem.n_p)], dim=1).contiguous()
-        Lam, _ = problem.solve_adjoint(G, tol=ctx.tol, precond=ctx.precond)
+        Lam, infos = problem.solve_adjoint(G, tol=ctx.tol, precond=ctx.precond)
+        _require_converged(infos, "adjoint solve")
         lam_u = Lam[:, : problem.n_u].contiguous()
         dnu = -sum(problem.dnu_dot(lam_u, U))
         grad_nu = torch.tensor(dnu, dtype=torch.float64, device=U.device)

@@ -194,6 +194,7 @@ struct stokes_problem {
   std::map<int, Work> work;
   double inner_tol = 1e-2;
   double refine_tol = 1e-4;
+  int restarts = 0;  // inner-CG preconditioners: 0 = one MINRES run, else at most this many cycles
   int maxit_outer = 20000, maxit_inner = 200;
   int check_every = 8;
   double setup_ms = 0.0;
@@ -994,7 +995,10 @@ int solve_core(stokes_problem* pb, Work& W64, int precond, int precision, double
       CK(hipMemsetAsync(pb->pcgQ.st, 0, sizeof(PcgState) * kRMax, st));
     }
   }
-  if (precision == STOKES_FP64 && !inner_pcg) {
+  // inner CG to a relative tolerance: one MINRES run as in Sec. 5.1 unless restarts on the
+  // true residual were asked for (stokes_set_restarts)
+  const bool restarted = inner_pcg && pb->restarts > 0;
+  if (precision == STOKES_FP64 && !restarted) {
     int rc = minres_run<double>(pb, W64, precond, tol, pb->maxit_outer, ro);
     if (rc) return rc;
     for (int c = 0; c < R; ++c) {
@@ -1028,7 +1032,7 @@ int solve_core(stokes_problem* pb, Work& W64, int precond, int precision, double
     double tol_k = tol;
     bool conv = false;
     cycles = 0;
-    for (int ir = 0; ir < 6 && !conv; ++ir) {
+    for (int ir = 0; ir < pb->restarts && !conv; ++ir) {
       int rc = minres_run<double>(pb, W64, precond, tol_k, pb->maxit_outer, ro);
       if (rc) return rc;
       ++cycles;
@@ -1068,6 +1072,7 @@ int solve_core(stokes_problem* pb, Work& W64, int precond, int precision, double
     hipLaunchKernelGGL(k_fill<double>, dim3(1024), dim3(256), 0, st, int64_t(n * R), x64, 0.0);
     CK(hipMemcpyAsync(r64, b64, sizeof(double) * n * R, hipMemcpyDeviceToDevice, st));
     double rel2[kRMax], relM[kRMax];
+    for (int c = 0; c < kRMax; ++c) rel2[c] = relM[c] = HUGE_VAL;
     bool conv = false;
     // The first cycle asks the FP32 MINRES for refine_tol; later ones only for the reduction
     // that remains (with a factor 2 of margin), never more than refine_tol per cycle.
@@ -1078,7 +1083,13 @@ int solve_core(stokes_problem* pb, Work& W64, int precond, int precision, double
       rc = minres_run<float>(pb, *W32, precond, tol_k, pb->maxit_outer, ro);
       if (rc) return rc;
       ++cycles;
-      for (int c = 0; c < R; ++c) iters_total[c] += ro.iters[c];
+      for (int c = 0; c < R; ++c) {
+        iters_total[c] += ro.iters[c];
+        if (ro.status[c] < 0) status[c] = ro.status[c];  // a breakdown of any cycle is kept
+      }
+      bool broke = false;
+      for (int c = 0; c < R; ++c) broke |= status[c] < 0;
+      if (broke) break;
       CK(accumulate<float>(R, int64_t(n * R), x64, (const float*)W32->x, st));
       rc = project_pressure(pb, R, x64);
       if (rc) return rc;
@@ -1095,7 +1106,7 @@ int solve_core(stokes_problem* pb, Work& W64, int precond, int precision, double
       tol_k = worst > 0.0 ? std::min(0.5, std::max(pb->refine_tol, 0.5 * tol / worst)) : pb->refine_tol;
     }
     for (int c = 0; c < R; ++c) {
-      status[c] = relM[c] <= tol ? 0 : STOKES_NOT_CONVERGED;
+      if (status[c] >= 0) status[c] = relM[c] <= tol ? 0 : STOKES_NOT_CONVERGED;
       eta_rel[c] = relM[c];
     }
   }
@@ -1340,6 +1351,13 @@ int stokes_set_refine_tol(stokes_problem* pb, double rtol) {
   return 0;
 }
 
+int stokes_set_restarts(stokes_problem* pb, int max_cycles) {
+  if (!pb) return STOKES_EINVAL;
+  if (max_cycles < 0 || max_cycles > 30) return fail(pb, STOKES_EINVAL, "restarts must be in 0..30");
+  pb->restarts = max_cycles;
+  return 0;
+}
+
 int stokes_set_maxit(stokes_problem* pb, int outer, int inner) {
   if (!pb) return STOKES_EINVAL;
   if (outer > 0) pb->maxit_outer = outer;
@@ -1502,16 +1520,20 @@ int stokes_dnu_dot(stokes_problem* pb, int nrhs, const double* lam_u, const doub
   if (rc) return rc;
   hipStream_t st = pb->stream;
   const int64_t n_u = pb->S.n_u;
-  for (int c = 0; c < nrhs; ++c) {
-    CK(spmv_resid<double>(1, pb->rs_A, pb->rowptr, pb->aend, pb->col, pb->val, u + size_t(c) * n_u, nullptr,
-                          (double*)W->q, pb->partials, pb->counter, nullptr, st));
-    CK(dot<double, double>(1, 0, n_u, lam_u + size_t(c) * n_u, (const double*)W->q, pb->partials, pb->counter,
-                           pb->scratch + c, st));
+  // results go through scratch[0..kRMax) in chunks of kRMax right-hand sides
+  for (int c0 = 0; c0 < nrhs; c0 += kRMax) {
+    const int nc = std::min(kRMax, nrhs - c0);
+    for (int c = 0; c < nc; ++c) {
+      CK(spmv_resid<double>(1, pb->rs_A, pb->rowptr, pb->aend, pb->col, pb->val, u + size_t(c0 + c) * n_u, nullptr,
+                            (double*)W->q, pb->partials, pb->counter, nullptr, st));
+      CK(dot<double, double>(1, 0, n_u, lam_u + size_t(c0 + c) * n_u, (const double*)W->q, pb->partials, pb->counter,
+                             pb->scratch + c, st));
+    }
+    double h[kRMax];
+    CK(hipMemcpyAsync(h, pb->scratch, sizeof(double) * nc, hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    for (int c = 0; c < nc; ++c) out[c0 + c] = h[c] / pb->nu;
   }
-  std::vector<double> h(nrhs);
-  CK(hipMemcpyAsync(h.data(), pb->scratch, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
-  CK(hipStreamSynchronize(st));
-  for (int c = 0; c < nrhs; ++c) out[c] = h[c] / pb->nu;
   return 0;
 }
 

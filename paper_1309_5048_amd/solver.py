@@ -89,6 +89,11 @@ class StokesProblem:
     def set_maxit(self, outer=0, inner=0):
         self._L.stokes_set_maxit(self._h, int(outer), int(inner))
 
+    def set_restarts(self, max_cycles):
+        """Inner-CG preconditioners: 0 = one MINRES run (the paper's method, default),
+        1..30 = MINRES restarted on the true residual at most that many times."""
+        self._check(self._L.stokes_set_restarts(self._h, int(max_cycles)), allow_nc=False)
+
     def profile(self, enable=-1):
         """Per-category kernel time (ms) and launch counts recorded with HIP events:
         spmv, trsv_fwd, trsv_bwd, lanczos, update.  enable: 1 start/reset, 0 stop, -1 read."""

@@ -7,9 +7,11 @@ configuration the benchmark times:
   C3  3D, N = 32, k' = 1, 16 right-hand sides in one batched solve
   C2  2D, N = 512, k' = 2, mixed FP32/FP64 refinement
 
-The oracle assembles these systems in seconds to about a minute but cannot run whole
-solves in test time, so the checks are what it can compute one by one, or properties that
-hold at any size:
+The oracle assembles these systems in seconds to about a minute and runs a C1 solve in
+about 12-25 s on one core, so the headline workload is compared whole: the stop count at
+tol 1e-8 and the converged u and p at tol 1e-13.  C3 compares two columns' stop counts and
+C4 one column's gradient with the oracle's.  Besides that, what the oracle can compute one
+by one, or properties that hold at any size:
   - assembled saddle matrix, pressure mass and IC(0) factor: every entry;
   - saddle product and preconditioner applications on full random vectors;
   - MINRES iterates after the first k iterations (the oracle runs the same k iterations);
@@ -23,7 +25,7 @@ import pytest
 torch = pytest.importorskip("torch")
 
 from oracle.oracle import PC_IC0, PC_ICPCG, PC_JACOBI, PQ_DIAG, Oracle  # noqa: E402
-from synthetic_inputs import WORKLOADS, forcing_modes, random_vector  # noqa: E402
+from synthetic_inputs import WORKLOADS, forcing_modes, random_vector, target_perturbations  # noqa: E402
 
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
 
@@ -31,6 +33,13 @@ pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
 def _rel(a, b):
     a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
     return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _close(a, b, tol):
+    """Norm-wise relative difference <= tol and every entry within tol of max |b|."""
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    assert _rel(a, b) <= tol, ("norm-wise", _rel(a, b))
+    assert np.abs(a - b).max() <= tol * np.abs(b).max(), ("entry-wise", np.abs(a - b).max() / np.abs(b).max())
 
 
 def _cuda(x):
@@ -129,6 +138,51 @@ def test_c1_converged(c1, pc):
     assert _zero_mean(gp, x[o.n_u:])
 
 
+def test_c1_stop_count_and_solution(c1):
+    """The headline workload whole: MINRES-IC(0) stop count at tol 1e-8 within +-1 of the
+    oracle's, and the converged u and p at tol 1e-13 within 1e-10 of the oracle's."""
+    gp, o, w = c1
+    f = o.load(1)
+    u, p, info = gp.solve(_cuda(f), tol=w["tol"])
+    print("[case] c1 oracle solve at tol %g" % w["tol"], flush=True)
+    uo, po, io = o.solve(f, tol=w["tol"])
+    print("[case] c1 stop counts: gpu %d oracle %d" % (info["iters"], io["iters"]), flush=True)
+    assert info["status"] == 0 and io["status"] == 0
+    assert abs(info["iters"] - io["iters"]) <= 1, (info["iters"], io["iters"])
+    u2, p2, info2 = gp.solve(_cuda(f), tol=1e-13)
+    print("[case] c1 oracle solve at tol 1e-13", flush=True)
+    uo2, po2, io2 = o.solve(f, tol=1e-13)
+    print("[case] c1 at 1e-13: gpu %d oracle %d iterations" % (info2["iters"], io2["iters"]), flush=True)
+    assert info2["status"] == 0
+    _close(u2.cpu().numpy(), uo2, 1e-10)
+    _close(p2.cpu().numpy(), po2, 1e-10)
+
+
+def test_c4_gradient_vs_oracle_adjoint(c1):
+    """C4 column 0 (forcing seed 2000, target seed 3000): dL/df = lambda_u and
+    dL/dnu = -lambda_u^T (A/nu) u of L = 0.5 ||u - u_t||^2 through the library's forward and
+    adjoint solves, against the oracle's forward and adjoint solves, at tol 1e-13."""
+    gp, o, w = c1
+    c4 = WORKLOADS["c4_2d_k2_n256_r8"]
+    F = o.load(1, forcing_modes(c4["seeds"][:1], 2))
+    uo, po, _ = o.solve(F[0], tol=1e-13)
+    ut = uo + 1e-2 * target_perturbations(o.n_u, 1)[0]
+    print("[case] c4 column 0: device forward and adjoint", flush=True)
+    u, p, info = gp.solve(_cuda(F[0]), tol=1e-13)
+    assert info["status"] == 0
+    g = np.concatenate([u.cpu().numpy() - ut, np.zeros(o.n_p)])
+    lam, infos = gp.solve_adjoint(_cuda(g), tol=1e-13)
+    assert infos[0]["status"] == 0
+    lam_u = lam[: o.n_u].contiguous()
+    dnu = -gp.dnu_dot(lam_u, u)[0]
+    print("[case] c4 column 0: oracle adjoint", flush=True)
+    lu, lp, io = o.adjoint(uo - ut, np.zeros(o.n_p), tol=1e-13)
+    assert io["status"] == 0
+    dnu_o = -o.dnu_dot(lu, uo)
+    _close(lam_u.cpu().numpy(), lu, 1e-7)
+    assert abs(dnu - dnu_o) <= 1e-7 * abs(dnu_o), (dnu, dnu_o)
+
+
 def _relres_Minv_jacobi(o, b, x):
     """The same with the Jacobi block M = blkdiag(Diag(A), Diag(Q)/(2 nu)), the fixed
     preconditioner that the inner Diag-CG variants approximate."""
@@ -215,6 +269,13 @@ def test_c3_batched(c3):
         b = np.concatenate([F[r], np.zeros(o.n_p)])
         assert _relres_Minv(o, b, np.concatenate([U[r], P[r]])) <= 2 * w["tol"], r
         assert _zero_mean(gp, P[r])
+    # stop counts of two columns against the oracle's (bar as for every 3D case: a
+    # rounding-level change alone moves a 3D stop by two, shown with the oracle alone)
+    for r in (0, R - 1):
+        print("[case] c3 oracle solve of column %d" % r, flush=True)
+        _, _, io = o.solve(F[r], tol=w["tol"])
+        assert io["status"] == 0
+        assert abs(infos[r]["iters"] - io["iters"]) <= 3, (r, infos[r]["iters"], io["iters"])
     # batched columns equal single-column solves
     U2, P2, _ = gp.solve_batched(_cuda(F), tol=1e-12)
     for r in (0, 7, R - 1):
