@@ -61,7 +61,14 @@ extern "C" {
 #define STOKES_PC_PCGAQ 5  /* PCG(A,Q) of Sec. 5.1: STOKES_PC_JPCG on the velocity block and
                               M_Q^{-1} r = 2 nu x, x from Diag(Q)-preconditioned CG on
                               Q x = r (same tolerance)                                     */
-/* STOKES_PC_ICPCG, STOKES_PC_JPCG and STOKES_PC_PCGAQ change with their input: by default
+#define STOKES_PC_ICPCG_AQ 7 /* IC(0)-PCG(A,Q) of Sec. 6.4 (the paper's best strategy, tables
+                              of IC(0)-PCG(A,Q)): STOKES_PC_ICPCG on the velocity block and
+                              M_Q^{-1} r = 2 nu x, x from CG on Q x = r preconditioned by
+                              IC(0) of the pressure mass matrix Q (natural order, pattern of
+                              tril(Q); built on first use), same inner tolerance; its fixed
+                              counterpart is blkdiag(IC(0) of A, IC(0) of Q / (2 nu))        */
+/* STOKES_PC_ICPCG, STOKES_PC_JPCG, STOKES_PC_PCGAQ and STOKES_PC_ICPCG_AQ change with their
+ * input: by default
  * MINRES runs once with them and stops on its own estimate, as in Sec. 5.1;
  * stokes_set_restarts selects restarts on the true residual instead.                  */
 #define STOKES_PC_IDEAL 3  /* Ideal(A,Q) of Sec. 5.1, M = blkdiag(A, Q/(2 nu)): each block
@@ -139,7 +146,7 @@ int stokes_set_inner_tol(stokes_problem* pb, double rtol);
 int stokes_set_maxit(stokes_problem* pb, int outer, int inner);
 
 /* Outer method of the inner-CG preconditioners (STOKES_PC_ICPCG, STOKES_PC_JPCG,
- * STOKES_PC_PCGAQ) in STOKES_FP64.  Inner CG stopped at a relative tolerance is a nonlinear
+ * STOKES_PC_PCGAQ, STOKES_PC_ICPCG_AQ) in STOKES_FP64.  Inner CG stopped at a relative tolerance is a nonlinear
  * preconditioner, while MINRES (Sec. 5) is built on a fixed SPD one, so its estimate |eta|
  * measures the residual in a norm that changes between applications.
  *   max_cycles = 0 (default): the paper's method (Sec. 5.1, Sec. 6.2/6.4 tables): one MINRES
@@ -147,8 +154,9 @@ int stokes_set_maxit(stokes_problem* pb, int outer, int inner);
  *     true residual landed.
  *   max_cycles in 1..30: MINRES restarted from the FP64 true residual until
  *     ||b - Acal x||_{M^-1} <= tol ||b||_{M^-1} for the fixed block preconditioner the inner
- *     solves approximate (M_A = IC(0) for STOKES_PC_ICPCG, Diag(A) otherwise; M_Q =
- *     Diag(Q)/(2 nu)), each cycle asking for the remaining reduction (at most 0.5), at most
+ *     solves approximate (M_A = IC(0) for STOKES_PC_ICPCG and STOKES_PC_ICPCG_AQ, Diag(A)
+ *     otherwise; M_Q = IC(0) of Q / (2 nu) for STOKES_PC_ICPCG_AQ, Diag(Q)/(2 nu)
+ *     otherwise), each cycle asking for the remaining reduction (at most 0.5), at most
  *     max_cycles cycles; status STOKES_NOT_CONVERGED if that norm still misses tol.
  * Other values: STOKES_EINVAL. */
 int stokes_set_restarts(stokes_problem* pb, int max_cycles);
@@ -218,7 +226,8 @@ int stokes_apply_precond(stokes_problem* pb, int precond, const double* r, doubl
 
 /* Copy the assembled matrices to HOST buffers (for checks).  which: 0 = saddle Acal
  * (rows n_u + n_p, columns sorted), 1 = the IC(0) factor L (rows n_u, lower triangle of
- * A's pattern, diagonal last).  Pass NULL arrays to query *nnz only. rowptr is int64. */
+ * A's pattern, diagonal last), 2 = the IC(0) factor of the pressure mass matrix Q (rows
+ * n_p, lower triangle of Q's pattern, diagonal last; factorised on first use, Sec. 6.4).  Pass NULL arrays to query *nnz only. rowptr is int64. */
 int stokes_export_csr(stokes_problem* pb, int which, int64_t* nnz, int64_t* rowptr, int32_t* col,
                       double* val);
 

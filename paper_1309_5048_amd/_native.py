@@ -15,7 +15,7 @@ STOKES_ENOMEM = -2
 STOKES_EHIP = -3
 STOKES_EBREAKDOWN = -4
 
-PC_IC0, PC_ICPCG, PC_JACOBI, PC_IDEAL, PC_JPCG, PC_PCGAQ, PC_IDEAL_A = 0, 1, 2, 3, 4, 5, 6
+PC_IC0, PC_ICPCG, PC_JACOBI, PC_IDEAL, PC_JPCG, PC_PCGAQ, PC_IDEAL_A, PC_ICPCG_AQ = 0, 1, 2, 3, 4, 5, 6, 7
 FP64, MIXED = 0, 1
 CAVITY_LID, CAVITY_VERIFY = 0, 1
 

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 
@@ -138,6 +139,19 @@ struct SchedPair {
   int rmax64 = 0, rmax32 = 0;
 };
 
+// An IC(0) factor with its triangular-solve schedules: the pattern (host), the factor
+// values (device), the dependency levels of both solves, and a strip partition of the
+// rows by height.
+struct FactorSched {
+  const LowerPattern* L = nullptr;
+  int64_t n = 0;
+  const double* Lval = nullptr;
+  const std::vector<int32_t>* lev_fwd = nullptr;
+  std::vector<int32_t>* lev_bwd = nullptr;
+  std::function<void(int, std::vector<int32_t>&, int*)> groups;
+  std::vector<std::unique_ptr<SchedPair>> scheds;
+};
+
 // Workspace of one (R, precision) combination; vectors interleaved [row][R].
 struct Work {
   int R = 0;
@@ -146,6 +160,7 @@ struct Work {
   void *x = nullptr, *q = nullptr, *b = nullptr, *y = nullptr;
   void *pr = nullptr, *pp = nullptr, *pq = nullptr, *pz = nullptr;  // inner PCG
   void *qr = nullptr, *qp = nullptr, *qq = nullptr, *qz = nullptr;  // pressure-block PCG
+  void* qy = nullptr;  // pressure-block IC(0): between the two triangular solves
   void *xr = nullptr, *br = nullptr;  // refinement: accumulated solution, original rhs (FP64)
 };
 
@@ -174,7 +189,7 @@ struct stokes_problem {
   double* Lval = nullptr;
   int* flag = nullptr;
   int ic_shift_steps = 0;
-  std::vector<std::unique_ptr<SchedPair>> scheds;
+  FactorSched fsA;  // IC(0) of A and its schedules
   MrScalars mr;
   PcgScalars pcg;
   // pressure-block CG (PCG(A,Q)): Q in CSR, its row ranges, FP32 values, scalars
@@ -182,12 +197,19 @@ struct stokes_problem {
   double* Qval = nullptr;
   float* Qval32 = nullptr;
   RowSplit rs_Q;
-  std::vector<int32_t> Qrowptr_h, split_Q_h;
+  std::vector<int32_t> Qrowptr_h, Qcol_h, split_Q_h;
   PcgScalars pcgQ;
+  // IC(0) of Q (IC(0)-PCG on the pressure block): lower pattern, values, levels, schedules
+  LowerPattern LQ;
+  std::vector<int32_t> levQ_fwd, levQ_bwd;
+  int32_t *LQrowptr = nullptr, *LQcol = nullptr;
+  int64_t* LQsrc = nullptr;
+  double* LQval = nullptr;
+  FactorSched fsQ;
   // inner CG iterations the last application needed, per velocity preconditioner and for
   // the pressure block (PCG(A,Q), Ideal(A,Q)): the first chunk queued before the host
   // reads the done flag
-  int pcg_expect[7] = {4, 4, 4, 4, 4, 4, 4}, pcgq_expect[2] = {4, 4};
+  int pcg_expect[8] = {4, 4, 4, 4, 4, 4, 4, 4}, pcgq_expect[3] = {4, 4, 4};
   double* scratch = nullptr;  // [64] small host-visible results
   double* partials = nullptr;
   unsigned int* counter = nullptr;
@@ -293,12 +315,12 @@ void prof_flush(stokes_problem* pb) {
 
 // Single-column layout of a schedule (see TrsvFastDev).  Returns 0 and leaves F.ok false
 // when a group needs more than 8 entries per lane (the general kernel then serves R = 1).
-int build_fast_layout(stokes_problem* pb, const TrsvSchedHost& H, TrsvSchedDev& D) {
+int build_fast_layout(stokes_problem* pb, const TrsvSchedHost& H, TrsvSchedDev& D, int64_t nrows, int64_t nnzL) {
   TrsvFastDev& F = D.fast;
   hipStream_t st = pb->stream;
   DevAlloc& m = pb->mem;
   const int G = H.ngroups, RPS = kTrsvRPS, E = H.E;
-  if (int64_t(pb->S.n_u) * 8 >= (int64_t(1) << 31) || (int64_t)pb->nnzL >= (int64_t(1) << 31)) return 0;
+  if (nrows * 8 >= (int64_t(1) << 31) || nnzL >= (int64_t(1) << 31)) return 0;
   std::vector<int32_t> gsp(G + 1, 0), gnp(G, 0), gep(G, 4);
   std::vector<int64_t> gb64(G + 1, 0), gb32(G + 1, 0);
   int64_t off64 = 0, off32 = 0;
@@ -394,7 +416,9 @@ int build_fast_layout(stokes_problem* pb, const TrsvSchedHost& H, TrsvSchedDev& 
   return 0;
 }
 
-int upload_schedule(stokes_problem* pb, const TrsvSchedHost& H, TrsvSchedDev& D, int rmax) {
+// Device form of a schedule of the factor Lval (nrows rows, nnzL entries).
+int upload_schedule(stokes_problem* pb, const TrsvSchedHost& H, TrsvSchedDev& D, int rmax, int64_t nrows,
+                    int64_t nnzL, const double* Lval) {
   hipStream_t st = pb->stream;
   DevAlloc& m = pb->mem;
   D.ngroups = H.ngroups;
@@ -403,7 +427,7 @@ int upload_schedule(stokes_problem* pb, const TrsvSchedHost& H, TrsvSchedDev& D,
   D.EP = (H.E + 3) / 4 * 4;
   D.nlevels = H.nlevels;
   D.nslots = H.nslots;
-  D.nrows = int(pb->S.n_u);
+  D.nrows = int(nrows);
   const size_t ns = size_t(H.nsteps);
   // per-lane records: values (via a permutation into L) and 32-bit slot ids
   std::vector<int64_t> vperm(ns * 64 * D.EP, -1);
@@ -461,9 +485,9 @@ int upload_schedule(stokes_problem* pb, const TrsvSchedHost& H, TrsvSchedDev& D,
   CK(hipMemsetAsync(D.done_count, 0, sizeof(unsigned int), st));
   CK(hipMemsetAsync(D.err, 0, sizeof(int), st));
   CK(hipStreamSynchronize(st));  // host vectors must outlive the asynchronous copies
-  int rc = build_fast_layout(pb, H, D);
+  int rc = build_fast_layout(pb, H, D, nrows, nnzL);
   if (rc) return rc;
-  CK(launch_trsv_gather(D, pb->Lval, st));
+  CK(launch_trsv_gather(D, Lval, st));
   CK(hipStreamSynchronize(st));
   return 0;
 }
@@ -477,48 +501,48 @@ int fit_rmax(const stokes_problem* pb, int nslots, bool fp32) {
 }
 
 // Largest rows-per-level of any (group, level) of a strip partition, over both solves.
-int max_rows_per_level(const stokes_problem* pb, const std::vector<int32_t>& group_of, int ngroups) {
+int max_rows_per_level(const FactorSched& fs, const std::vector<int32_t>& group_of, int ngroups) {
   int worst = 0;
   for (int dir = 0; dir < 2; ++dir) {
-    const auto& lev = dir == 0 ? pb->lev_fwd : pb->lev_bwd;
+    const auto& lev = dir == 0 ? *fs.lev_fwd : *fs.lev_bwd;
     int nl = 0;
     for (int32_t l : lev) nl = std::max(nl, l + 1);
     std::vector<int32_t> cnt(size_t(ngroups) * nl, 0);
-    for (int64_t i = 0; i < pb->S.n_u; ++i) worst = std::max(worst, ++cnt[size_t(group_of[i]) * nl + lev[i]]);
+    for (int64_t i = 0; i < fs.n; ++i) worst = std::max(worst, ++cnt[size_t(group_of[i]) * nl + lev[i]]);
   }
   return worst;
+}
+
+// Backward dependency levels: row i after every j > i with L_ji != 0.
+void backward_levels(const LowerPattern& L, int64_t n, std::vector<int32_t>& lev) {
+  lev.assign(n, 0);
+  for (int64_t j = n - 1; j >= 0; --j) {
+    const int lj = lev[j];
+    for (int32_t k = L.rowptr[j]; k < L.rowptr[j + 1] - 1; ++k) {
+      int32_t& li = lev[L.col[k]];
+      li = std::max(li, lj + 1);
+    }
+  }
 }
 
 // Schedule pair usable for R columns in the given precision (built on first use).  The
 // strip height is the largest that keeps one step per level (<= kTrsvRPS rows of a level
 // per group), reduced further while the LDS window does not fit R columns or the groups
 // cannot all be resident at once.
-int get_schedule(stokes_problem* pb, int R, bool fp32, SchedPair** out) {
-  (void)R;  // any width: the solve kernel splits wide batches into column chunks
-  for (auto& sp : pb->scheds)
+int make_schedule(stokes_problem* pb, FactorSched& fs, bool fp32, SchedPair** out) {
+  for (auto& sp : fs.scheds)
     if ((fp32 ? sp->rmax32 : sp->rmax64) >= 1) {
       *out = sp.get();
       return 0;
     }
-  if (pb->lev_bwd.empty()) {
-    // backward levels: row i after every j > i with L_ji != 0
-    const int64_t n = pb->S.n_u;
-    pb->lev_bwd.assign(n, 0);
-    for (int64_t j = n - 1; j >= 0; --j) {
-      const int lj = pb->lev_bwd[j];
-      for (int32_t k = pb->L.rowptr[j]; k < pb->L.rowptr[j + 1] - 1; ++k) {
-        int32_t& li = pb->lev_bwd[pb->L.col[k]];
-        li = std::max(li, lj + 1);
-      }
-    }
-  }
+  if (fs.lev_bwd->empty()) backward_levels(*fs.L, fs.n, *fs.lev_bwd);
   const int strips[8] = {32, 16, 8, 4, 2, 1, 0, 0};
   int first = 0;
   for (int si = 0; strips[si] > 0; ++si) {
     std::vector<int32_t> group_of;
     int ngroups = 0;
-    strip_groups(pb->S, strips[si], group_of, &ngroups);
-    if (max_rows_per_level(pb, group_of, ngroups) <= kTrsvRPS) {
+    fs.groups(strips[si], group_of, &ngroups);
+    if (max_rows_per_level(fs, group_of, ngroups) <= kTrsvRPS) {
       first = si;
       break;
     }
@@ -527,15 +551,15 @@ int get_schedule(stokes_problem* pb, int R, bool fp32, SchedPair** out) {
   for (int si = first; strips[si] > 0; ++si) {
     const int strip = strips[si];
     bool exists = false;
-    for (auto& sp : pb->scheds) exists |= (sp->strip == strip);
+    for (auto& sp : fs.scheds) exists |= (sp->strip == strip);
     if (exists) continue;
     std::vector<int32_t> group_of;
     int ngroups = 0;
-    strip_groups(pb->S, strip, group_of, &ngroups);
+    fs.groups(strip, group_of, &ngroups);
     TrsvSchedHost hf, hb;
     std::string e;
-    if (!build_trsv_schedule(pb->L, pb->S.n_u, +1, group_of, ngroups, hf, e) ||
-        !build_trsv_schedule(pb->L, pb->S.n_u, -1, group_of, ngroups, hb, e))
+    if (!build_trsv_schedule(*fs.L, fs.n, +1, group_of, ngroups, hf, e) ||
+        !build_trsv_schedule(*fs.L, fs.n, -1, group_of, ngroups, hb, e))
       return fail(pb, STOKES_EINVAL, e);
     const int nsl = std::max(hf.nslots, hb.nslots);
     auto sp = std::make_unique<SchedPair>();
@@ -552,13 +576,14 @@ int get_schedule(stokes_problem* pb, int R, bool fp32, SchedPair** out) {
     sp->rmax64 = resident(sp->rmax64, false);
     sp->rmax32 = resident(sp->rmax32, true);
     if (sp->rmax64 == 0 && sp->rmax32 == 0) continue;
-    int rc = upload_schedule(pb, hf, sp->fwd, std::max(sp->rmax64, sp->rmax32));
+    const int64_t nnzL = int64_t(fs.L->col.size());
+    int rc = upload_schedule(pb, hf, sp->fwd, std::max(sp->rmax64, sp->rmax32), fs.n, nnzL, fs.Lval);
     if (rc) return rc;
-    rc = upload_schedule(pb, hb, sp->bwd, std::max(sp->rmax64, sp->rmax32));
+    rc = upload_schedule(pb, hb, sp->bwd, std::max(sp->rmax64, sp->rmax32), fs.n, nnzL, fs.Lval);
     if (rc) return rc;
     CK(hipStreamSynchronize(pb->stream));
-    pb->scheds.push_back(std::move(sp));
-    SchedPair* last = pb->scheds.back().get();
+    fs.scheds.push_back(std::move(sp));
+    SchedPair* last = fs.scheds.back().get();
     // the first strip whose slots fit: wider batches than its rmax are solved in column
     // chunks (fewer groups and crossings beat unchunked narrower strips)
     if ((fp32 ? last->rmax32 : last->rmax64) >= 1) {
@@ -567,6 +592,13 @@ int get_schedule(stokes_problem* pb, int R, bool fp32, SchedPair** out) {
     }
   }
   return fail(pb, STOKES_EINVAL, "no triangular-solve schedule fits the LDS budget");
+}
+
+// Schedules of the IC(0) factor of A (any width: the solve kernel splits wide batches
+// into column chunks).
+int get_schedule(stokes_problem* pb, int R, bool fp32, SchedPair** out) {
+  (void)R;
+  return make_schedule(pb, pb->fsA, fp32, out);
 }
 
 int get_work(stokes_problem* pb, int R, bool fp32, Work** out) {
@@ -602,6 +634,7 @@ int get_work(stokes_problem* pb, int R, bool fp32, Work** out) {
   W.qp = get(np);
   W.qq = get(np);
   W.qz = get(np);
+  W.qy = get(np);
   if (pb->mem.err != hipSuccess) return fail_hip(pb, pb->mem.err, "workspace allocation", __LINE__);
   pb->work[key] = W;
   *out = &pb->work[key];
@@ -682,7 +715,8 @@ int precond_velocity(stokes_problem* pb, int precond, Work& W, SchedPair* sp, co
   }
   const bool ideal = precond == STOKES_PC_IDEAL || precond == STOKES_PC_IDEAL_A;
   const bool jacobi_cg = precond == STOKES_PC_JPCG || precond == STOKES_PC_PCGAQ || ideal;
-  if (precond == STOKES_PC_ICPCG || jacobi_cg) {
+  const bool ic_cg = precond == STOKES_PC_ICPCG || precond == STOKES_PC_ICPCG_AQ;
+  if (ic_cg || jacobi_cg) {
     const double rtol_in = ideal ? kIdealTol : pb->inner_tol;
     const int maxit_in = ideal ? kIdealMaxit : pb->maxit_inner;
     int& expect = pb->pcg_expect[precond];
@@ -701,8 +735,8 @@ int precond_velocity(stokes_problem* pb, int precond, Work& W, SchedPair* sp, co
     CK(pcg_init2<T>(R, n_u, (const T*)W.pz, (T*)W.pp, s, rtol_in, maxit_in, skip, outer_st, st));
     int ip = 0;
     auto iter = [&]() -> hipError_t {
-      hipError_t e = pcg_spmv<T>(R, pb->rs_A, pb->rowptr, pb->aend, pb->col, val, (const T*)W.pp, (T*)W.pq, s,
-                                 precond == STOKES_PC_ICPCG, st);
+      hipError_t e = pcg_spmv<T>(R, pb->rs_A, pb->rowptr, pb->aend, pb->col, val, (const T*)W.pp, (T*)W.pq, s, ic_cg,
+                                 st);
       if (e == hipSuccess && jacobi_cg)
         e = pcg_axpy_jacobi<T>(R, n_u, (const T*)W.pp, (const T*)W.pq, pb->diagA, zout, (T*)W.pr, (T*)W.pz, s, ip,
                                st);
@@ -730,7 +764,8 @@ int ensure_pressure_cg(stokes_problem* pb) {
   const int nlo = S.nlo, kp = S.kp, dim = S.dim;
   const int64_t np = S.n_p;
   std::vector<int32_t>& rp = pb->Qrowptr_h;
-  std::vector<int32_t> cl;
+  std::vector<int32_t>& cl = pb->Qcol_h;
+  cl.clear();
   rp.assign(size_t(np) + 1, 0);
   for (int64_t r = 0; r < np; ++r) {
     int i[3] = {int(r % nlo), dim > 1 ? int((r / nlo) % nlo) : 0, dim > 2 ? int(r / (int64_t(nlo) * nlo)) : 0};
@@ -768,12 +803,80 @@ int ensure_pressure_cg(stokes_problem* pb) {
   return 0;
 }
 
+// IC(0) of the pressure mass matrix Q on the pattern of tril(Q) in natural order, and its
+// triangular-solve schedules (pressure rows in strips of the last direction), built on
+// first use.  Q is SPD; a non-positive pivot is reported as a breakdown (no shifts).
+int ensure_pressure_ic0(stokes_problem* pb) {
+  if (pb->LQval != nullptr) return 0;
+  int rc = ensure_pressure_cg(pb);
+  if (rc) return rc;
+  const Spaces& S = pb->S;
+  const int64_t np = S.n_p;
+  LowerPattern& L = pb->LQ;
+  L.rowptr.assign(size_t(np) + 1, 0);
+  L.col.clear();
+  L.src.clear();
+  for (int64_t r = 0; r < np; ++r) {  // Q's columns are sorted: the diagonal ends the lower part
+    for (int32_t k = pb->Qrowptr_h[r]; k < pb->Qrowptr_h[r + 1]; ++k) {
+      if (pb->Qcol_h[k] > r) break;
+      L.col.push_back(pb->Qcol_h[k]);
+      L.src.push_back(k);
+    }
+    if (L.col.empty() || L.col.back() != r) return fail(pb, STOKES_EINVAL, "pressure mass matrix without a diagonal");
+    L.rowptr[size_t(r) + 1] = int32_t(L.col.size());
+  }
+  int nlev = 0;
+  forward_levels(L, np, pb->levQ_fwd, &nlev);
+  std::vector<int32_t> lptr(size_t(nlev) + 1, 0), rows(static_cast<size_t>(np));
+  for (int64_t i = 0; i < np; ++i) lptr[pb->levQ_fwd[i] + 1]++;
+  for (int l = 0; l < nlev; ++l) lptr[l + 1] += lptr[l];
+  std::vector<int32_t> fillp(lptr.begin(), lptr.end() - 1);
+  for (int64_t i = 0; i < np; ++i) rows[fillp[pb->levQ_fwd[i]]++] = int32_t(i);
+  DevAlloc& m = pb->mem;
+  hipStream_t st = pb->stream;
+  pb->LQrowptr = m.upload(L.rowptr, st);
+  pb->LQcol = m.upload(L.col, st);
+  pb->LQsrc = m.upload(L.src, st);
+  int32_t* lrows = m.upload(rows, st);
+  double* lqval = m.get<double>(L.col.size());
+  if (m.err != hipSuccess) return fail_hip(pb, m.err, "IC(0) of Q allocation", __LINE__);
+  CK(ic0_factor(np, int64_t(L.col.size()), pb->LQsrc, pb->LQrowptr, pb->LQcol, pb->Qval, 0.0, lqval, lrows, lptr,
+                pb->flag, st));
+  int fl = 0;
+  CK(hipMemcpyAsync(&fl, pb->flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));  // also: the host vectors outlive the copies
+  if (fl >= 0) return fail(pb, STOKES_EBREAKDOWN, "IC(0) of the pressure mass matrix: non-positive pivot");
+  FactorSched& fs = pb->fsQ;
+  fs.L = &pb->LQ;
+  fs.n = np;
+  fs.Lval = lqval;
+  fs.lev_fwd = &pb->levQ_fwd;
+  fs.lev_bwd = &pb->levQ_bwd;
+  fs.groups = [pb](int strip, std::vector<int32_t>& g, int* ng) {
+    // pressure row r has last-direction index r / inner
+    const Spaces& S = pb->S;
+    int64_t inner = 1;
+    for (int d = 0; d + 1 < S.dim; ++d) inner *= S.nlo;
+    g.assign(size_t(S.n_p), 0);
+    for (int64_t r = 0; r < S.n_p; ++r) g[size_t(r)] = int32_t((r / inner) / strip);
+    *ng = int((S.nlo + strip - 1) / strip);
+  };
+  SchedPair* sp = nullptr;
+  rc = make_schedule(pb, fs, false, &sp);
+  if (rc) return rc;
+  pb->LQval = lqval;
+  return 0;
+}
+
 // Pressure block of the PCG(A,Q) and Ideal(A,Q) preconditioners: zout_p = 2 nu Q^{-1} vin_p
 // by Diag(Q)-preconditioned CG (x0 = 0, relative tolerance inner_tol, or kIdealTol for
 // Ideal(A,Q)), and the dot v_p . z_p into dot_out[R].  vin_p / zout_p point at the pressure
 // rows (row n_u).
+// Inner solver of the pressure block.
+enum { PQ_CG_JACOBI = 0, PQ_CG_IDEAL = 1, PQ_CG_IC0 = 2 };
+
 template <typename T>
-int precond_pressure(stokes_problem* pb, Work& W, bool ideal, const T* vin_p, T* zout_p, double* dot_out,
+int precond_pressure(stokes_problem* pb, Work& W, int kind, const T* vin_p, T* zout_p, double* dot_out,
                      const int* skip, const MinresState* outer_st) {
   const int R = W.R;
   const bool fp32 = W.fp32;
@@ -781,25 +884,55 @@ int precond_pressure(stokes_problem* pb, Work& W, bool ideal, const T* vin_p, T*
   const int64_t n_p = pb->S.n_p;
   const T* qval = fp32 ? (const T*)pb->Qval32 : (const T*)pb->Qval;
   PcgScalars& s = pb->pcgQ;
+  const bool ic0 = kind == PQ_CG_IC0;
+  SchedPair* qsp = nullptr;
+  if (ic0) {
+    int rc = ensure_pressure_ic0(pb);
+    if (rc) return rc;
+    if ((rc = make_schedule(pb, pb->fsQ, fp32, &qsp))) return rc;
+  }
+  // z = M^{-1} r with rho = r.z: Jacobi, or the IC(0) triangular solves of Q (fused dot)
+  auto inner_precond = [&](double* rho_out, const int* sk) -> hipError_t {
+    if (!ic0) return pcg_jacobi<T>(R, n_p, (const T*)W.qr, pb->diagQ, (T*)W.qz, s, rho_out, sk, st);
+    hipError_t e = launch_trsv(qsp->fwd, fp32, R, W.qr, W.qy, nullptr, nullptr, sk, st);
+    if (e != hipSuccess) return e;
+    return launch_trsv(qsp->bwd, fp32, R, W.qy, W.qz, W.qr, rho_out, sk, st);
+  };
   CK(pcg_init<T>(R, n_p, vin_p, (T*)W.qr, zout_p, s, skip, st));
-  CK(pcg_jacobi<T>(R, n_p, (const T*)W.qr, pb->diagQ, (T*)W.qz, s, s.rho, skip, st));
-  const double rtol_in = ideal ? kIdealTol : pb->inner_tol;
-  const int maxit_in = ideal ? kIdealMaxit : pb->maxit_inner;
-  int& expect = pb->pcgq_expect[ideal ? 1 : 0];
+  CK(inner_precond(s.rho, skip));
+  const double rtol_in = kind == PQ_CG_IDEAL ? kIdealTol : pb->inner_tol;
+  const int maxit_in = kind == PQ_CG_IDEAL ? kIdealMaxit : pb->maxit_inner;
+  int& expect = pb->pcgq_expect[kind];
   CK(pcg_init2<T>(R, n_p, (const T*)W.qz, (T*)W.qp, s, rtol_in, maxit_in, skip, outer_st, st));
   int ip = 0;
   auto iter = [&]() -> hipError_t {
     hipError_t e = pcg_spmv<T>(R, pb->rs_Q, pb->Qrowptr, nullptr, pb->Qcol, qval, (const T*)W.qp, (T*)W.qq, s, false, st);
-    if (e == hipSuccess)
+    if (e == hipSuccess && !ic0)
       e = pcg_axpy_jacobi<T>(R, n_p, (const T*)W.qp, (const T*)W.qq, pb->diagQ, zout_p, (T*)W.qr, (T*)W.qz, s, ip, st);
+    if (e == hipSuccess && ic0) {
+      e = pcg_axpy<T>(R, n_p, (const T*)W.qp, (const T*)W.qq, zout_p, (T*)W.qr, s, ip, st);
+      if (e == hipSuccess) e = inner_precond(s.rho + (1 - ip) * kRMax, s.alldone);
+    }
     if (e == hipSuccess) e = pcg_pupdate<T>(R, n_p, (const T*)W.qz, (T*)W.qp, s, ip, st);
     ip = 1 - ip;
     return e;
   };
   if (int e = pcg_run(pb, s, R, maxit_in, &expect, iter)) return e;
+  if (qsp) {
+    int rc = check_trsv_err(pb, qsp);
+    if (rc) return rc;
+  }
   CK(scale_skip<T>(n_p * R, zout_p, 2.0 * pb->nu, skip, st));
   CK(dot<T, T>(R, 0, n_p, vin_p, zout_p, pb->partials, pb->counter, dot_out, st));
   return 0;
+}
+
+// Pressure-block inner solver of a preconditioner code (-1: Diag(Q) in the vector kernels).
+int pressure_kind(int precond) {
+  if (precond == STOKES_PC_PCGAQ) return PQ_CG_JACOBI;
+  if (precond == STOKES_PC_IDEAL) return PQ_CG_IDEAL;
+  if (precond == STOKES_PC_ICPCG_AQ) return PQ_CG_IC0;
+  return -1;
 }
 
 struct RunOut {
@@ -816,12 +949,12 @@ int minres_run(stokes_problem* pb, Work& W, int precond, double tol, int maxit, 
   hipStream_t st = pb->stream;
   const int64_t n_u = pb->S.n_u, n = n_u + pb->S.n_p;
   SchedPair* sp = nullptr;
-  if (precond == STOKES_PC_IC0 || precond == STOKES_PC_ICPCG) {
+  if (precond == STOKES_PC_IC0 || precond == STOKES_PC_ICPCG || precond == STOKES_PC_ICPCG_AQ) {
     int rc = get_schedule(pb, R, fp32, &sp);
     if (rc) return rc;
   }
-  const bool pcg_q = precond == STOKES_PC_PCGAQ || precond == STOKES_PC_IDEAL;
-  const bool ideal = precond == STOKES_PC_IDEAL;
+  const int qkind = pressure_kind(precond);
+  const bool pcg_q = qkind >= 0;
   if (pcg_q) {
     int rc = ensure_pressure_cg(pb);
     if (rc) return rc;
@@ -840,7 +973,7 @@ int minres_run(stokes_problem* pb, Work& W, int precond, double tol, int maxit, 
   int rc = precond_velocity<T>(pb, precond, W, sp, v[0], z[0], s.red + RED_G2U * kRMax, nullptr, nullptr, nullptr);
   if (rc) return rc;
   if (pcg_q) {  // the pressure block replaces the Diag(Q) part the vector kernel wrote
-    rc = precond_pressure<T>(pb, W, ideal, v[0] + n_u * R, z[0] + n_u * R, s.red + RED_G2P * kRMax, nullptr, nullptr);
+    rc = precond_pressure<T>(pb, W, qkind, v[0] + n_u * R, z[0] + n_u * R, s.red + RED_G2P * kRMax, nullptr, nullptr);
     if (rc) return rc;
   }
   CK(mr_init_state(R, s, tol, maxit, st));
@@ -870,7 +1003,7 @@ int minres_run(stokes_problem* pb, Work& W, int precond, double tol, int maxit, 
                                nullptr);
       if (rc) return rc;
       if (pcg_q) {
-        rc = precond_pressure<T>(pb, W, ideal, v[1 - p] + n_u * R, z[1 - p] + n_u * R,
+        rc = precond_pressure<T>(pb, W, qkind, v[1 - p] + n_u * R, z[1 - p] + n_u * R,
                                  s.red + ((size_t)p * RED_KINDS + RED_G2P) * kRMax, s.alldone + p, s.st + p * kRMax);
         if (rc) return rc;
       }
@@ -936,6 +1069,12 @@ int true_residuals(stokes_problem* pb, Work& W, int precond, const double* b, co
                    precond == STOKES_PC_IDEAL || precond == STOKES_PC_IDEAL_A)
                       ? STOKES_PC_JACOBI
                       : STOKES_PC_IC0;
+  // IC(0)-PCG on Q approximates the fixed pressure block IC(0) of Q / (2 nu)
+  const bool icq = precond == STOKES_PC_ICPCG_AQ;
+  if (icq) {
+    int rc = ensure_pressure_ic0(pb);
+    if (rc) return rc;
+  }
   for (int pass = 0; pass < 2; ++pass) {
     const double* vec = pass == 0 ? r : b;
     double* o = out + 2 * R + pass * 2 * R;
@@ -950,13 +1089,22 @@ int true_residuals(stokes_problem* pb, Work& W, int precond, const double* b, co
       CK(launch_trsv(sp->fwd, false, R, vec, W.y, nullptr, nullptr, nullptr, st));
       CK(launch_trsv(sp->bwd, false, R, W.y, W.v[0], vec, o + R, nullptr, st));
     }
+    if (icq) {  // pressure part r_p . (L_Q L_Q^T)^{-1} r_p, scaled by 2 nu below
+      SchedPair* qsp = nullptr;
+      int rc = make_schedule(pb, pb->fsQ, false, &qsp);
+      if (rc) return rc;
+      const double* vp = vec + size_t(n_u) * R;
+      CK(launch_trsv(qsp->fwd, false, R, vp, W.qy, nullptr, nullptr, nullptr, st));
+      CK(launch_trsv(qsp->bwd, false, R, W.qy, W.qz, vp, o, nullptr, st));
+    }
   }
   double h[6 * kRMax];
   CK(hipMemcpyAsync(h, out, sizeof(double) * 6 * R, hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));
+  const double sp_ = icq ? 2.0 * pb->nu : 1.0;
   for (int c = 0; c < R; ++c) {
     const double rr = h[c], bb = h[R + c];
-    const double rM = h[2 * R + c] + h[3 * R + c], bM = h[4 * R + c] + h[5 * R + c];
+    const double rM = sp_ * h[2 * R + c] + h[3 * R + c], bM = sp_ * h[4 * R + c] + h[5 * R + c];
     rel2[c] = bb > 0 ? std::sqrt(rr / bb) : 0.0;
     relM[c] = bM > 0 ? std::sqrt(std::max(0.0, rM) / bM) : 0.0;
   }
@@ -981,10 +1129,11 @@ int solve_core(stokes_problem* pb, Work& W64, int precond, int precision, double
   int status[kRMax] = {0};
   double eta_rel[kRMax] = {0};
   int cycles = 1;
-  const bool inner_pcg = precond == STOKES_PC_ICPCG || precond == STOKES_PC_JPCG || precond == STOKES_PC_PCGAQ;
+  const bool inner_pcg = precond == STOKES_PC_ICPCG || precond == STOKES_PC_JPCG || precond == STOKES_PC_PCGAQ ||
+                         precond == STOKES_PC_ICPCG_AQ;
   // Ideal(A,Q), Ideal(A) + Diag(Q): fixed preconditioners up to rounding, one MINRES run
   // (no restarts)
-  const bool pcg_q = precond == STOKES_PC_PCGAQ || precond == STOKES_PC_IDEAL;
+  const bool pcg_q = pressure_kind(precond) >= 0;
   const bool counts_inner = inner_pcg || precond == STOKES_PC_IDEAL || precond == STOKES_PC_IDEAL_A;
   // inner CG totals count over every refinement cycle of this solve
   if (counts_inner) {
@@ -1145,7 +1294,7 @@ int solve_core(stokes_problem* pb, Work& W64, int precond, int precision, double
 
 int check_args_solve(stokes_problem* pb, double tol, int precond, int precision) {
   if (!(tol > 0.0) || !(tol < 1.0)) return fail(pb, STOKES_EINVAL, "tol must be in (0, 1)");
-  if (precond < 0 || precond > 6) return fail(pb, STOKES_EINVAL, "unknown preconditioner");
+  if (precond < 0 || precond > 7) return fail(pb, STOKES_EINVAL, "unknown preconditioner");
   if (precision != STOKES_FP64 && precision != STOKES_MIXED) return fail(pb, STOKES_EINVAL, "unknown precision");
   if ((precond == STOKES_PC_IDEAL || precond == STOKES_PC_IDEAL_A) && precision != STOKES_FP64)
     return fail(pb, STOKES_EINVAL, "the Ideal preconditioners need STOKES_FP64 (their inner tolerance is below FP32 rounding)");
@@ -1296,6 +1445,13 @@ static int stokes_setup_impl(int n, int p, int dim, double nu, stokes_problem* p
   }
   // triangular-solve schedule for single right-hand sides
   {
+    FactorSched& fs = pb->fsA;
+    fs.L = &pb->L;
+    fs.n = pb->S.n_u;
+    fs.Lval = pb->Lval;
+    fs.lev_fwd = &pb->lev_fwd;
+    fs.lev_bwd = &pb->lev_bwd;
+    fs.groups = [pb](int strip, std::vector<int32_t>& g, int* ng) { strip_groups(pb->S, strip, g, ng); };
     SchedPair* sp = nullptr;
     int rc = get_schedule(pb, 1, false, &sp);
     if (rc) return rc;
@@ -1329,7 +1485,7 @@ int stokes_set_nu(stokes_problem* pb, double nu) {
   hipLaunchKernelGGL(k_gather_diag, dim3(256), dim3(256), 0, st, pb->S.n_u, pb->Lrowptr, pb->Lsrc, pb->val, pb->diagA);
   CK(hipGetLastError());
   CK(convert<double, float>(pb->nnz, pb->val, pb->val32, st));
-  for (auto& sp : pb->scheds) {
+  for (auto& sp : pb->fsA.scheds) {
     CK(launch_trsv_gather(sp->fwd, pb->Lval, st));
     CK(launch_trsv_gather(sp->bwd, pb->Lval, st));
   }
@@ -1547,7 +1703,7 @@ int stokes_apply(stokes_problem* pb, const double* x, double* y) {
 }
 
 int stokes_apply_precond(stokes_problem* pb, int precond, const double* r, double* y, int* inner_iters) {
-  if (!pb || !r || !y || precond < 0 || precond > 6) return fail(pb, STOKES_EINVAL, "bad arguments");
+  if (!pb || !r || !y || precond < 0 || precond > 7) return fail(pb, STOKES_EINVAL, "bad arguments");
   if (inner_iters) *inner_iters = 0;
   Work* W = nullptr;
   int rc = get_work(pb, 1, false, &W);
@@ -1559,8 +1715,10 @@ int stokes_apply_precond(stokes_problem* pb, int precond, const double* r, doubl
   CK(hipGetLastError());
   if (precond != STOKES_PC_JACOBI) {
     SchedPair* sp = nullptr;
-    const bool pq_cg = precond == STOKES_PC_PCGAQ || precond == STOKES_PC_IDEAL;
-    const bool jac = precond == STOKES_PC_JPCG || precond == STOKES_PC_IDEAL_A || pq_cg;
+    const int qkind = pressure_kind(precond);
+    const bool pq_cg = qkind >= 0;
+    const bool jac = precond == STOKES_PC_JPCG || precond == STOKES_PC_IDEAL_A || precond == STOKES_PC_PCGAQ ||
+                     precond == STOKES_PC_IDEAL;
     if (!jac && (rc = get_schedule(pb, 1, false, &sp))) return rc;
     if (precond != STOKES_PC_IC0) CK(hipMemsetAsync(pb->pcg.st, 0, sizeof(PcgState) * kRMax, st));
     rc = precond_velocity<double>(pb, precond, *W, sp, r, y, pb->scratch + 100, nullptr, nullptr, nullptr);
@@ -1570,8 +1728,7 @@ int stokes_apply_precond(stokes_problem* pb, int precond, const double* r, doubl
     if (pq_cg) {
       if ((rc = ensure_pressure_cg(pb))) return rc;
       CK(hipMemsetAsync(pb->pcgQ.st, 0, sizeof(PcgState) * kRMax, st));
-      rc = precond_pressure<double>(pb, *W, precond == STOKES_PC_IDEAL, r + n_u, y + n_u, pb->scratch + 101, nullptr,
-                                    nullptr);
+      rc = precond_pressure<double>(pb, *W, qkind, r + n_u, y + n_u, pb->scratch + 101, nullptr, nullptr);
       if (rc) return rc;
       PcgState pq;
       CK(hipMemcpyAsync(&pq, pb->pcgQ.st, sizeof(PcgState), hipMemcpyDeviceToHost, st));
@@ -1590,16 +1747,20 @@ int stokes_apply_precond(stokes_problem* pb, int precond, const double* r, doubl
 }
 
 int stokes_export_csr(stokes_problem* pb, int which, int64_t* nnz, int64_t* rowptr, int32_t* col, double* val) {
-  if (!pb || (which != 0 && which != 1)) return fail(pb, STOKES_EINVAL, "bad arguments to stokes_export_csr");
-  const auto& rp = which == 0 ? pb->P.rowptr : pb->L.rowptr;
-  const auto& cl = which == 0 ? pb->P.col : pb->L.col;
+  if (!pb || which < 0 || which > 2) return fail(pb, STOKES_EINVAL, "bad arguments to stokes_export_csr");
+  if (which == 2) {
+    int rc = ensure_pressure_ic0(pb);
+    if (rc) return rc;
+  }
+  const auto& rp = which == 0 ? pb->P.rowptr : (which == 1 ? pb->L.rowptr : pb->LQ.rowptr);
+  const auto& cl = which == 0 ? pb->P.col : (which == 1 ? pb->L.col : pb->LQ.col);
   if (nnz) *nnz = int64_t(cl.size());
   if (rowptr)
     for (size_t i = 0; i < rp.size(); ++i) rowptr[i] = rp[i];
   if (col) std::memcpy(col, cl.data(), cl.size() * sizeof(int32_t));
   if (val) {
-    CK(hipMemcpyAsync(val, which == 0 ? pb->val : pb->Lval, cl.size() * sizeof(double), hipMemcpyDeviceToHost,
-                      pb->stream));
+    CK(hipMemcpyAsync(val, which == 0 ? pb->val : (which == 1 ? pb->Lval : pb->LQval), cl.size() * sizeof(double),
+                      hipMemcpyDeviceToHost, pb->stream));
     CK(hipStreamSynchronize(pb->stream));
   }
   return 0;
@@ -1614,9 +1775,9 @@ int stokes_export_pressure_mass(stokes_problem* pb, double* diagQ, double* w) {
 }
 
 int stokes_levels(const stokes_problem* pb, int* fwd_levels, int* bwd_levels) {
-  if (!pb || pb->scheds.empty()) return STOKES_EINVAL;
-  if (fwd_levels) *fwd_levels = pb->scheds[0]->fwd.nlevels;
-  if (bwd_levels) *bwd_levels = pb->scheds[0]->bwd.nlevels;
+  if (!pb || pb->fsA.scheds.empty()) return STOKES_EINVAL;
+  if (fwd_levels) *fwd_levels = pb->fsA.scheds[0]->fwd.nlevels;
+  if (bwd_levels) *bwd_levels = pb->fsA.scheds[0]->bwd.nlevels;
   return 0;
 }
 

@@ -208,11 +208,12 @@ class StokesProblem:
         return y, it.value
 
     def export_csr(self, which=0):
-        """(indptr int64, indices int32, data float64) numpy arrays; which 0 = saddle, 1 = IC(0) L."""
+        """(indptr int64, indices int32, data float64) numpy arrays; which 0 = saddle, 1 = IC(0) of A,
+        2 = IC(0) of the pressure mass matrix Q."""
         nnz = ctypes.c_int64()
         self._check(self._L.stokes_export_csr(self._h, int(which), ctypes.byref(nnz), None, None, None),
                     allow_nc=False)
-        rows = self.n_u + self.n_p if which == 0 else self.n_u
+        rows = {0: self.n_u + self.n_p, 1: self.n_u, 2: self.n_p}[which]
         ptr = np.zeros(rows + 1, np.int64)
         col = np.zeros(nnz.value, np.int32)
         val = np.zeros(nnz.value, np.float64)

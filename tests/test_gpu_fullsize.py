@@ -125,9 +125,15 @@ def test_c1_first_iterations(c1):
 
 @pytest.mark.parametrize("pc", [PC_IC0, PC_ICPCG])
 def test_c1_converged(c1, pc):
+    """Converged at tol 1e-8 in the IC(0)-block norm, formed by the oracle: MINRES-IC(0), and
+    inner IC(0)-CG with MINRES restarted on the true residual (stokes_set_restarts)."""
     gp, o, w = c1
     f = o.load(1)
-    u, p, info = gp.solve(_cuda(f), tol=w["tol"], precond=pc)
+    gp.set_restarts(6 if pc == PC_ICPCG else 0)
+    try:
+        u, p, info = gp.solve(_cuda(f), tol=w["tol"], precond=pc)
+    finally:
+        gp.set_restarts(0)
     assert info["status"] == 0
     x = np.concatenate([u.cpu().numpy(), p.cpu().numpy()])
     b = np.concatenate([f, np.zeros(o.n_p)])
@@ -194,8 +200,8 @@ def _relres_Minv_jacobi(o, b, x):
 
 def test_c1_cavity_pcg_AQ(c1):
     """The lid-driven cavity on the C1 mesh: the device load (Nitsche form l_h) against the
-    oracle's at every entry, then PCG(A,Q) (inner Diag-CG on A and Q to 1e-2, refined on the
-    true residual) and the other variants with inner CG: the oracle-formed residual in the
+    oracle's at every entry, then PCG(A,Q) (inner Diag-CG on A and Q to 1e-2, MINRES
+    restarted on the true residual) and PCG(A), Diag(Q): the oracle-formed residual in the
     Jacobi-block norm meets tol."""
     from paper_1309_5048_amd import CAVITY_LID, PC_JPCG, PC_PCGAQ
     gp, o, w = c1
@@ -207,7 +213,11 @@ def test_c1_cavity_pcg_AQ(c1):
     gp.set_inner_tol(1e-2)
     for pc in (PC_PCGAQ, PC_JPCG):
         print("[case] c1 cavity solve, precond %d" % pc, flush=True)
-        u, p, info = gp.solve(f, tol=w["tol"], precond=pc)
+        gp.set_restarts(6)
+        try:
+            u, p, info = gp.solve(f, tol=w["tol"], precond=pc)
+        finally:
+            gp.set_restarts(0)
         assert info["status"] == 0
         x = np.concatenate([u.cpu().numpy(), p.cpu().numpy()])
         rel = _relres_Minv_jacobi(o, b, x)

@@ -14,7 +14,8 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
-from oracle.oracle import PC_EXACT, PC_IC0, PC_ICPCG, PC_JACOBI, PC_JPCG, PQ_DIAG, PQ_EXACT, PQ_JPCG, Oracle  # noqa: E402
+from oracle.oracle import (PC_EXACT, PC_IC0, PC_ICPCG, PC_JACOBI, PC_JPCG, PQ_DIAG, PQ_EXACT, PQ_ICPCG,  # noqa: E402
+                           PQ_JPCG, Oracle)
 from synthetic_inputs import forcing_modes, random_vector  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -237,18 +238,63 @@ def _pcg_AQ_restarted(gp, o):
     _close(p2.cpu().numpy(), po2, 1e-10)
 
 
-@pytest.mark.parametrize("pc", ["icpcg", "jpcg", "pcgAQ"])
+def test_ic0_pressure_factor(pair):
+    """IC(0) of the pressure mass matrix (Sec. 6.4), factorised on the device, against the
+    oracle's factor: same pattern (tril Q), every entry within 1e-12."""
+    gp, o = pair
+    ptr, col, val = gp.export_csr(2)
+    assert o.ic0_q() == 0
+    optr, ocol, oval = o.csr("LQ")
+    assert np.array_equal(ptr, optr) and np.array_equal(col, ocol)
+    assert np.abs(val - oval).max() <= 1e-12 * np.abs(oval).max()
+
+
+def test_icpcg_AQ_application(pair):
+    """One application of IC(0)-PCG(A,Q) (library code 7): IC(0)-CG on A and on Q at the
+    inner tolerance 1e-2 against the oracle's (PC_ICPCG, PQ_ICPCG).  IC(0) of Q is Q's
+    Cholesky factor here, so CG on Q stops after one iteration, as the paper reports."""
+    from paper_1309_5048_amd import PC_ICPCG_AQ
+    gp, o = pair
+    r = random_vector(o.n, 23)
+    z, it = gp.apply_precond(_cuda(r), PC_ICPCG_AQ)
+    zo, ito = o.precond(r, pc_A=PC_ICPCG, pc_Q=PQ_ICPCG, inner_tol=1e-2)
+    _, ita = o.precond(r, pc_A=PC_ICPCG, pc_Q=PQ_DIAG, inner_tol=1e-2)
+    assert ito - ita == 1, (ito, ita)  # one pressure iteration
+    assert abs(it - ito) <= 1, (it, ito)
+    _close(z.cpu().numpy()[o.n_u:], zo[o.n_u:], 1e-9)
+    assert _rel(z.cpu().numpy(), zo) <= 1e-9
+
+
+def test_icpcg_AQ_restarted(pair):
+    """IC(0)-PCG(A,Q) with MINRES restarted on the true residual (stokes_set_restarts):
+    converged in the norm of blkdiag(IC(0) of A, IC(0) of Q / (2 nu)), and at tol 1e-13 the
+    oracle's restarted solve."""
+    from paper_1309_5048_amd import PC_ICPCG_AQ
+    gp, o = pair
+    f = o.load(1)
+    with _restarted(gp):
+        u, p, info = gp.solve(_cuda(f), tol=1e-8, precond=PC_ICPCG_AQ)
+        u2, p2, _ = gp.solve(_cuda(f), tol=1e-13, precond=PC_ICPCG_AQ)
+    assert info["status"] == 0 and info["relres_true_Minv"] <= 1e-8
+    uo, po, io = o.solve_refined(f, tol=1e-8, pc_A=PC_ICPCG, pc_Q=PQ_ICPCG)
+    assert abs(info["relres_true_Minv"] - io["relres_true_Minv"]) <= 0.5 * io["relres_true_Minv"] + 1e-10
+    uo2, po2, _ = o.solve_refined(f, tol=1e-13, pc_A=PC_ICPCG, pc_Q=PQ_ICPCG)
+    _close(u2.cpu().numpy(), uo2, 1e-10)
+    _close(p2.cpu().numpy(), po2, 1e-10)
+
+
+@pytest.mark.parametrize("pc", ["icpcg", "jpcg", "pcgAQ", "icpcgAQ"])
 def test_paper_inner_pcg_single_run(pair, pc):
     """The paper's outer method for the inner-CG blocks (Sec. 5.1; Sec. 6.2 and 6.4 tables):
     one MINRES run whose preconditioner is inner PCG at the tables' inner tolerance 1e-6,
     stopped on |eta| <= tol gamma_1 (the library's default, no restarts), against the
     oracle's plain MINRES with the same inner PCG: stop counts at tol 1e-8 and solutions at
     tol 1e-13."""
-    from paper_1309_5048_amd import PC_PCGAQ
+    from paper_1309_5048_amd import PC_ICPCG_AQ, PC_PCGAQ
     gp, o = pair
-    code = {"icpcg": PC_ICPCG, "jpcg": PC_JPCG, "pcgAQ": PC_PCGAQ}[pc]
-    pa = PC_ICPCG if pc == "icpcg" else PC_JPCG
-    pq = PQ_JPCG if pc == "pcgAQ" else PQ_DIAG
+    code = {"icpcg": PC_ICPCG, "jpcg": PC_JPCG, "pcgAQ": PC_PCGAQ, "icpcgAQ": PC_ICPCG_AQ}[pc]
+    pa = PC_ICPCG if pc in ("icpcg", "icpcgAQ") else PC_JPCG
+    pq = {"pcgAQ": PQ_JPCG, "icpcgAQ": PQ_ICPCG}.get(pc, PQ_DIAG)
     f = o.load(1)
     gp.set_inner_tol(1e-6)
     try:
@@ -358,14 +404,15 @@ def test_cavity_load(pair):
     _close(p.cpu().numpy(), po, 1e-10)
 
 
-@pytest.mark.parametrize("pc,nrhs", [("icpcg", 3), ("jpcg", 3), ("pcgAQ", 3), ("pcgAQ", 16), ("ideal", 3)])
+@pytest.mark.parametrize("pc,nrhs", [("icpcg", 3), ("jpcg", 3), ("pcgAQ", 3), ("pcgAQ", 16), ("ideal", 3),
+                                     ("icpcgAQ", 8)])
 def test_batched_inner_cg(pair, pc, nrhs):
     """Batched solves (R = 8 or 16 interleaved columns) with the inner-CG preconditioners:
     every column converges and matches the oracle's single-column solve (refined MINRES
     for the inner-CG blocks, exact block solves for Ideal(A,Q))."""
-    from paper_1309_5048_amd import PC_IDEAL, PC_PCGAQ
+    from paper_1309_5048_amd import PC_ICPCG_AQ, PC_IDEAL, PC_PCGAQ
     gp, o = pair
-    code = {"icpcg": PC_ICPCG, "jpcg": PC_JPCG, "pcgAQ": PC_PCGAQ, "ideal": PC_IDEAL}[pc]
+    code = {"icpcg": PC_ICPCG, "jpcg": PC_JPCG, "pcgAQ": PC_PCGAQ, "ideal": PC_IDEAL, "icpcgAQ": PC_ICPCG_AQ}[pc]
     modes = forcing_modes(list(range(4000, 4000 + nrhs)), o.dim)
     F = o.load(1, modes)
     tol = 1e-11 if pc == "ideal" else 1e-13
@@ -378,8 +425,8 @@ def test_batched_inner_cg(pair, pc, nrhs):
             uo, po, _ = o.solve(F[r], tol=tol, pc_A=PC_EXACT, pc_Q=PQ_EXACT)
             bar = 1e-8
         else:
-            pa = PC_ICPCG if pc == "icpcg" else PC_JPCG
-            pq = PQ_JPCG if pc == "pcgAQ" else PQ_DIAG
+            pa = PC_ICPCG if pc in ("icpcg", "icpcgAQ") else PC_JPCG
+            pq = {"pcgAQ": PQ_JPCG, "icpcgAQ": PQ_ICPCG}.get(pc, PQ_DIAG)
             uo, po, _ = o.solve_refined(F[r], tol=tol, pc_A=pa, pc_Q=pq)
             bar = 1e-10
         _close(U[r].cpu().numpy(), uo, bar)
@@ -501,7 +548,7 @@ def test_edge_cases():
         gp.solve(_cuda(Oracle(6, 2).load(1)), tol=2.0)
     with pytest.raises(StokesError):
         StokesProblem(4, 5, 2, 1.0)
-    for pc in (-1, 7):  # preconditioner codes outside 0..6
+    for pc in (-1, 8):  # preconditioner codes outside 0..7
         with pytest.raises(StokesError):
             gp.solve(_cuda(Oracle(6, 2).load(1)), tol=1e-8, precond=pc)
     gp.set_maxit(2, 0)
