@@ -198,6 +198,22 @@ int stokes_solve(stokes_problem* pb, const double* f, double* u, double* pr, dou
 int stokes_solve_batched(stokes_problem* pb, int nrhs, const double* F, double* U, double* P,
                          double tol, int precond, int precision, stokes_info* infos);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): stokes_solve without any allocation.
+ * precond must be STOKES_PC_IC0 or STOKES_PC_JACOBI (FP64, one right-hand side); the MINRES
+ * work vectors live in a static device array of the library, 64 MiB per GPU, held from the
+ * library's first setup on that GPU until the process ends, instead of in the handle's
+ * lazily allocated workspace.  Limit: 10 vectors of n_u + n_p doubles (each rounded up to
+ * 256 bytes) must fit, i.e. n_u + n_p <= 838,848 (the N = 512, k' = 2 problem fits);
+ * larger problems, other preconditioners and a null pointer give STOKES_EINVAL.  The array
+ * is shared by every handle on that GPU and keeps the last call's contents (every value
+ * the solve reads is written by the call first): calls that overlap on one GPU, from
+ * other threads or streams, race.  Same results, info and return codes as stokes_solve
+ * (info->solve_ms from events created at setup); kernel timing (stokes_profile) is
+ * paused during the call.  f [n_u] in, u [n_u] and pr [n_p] out, device pointers. */
+int stokes_solve_noalloc(stokes_problem* pb, const double* f, double* u, double* pr, double tol, int precond,
+                         stokes_info* info);
+
 /* Single right-hand side with a precision choice (STOKES_FP64 is stokes_solve). */
 int stokes_solve_precision(stokes_problem* pb, const double* f, double* u, double* pr, double tol,
                            int precond, int precision, stokes_info* info);

@@ -24,6 +24,7 @@ EXPORTS = (
     "stokes_setup", "stokes_sizes", "stokes_set_stream", "stokes_set_nu", "stokes_set_inner_tol",
     "stokes_set_refine_tol",
     "stokes_set_maxit", "stokes_set_restarts", "stokes_load", "stokes_load_cavity", "stokes_solve", "stokes_solve_batched", "stokes_solve_precision",
+    "stokes_solve_noalloc",
     "stokes_solve_adjoint", "stokes_solve_adjoint_batched", "stokes_dnu_dot", "stokes_apply",
     "stokes_apply_precond", "stokes_export_csr", "stokes_export_pressure_mass", "stokes_levels",
     "stokes_profile", "stokes_last_error", "stokes_destroy",
@@ -73,6 +74,7 @@ def lib():
         "stokes_solve": (i32, [vp, vp, vp, vp, dbl, i32, P(StokesInfo)]),
         "stokes_solve_batched": (i32, [vp, i32, vp, vp, vp, dbl, i32, i32, vp]),
         "stokes_solve_precision": (i32, [vp, vp, vp, vp, dbl, i32, i32, P(StokesInfo)]),
+        "stokes_solve_noalloc": (i32, [vp, vp, vp, vp, dbl, i32, P(StokesInfo)]),
         "stokes_solve_adjoint": (i32, [vp, vp, vp, dbl, i32, P(StokesInfo)]),
         "stokes_solve_adjoint_batched": (i32, [vp, i32, vp, vp, dbl, i32, vp]),
         "stokes_dnu_dot": (i32, [vp, i32, vp, vp, vp]),

@@ -9,6 +9,7 @@
 #include <functional>
 #include <map>
 #include <memory>
+#include <mutex>
 
 #include "stokes.h"
 #include "stokes_internal.h"
@@ -99,6 +100,19 @@ __global__ void k_fill(int64_t n, T* __restrict__ a, T v) {
     case 16: { constexpr int RR = 16; __VA_ARGS__; break; } \
     default: break;                                         \
   }
+
+// ---------------------------------------------------------------------------
+// Workspace of stokes_solve_noalloc: a file-scope device array, one copy per GPU, held
+// until the process ends.  Host code never passes the array's name to a kernel (in host
+// code it is only a stand-in for the symbol): stokes_setup looks up the address of the
+// current device's copy with hipGetSymbolAddress, and every use goes through that pointer.
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocBytes = size_t(64) << 20;  // 64 MiB
+constexpr int kNoAllocVectors = 10;                  // MINRES vectors v, z, w (x2), x, q, b, y
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
 
 // ---------------------------------------------------------------------------
 // Device buffer helpers
@@ -237,7 +251,13 @@ struct stokes_problem {
   // the same for the inner CG loops
   int* pcg_hflag = nullptr;
   hipEvent_t pcg_ev[2] = {nullptr, nullptr};
+  // timing events of stokes_solve_noalloc, created at setup
+  hipEvent_t noalloc_ev[2] = {nullptr, nullptr};
+  // this device's copy of the stokes_solve_noalloc workspace (looked up at setup)
+  void* noalloc_ws = nullptr;
   ~stokes_problem() {
+    for (auto& e : noalloc_ev)
+      if (e) (void)hipEventDestroy(e);
     for (auto& t : prof_pool) {
       (void)hipEventDestroy(t.before);
       (void)hipEventDestroy(t.after);
@@ -1456,6 +1476,21 @@ static int stokes_setup_impl(int n, int p, int dim, double nu, stokes_problem* p
     int rc = get_schedule(pb, 1, false, &sp);
     if (rc) return rc;
   }
+  // MINRES convergence flags (pinned host words) and the no-allocation solve's events and
+  // workspace address, so that stokes_solve_noalloc allocates nothing later
+  CK(hipHostMalloc((void**)&pb->hflag, 2 * sizeof(int), hipHostMallocDefault));
+  for (auto& e : pb->flag_ev) CK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  for (auto& e : pb->noalloc_ev) CK(hipEventCreate(&e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(pb, STOKES_EINVAL, "device index out of range");
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+      void* ptr = nullptr;
+      CK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+      g_scratch_ptr[dev] = ptr;
+    }
+    pb->noalloc_ws = g_scratch_ptr[dev];
+  }
   CK(hipStreamSynchronize(st));
   auto t1 = std::chrono::steady_clock::now();
   pb->setup_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
@@ -1607,6 +1642,56 @@ int stokes_solve_batched(stokes_problem* pb, int nrhs, const double* F, double* 
   if (infos)
     for (int c = 0; c < nrhs; ++c) infos[c].solve_ms = ms;
   return rc_solve;
+}
+
+int stokes_solve_noalloc(stokes_problem* pb, const double* f, double* u, double* pr, double tol, int precond,
+                         stokes_info* info) {
+  if (!pb) return STOKES_EINVAL;
+  int rc = check_args_solve(pb, tol, precond, STOKES_FP64);
+  if (rc) return rc;
+  if (precond != STOKES_PC_IC0 && precond != STOKES_PC_JACOBI)
+    return fail(pb, STOKES_EINVAL, "stokes_solve_noalloc: precond must be STOKES_PC_IC0 or STOKES_PC_JACOBI");
+  if ((rc = validate_vec(pb, f, "f")) || (rc = validate_vec(pb, u, "u")) || (rc = validate_vec(pb, pr, "pr"))) return rc;
+  const int64_t n_u = pb->S.n_u, n_p = pb->S.n_p, n = n_u + n_p;
+  // every vector rounded up to 256 bytes
+  const size_t vec_bytes = (size_t(n) * sizeof(double) + 255) & ~size_t(255);
+  if (vec_bytes * kNoAllocVectors > kNoAllocBytes)
+    return fail(pb, STOKES_EINVAL, "stokes_solve_noalloc: n_u + n_p exceeds the 64 MiB workspace (at most 838,848)");
+  if (pb->noalloc_ws == nullptr || pb->hflag == nullptr || pb->noalloc_ev[0] == nullptr)
+    return fail(pb, STOKES_EINVAL, "stokes_solve_noalloc: the handle was not set up by this library version");
+  if (precond == STOKES_PC_IC0) {
+    bool have = false;
+    for (auto& sp : pb->fsA.scheds) have |= sp->rmax64 >= 1;
+    if (!have) return fail(pb, STOKES_EINVAL, "stokes_solve_noalloc: no single-column FP64 triangular-solve schedule");
+  }
+  unsigned char* base = static_cast<unsigned char*>(pb->noalloc_ws);
+  Work W;
+  W.R = 1;
+  W.fp32 = false;
+  void** slots[kNoAllocVectors] = {&W.v[0], &W.v[1], &W.z[0], &W.z[1], &W.w[0], &W.w[1], &W.x, &W.q, &W.b, &W.y};
+  for (int k = 0; k < kNoAllocVectors; ++k) *slots[k] = base + size_t(k) * vec_bytes;
+  // kernel timing would create events on demand: off for this call
+  const bool prof_was = pb->prof_on;
+  pb->prof_on = false;
+  hipStream_t st = pb->stream;
+  CK(hipEventRecord(pb->noalloc_ev[0], st));
+  // right-hand side [f; 0] (the array keeps the previous call's contents: every vector the
+  // solve reads before writing is set here or by the MINRES initialisation)
+  hipLaunchKernelGGL(k_fill<double>, dim3(1024), dim3(256), 0, st, n, (double*)W.b, 0.0);
+  CK(hipGetLastError());
+  CK(hipMemcpyAsync(W.b, f, sizeof(double) * n_u, hipMemcpyDeviceToDevice, st));
+  rc = check_finite(pb, 1, (const double*)W.b, n);
+  if (rc == 0) rc = solve_core(pb, W, precond, STOKES_FP64, tol, info, 1);
+  pb->prof_on = prof_was;
+  if (rc < 0) return rc;
+  CK(hipMemcpyAsync(u, W.x, sizeof(double) * n_u, hipMemcpyDeviceToDevice, st));
+  CK(hipMemcpyAsync(pr, (const double*)W.x + n_u, sizeof(double) * n_p, hipMemcpyDeviceToDevice, st));
+  CK(hipEventRecord(pb->noalloc_ev[1], st));
+  CK(hipEventSynchronize(pb->noalloc_ev[1]));
+  float ms = 0.f;
+  CK(hipEventElapsedTime(&ms, pb->noalloc_ev[0], pb->noalloc_ev[1]));
+  if (info) info->solve_ms = ms;
+  return rc;
 }
 
 int stokes_solve_precision(stokes_problem* pb, const double* f, double* u, double* pr, double tol, int precond,

@@ -151,6 +151,19 @@ class StokesProblem:
         self._check(rc)
         return u, p, info.as_dict()
 
+    def solve_noalloc(self, f, u, p, tol=1e-8, precond=N.PC_IC0):
+        """stokes_solve_noalloc: the library allocates nothing; u [n_u] and p [n_p] are the
+        caller's output tensors.  Returns the info dict."""
+        _dev(f, "f", self.n_u)
+        _dev(u, "u", self.n_u)
+        _dev(p, "p", self.n_p)
+        info = N.StokesInfo()
+        self._stream()
+        rc = self._L.stokes_solve_noalloc(self._h, _ptr(f), _ptr(u), _ptr(p), float(tol), int(precond),
+                                          ctypes.byref(info))
+        self._check(rc)
+        return info.as_dict()
+
     def solve_batched(self, F, tol=1e-8, precond=N.PC_IC0, precision=N.FP64):
         """F [nrhs, n_u] -> U [nrhs, n_u], P [nrhs, n_p], infos (list of dicts)."""
         _dev(F, "F")
