@@ -321,6 +321,8 @@ def main():
 
     torch.cuda.set_device(0)
     N, kp, dim, tol = 256, 2, 2, 1e-8
+    if args.only == "c1-ic0":  # the headline solves alone
+        args.no_extra = args.no_cpu = True
     if args.only and not args.only.startswith("c1-"):
         extra = {}
         log("workload %s alone" % args.only)

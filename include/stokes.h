@@ -87,7 +87,10 @@ extern "C" {
 #define STOKES_FP64 0  /* everything in double precision                                  */
 #define STOKES_MIXED 1 /* iterative refinement: FP64 true residual, zero-mean projection
                           and Lanczos/Givens scalars; inner MINRES with FP32 matrices,
-                          FP32 IC(0) factors and triangular solves, FP32 accumulation   */
+                          FP32 IC(0) factors and triangular solves, FP32 accumulation.
+                          Refines until the true M^{-1}-norm residual is <= tol / 10,
+                          so that the solution's error stays within that of an FP64 solve
+                          at tol (status 0 once it is <= tol)                             */
 
 typedef struct stokes_problem stokes_problem; /* opaque: owns all device matrices,
                                                   factors, schedules and workspaces   */
@@ -163,7 +166,7 @@ int stokes_set_restarts(stokes_problem* pb, int max_cycles);
 
 /* STOKES_MIXED refinement: relative residual reduction asked of the first FP32 inner MINRES
  * (default 1e-4, must be < 1).  Later cycles ask for the reduction still missing to reach
- * tol (with a factor 2 of margin), but never for more than rtol.  At most 30 cycles.
+ * tol / 10 (with a factor 2 of margin), but never for more than rtol.  At most 30 cycles.
  * Non-positive values keep the current setting. */
 int stokes_set_refine_tol(stokes_problem* pb, double rtol);
 
