@@ -11,7 +11,12 @@ Preconditioner codes (block-diagonal M = blkdiag(M_A, M_Q), paper Sec. 5.1):
         3 IC(0) of Q applied once, 4 IC(0)-PCG on Q
 Forcing problems: 0 none, 1 manufactured curl solution with p = prod cos(pi x),
   2 the paper's square-domain solution (Sec. 6.2, divergence-free sign),
-  3 pure gradient forcing f = grad(sin(2 pi x) cos(pi y) [cos(pi z)]).
+  3 pure gradient forcing f = grad(sin(2 pi x) cos(pi y) [cos(pi z)]),
+  4 (1/8 annulus) u = curl(a^2 b^2), a = (r^2 - 1)(r^2 - 4), b = y (y - x); p = x y^2.
+Geometry (Sec. 3.2): GEOM_SQUARE the identity map on the unit square/cube, GEOM_ANNULUS
+  (2D) one eighth of the annulus 1 < r < 2, 0 < theta < pi/4 (Sec. 6.3) by the polar map
+  r = 1 + xi_0, theta = (pi/4) xi_1; velocities by the Piola transform, pressures by the
+  integral-preserving one.  evaluate() takes parametric points.
 """
 import ctypes
 import os
@@ -24,6 +29,7 @@ _SRC = os.path.join(_HERE, "stokes_oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 PC_IC0, PC_ICPCG, PC_JACOBI, PC_EXACT, PC_JPCG = 0, 1, 2, 3, 4
+GEOM_SQUARE, GEOM_ANNULUS = 0, 1
 PQ_DIAG, PQ_EXACT, PQ_JPCG, PQ_IC0, PQ_ICPCG = 0, 1, 2, 3, 4
 
 
@@ -107,12 +113,13 @@ class Oracle:
     pressure degree kp (= k'), velocity degree kp+1, viscosity nu; cpen < 0 selects the
     paper's C_pen = 5(k'+1)."""
 
-    def __init__(self, N, kp, dim=2, nu=1.0, cpen=-1.0, pattern_only=False):
+    def __init__(self, N, kp, dim=2, nu=1.0, cpen=-1.0, pattern_only=False, geometry=0):
         self._L = lib()
-        self.h = self._L.or_setup(int(N), int(kp), int(dim), float(nu), float(cpen), int(bool(pattern_only)))
+        flags = int(bool(pattern_only)) | (2 if geometry == GEOM_ANNULUS else 0)
+        self.h = self._L.or_setup(int(N), int(kp), int(dim), float(nu), float(cpen), flags)
         if not self.h:
             raise ValueError("oracle setup rejected the arguments")
-        self.N, self.kp, self.dim, self.nu = N, kp, dim, nu
+        self.N, self.kp, self.dim, self.nu, self.geometry = N, kp, dim, nu, geometry
         a, b = ctypes.c_int64(), ctypes.c_int64()
         self._L.or_sizes(self.h, ctypes.byref(a), ctypes.byref(b))
         self.n_u, self.n_p = a.value, b.value
@@ -290,7 +297,8 @@ class Oracle:
         return float(self._L.or_dnu_dot(self.h, _p(_f64(lam_u)), _p(_f64(u))))
 
     def evaluate(self, u, p, pts):
-        """Discrete fields at points pts[npts, dim]: returns [npts, dim+2] = (u..., div u, p)."""
+        """Discrete fields at the physical images of parametric points pts[npts, dim]:
+        returns [npts, dim+2] = (u..., div u, p)."""
         pts = _f64(pts)
         out = np.zeros((pts.shape[0], self.dim + 2))
         self._L.or_eval(self.h, _p(_f64(u)), _p(_f64(p)), int(pts.shape[0]), _p(pts), _p(out))

@@ -28,7 +28,12 @@
 //     factorisation restarts on A + alpha*diag(A), alpha = 1e-3, 1e-2, 1e-1;
 //   * inner PCG stops when ||r||_2 <= rtol ||b||_2 (x0 = 0, test after each update, <= 200 its);
 //   * MINRES stops when |eta_j| <= tol * gamma_1 (relative M^{-1}-norm residual, x0 = 0);
-//   * zero-mean pressure: p <- p - (w.p)/(w.1) with w_k = integral of phi_k.
+//   * zero-mean pressure: p <- p - (w.p)/(w.1) with w_k = integral of phi_k;
+//   * mapped geometry (Sec. 3.2, the 1/8 annulus of Sec. 6.3): polar map r = 1 + xi_0,
+//     theta = (pi/4) xi_1 onto 1 < r < 2, 0 < theta < pi/4; k'+3 Gauss points per direction
+//     for the matrices (k'+5 for loads and errors), the integrands being rational there;
+//     h_F = 1/(N |DF^{-1} n|), the element length normal to the face (Bazilevs' definition,
+//     equal to 1/N on the identity map).
 
 #include <algorithm>
 #include <array>
@@ -154,6 +159,7 @@ void eval_on_element(const Space1D& s, int e, const std::vector<double>& xs,
 // ---------------------------------------------------------------------------
 struct Problem {
   int N = 0, kp = 0, dim = 0;
+  int geom = 0;                       // 0: identity map (unit square/cube); 1: 1/8 annulus (2D)
   double nu = 1.0, cpen = 0.0, h = 0.0;
   int pdeg = 0;                       // velocity degree p = k'+1
   Space1D sp_hi, sp_lo;               // 1D spaces of degree p and k'
@@ -165,7 +171,11 @@ struct Problem {
   std::vector<int64_t> A_ptr, B_ptr, Q_ptr;
   std::vector<int32_t> A_col, B_col, Q_col;
   std::vector<double> A_val, B_val, Q_val;
-  std::vector<double> diagQ, wvec;    // diag(Q) and w = Q 1 (integral of each phi_k)
+  std::vector<double> diagQ, wvec;    // diag(Q) and w_k = integral of phi_k
+  // Coefficients of the constant function 1 in the pressure space: all ones on the identity
+  // map; on a mapped domain phi_k = phihat_k / J, and kappa = Q^{-1} w (the L2 projection of
+  // the constant, which lies in the space).  The pressure is unique up to multiples of kappa.
+  std::vector<double> kappa;
 
   // IC(0) factor of A: lower triangle of A's pattern, diagonal stored last in each row.
   bool have_L = false;
@@ -431,6 +441,95 @@ void sym_grad(const VelEval& f, double eps[3][3]) {
 }
 
 // ---------------------------------------------------------------------------
+// Geometry map F (Sec. 3.2): the physical domain is the image of the parametric unit
+// square/cube.  geom 0: the identity.  geom 1 (2D): one eighth of an annulus (Sec. 6.3),
+// the polar map x = r cos(theta), y = r sin(theta) with r = 1 + xi_0, theta = (pi/4) xi_1.
+// At a parametric point: x = F(xi), the Jacobian matrix DF[a][b] = dx_a/dxi_b, its
+// inverse, J = det DF and the second derivatives dDF[k][a][b] = d(DF[a][b])/dxi_k.
+// ---------------------------------------------------------------------------
+struct GeoPoint {
+  double x[3];
+  double DF[3][3], Finv[3][3], J;
+  double dDF[3][3][3];
+};
+
+void geometry(const Problem& P, const double* xi, GeoPoint& g) {
+  for (int a = 0; a < 3; ++a) {
+    g.x[a] = a < P.dim ? xi[a] : 0.0;
+    for (int b = 0; b < 3; ++b) {
+      g.DF[a][b] = g.Finv[a][b] = (a == b) ? 1.0 : 0.0;
+      for (int k = 0; k < 3; ++k) g.dDF[k][a][b] = 0.0;
+    }
+  }
+  g.J = 1.0;
+  if (P.geom == 0) return;
+  const double al = kPi / 4.0, r = 1.0 + xi[0], t = al * xi[1];
+  const double c = std::cos(t), s = std::sin(t);
+  g.x[0] = r * c;
+  g.x[1] = r * s;
+  g.DF[0][0] = c;
+  g.DF[0][1] = -al * r * s;
+  g.DF[1][0] = s;
+  g.DF[1][1] = al * r * c;
+  g.J = g.DF[0][0] * g.DF[1][1] - g.DF[0][1] * g.DF[1][0];
+  g.Finv[0][0] = g.DF[1][1] / g.J;
+  g.Finv[0][1] = -g.DF[0][1] / g.J;
+  g.Finv[1][0] = -g.DF[1][0] / g.J;
+  g.Finv[1][1] = g.DF[0][0] / g.J;
+  // d/dxi_0 = d/dr
+  g.dDF[0][0][1] = -al * s;
+  g.dDF[0][1][1] = al * c;
+  // d/dxi_1 = (pi/4) d/dtheta
+  g.dDF[1][0][0] = -al * s;
+  g.dDF[1][0][1] = -al * al * r * c;
+  g.dDF[1][1][0] = al * c;
+  g.dDF[1][1][1] = -al * al * r * s;
+}
+
+// Piola transform of a velocity basis function (the inverse of the pullback iota_u of
+// Sec. 3.2): Phi = DF Phihat / J.  With M = DF / J, the parametric derivatives are
+// dPhi_a/dxi_k = sum_b (dM_k[a][b] Phihat_b + M[a][b] dPhihat_b/dxi_k), where
+// dM_k = dDF[k]/J - DF (dJ/dxi_k)/J^2 and dJ/dxi_k = J trace(Finv dDF[k]); the physical
+// gradient is dPhi_a/dx_m = sum_k (dPhi_a/dxi_k) Finv[k][m].  On entry v holds Phihat and
+// its parametric gradient; on exit the physical value and gradient.
+void piola(const Problem& P, const GeoPoint& g, VelEval& v) {
+  if (P.geom == 0) return;
+  const int d = P.dim;
+  double M[3][3] = {{0}}, dM[3][3][3] = {{{0}}};
+  for (int a = 0; a < d; ++a)
+    for (int b = 0; b < d; ++b) M[a][b] = g.DF[a][b] / g.J;
+  for (int k = 0; k < d; ++k) {
+    double tr = 0.0;
+    for (int a = 0; a < d; ++a)
+      for (int b = 0; b < d; ++b) tr += g.Finv[a][b] * g.dDF[k][b][a];
+    const double dJ = g.J * tr;
+    for (int a = 0; a < d; ++a)
+      for (int b = 0; b < d; ++b) dM[k][a][b] = g.dDF[k][a][b] / g.J - g.DF[a][b] * dJ / (g.J * g.J);
+  }
+  double val[3] = {0, 0, 0}, dxi[3][3] = {{0}};
+  for (int a = 0; a < d; ++a)
+    for (int b = 0; b < d; ++b) {
+      val[a] += M[a][b] * v.val[b];
+      for (int k = 0; k < d; ++k) dxi[a][k] += dM[k][a][b] * v.val[b] + M[a][b] * v.grad[b][k];
+    }
+  for (int a = 0; a < 3; ++a) {
+    v.val[a] = val[a];
+    for (int m = 0; m < 3; ++m) {
+      double s = 0.0;
+      if (a < d && m < d)
+        for (int k = 0; k < d; ++k) s += dxi[a][k] * g.Finv[k][m];
+      v.grad[a][m] = s;
+    }
+  }
+}
+
+// Gauss points per direction of the matrices: k'+2 is exact on the identity map; the
+// mapped integrands are rational, one more point is taken there.
+int matrix_points(const Problem& P) { return P.kp + 2 + (P.geom ? 1 : 0); }
+// Loads and error norms: k'+4 points, k'+5 on the mapped domain.
+int load_points(const Problem& P) { return P.kp + 4 + (P.geom ? 1 : 0); }
+
+// ---------------------------------------------------------------------------
 // Assembly (Sec. 4): for every element, Gauss quadrature with k'+2 points per
 // direction (exact for these polynomial integrands on the identity map):
 //   A_ij  += 2 nu (sym grad Phi_j : sym grad Phi_i)
@@ -454,7 +553,7 @@ void build_tabs_for_element(const Problem& P, const int* e, const std::vector<do
 }
 
 void assemble(Problem& P) {
-  int nq = P.kp + 2;
+  int nq = matrix_points(P);
   std::vector<double> xq, wq;
   gauss_legendre01(nq, xq, wq);
   P.diagQ.assign(P.np_dofs, 0.0);
@@ -476,10 +575,19 @@ void assemble(Problem& P) {
         for (q[2] = 0; q[2] < nq2; ++q[2])
           for (q[1] = 0; q[1] < nq; ++q[1])
             for (q[0] = 0; q[0] < nq; ++q[0]) {
-              double wt = vol;
-              for (int dir = 0; dir < P.dim; ++dir) wt *= wq[q[dir]];
+              double wt = vol, xi[3] = {0, 0, 0};
+              for (int dir = 0; dir < P.dim; ++dir) {
+                wt *= wq[q[dir]];
+                xi[dir] = (e[dir] + xq[q[dir]]) * P.h;
+              }
               tensor_eval_velocity(P, e, tabs, q, ve);
               tensor_eval_pressure(P, e, tabs, q, pe);
+              // physical quantities: dx = J dxi, Piola velocities, pressures phihat / J
+              GeoPoint geo;
+              geometry(P, xi, geo);
+              wt *= geo.J;
+              for (VelEval& v : ve) piola(P, geo, v);
+              for (PreEval& pp : pe) pp.val /= geo.J;
               std::vector<std::array<std::array<double, 3>, 3>> eps(ve.size());
               for (size_t i = 0; i < ve.size(); ++i) {
                 double t[3][3];
@@ -511,8 +619,8 @@ void assemble(Problem& P) {
           for (int side = 0; side < 2; ++side) {
             if (side == 0 && e[fdir] != 0) continue;
             if (side == 1 && e[fdir] != P.N - 1) continue;
-            double nrm[3] = {0, 0, 0};
-            nrm[fdir] = side == 0 ? -1.0 : 1.0;
+            double nhat[3] = {0, 0, 0};  // parametric outward normal
+            nhat[fdir] = side == 0 ? -1.0 : 1.0;
             // Face points: tensor Gauss rule in the tangential directions, fixed coordinate
             // 0 or 1 in direction fdir.
             Tab1D ftabs[3][2];
@@ -531,17 +639,37 @@ void assemble(Problem& P) {
             double farea = 1.0;
             for (int dir = 0; dir < P.dim; ++dir)
               if (dir != fdir) farea *= P.h;
-            double hF = P.h;
             int nqd[3] = {1, 1, 1};
             for (int dir = 0; dir < P.dim; ++dir) nqd[dir] = (dir == fdir) ? 1 : nq;
             int qf[3] = {0, 0, 0};
             for (qf[2] = 0; qf[2] < nqd[2]; ++qf[2])
               for (qf[1] = 0; qf[1] < nqd[1]; ++qf[1])
                 for (qf[0] = 0; qf[0] < nqd[0]; ++qf[0]) {
-                  double wt = farea;
-                  for (int dir = 0; dir < P.dim; ++dir)
+                  double wt = farea, xi[3] = {0, 0, 0};
+                  for (int dir = 0; dir < P.dim; ++dir) {
                     if (dir != fdir) wt *= wq[qf[dir]];
+                    xi[dir] = dir == fdir ? (side == 0 ? 0.0 : 1.0) : (e[dir] + xq[qf[dir]]) * P.h;
+                  }
                   tensor_eval_velocity(P, e, ftabs, qf, ve);
+                  // physical outward normal n = Finv^T nhat / |Finv^T nhat|, surface measure
+                  // dS = J |Finv^T nhat| dS_hat, and h_F = 1 / (N |Finv n|)
+                  GeoPoint geo;
+                  geometry(P, xi, geo);
+                  double m[3] = {0, 0, 0}, mn = 0.0;
+                  for (int a = 0; a < 3; ++a) {
+                    for (int b = 0; b < 3; ++b) m[a] += geo.Finv[b][a] * nhat[b];
+                    mn += m[a] * m[a];
+                  }
+                  mn = std::sqrt(mn);
+                  double nrm[3], fn[3] = {0, 0, 0}, fnn = 0.0;
+                  for (int a = 0; a < 3; ++a) nrm[a] = m[a] / mn;
+                  for (int a = 0; a < 3; ++a) {
+                    for (int b = 0; b < 3; ++b) fn[a] += geo.Finv[a][b] * nrm[b];
+                    fnn += fn[a] * fn[a];
+                  }
+                  const double hF = 1.0 / (P.N * std::sqrt(fnn));
+                  wt *= geo.J * mn;
+                  for (VelEval& v : ve) piola(P, geo, v);
                   std::vector<std::array<double, 3>> tr(ve.size());  // (sym grad Phi) n
                   for (size_t i = 0; i < ve.size(); ++i) {
                     double t[3][3];
@@ -578,7 +706,9 @@ void assemble(Problem& P) {
 // Problem 2: the paper's square-domain solution (Sec. 6.2) with the sign of the
 // second velocity component chosen so that the field is divergence free.
 // Problem 3: a pure gradient f = grad(phi), phi = sin(2 pi x) cos(pi y) [cos(pi z)].
+// Problem 4 (1/8 annulus): see AnnulusPsi below.
 // Optional sinusoid modes are added: f_d += a_{d,m} sin(pi k_m . x + ph_{d,m}).
+// Every forcing is evaluated at the physical point x = F(xi).
 // ---------------------------------------------------------------------------
 struct Phi1 {  // phi(t) = t^2 (1-t)^2 and derivatives
   static double f0(double t) { return t * t * (1 - t) * (1 - t); }
@@ -586,6 +716,69 @@ struct Phi1 {  // phi(t) = t^2 (1-t)^2 and derivatives
   static double f2(double t) { return 2 - 12 * t + 12 * t * t; }
   static double f3(double t) { return -12 + 24 * t; }
 };
+
+// Bivariate polynomials, sum c[i][j] x^i y^j (degree < 16), for the annulus solution.
+struct Poly2 {
+  double c[16][16] = {{0}};
+};
+Poly2 poly_mul(const Poly2& a, const Poly2& b) {
+  Poly2 r;
+  for (int i = 0; i < 16; ++i)
+    for (int j = 0; j < 16; ++j)
+      if (a.c[i][j] != 0.0)
+        for (int k = 0; i + k < 16; ++k)
+          for (int l = 0; j + l < 16; ++l) r.c[i + k][j + l] += a.c[i][j] * b.c[k][l];
+  return r;
+}
+Poly2 poly_dx(const Poly2& a) {
+  Poly2 r;
+  for (int i = 1; i < 16; ++i)
+    for (int j = 0; j < 16; ++j) r.c[i - 1][j] = i * a.c[i][j];
+  return r;
+}
+Poly2 poly_dy(const Poly2& a) {
+  Poly2 r;
+  for (int i = 0; i < 16; ++i)
+    for (int j = 1; j < 16; ++j) r.c[i][j - 1] = j * a.c[i][j];
+  return r;
+}
+double poly_at(const Poly2& a, double x, double y) {
+  double s = 0.0, xp = 1.0;
+  for (int i = 0; i < 16; ++i, xp *= x) {
+    double yp = 1.0;
+    for (int j = 0; j < 16; ++j, yp *= y) s += a.c[i][j] * xp * yp;
+  }
+  return s;
+}
+
+// Problem 4, on the 1/8 annulus: u = curl psi = (psi_y, -psi_x) with psi = a^2 b^2,
+// a = (x^2 + y^2 - 1)(x^2 + y^2 - 4) (zero on the arcs r = 1, 2), b = y (y - x) (zero on
+// the sides theta = 0, pi/4): psi and grad psi vanish on the boundary, so u = 0 there and
+// div u = 0; p = x y^2 (its mean is removed by the error routine).  The derivatives of psi
+// up to third order are tabulated once.
+struct AnnulusPsi {
+  Poly2 d[4][4];  // d[i][j] = d^{i+j} psi / dx^i dy^j, i + j <= 3
+  AnnulusPsi() {
+    Poly2 r2m1, r2m4, b;
+    r2m1.c[2][0] = 1; r2m1.c[0][2] = 1; r2m1.c[0][0] = -1;
+    r2m4.c[2][0] = 1; r2m4.c[0][2] = 1; r2m4.c[0][0] = -4;
+    b.c[0][2] = 1;    // y^2
+    b.c[1][1] = -1;   // - x y
+    const Poly2 a = poly_mul(r2m1, r2m4);
+    const Poly2 ab = poly_mul(a, b);
+    d[0][0] = poly_mul(ab, ab);
+    for (int i = 0; i <= 3; ++i)
+      for (int j = 0; i + j <= 3; ++j) {
+        if (i == 0 && j == 0) continue;
+        d[i][j] = j > 0 ? poly_dy(d[i][j - 1]) : poly_dx(d[i - 1][j]);
+      }
+  }
+  double at(int i, int j, const double* x) const { return poly_at(d[i][j], x[0], x[1]); }
+};
+const AnnulusPsi& annulus_psi() {
+  static const AnnulusPsi A;
+  return A;
+}
 
 // Exact fields for error norms: velocity, velocity gradient, pressure.
 void exact_solution(int problem, int dim, const double* x, double* u, double g[3][3], double* p) {
@@ -654,6 +847,15 @@ void exact_solution(int problem, int dim, const double* x, double* u, double g[3
     double G = 456 + xx * xx * (228 - 5 * q) + 2 * xx * (-228 + q) + 2 * xx * xx * xx * (-36 + q) +
                xx * xx * xx * xx * (12 + q);
     *p = -424 + 156 * std::exp(1.0) + q * (-456 + ex * G);
+  } else if (problem == 4 && dim == 2) {
+    const AnnulusPsi& A = annulus_psi();
+    u[0] = A.at(0, 1, x);
+    u[1] = -A.at(1, 0, x);
+    g[0][0] = A.at(1, 1, x);
+    g[0][1] = A.at(0, 2, x);
+    g[1][0] = -A.at(2, 0, x);
+    g[1][1] = -A.at(1, 1, x);
+    *p = x[0] * x[1] * x[1];
   } else if (problem == 3) {
     // u = 0, p = phi (up to its mean)
     double v = std::sin(2 * kPi * x[0]) * std::cos(kPi * x[1]);
@@ -721,6 +923,13 @@ void forcing(int problem, int dim, double nu, const double* x, double* f) {
     double py = dq * (-456 + ex * G) + q * ex * Gq * dq;
     f[0] = -nu * lap0 + px;
     f[1] = -nu * lap1 + py;
+  } else if (problem == 4 && dim == 2) {
+    // f = -nu Lap u + grad p, Lap u = (psi_yxx + psi_yyy, -(psi_xxx + psi_xyy))
+    const AnnulusPsi& A = annulus_psi();
+    const double lap0 = A.at(2, 1, x) + A.at(0, 3, x);
+    const double lap1 = -(A.at(3, 0, x) + A.at(1, 2, x));
+    f[0] = -nu * lap0 + x[1] * x[1];
+    f[1] = -nu * lap1 + 2.0 * x[0] * x[1];
   } else if (problem == 3) {
     double a = std::sin(2 * kPi * x[0]), da = 2 * kPi * std::cos(2 * kPi * x[0]);
     double b = std::cos(kPi * x[1]), db = -kPi * std::sin(kPi * x[1]);
@@ -739,7 +948,7 @@ void forcing(int problem, int dim, double nu, const double* x, double* f) {
 void load_vector(const Problem& P, int problem, int nmodes, const double* amp, const int32_t* wave,
                  const double* phase, double* fout) {
   std::fill(fout, fout + P.nu_dofs, 0.0);
-  int nq = P.kp + 4;
+  int nq = load_points(P);
   std::vector<double> xq, wq;
   gauss_legendre01(nq, xq, wq);
   double vol = 1.0;
@@ -757,11 +966,15 @@ void load_vector(const Problem& P, int problem, int nmodes, const double* amp, c
         for (q[2] = 0; q[2] < nq2; ++q[2])
           for (q[1] = 0; q[1] < nq; ++q[1])
             for (q[0] = 0; q[0] < nq; ++q[0]) {
-              double wt = vol, x[3] = {0, 0, 0};
+              double wt = vol, xi[3] = {0, 0, 0};
               for (int dir = 0; dir < P.dim; ++dir) {
                 wt *= wq[q[dir]];
-                x[dir] = (e[dir] + xq[q[dir]]) * P.h;
+                xi[dir] = (e[dir] + xq[q[dir]]) * P.h;
               }
+              GeoPoint geo;
+              geometry(P, xi, geo);
+              wt *= geo.J;
+              const double* x = geo.x;  // forcing at the physical point
               double f[3];
               forcing(problem, P.dim, P.nu, x, f);
               for (int d = 0; d < P.dim; ++d)
@@ -771,7 +984,8 @@ void load_vector(const Problem& P, int problem, int nmodes, const double* amp, c
                   f[d] += amp[d * nmodes + m] * std::sin(arg);
                 }
               tensor_eval_velocity(P, e, tabs, q, ve);
-              for (const VelEval& v : ve) {
+              for (VelEval& v : ve) {
+                piola(P, geo, v);
                 double s = 0;
                 for (int a = 0; a < P.dim; ++a) s += f[a] * v.val[a];
                 fout[v.g] += wt * s;
@@ -1261,14 +1475,16 @@ MinresOut minres(const Problem& P, const double* b, double* x, double tol, int m
 }
 
 // Zero-mean pressure (Sec. 3.2; imposed by filtering after the solve, Sec. 6.4): p <- p - (w.p)/(w.1).
+// Zero-mean pressure (the L2 mean, Sec. 3.2): p <- p - (w.p)/(w.kappa) kappa, kappa the
+// coefficients of the constant function (all ones on the identity map).
 void project_pressure(const Problem& P, double* p) {
   double wp = 0, w1 = 0;
   for (int64_t k = 0; k < P.np_dofs; ++k) {
     wp += P.wvec[k] * p[k];
-    w1 += P.wvec[k];
+    w1 += P.wvec[k] * P.kappa[k];
   }
   double m = wp / w1;
-  for (int64_t k = 0; k < P.np_dofs; ++k) p[k] -= m;
+  for (int64_t k = 0; k < P.np_dofs; ++k) p[k] -= m * P.kappa[k];
 }
 
 // Residual norms of the original system: ||b - Acal x||_2 / ||b||_2 and the M^{-1}-norm
@@ -1325,9 +1541,12 @@ extern "C" {
 // [0] iters [1] inner_total [2] status [3] ic_shift_steps [4] relres_est (|eta|/gamma1)
 // [5] relres_true_2 [6] relres_true_Minv
 // flags bit 0: build the sparsity patterns only (no quadrature), for size checks.
+// flags: bit 0 pattern only (no assembly); bit 1 the 1/8-annulus geometry (2D).
 void* or_setup(int N, int kp, int dim, double nu, double cpen, int flags) {
   if (N < 1 || kp < 1 || (dim != 2 && dim != 3) || !(nu > 0)) return nullptr;
+  if ((flags & 2) && dim != 2) return nullptr;
   Problem* P = new Problem();
+  P->geom = (flags & 2) ? 1 : 0;
   P->N = N;
   P->kp = kp;
   P->dim = dim;
@@ -1352,7 +1571,11 @@ void* or_setup(int N, int kp, int dim, double nu, double cpen, int flags) {
   P->np_dofs = 1;
   for (int dir = 0; dir < dim; ++dir) P->np_dofs *= P->sp_lo.nfun;
   build_patterns(*P);
-  if (!(flags & 1)) assemble(*P);
+  P->kappa.assign(P->np_dofs, 1.0);
+  if (!(flags & 1)) {
+    assemble(*P);
+    if (P->geom != 0) pcg_Q(*P, PCQ_JPCG, P->wvec.data(), P->kappa.data(), 1e-14, 100000);
+  }
   return P;
 }
 
@@ -1434,7 +1657,7 @@ void or_load(void* h, int problem, int nrhs, int nmodes, const double* amp, cons
 // unknown kind.
 int or_load_cavity(void* h, int kind, double* f) {
   Problem* P = static_cast<Problem*>(h);
-  if (P->dim != 2 || kind < 0 || kind > 1) return -1;
+  if (P->dim != 2 || P->geom != 0 || kind < 0 || kind > 1) return -1;  // the cavity is the unit square
   cavity_load(*P, kind, f);
   return 0;
 }
@@ -1499,10 +1722,11 @@ int or_adjoint(void* h, const double* g_u, const double* g_p, double* lam_u, dou
   int64_t nu = P->nu_dofs, np = P->np_dofs, n = nu + np;
   std::vector<double> b(n, 0.0), x(n);
   std::memcpy(b.data(), g_u, nu * sizeof(double));
+  // P^T g_p for the projection P = I - kappa w^T / (w.kappa)
   double s1 = 0, w1 = 0;
   for (int64_t k = 0; k < np; ++k) {
-    s1 += g_p[k];
-    w1 += P->wvec[k];
+    s1 += P->kappa[k] * g_p[k];
+    w1 += P->wvec[k] * P->kappa[k];
   }
   for (int64_t k = 0; k < np; ++k) b[nu + k] = g_p[k] - P->wvec[k] * s1 / w1;
   int rc = or_minres(h, b.data(), x.data(), tol, maxit, pcA, pcQ, inner_tol, 0, info, nullptr, nullptr);
@@ -1520,7 +1744,8 @@ double or_dnu_dot(void* h, const double* lam_u, const double* u) {
   return dot(lam_u, au.data(), P->nu_dofs) / P->nu;
 }
 
-// Discrete solution evaluation at physical points: velocity, its divergence, pressure.
+// Discrete solution evaluation at parametric points (the physical points F(xi); on the
+// identity map the two coincide): velocity, its divergence, pressure.
 // pts [npts][dim]; out [npts][dim + 2] = (u_1..u_dim, div u, p).
 void or_eval(void* h, const double* u, const double* p, int64_t npts, const double* pts, double* out) {
   Problem* P = static_cast<Problem*>(h);
@@ -1541,6 +1766,10 @@ void or_eval(void* h, const double* u, const double* p, int64_t npts, const doub
     std::vector<PreEval> pe;
     tensor_eval_velocity(*P, e, tabs, q, ve);
     tensor_eval_pressure(*P, e, tabs, q, pe);
+    GeoPoint geo;
+    geometry(*P, pts + t * dim, geo);
+    for (VelEval& v : ve) piola(*P, geo, v);
+    for (PreEval& pp : pe) pp.val /= geo.J;
     double* o = out + t * (dim + 2);
     for (int k = 0; k < dim + 2; ++k) o[k] = 0;
     for (const VelEval& v : ve) {
@@ -1556,7 +1785,7 @@ void or_eval(void* h, const double* u, const double* p, int64_t npts, const doub
 void or_errors(void* h, int problem, const double* u, const double* p, double* out) {
   Problem* P = static_cast<Problem*>(h);
   int dim = P->dim;
-  int nq = P->kp + 4;
+  int nq = load_points(*P);
   std::vector<double> xq, wq;
   gauss_legendre01(nq, xq, wq);
   double vol = 1.0;
@@ -1579,11 +1808,15 @@ void or_errors(void* h, int problem, const double* u, const double* p, double* o
           for (q[2] = 0; q[2] < nq2; ++q[2])
             for (q[1] = 0; q[1] < nq; ++q[1])
               for (q[0] = 0; q[0] < nq; ++q[0]) {
-                double wt = vol, x[3] = {0, 0, 0};
+                double wt = vol, xi[3] = {0, 0, 0};
                 for (int dir = 0; dir < dim; ++dir) {
                   wt *= wq[q[dir]];
-                  x[dir] = (e[dir] + xq[q[dir]]) * P->h;
+                  xi[dir] = (e[dir] + xq[q[dir]]) * P->h;
                 }
+                GeoPoint geo;
+                geometry(*P, xi, geo);
+                wt *= geo.J;
+                const double* x = geo.x;
                 double ue[3], ge[3][3], pex;
                 exact_solution(problem, dim, x, ue, ge, &pex);
                 if (pass == 0) {
@@ -1592,6 +1825,8 @@ void or_errors(void* h, int problem, const double* u, const double* p, double* o
                 }
                 tensor_eval_velocity(*P, e, tabs, q, ve);
                 tensor_eval_pressure(*P, e, tabs, q, pe);
+                for (VelEval& v : ve) piola(*P, geo, v);
+                for (PreEval& pp : pe) pp.val /= geo.J;
                 double uh[3] = {0, 0, 0}, gh[3][3] = {{0}}, ph = 0;
                 for (const VelEval& v : ve)
                   for (int a = 0; a < 3; ++a) {
@@ -1607,7 +1842,9 @@ void or_errors(void* h, int problem, const double* u, const double* p, double* o
               }
         }
     if (pass == 0) {
-      pmean = pm;
+      double area = 0.0;  // |Omega| = w . kappa, the integral of the constant function
+      for (int64_t k = 0; k < P->np_dofs; ++k) area += P->wvec[k] * P->kappa[k];
+      pmean = pm / area;
     } else {
       out[0] = std::sqrt(h1);
       out[1] = std::sqrt(l2u);
