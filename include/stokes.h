@@ -131,6 +131,24 @@ typedef struct {
  * nu > 0.  On success *out owns the problem; on failure *out = NULL. */
 int stokes_setup(int n, int p, int dim, double nu, stokes_problem** out);
 
+/* The same on a mapped domain (Sec. 3.2): the discrete spaces are pushed forward from the
+ * parametric unit square by the geometry map F, velocities by the Piola transform
+ * Phi = DF Phihat / det DF (divergence and normal component preserving), pressures by the
+ * integral-preserving transform phi = phihat / det DF.
+ *   STOKES_GEOMETRY_SQUARE:  the identity map (stokes_setup).
+ *   STOKES_GEOMETRY_ANNULUS: one eighth of the annulus 1 < r < 2, 0 < theta < pi/4 (the
+ *     domain of Sec. 6.3) by the polar map x = r cos(theta), y = r sin(theta),
+ *     r = 1 + xi_0, theta = (pi/4) xi_1; 2D only.  Nitsche face terms use the physical
+ *     outward normal and h_F = 1/(N |DF^{-1} n|), the element length normal to the face;
+ *     matrices use k'+3 Gauss points per direction, loads k'+5.  The zero-mean pressure
+ *     subtracts multiples of the constant function, whose coefficients are Q^{-1} w here.
+ *     stokes_load evaluates the forcing at the physical points; stokes_load_cavity
+ *     returns STOKES_EINVAL.
+ * Other values, or the annulus with dim = 3: STOKES_EINVAL. */
+#define STOKES_GEOMETRY_SQUARE 0
+#define STOKES_GEOMETRY_ANNULUS 1
+int stokes_setup_geometry(int n, int p, int dim, double nu, int geometry, stokes_problem** out);
+
 /* Sizes: n_u velocity unknowns, n_p pressure unknowns. */
 int stokes_sizes(const stokes_problem* pb, int64_t* n_u, int64_t* n_p);
 
@@ -222,7 +240,8 @@ int stokes_solve_precision(stokes_problem* pb, const double* f, double* u, doubl
                            int precond, int precision, stokes_info* info);
 
 /* Adjoint solve for a loss L(u, p) of the zero-mean solution: with g = [g_u; g_p]
- * [n_u + n_p] (dL/du, dL/dp), solves Acal lambda = [g_u; g_p - w (1.g_p)/(w.1)]
+ * [n_u + n_p] (dL/du, dL/dp), solves Acal lambda = [g_u; g_p - w (kappa.g_p)/(w.kappa)]
+ * (kappa the constant function's pressure coefficients, all ones on the unit square)
  * (Acal is symmetric, same MINRES and preconditioner); lambda [n_u + n_p] out with a
  * zero-mean pressure part.  Then dL/df = lambda_u and dL/dnu = -lambda_u^T (A/nu) u. */
 int stokes_solve_adjoint(stokes_problem* pb, const double* g, double* lambda, double tol, int precond,

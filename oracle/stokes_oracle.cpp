@@ -1574,7 +1574,15 @@ void* or_setup(int N, int kp, int dim, double nu, double cpen, int flags) {
   P->kappa.assign(P->np_dofs, 1.0);
   if (!(flags & 1)) {
     assemble(*P);
-    if (P->geom != 0) pcg_Q(*P, PCQ_JPCG, P->wvec.data(), P->kappa.data(), 1e-14, 100000);
+    // kappa = Q^{-1} w by CG preconditioned with IC(0) of Q (Q's Cholesky factor for the
+    // polar map, where 1/J depends on xi_0 alone and Q keeps its Kronecker structure)
+    if (P->geom != 0) {
+      if (ic0_Q(*P) != 0) {
+        delete P;
+        return nullptr;
+      }
+      pcg_Q(*P, PCQ_ICPCG, P->wvec.data(), P->kappa.data(), 1e-15, 50);
+    }
   }
   return P;
 }

@@ -18,10 +18,11 @@ STOKES_EBREAKDOWN = -4
 PC_IC0, PC_ICPCG, PC_JACOBI, PC_IDEAL, PC_JPCG, PC_PCGAQ, PC_IDEAL_A, PC_ICPCG_AQ = 0, 1, 2, 3, 4, 5, 6, 7
 FP64, MIXED = 0, 1
 CAVITY_LID, CAVITY_VERIFY = 0, 1
+GEOMETRY_SQUARE, GEOMETRY_ANNULUS = 0, 1
 
 # every exported entry point declared in include/stokes.h
 EXPORTS = (
-    "stokes_setup", "stokes_sizes", "stokes_set_stream", "stokes_set_nu", "stokes_set_inner_tol",
+    "stokes_setup", "stokes_setup_geometry", "stokes_sizes", "stokes_set_stream", "stokes_set_nu", "stokes_set_inner_tol",
     "stokes_set_refine_tol",
     "stokes_set_maxit", "stokes_set_restarts", "stokes_load", "stokes_load_cavity", "stokes_solve", "stokes_solve_batched", "stokes_solve_precision",
     "stokes_solve_noalloc",
@@ -62,6 +63,7 @@ def lib():
     P = ctypes.POINTER
     sig = {
         "stokes_setup": (i32, [i32, i32, i32, dbl, P(vp)]),
+        "stokes_setup_geometry": (i32, [i32, i32, i32, dbl, i32, P(vp)]),
         "stokes_sizes": (i32, [vp, P(i64), P(i64)]),
         "stokes_set_stream": (i32, [vp, vp]),
         "stokes_set_nu": (i32, [vp, dbl]),

@@ -197,7 +197,10 @@ struct stokes_problem {
   double* val = nullptr;
   float* val32 = nullptr;
   double *diagQ = nullptr, *w = nullptr, *diagA = nullptr;
-  double w1 = 1.0;
+  // coefficients of the constant function in the pressure space: null on the identity map
+  // (all ones); Q^{-1} w on a mapped domain (phi = phihat / J)
+  double* kappa = nullptr;
+  double w1 = 1.0;  // w . kappa = |Omega|
   int32_t *Lrowptr = nullptr, *Lcol = nullptr, *level_rows = nullptr;
   int64_t* Lsrc = nullptr;
   double* Lval = nullptr;
@@ -516,7 +519,7 @@ int upload_schedule(stokes_problem* pb, const TrsvSchedHost& H, TrsvSchedDev& D,
 int fit_rmax(const stokes_problem* pb, int nslots, bool fp32) {
   const int rs[3] = {16, 8, 1};
   for (int r : rs)
-    if (trsv_shmem_bytes(nslots, fp32, r) <= pb->lds_max) return r;
+    if (trsv_shmem_bytes(nslots, fp32, r) + trsv_static_shmem(r) <= pb->lds_max) return r;
   return 0;
 }
 
@@ -590,8 +593,11 @@ int make_schedule(stokes_problem* pb, FactorSched& fs, bool fp32, SchedPair** ou
     auto resident = [&](int r, bool f32) {
       if (r == 0) return 0;
       const size_t sh = trsv_shmem_bytes(nsl, f32, r);
-      const int per_cu = int(std::max<size_t>(1, std::min<size_t>(8, pb->lds_per_cu / std::max<size_t>(sh, 1))));
-      return ngroups <= per_cu * pb->num_cu ? r : 0;
+      int per_cu = int(std::max<size_t>(1, std::min<size_t>(8, pb->lds_per_cu / std::max<size_t>(sh, 1))));
+      // the batched kernels' blocks (five wavefronts of up to 256 registers) fit once per CU
+      if (r >= 8) per_cu = 1;
+      if (ngroups <= per_cu * pb->num_cu) return r;
+      return (r >= 8 && ngroups <= pb->num_cu * 8) ? 1 : 0;  // then single columns only
     };
     sp->rmax64 = resident(sp->rmax64, false);
     sp->rmax32 = resident(sp->rmax32, true);
@@ -899,7 +905,7 @@ enum { PQ_CG_JACOBI = 0, PQ_CG_IDEAL = 1, PQ_CG_IC0 = 2 };
 
 template <typename T>
 int precond_pressure(stokes_problem* pb, Work& W, int kind, const T* vin_p, T* zout_p, double* dot_out,
-                     const int* skip, const MinresState* outer_st) {
+                     const int* skip, const MinresState* outer_st, double rtol_set = 0.0, int maxit_set = 0) {
   const int R = W.R;
   const bool fp32 = W.fp32;
   hipStream_t st = pb->stream;
@@ -922,8 +928,8 @@ int precond_pressure(stokes_problem* pb, Work& W, int kind, const T* vin_p, T* z
   };
   CK(pcg_init<T>(R, n_p, vin_p, (T*)W.qr, zout_p, s, skip, st));
   CK(inner_precond(s.rho, skip));
-  const double rtol_in = kind == PQ_CG_IDEAL ? kIdealTol : pb->inner_tol;
-  const int maxit_in = kind == PQ_CG_IDEAL ? kIdealMaxit : pb->maxit_inner;
+  const double rtol_in = rtol_set > 0.0 ? rtol_set : (kind == PQ_CG_IDEAL ? kIdealTol : pb->inner_tol);
+  const int maxit_in = maxit_set > 0 ? maxit_set : (kind == PQ_CG_IDEAL ? kIdealMaxit : pb->maxit_inner);
   int& expect = pb->pcgq_expect[kind];
   CK(pcg_init2<T>(R, n_p, (const T*)W.qz, (T*)W.qp, s, rtol_in, maxit_in, skip, outer_st, st));
   int ip = 0;
@@ -1072,7 +1078,7 @@ int project_pressure(stokes_problem* pb, int R, double* x) {
   R_SWITCH(R, hipLaunchKernelGGL((k_pdot<RR>), dim3(vec_blocks(n_p)), dim3(kVT), 0, pb->stream, n_p, n_u, pb->w, x,
                                  pb->partials, pb->counter, pb->scratch));
   CK(hipGetLastError());
-  CK(sub_mean<double>(R, n_u, n_u + n_p, x, pb->scratch, pb->w1, pb->stream));
+  CK(sub_mean<double>(R, n_u, n_u + n_p, x, pb->scratch, pb->w1, pb->kappa, pb->stream));
   return 0;
 }
 
@@ -1345,15 +1351,20 @@ int check_finite(stokes_problem* pb, int R, const double* interleaved, int64_t l
 // ===========================================================================
 extern "C" {
 
-static int stokes_setup_impl(int n, int p, int dim, double nu, stokes_problem* pb);
+static int stokes_setup_impl(int n, int p, int dim, double nu, int geometry, stokes_problem* pb);
 
 int stokes_setup(int n, int p, int dim, double nu, stokes_problem** out) {
+  return stokes_setup_geometry(n, p, dim, nu, STOKES_GEOMETRY_SQUARE, out);
+}
+
+int stokes_setup_geometry(int n, int p, int dim, double nu, int geometry, stokes_problem** out) {
   if (out == nullptr) return STOKES_EINVAL;
   *out = nullptr;
   if (n < 1 || n > 4096 || p < 1 || p > 3 || (dim != 2 && dim != 3) || !(nu > 0.0) || !std::isfinite(nu))
     return STOKES_EINVAL;
+  if (geometry != STOKES_GEOMETRY_SQUARE && !(geometry == STOKES_GEOMETRY_ANNULUS && dim == 2)) return STOKES_EINVAL;
   stokes_problem* pb = new stokes_problem();
-  const int rc = stokes_setup_impl(n, p, dim, nu, pb);
+  const int rc = stokes_setup_impl(n, p, dim, nu, geometry, pb);
   if (rc != 0) {
     if (!pb->err.empty()) fprintf(stderr, "stokes_setup: %s\n", pb->err.c_str());
     (void)hipStreamSynchronize(pb->stream);
@@ -1364,9 +1375,10 @@ int stokes_setup(int n, int p, int dim, double nu, stokes_problem** out) {
   return 0;
 }
 
-static int stokes_setup_impl(int n, int p, int dim, double nu, stokes_problem* pb) {
+static int stokes_setup_impl(int n, int p, int dim, double nu, int geometry, stokes_problem* pb) {
   auto t0 = std::chrono::steady_clock::now();
   pb->S = make_spaces(n, p, dim);
+  pb->S.geom = geometry;
   pb->nu = nu;
   pb->cpen = 5.0 * (p + 1);
   int dev = 0;
@@ -1482,6 +1494,28 @@ static int stokes_setup_impl(int n, int p, int dim, double nu, stokes_problem* p
     int rc = get_schedule(pb, 1, false, &sp);
     if (rc) return rc;
   }
+  // Mapped domain: the constant function's pressure coefficients kappa = Q^{-1} w and
+  // w1 = w . kappa = |Omega|.  kappa spans the kernel of B^T, so every right-hand side's
+  // pressure part is made orthogonal to it: it is solved to rounding, by CG preconditioned
+  // with IC(0) of Q (Q's Cholesky factor for the polar map, where 1/J depends on xi_0 alone
+  // and Q keeps its Kronecker structure; one or two iterations).
+  if (pb->S.geom != 0) {
+    int rc = ensure_pressure_ic0(pb);
+    if (rc) return rc;
+    Work* W = nullptr;
+    if ((rc = get_work(pb, 1, false, &W))) return rc;
+    pb->kappa = m.get<double>(pb->S.n_p);
+    if (m.err != hipSuccess) return fail_hip(pb, m.err, "allocation", __LINE__);
+    CK(hipMemsetAsync(pb->pcgQ.st, 0, sizeof(PcgState) * kRMax, st));
+    rc = precond_pressure<double>(pb, *W, PQ_CG_IC0, pb->w, pb->kappa, pb->scratch + 102, nullptr, nullptr, 1e-15, 50);
+    if (rc) return rc;
+    CK(scale(pb->S.n_p, pb->kappa, 1.0 / (2.0 * nu), st));
+    hipLaunchKernelGGL((k_pdot<1>), dim3(vec_blocks(pb->S.n_p)), dim3(kVT), 0, st, pb->S.n_p, int64_t(0), pb->w,
+                       pb->kappa, pb->partials, pb->counter, pb->scratch);
+    CK(hipGetLastError());
+    CK(hipMemcpyAsync(&pb->w1, pb->scratch, sizeof(double), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+  }
   // MINRES convergence flags (pinned host words) and the no-allocation solve's events and
   // workspace address, so that stokes_solve_noalloc allocates nothing later
   CK(hipHostMalloc((void**)&pb->hflag, 2 * sizeof(int), hipHostMallocDefault));
@@ -1589,6 +1623,7 @@ int stokes_load(stokes_problem* pb, const stokes_forcing* spec, int nrhs, double
 }
 
 int stokes_load_cavity(stokes_problem* pb, int kind, double* f_dev) {
+  if (pb && pb->S.geom != 0) return fail(pb, STOKES_EINVAL, "stokes_load_cavity: the cavity is the unit square");
   if (!pb || !f_dev) return fail(pb, STOKES_EINVAL, "bad arguments to stokes_load_cavity");
   if (pb->S.dim != 2) return fail(pb, STOKES_EINVAL, "stokes_load_cavity: 2D problems only");
   if (kind != STOKES_CAVITY_LID && kind != STOKES_CAVITY_VERIFY)
@@ -1732,8 +1767,8 @@ int stokes_solve_adjoint_batched(stokes_problem* pb, int nrhs, const double* G, 
     CK(hipMemcpy2DAsync((double*)W->b + c, sizeof(double) * R, G + size_t(c) * n, sizeof(double), sizeof(double), n,
                         hipMemcpyDeviceToDevice, st));
   if ((rc = check_finite(pb, R, (const double*)W->b, n))) return rc;
-  // P^T g_p = g_p - w (1 . g_p) / (w . 1)
-  R_SWITCH(R, hipLaunchKernelGGL((k_pdot<RR>), dim3(vec_blocks(n_p)), dim3(kVT), 0, st, n_p, n_u, nullptr,
+  // P^T g_p = g_p - w (kappa . g_p) / (w . kappa), kappa the constant's coefficients
+  R_SWITCH(R, hipLaunchKernelGGL((k_pdot<RR>), dim3(vec_blocks(n_p)), dim3(kVT), 0, st, n_p, n_u, pb->kappa,
                                  (const double*)W->b, pb->partials, pb->counter, pb->scratch);
            hipLaunchKernelGGL((k_sub_w<RR>), dim3(256), dim3(256), 0, st, n_u, n_p, (double*)W->b, pb->w, pb->scratch,
                               pb->w1));

@@ -127,6 +127,7 @@ __global__ void k_gauss_points(int nq, double* __restrict__ xq) {
 
 struct AsmArgs {
   int N, kp, dim, nq;
+  int geom;  // 0: identity map; 1: polar map of the 1/8 annulus (2D)
   double nu, cpen;
   int64_t n_u;
   int vcnt[3][3], vshift[3][3], vdeg[3][3];
@@ -138,6 +139,7 @@ struct AsmArgs {
   const double* tv_hi;
   const double* td_hi;
   const double* wq;
+  const double* xq;  // Gauss points on [0,1] of the rule
 };
 
 struct Fun {
@@ -210,8 +212,82 @@ __device__ __forceinline__ void eval_fun(const AsmArgs& a, const Fun& f, const i
   }
 }
 
+// ---------------------------------------------------------------------------
+// Mapped geometry (Sec. 3.2), 2D: the polar map of one eighth of the annulus 1 < r < 2,
+// 0 < theta < pi/4 (Sec. 6.3), x = r cos(theta), y = r sin(theta), r = 1 + xi_0,
+// theta = (pi/4) xi_1.  Velocities are Piola transforms Phi = DF Phihat / J, pressures
+// phihat / J.  Quadrature: k'+3 points per direction for the matrices, k'+5 for loads.
+// ---------------------------------------------------------------------------
+struct Geo {
+  double x[2];
+  double DF[2][2], Finv[2][2], J;
+  double dDF[2][2][2];  // dDF[k][a][b] = d DF[a][b] / d xi_k
+};
+
+__device__ void polar_point(double xi0, double xi1, Geo& g) {
+  const double al = 0.25 * kPiD, r = 1.0 + xi0, th = al * xi1;
+  const double c = cos(th), s = sin(th);
+  g.x[0] = r * c;
+  g.x[1] = r * s;
+  g.DF[0][0] = c;
+  g.DF[0][1] = -al * r * s;
+  g.DF[1][0] = s;
+  g.DF[1][1] = al * r * c;
+  g.J = al * r;
+  g.Finv[0][0] = c;
+  g.Finv[0][1] = s;
+  g.Finv[1][0] = -s / (al * r);
+  g.Finv[1][1] = c / (al * r);
+  // radial derivatives
+  g.dDF[0][0][0] = 0.0;
+  g.dDF[0][0][1] = -al * s;
+  g.dDF[0][1][0] = 0.0;
+  g.dDF[0][1][1] = al * c;
+  // angular derivatives (d/dxi_1 = (pi/4) d/dtheta)
+  g.dDF[1][0][0] = -al * s;
+  g.dDF[1][0][1] = -al * al * r * c;
+  g.dDF[1][1][0] = al * c;
+  g.dDF[1][1][1] = -al * al * r * s;
+}
+
+// Parametric coordinate of table point q of element e (Gauss point, or the element ends).
+__device__ __forceinline__ double table_xi(const AsmArgs& a, int e, int q) {
+  const double t = q < a.nq ? a.xq[q] : (q == a.nq ? 0.0 : 1.0);
+  return (e + t) / a.N;
+}
+
+// Physical value and gradient of the Piola transform of Phihat = B e_c (parametric value B,
+// parametric gradient G): Phi = B DF[:, c] / J; its parametric derivatives
+// d_k Phi_a = G_k DF[a][c] / J + B d_k(DF[a][c] / J) with d_k J = J trace(Finv dDF[k]),
+// then grad_x Phi_a = sum_k d_k Phi_a Finv[k][m].
+__device__ void piola2(const Geo& g, int c, double B, const double* G, double* val, double grad[2][2]) {
+  double dJ[2];
+  for (int k = 0; k < 2; ++k) {
+    double tr = 0.0;
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) tr += g.Finv[a][b] * g.dDF[k][b][a];
+    dJ[k] = g.J * tr;
+  }
+  double dxi[2][2];
+  for (int a = 0; a < 2; ++a) {
+    val[a] = B * g.DF[a][c] / g.J;
+    for (int k = 0; k < 2; ++k)
+      dxi[a][k] = G[k] * g.DF[a][c] / g.J + B * (g.dDF[k][a][c] / g.J - g.DF[a][c] * dJ[k] / (g.J * g.J));
+  }
+  for (int a = 0; a < 2; ++a)
+    for (int m = 0; m < 2; ++m) grad[a][m] = dxi[a][0] * g.Finv[0][m] + dxi[a][1] * g.Finv[1][m];
+}
+
+__device__ __forceinline__ void sym2(const double G[2][2], double E[2][2]) {
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) E[a][b] = 0.5 * (G[a][b] + G[b][a]);
+}
+
+__device__ double entry_value_mapped(const AsmArgs& a, int64_t gi, int64_t gj);
+
 // Value of one saddle-matrix entry (row DOF gi, column DOF gj).
 __device__ double entry_value(const AsmArgs& a, int64_t gi, int64_t gj) {
+  if (a.geom != 0) return entry_value_mapped(a, gi, gj);
   Fun fi, fj;
   decode_dof(a, gi, fi);
   decode_dof(a, gj, fj);
@@ -299,6 +375,94 @@ __device__ double entry_value(const AsmArgs& a, int64_t gi, int64_t gj) {
   return sum;
 }
 
+// The same on the mapped domain (2D): the volume integrands in physical form with dx =
+// J dxi; B_kj = -int phi_k div Phi_j dx = -int phihat_k div Phi_j dxi (phi = phihat / J);
+// boundary faces with the physical outward normal n = Finv^T nhat / |Finv^T nhat|, surface
+// measure J |Finv^T nhat| dshat and h_F = 1 / (N |Finv n|).
+__device__ double entry_value_mapped(const AsmArgs& a, int64_t gi, int64_t gj) {
+  Fun fi, fj;
+  decode_dof(a, gi, fi);
+  decode_dof(a, gj, fj);
+  int lo[3], hi[3];
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = max(fi.elo[d], fj.elo[d]);
+    hi[d] = min(fi.ehi[d], fj.ehi[d]);
+  }
+  const double h = 1.0 / a.N;
+  const int nq = a.nq;
+  const bool vel_i = fi.comp >= 0, vel_j = fj.comp >= 0;
+  double sum = 0.0;
+  int e[3] = {0, 0, 0}, q[3] = {0, 0, 0};
+  for (e[1] = lo[1]; e[1] <= hi[1]; ++e[1])
+    for (e[0] = lo[0]; e[0] <= hi[0]; ++e[0])
+      for (q[1] = 0; q[1] < nq; ++q[1])
+        for (q[0] = 0; q[0] < nq; ++q[0]) {
+          const double wt = h * h * a.wq[q[0]] * a.wq[q[1]];
+          Geo g;
+          polar_point(table_xi(a, e[0], q[0]), table_xi(a, e[1], q[1]), g);
+          double Bi, Gi[3] = {0, 0, 0}, Bj, Gj[3] = {0, 0, 0};
+          eval_fun(a, fi, e, q, &Bi, Gi);
+          eval_fun(a, fj, e, q, &Bj, Gj);
+          double vi[2], vj[2], gri[2][2], grj[2][2];
+          if (vel_i) piola2(g, fi.comp, Bi, Gi, vi, gri);
+          if (vel_j) piola2(g, fj.comp, Bj, Gj, vj, grj);
+          if (vel_i && vel_j) {
+            double Ei[2][2], Ej[2][2];
+            sym2(gri, Ei);
+            sym2(grj, Ej);
+            double t = 0.0;
+            for (int x = 0; x < 2; ++x)
+              for (int y = 0; y < 2; ++y) t += Ei[x][y] * Ej[x][y];
+            sum += wt * g.J * 2.0 * a.nu * t;
+          } else if (vel_i && !vel_j) {  // B^T entry
+            sum -= wt * Bj * (gri[0][0] + gri[1][1]);
+          } else if (!vel_i && vel_j) {  // B entry
+            sum -= wt * Bi * (grj[0][0] + grj[1][1]);
+          }
+        }
+  if (vel_i && vel_j) {
+    for (int fd = 0; fd < 2; ++fd)
+      for (int side = 0; side < 2; ++side) {
+        const int eb = side == 0 ? 0 : a.N - 1;
+        if (lo[fd] > eb || hi[fd] < eb) continue;
+        const int t = 1 - fd;
+        const double sgn = side == 0 ? -1.0 : 1.0;
+        e[fd] = eb;
+        q[fd] = side == 0 ? nq : nq + 1;
+        for (e[t] = lo[t]; e[t] <= hi[t]; ++e[t])
+          for (int qq = 0; qq < nq; ++qq) {
+            q[t] = qq;
+            Geo g;
+            polar_point(table_xi(a, e[0], q[0]), table_xi(a, e[1], q[1]), g);
+            // m = Finv^T nhat, nhat = sgn e_fd
+            double m[2] = {sgn * g.Finv[fd][0], sgn * g.Finv[fd][1]};
+            const double mn = sqrt(m[0] * m[0] + m[1] * m[1]);
+            const double n[2] = {m[0] / mn, m[1] / mn};
+            const double fn0 = g.Finv[0][0] * n[0] + g.Finv[0][1] * n[1];
+            const double fn1 = g.Finv[1][0] * n[0] + g.Finv[1][1] * n[1];
+            const double hF = 1.0 / (a.N * sqrt(fn0 * fn0 + fn1 * fn1));
+            const double ws = h * a.wq[qq] * g.J * mn;
+            double Bi, Gi[3] = {0, 0, 0}, Bj, Gj[3] = {0, 0, 0};
+            eval_fun(a, fi, e, q, &Bi, Gi);
+            eval_fun(a, fj, e, q, &Bj, Gj);
+            double vi[2], vj[2], gri[2][2], grj[2][2], Ei[2][2], Ej[2][2];
+            piola2(g, fi.comp, Bi, Gi, vi, gri);
+            piola2(g, fj.comp, Bj, Gj, vj, grj);
+            sym2(gri, Ei);
+            sym2(grj, Ej);
+            double ti_vj = 0.0, tj_vi = 0.0;
+            for (int x = 0; x < 2; ++x) {
+              ti_vj += (Ei[x][0] * n[0] + Ei[x][1] * n[1]) * vj[x];
+              tj_vi += (Ej[x][0] * n[0] + Ej[x][1] * n[1]) * vi[x];
+            }
+            const double vv = vi[0] * vj[0] + vi[1] * vj[1];
+            sum += ws * 2.0 * a.nu * (-(ti_vj + tj_vi) + (a.cpen / hF) * vv);
+          }
+      }
+  }
+  return sum;
+}
+
 // One wavefront per row; lanes over the row's entries.
 __global__ void k_assemble_saddle(AsmArgs a, int64_t nrows, const int32_t* __restrict__ rowptr,
                                   const int32_t* __restrict__ col, double* __restrict__ val) {
@@ -332,7 +496,15 @@ __global__ void k_pressure_mass(AsmArgs a, double* __restrict__ diagQ, double* _
               for (int d = 0; d < a.dim; ++d) wt *= a.wq[q[d]];
               double B, G[3];
               eval_fun(a, f, e, q, &B, G);
-              s2 += wt * B * B;
+              // on the map phi = phihat / J and dx = J dxi: int phi^2 dx = int phihat^2 / J dxi,
+              // int phi dx = int phihat dxi
+              double ij = 1.0;
+              if (a.geom != 0) {
+                Geo g;
+                polar_point(table_xi(a, e[0], q[0]), table_xi(a, e[1], q[1]), g);
+                ij = 1.0 / g.J;
+              }
+              s2 += wt * B * B * ij;
               s1 += wt * B;
             }
   diagQ[k] = s2;
@@ -368,7 +540,13 @@ __device__ double q_entry(const AsmArgs& a, int64_t k, int64_t l) {
               double Bk, Bl, G[3];
               eval_fun(a, fk, e, q, &Bk, G);
               eval_fun(a, fl, e, q, &Bl, G);
-              s += wt * Bk * Bl;
+              double ij = 1.0;
+              if (a.geom != 0) {
+                Geo g;
+                polar_point(table_xi(a, e[0], q[0]), table_xi(a, e[1], q[1]), g);
+                ij = 1.0 / g.J;
+              }
+              s += wt * Bk * Bl * ij;
             }
   return s;
 }
@@ -465,20 +643,40 @@ __global__ void k_load_vector(AsmArgs a, ModeArgs m, double* __restrict__ f) {
                 wt *= a.wq[q[d]];
                 x[d] = (e[d] + m.xq[q[d]]) * h;
               }
-              double fv = 0.0;
-              if (m.manufactured) {
-                double fm[3];
-                manufactured_force(a.dim, a.nu, x, fm);
-                fv = fm[c];
-              }
-              for (int k = 0; k < M; ++k) {
-                double arg = m.phase[((size_t)r * a.dim + c) * M + k];
-                for (int d = 0; d < a.dim; ++d) arg += kPiD * m.wave[((size_t)r * M + k) * a.dim + d] * x[d];
-                fv += m.amp[((size_t)r * a.dim + c) * M + k] * sin(arg);
-              }
               double B, G[3];
               eval_fun(a, fi, e, q, &B, G);
-              sum += wt * fv * B;
+              if (a.geom == 0) {
+                double fv = 0.0;
+                if (m.manufactured) {
+                  double fm[3];
+                  manufactured_force(a.dim, a.nu, x, fm);
+                  fv = fm[c];
+                }
+                for (int k = 0; k < M; ++k) {
+                  double arg = m.phase[((size_t)r * a.dim + c) * M + k];
+                  for (int d = 0; d < a.dim; ++d) arg += kPiD * m.wave[((size_t)r * M + k) * a.dim + d] * x[d];
+                  fv += m.amp[((size_t)r * a.dim + c) * M + k] * sin(arg);
+                }
+                sum += wt * fv * B;
+              } else {
+                // f at the physical point; f . Phi dx = B (DF[:, c] . f) dxi
+                Geo g;
+                polar_point(x[0], x[1], g);
+                double fv[2] = {0.0, 0.0};
+                if (m.manufactured) {
+                  double fm[3];
+                  manufactured_force(2, a.nu, g.x, fm);
+                  fv[0] = fm[0];
+                  fv[1] = fm[1];
+                }
+                for (int d = 0; d < 2; ++d)
+                  for (int k = 0; k < M; ++k) {
+                    double arg = m.phase[((size_t)r * 2 + d) * M + k];
+                    for (int b = 0; b < 2; ++b) arg += kPiD * m.wave[((size_t)r * M + k) * 2 + b] * g.x[b];
+                    fv[d] += m.amp[((size_t)r * 2 + d) * M + k] * sin(arg);
+                  }
+                sum += wt * B * (g.DF[0][c] * fv[0] + g.DF[1][c] * fv[1]);
+              }
             }
   f[(size_t)r * a.n_u + i] = sum;
 }
@@ -562,6 +760,7 @@ struct Tables {
 
 static AsmArgs make_args(const Spaces& S, double nu, double cpen, int nq, const Tables& T) {
   AsmArgs a;
+  a.geom = S.geom;
   a.N = S.N;
   a.kp = S.kp;
   a.dim = S.dim;
@@ -582,8 +781,14 @@ static AsmArgs make_args(const Spaces& S, double nu, double cpen, int nq, const 
   a.tv_hi = T.v_hi;
   a.td_hi = T.d_hi;
   a.wq = T.wq;
+  a.xq = T.xq;
   return a;
 }
+
+// Gauss points per direction: k'+2 (matrices) and k'+4 (loads) are exact on the identity
+// map; the mapped integrands are rational, one more point is taken there.
+static int matrix_points(const Spaces& S) { return S.kp + 2 + (S.geom ? 1 : 0); }
+static int load_points(const Spaces& S) { return S.kp + 4 + (S.geom ? 1 : 0); }
 
 static hipError_t build_tables(const Spaces& S, int nq, Tables& T, hipStream_t st) {
   const size_t npt = (size_t)S.N * (nq + 2);
@@ -614,7 +819,7 @@ static void free_tables(Tables& T) {
 hipError_t assemble_saddle(const Spaces& S, double nu, double cpen, const int32_t* rowptr, const int32_t* col,
                            double* val, double* diagQ, double* w, hipStream_t st) {
   Tables T;
-  const int nq = S.kp + 2;
+  const int nq = matrix_points(S);
   hipError_t e = build_tables(S, nq, T, st);
   if (e != hipSuccess) {
     free_tables(T);
@@ -634,7 +839,7 @@ hipError_t assemble_saddle(const Spaces& S, double nu, double cpen, const int32_
 
 hipError_t assemble_Q(const Spaces& S, const int32_t* rowptr, const int32_t* col, double* val, hipStream_t st) {
   Tables T;
-  const int nq = S.kp + 2;
+  const int nq = matrix_points(S);
   hipError_t e = build_tables(S, nq, T, st);
   if (e != hipSuccess) {
     free_tables(T);
@@ -653,7 +858,7 @@ hipError_t assemble_Q(const Spaces& S, const int32_t* rowptr, const int32_t* col
 hipError_t assemble_load(const Spaces& S, double nu, int manufactured, int nmodes, int nrhs, const double* amp_d,
                          const int32_t* wave_d, const double* phase_d, double* f, hipStream_t st) {
   Tables T;
-  const int nq = S.kp + 4;
+  const int nq = load_points(S);
   hipError_t e = build_tables(S, nq, T, st);
   if (e != hipSuccess) {
     free_tables(T);
@@ -677,6 +882,7 @@ hipError_t assemble_load(const Spaces& S, double nu, int manufactured, int nmode
 }
 
 hipError_t assemble_load_cavity(const Spaces& S, double nu, double cpen, int kind, double* f, hipStream_t st) {
+  if (S.geom != 0) return hipErrorInvalidValue;  // the cavity is the unit square
   Tables T;
   const int nq = S.kp + 2;
   hipError_t e = build_tables(S, nq, T, st);

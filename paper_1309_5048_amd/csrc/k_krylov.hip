@@ -525,10 +525,18 @@ __global__ __launch_bounds__(kVT) void k_dot(int64_t r0, int64_t r1, const Ta* _
 
 // Zero-mean pressure: p_c -= (w . p_c) / (w . 1), rows [n_u, n).  mean computed by k_dot.
 template <typename T, int R>
-__global__ void k_sub_mean(int64_t n_u, int64_t n, T* __restrict__ x, const double* __restrict__ wp, double w1) {
-  for (int64_t i = n_u + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+__global__ void k_sub_mean(int64_t n_u, int64_t n, T* __restrict__ x, const double* __restrict__ wp, double w1,
+                           const double* __restrict__ kappa) {
+  for (int64_t i = n_u + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    if (kappa == nullptr) {
 #pragma unroll
-    for (int c = 0; c < R; ++c) x[(size_t)i * R + c] = T((double)x[(size_t)i * R + c] - wp[c] / w1);
+      for (int c = 0; c < R; ++c) x[(size_t)i * R + c] = T((double)x[(size_t)i * R + c] - wp[c] / w1);
+    } else {
+      const double kv = kappa[i - n_u];
+#pragma unroll
+      for (int c = 0; c < R; ++c) x[(size_t)i * R + c] = T((double)x[(size_t)i * R + c] - (wp[c] / w1) * kv);
+    }
+  }
 }
 
 // Column-major [R][len] (stride ld) <-> interleaved [len][R], with type conversion.
@@ -853,8 +861,9 @@ hipError_t dot(int R, int64_t r0, int64_t r1, const Ta* a, const Tb* b, double* 
 }
 
 template <typename T>
-hipError_t sub_mean(int R, int64_t n_u, int64_t n, T* x, const double* wp, double w1, hipStream_t st) {
-  STK_R_SWITCH(R, hipLaunchKernelGGL((k_sub_mean<T, RR>), dim3(256), dim3(256), 0, st, n_u, n, x, wp, w1));
+hipError_t sub_mean(int R, int64_t n_u, int64_t n, T* x, const double* wp, double w1, const double* kappa,
+                    hipStream_t st) {
+  STK_R_SWITCH(R, hipLaunchKernelGGL((k_sub_mean<T, RR>), dim3(256), dim3(256), 0, st, n_u, n, x, wp, w1, kappa));
   return hipGetLastError();
 }
 
@@ -975,7 +984,7 @@ hipError_t pcg_pupdate(int R, int64_t n_u, const T* z, T* pv, const PcgScalars& 
   template hipError_t mr_update<T>(int, int64_t, const T*, const T*, T*, T*, const MrScalars&, int, hipStream_t);    \
   template hipError_t spmv_resid<T>(int, const RowSplit&, const int32_t*, const int32_t*, const int32_t*, const T*,  \
                                     const T*, const T*, T*, double*, unsigned int*, double*, hipStream_t);           \
-  template hipError_t sub_mean<T>(int, int64_t, int64_t, T*, const double*, double, hipStream_t);                    \
+  template hipError_t sub_mean<T>(int, int64_t, int64_t, T*, const double*, double, const double*, hipStream_t);                    \
   template hipError_t pcg_init<T>(int, int64_t, const T*, T*, T*, const PcgScalars&, const int*, hipStream_t);       \
   template hipError_t pcg_init2<T>(int, int64_t, const T*, T*, const PcgScalars&, double, int, const int*,           \
                                    const MinresState*, hipStream_t);                                                 \

@@ -137,7 +137,7 @@ __device__ __forceinline__ T octet_sum(T v) {
   return v;
 }
 
-enum { CTR_COMPUTED = 0, CTR_HALO = 1, CTR_ERR = 3 };
+enum { CTR_COMPUTED = 0, CTR_HALO = 1, CTR_ERR = 3, CTR_WAVE0 = 4 };  // CTR_WAVE0 + w: compute wave w
 
 template <typename T>
 struct RowRec;
@@ -167,7 +167,21 @@ struct Vec16<float> {
 // Halo wavefront: entries are staged in order; lane j of a round watches entry pos + j.
 // An entry is ready when its R values are no longer the sentinel and the compute wave has
 // finished the steps that still read the slot's previous occupant.
-template <typename T, int R>
+// Steps computed by every compute wave: the counter CTR_COMPUTED (one compute wave, NW = 0)
+// or the least of the NW per-wave counters from CTR_WAVE0 on.
+template <int NW>
+__device__ __forceinline__ int computed_steps(int* ctr) {
+  if constexpr (NW == 0) {
+    return lds_load(&ctr[CTR_COMPUTED]);
+  } else {
+    int m = lds_load(&ctr[CTR_WAVE0]);
+#pragma unroll
+    for (int w = 1; w < NW; ++w) m = min(m, lds_load(&ctr[CTR_WAVE0 + w]));
+    return m;
+  }
+}
+
+template <typename T, int R, int NW = 0>
 __device__ __forceinline__ void halo_wave(const int32_t* __restrict__ grp_halo_ptr, const int32_t* __restrict__ halo_row,
                                           const int32_t* __restrict__ halo_slot,
                                           const int32_t* __restrict__ halo_free, int nrows, int nslots, int ld,
@@ -194,7 +208,7 @@ __device__ __forceinline__ void halo_wave(const int32_t* __restrict__ grp_halo_p
         v[c] = dev_load(out + (size_t)row * ld + c);
         ready = ready && !is_sentinel(v[c]);
       }
-      ready = ready && lds_load(&ctr[CTR_COMPUTED]) >= fr;
+      ready = ready && computed_steps<NW>(ctr) >= fr;
     }
     const unsigned long long notready = __ballot(!ready);
     int count = notready ? __ffsll((long long)notready) - 1 : 64;
@@ -408,6 +422,192 @@ __global__ __launch_bounds__(kTrsvThreads) __attribute__((amdgpu_waves_per_eu(1,
       for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
       if (lane == 0) dev_store(a.partials + (size_t)g * R + c, v);
     }
+    if (lane == 0) {
+      wait_vm_stores();
+      const unsigned int prev = __hip_atomic_fetch_add(a.done_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (prev == (unsigned int)(a.ngroups - 1)) {
+        for (int c = 0; c < R; ++c) {
+          double v = 0.0;
+          for (int k = 0; k < a.ngroups; ++k) v += dev_load(a.partials + (size_t)k * R + c);
+          dot_out[c] = v;
+        }
+        __hip_atomic_store(a.done_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Batched solve with the columns split over W compute wavefronts plus the halo wavefront.
+// Compute wave w owns columns [w RC, (w + 1) RC), RC = R / W, so each dependency is G =
+// RC / (16 bytes of T) 16-byte LDS gathers and a step issues all its gathers before the
+// FMAs, as the single-column step does.  The waves walk the same steps and read the same
+// factor records; they share no values (each reads and writes only its own columns of the
+// LDS slots), so they run independently.  The halo wave refills a slot only after every
+// compute wave has finished the steps that read its previous occupant (least of the
+// per-wave counters).
+// ---------------------------------------------------------------------------
+template <typename T, int R, int EP, int D, int W>
+__global__ __launch_bounds__(64 * (W + 1)) void k_trsv_cols(
+    TrsvArgs a, const T* __restrict__ sval, const typename RowRec<T>::type* __restrict__ srinfo,
+    const T* __restrict__ rd_s, T* __restrict__ out, T* __restrict__ dummy, int with_dot,
+    double* __restrict__ dot_out, const int* __restrict__ skip) {
+  using V = typename Vec16<T>::type;
+  constexpr int VN = Vec16<T>::n;
+  constexpr int RC = R / W;
+  constexpr int G = RC / VN;  // 16-byte gathers per entry
+  static_assert(G >= 1 && G * VN == RC && W * RC == R && W <= 8 && D >= 2, "column split");
+  constexpr int NV = EP / VN;
+  constexpr int SH = __builtin_ctz(R * sizeof(T));  // slot id -> byte offset in xs
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double sdot[R];
+  if (skip != nullptr && *skip) return;
+  int* ctr = reinterpret_cast<int*>(smem);
+  T* xs = reinterpret_cast<T*>(smem + 64);
+
+  const int g = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int wid = tid >> 6;
+  const int lane = tid & 63;
+  const int s0 = a.grp_step_ptr[g], s1 = a.grp_step_ptr[g + 1];
+  if (tid < 16) ctr[tid] = 0;
+  if (tid < R) {
+    xs[tid] = T(0);  // slot 0: the zero slot read by padding entries
+    sdot[tid] = 0.0;
+  }
+  __syncthreads();
+
+  if (wid < W) {
+    // ------------------------------ compute waves -----------------------------
+    const int cb = wid * RC;
+    const int q = lane % kTrsvG;
+    const int r = lane / kTrsvG;
+    double dotacc[RC];
+#pragma unroll
+    for (int c = 0; c < RC; ++c) dotacc[c] = 0.0;
+    V pv[D][NV];
+    uint4 ps[D][EP / 4];
+    typename RowRec<T>::type pri[D];
+    V prh[D][G], pdt[D][G];  // right-hand side and dot-vector entries of this wave's columns
+    int prow[D];
+    int halo_seen = 0;
+    const T* sval_l = sval + (size_t)lane * EP;
+    const uint32_t* ssrc_l = a.ssrc + (size_t)lane * EP;
+    const typename RowRec<T>::type* sri_l = srinfo + r;
+    const T* rd_l = rd_s + (size_t)r * 2 * R + cb;
+    const int32_t* srow_l = a.srow + r;
+    auto load = [&](int d, int ss) {
+      const V* vp = reinterpret_cast<const V*>(sval_l + (size_t)ss * 64 * EP);
+#pragma unroll
+      for (int k = 0; k < NV; ++k) pv[d][k] = vp[k];
+      const uint4* sp = reinterpret_cast<const uint4*>(ssrc_l + (size_t)ss * 64 * EP);
+#pragma unroll
+      for (int k = 0; k < EP / 4; ++k) ps[d][k] = sp[k];
+      pri[d] = sri_l[(size_t)ss * kTrsvRPS];
+      const V* rp = reinterpret_cast<const V*>(rd_l + (size_t)ss * kTrsvRPS * 2 * R);
+#pragma unroll
+      for (int k = 0; k < G; ++k) {
+        prh[d][k] = rp[k];
+        pdt[d][k] = rp[R / VN + k];
+      }
+      prow[d] = srow_l[(size_t)ss * kTrsvRPS];
+    };
+    // The same software pipeline as the single-wave kernel: D register buffers, the loads
+    // of step ss + D - 1 issued between the gathers of step ss and their use.
+    if (s1 > s0) {
+#pragma unroll
+      for (int d = 0; d + 1 < D; ++d) {
+        load(d, min(s0 + d, s1 - 1));
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      int s = s0;
+      do {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          const int ss = s + d;
+          const int k = ss - s0;
+          const bool live = ss < s1;
+          if (live && pri[d].need > halo_seen)
+            halo_seen = lds_wait<false, false>(&ctr[CTR_HALO], pri[d].need, &ctr[CTR_ERR], a.err);
+          V xv[EP][G];
+#pragma unroll
+          for (int e = 0; e < EP; ++e) {
+            const unsigned src = reinterpret_cast<const unsigned*>(&ps[d][e / 4])[e % 4];
+            const V* xp = reinterpret_cast<const V*>(reinterpret_cast<const unsigned char*>(xs + cb) + (src << SH));
+#pragma unroll
+            for (int k = 0; k < G; ++k) xv[e][k] = xp[k];
+          }
+          __builtin_amdgcn_sched_barrier(0);
+          load((d + D - 1) % D, min(ss + D - 1, s1 - 1));
+          __builtin_amdgcn_sched_barrier(0);
+          T acc[RC], acc2[RC];
+#pragma unroll
+          for (int c = 0; c < RC; ++c) acc[c] = acc2[c] = T(0);
+#pragma unroll
+          for (int e = 0; e < EP; ++e) {
+            const T v = reinterpret_cast<const T*>(&pv[d][e / VN])[e % VN];
+            const T* xe = reinterpret_cast<const T*>(&xv[e][0]);
+#pragma unroll
+            for (int c = 0; c < RC; ++c) {
+              if (e & 1)
+                acc2[c] = fma(v, xe[c], acc2[c]);
+              else
+                acc[c] = fma(v, xe[c], acc[c]);
+            }
+          }
+          T res[RC];
+          const T* rh = reinterpret_cast<const T*>(&prh[d][0]);
+#pragma unroll
+          for (int c = 0; c < RC; ++c) res[c] = (rh[c] - octet_sum(acc[c] + acc2[c])) * pri[d].dinv;
+          // lane q of the octet stores column q % RC of the row (RC <= 8 lanes; lanes with
+          // the same column store the same value; padding rows and steps past the end store
+          // to the dummy location), so the store is issued on every path
+          static_assert(RC <= kTrsvG, "one column per lane of the octet");
+          const bool real = live && prow[d] >= 0;
+          const int cq = q % RC;
+          T sv = res[0];
+#pragma unroll
+          for (int c = 1; c < RC; ++c)
+            if (cq == c) sv = res[c];
+          dev_store(real ? out + (size_t)prow[d] * a.ld + cb + cq : dummy, sv);
+          if (live) {
+            if (q == 0) {
+              if (prow[d] >= 0) {
+                const T* dt = reinterpret_cast<const T*>(&pdt[d][0]);
+#pragma unroll
+                for (int c = 0; c < RC; ++c) dotacc[c] += (double)res[c] * (double)dt[c];
+              }
+              T* xp = xs + (size_t)pri[d].slot * R + cb;
+#pragma unroll
+              for (int c = 0; c < RC; ++c) xp[c] = res[c];
+            }
+            if (lane == 0) lds_signal(&ctr[CTR_WAVE0 + wid], k + 1);
+          }
+        }
+        s += D;
+      } while (s < s1);
+    }
+    if (with_dot) {
+#pragma unroll
+      for (int c = 0; c < RC; ++c) {
+        double v = dotacc[c];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) sdot[cb + c] = v;
+      }
+    }
+  } else {
+    // ------------------------------- halo wave --------------------------------
+    halo_wave<T, R, W>(a.grp_halo_ptr, a.halo_row, a.halo_slot, a.halo_free, a.nrows, a.nslots, a.ld, a.err, g,
+                       lane, ctr, xs, out);
+  }
+  __syncthreads();
+  if (tid == 0 && lds_load(&ctr[CTR_ERR]) != 0) raise_err(a.err);
+
+  // fused dot product: the group's partials of all R columns (device scope), then a ticket;
+  // the last group adds the partials in group order
+  if (with_dot && wid == 0) {
+    if (lane < R) dev_store(a.partials + (size_t)g * R + lane, sdot[lane]);
     if (lane == 0) {
       wait_vm_stores();
       const unsigned int prev = __hip_atomic_fetch_add(a.done_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -814,8 +1014,24 @@ static hipError_t launch_trsv_t(const TrsvSchedDev& S, const T* sval, const type
   hipLaunchKernelGGL((k_trsv_gather_rhs<T, R>), dim3(1024), dim3(256), 0, st, nrow_slots, S.srow, rhs, dotv, ld,
                      rd_s, out, skip);
   const size_t shmem = trsv_shmem_t<T, R>(S.nslots);
-  auto fn = k_trsv<T, R, EP, D>;
-  hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+  // R >= 8: the columns split over W compute wavefronts of RC = max(16 bytes, R / 4)
+  // columns each (4 waves for R = 16, 4 or 2 for R = 8), with a prefetch depth that keeps
+  // the step buffers in the 256 registers two waves per SIMD allow
+  constexpr int RC = R / 4 > Vec16<T>::n ? R / 4 : Vec16<T>::n;
+  constexpr int W = R >= 8 ? R / RC : 0;
+  constexpr int GC = RC / Vec16<T>::n;
+  constexpr int DC = GC == 1 ? (EP <= 4 ? 7 : (EP <= 8 ? 5 : (EP <= 12 ? 3 : 2)))
+                             : (EP <= 4 ? 5 : (EP <= 8 ? 3 : 2));
+  const void* fn;
+  int threads;
+  if constexpr (W > 0) {
+    fn = (const void*)k_trsv_cols<T, R, EP, DC, W>;
+    threads = 64 * (W + 1);
+  } else {
+    fn = (const void*)k_trsv<T, R, EP, D>;
+    threads = kTrsvThreads;
+  }
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
   if (e != hipSuccess) return e;
   const T* rd_sc = rd_s;
   int with_dot = dotv != nullptr ? 1 : 0;
@@ -824,7 +1040,7 @@ static hipError_t launch_trsv_t(const TrsvSchedDev& S, const T* sval, const type
   // An ordinary launch: the host has checked that every group fits on the chip at once,
   // so all groups are dispatched together (a cooperative launch adds tens of microseconds
   // of queue synchronisation around the kernel and is not needed for that).
-  e = hipLaunchKernel((const void*)fn, dim3(S.ngroups), dim3(kTrsvThreads), args, shmem, st);
+  e = hipLaunchKernel(fn, dim3(S.ngroups), dim3(threads), args, shmem, st);
   if (tm && tm->after) (void)hipEventRecord(tm->after, st);
   return e;
 }
@@ -856,7 +1072,7 @@ static hipError_t launch_trsv_p(const TrsvSchedDev& S, const T* sval, const type
   e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
   if (e != hipSuccess) return e;
   int Rc = R;
-  while (Rc > 1 && (Rc > S.rmax || trsv_shmem_bytes(S.nslots, sizeof(T) == 4, Rc) > (size_t)lds_max))
+  while (Rc > 1 && (Rc > S.rmax || trsv_shmem_bytes(S.nslots, sizeof(T) == 4, Rc) + trsv_static_shmem(Rc) > (size_t)lds_max))
     Rc = Rc > 8 ? 8 : 1;
   if (R % Rc != 0) return hipErrorInvalidValue;
   for (int c0 = 0; c0 < R; c0 += Rc) {

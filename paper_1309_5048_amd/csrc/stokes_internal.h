@@ -23,6 +23,7 @@ struct Spaces {
   int64_t voff[4] = {0};                 // component offsets in the velocity numbering
   int64_t n_u = 0, n_p = 0;
   int nlo = 0, nhi = 0;                  // N + k', N + k' + 1 (1D function counts)
+  int geom = 0;                          // 0: identity map; 1: polar 1/8 annulus (2D)
 };
 
 Spaces make_spaces(int N, int kp, int dim);
@@ -374,6 +375,8 @@ hipError_t launch_trsv(const TrsvSchedDev& S, bool fp32, int R, const void* rhs,
                        double* dot_out, const int* skip, hipStream_t st, const TrsvTiming* tm = nullptr);
 hipError_t launch_trsv_gather(const TrsvSchedDev& S, const double* Lval, hipStream_t st);
 size_t trsv_shmem_bytes(int nslots, bool fp32, int R);
+// Static LDS of the solve kernels beside the dynamic part (the batched kernels' dot partials).
+inline size_t trsv_static_shmem(int R) { return R >= 8 ? 256 : 0; }
 
 // Row ranges of the CSR row kernels: block b owns rows split[b] .. split[b+1]-1 (device
 // array of nb+1 entries), ranges balanced by entries on the host.
@@ -411,7 +414,9 @@ template <typename Ta, typename Tb>
 hipError_t dot(int R, int64_t r0, int64_t r1, const Ta* a, const Tb* b, double* partials, unsigned int* counter,
                double* out, hipStream_t st);
 template <typename T>
-hipError_t sub_mean(int R, int64_t n_u, int64_t n, T* x, const double* wp, double w1, hipStream_t st);
+// x_p -= (wp[c] / w1) kappa (kappa = nullptr: the all-ones vector, the identity map's constant)
+hipError_t sub_mean(int R, int64_t n_u, int64_t n, T* x, const double* wp, double w1, const double* kappa,
+                    hipStream_t st);
 template <typename Ts, typename Td>
 hipError_t to_interleaved(int R, int64_t len, const Ts* src, int64_t ld, Td* dst, int64_t dst_off, hipStream_t st);
 template <typename Ts, typename Td>

@@ -692,26 +692,28 @@ def test_iteration_counts_ic_pcg_cavity_k2(paper):
 # none in 2D for k' <= 2.  This is the reading behind the stop-count bar of the GPU tests.
 # ---------------------------------------------------------------------------
 def test_stop_counts_move_by_two_under_rounding():
+    from oracle.oracle import GEOM_ANNULUS
     from synthetic_inputs import forcing_modes
     moved = {}
     try:
-        for (N, kp, dim) in [(16, 1, 2), (12, 2, 2), (5, 3, 2), (4, 1, 3)]:
-            o = Oracle(N, kp, dim)
+        for (N, kp, dim, geo, pc) in [(16, 1, 2, 0, PC_IC0), (12, 2, 2, 0, PC_IC0), (5, 3, 2, 0, PC_IC0),
+                                      (4, 1, 3, 0, PC_IC0), (10, 2, 2, GEOM_ANNULUS, PC_JACOBI)]:
+            o = Oracle(N, kp, dim, geometry=geo)
             o.ic0()
             F = [o.load(1)] + list(o.load(1, forcing_modes(list(range(1000, 1006)), dim)))
             d = []
             for f in F:
                 b = np.concatenate([f, np.zeros(o.n_p)])
                 Oracle.set_sum_order(False)
-                _, i0 = o.minres(b, tol=1e-8)
+                _, i0 = o.minres(b, tol=1e-8, pc_A=pc)
                 Oracle.set_sum_order(True)
-                _, i1 = o.minres(b, tol=1e-8)
+                _, i1 = o.minres(b, tol=1e-8, pc_A=pc)
                 d.append(i1["iters"] - i0["iters"])
-            moved[(N, kp, dim)] = d
+            moved[(N, kp, dim, geo)] = d
     finally:
         Oracle.set_sum_order(False)
-    assert all(x == 0 for x in moved[(16, 1, 2)] + moved[(12, 2, 2)]), moved
-    for key in ((5, 3, 2), (4, 1, 3)):
+    assert all(x == 0 for x in moved[(16, 1, 2, 0)] + moved[(12, 2, 2, 0)]), moved
+    for key in ((5, 3, 2, 0), (4, 1, 3, 0), (10, 2, 2, GEOM_ANNULUS)):
         assert any(x != 0 for x in moved[key]), moved
         assert all(abs(x) <= 2 for x in moved[key]), moved
 
