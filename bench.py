@@ -292,6 +292,22 @@ def c4_variant(tol, extra):
         torch.cuda.empty_cache()
 
 
+def copy_probe(mib, out):
+    """A plain elementwise copy of mib MiB, three times (the reference for scaling memory
+    counters)."""
+    if mib <= 0:
+        return
+    import torch
+    nbytes = mib << 20
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)
+    sync()
+    out["copy_probe_bytes"] = nbytes
+    log("copy probe: 3 x %d bytes read and written" % nbytes)
+
+
 ONLY = ("c1-ic0", "c1-pcgAQ", "c1-jpcg", "c1-icpcg", "c1-icpcgAQ", "c1-ideal", "c2-fp64", "c2-mixed", "c3", "c4")
 
 
@@ -332,7 +348,9 @@ def main():
             c3_variant(tol, extra, "c3")
         else:
             c4_variant(tol, extra)
-        print(json.dumps({"only": args.only, "results": extra}), flush=True)
+        out = {"only": args.only, "results": extra}
+        copy_probe(args.copy_probe, out)
+        print(json.dumps(out), flush=True)
         return
 
     log("setup N=%d k'=%d dim=%d" % (N, kp, dim))
@@ -436,15 +454,7 @@ def main():
     else:
         gp.close()
 
-    if args.copy_probe > 0:
-        nbytes = args.copy_probe << 20
-        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            torch.mul(src, 1.0, out=dst)
-        sync()
-        out["copy_probe_bytes"] = nbytes
-        log("copy probe: 3 x %d bytes read and written" % nbytes)
+    copy_probe(args.copy_probe, out)
     if not args.no_cpu:
         log("cpu baseline (oracle, 1 core, one whole solve)")
         out["cpu_baseline"] = cpu_baseline(N, kp, dim, tol)

@@ -124,9 +124,11 @@ typedef struct {
   const double* phase;  /* [nrhs][dim][nmodes]                                          */
 } stokes_forcing;
 
-/* Build the problem: spaces and sparsity (host), Gauss-quadrature assembly of A, B, B^T,
- * diag(Q) and w = Q 1 (device), level schedules of the triangular solves (host) and the
- * IC(0) factor (device, shift retries alpha = 1e-3, 1e-2, 1e-1 of diag(A) on breakdown).
+/* Build the problem: the spaces of Sec. 3.2 and their sparsity (host), Gauss-quadrature
+ * assembly of A (the Nitsche form of Sec. 4, eq. nitsche_lhs), B, B^T (eq. stokes_linsys),
+ * diag(Q) and w (integrals of the pressure functions) (device), level schedules of the
+ * triangular solves (host) and the IC(0) factor of A (Sec. 6.4; device, shift retries
+ * alpha = 1e-3, 1e-2, 1e-1 of diag(A) on breakdown).
  * n: elements per direction (1..4096); p: pressure degree k' (1..3); dim: 2 or 3;
  * nu > 0.  On success *out owns the problem; on failure *out = NULL. */
 int stokes_setup(int n, int p, int dim, double nu, stokes_problem** out);
@@ -206,13 +208,15 @@ int stokes_load(stokes_problem* pb, const stokes_forcing* spec, int nrhs, double
 #define STOKES_CAVITY_VERIFY 1
 int stokes_load_cavity(stokes_problem* pb, int kind, double* f_dev);
 
-/* Solve [A B^T; B 0][u; p] = [f; 0] from x0 = 0: f [n_u] in, u [n_u] and pr [n_p] out
- * (pr has zero mean, w.pr = 0).  tol: relative M^{-1}-norm residual (e.g. 1e-8).
+/* Solve [A B^T; B 0][u; p] = [f; 0] (eq. stokes_linsys) by preconditioned MINRES (Sec. 5)
+ * from x0 = 0: f [n_u] in, u [n_u] and pr [n_p] out (pr has zero mean, w.pr = 0, the
+ * filtering of Sec. 6.2).  tol: relative M^{-1}-norm residual (e.g. 1e-8).
  * precond: STOKES_PC_*.  info may be NULL. */
 int stokes_solve(stokes_problem* pb, const double* f, double* u, double* pr, double tol, int precond,
                  stokes_info* info);
 
-/* nrhs independent solves in one launch sequence (block SpMM / block triangular solves,
+/* nrhs independent solves of Sec. 5's MINRES in one launch sequence (block SpMM / block
+ * triangular solves,
  * per-column Lanczos and Givens scalars, converged columns frozen).  F [nrhs][n_u],
  * U [nrhs][n_u], P [nrhs][n_p]; infos [nrhs] may be NULL.  precision: STOKES_FP64 or
  * STOKES_MIXED.  nrhs in 1..16. */
@@ -239,7 +243,8 @@ int stokes_solve_noalloc(stokes_problem* pb, const double* f, double* u, double*
 int stokes_solve_precision(stokes_problem* pb, const double* f, double* u, double* pr, double tol,
                            int precond, int precision, stokes_info* info);
 
-/* Adjoint solve for a loss L(u, p) of the zero-mean solution: with g = [g_u; g_p]
+/* Adjoint solve for a loss L(u, p) of the zero-mean solution (Acal is symmetric, Sec. 5,
+ * so the transposed system is solved by the same MINRES): with g = [g_u; g_p]
  * [n_u + n_p] (dL/du, dL/dp), solves Acal lambda = [g_u; g_p - w (kappa.g_p)/(w.kappa)]
  * (kappa the constant function's pressure coefficients, all ones on the unit square)
  * (Acal is symmetric, same MINRES and preconditioner); lambda [n_u + n_p] out with a
@@ -251,8 +256,10 @@ int stokes_solve_adjoint(stokes_problem* pb, const double* g, double* lambda, do
 int stokes_solve_adjoint_batched(stokes_problem* pb, int nrhs, const double* G, double* Lambda,
                                  double tol, int precond, stokes_info* infos);
 
-/* out[r] = lam_u[r]^T A u[r] / nu for r < nrhs (device arrays [nrhs][n_u]); out is a
- * HOST array of nrhs doubles.  Synchronises the stream. */
+/* out[r] = lam_u[r]^T A u[r] / nu for r < nrhs (device arrays [nrhs][n_u]): the viscosity
+ * derivative of the adjoint gradient, A being proportional to nu (the form a and the Nitsche
+ * terms of Sec. 4 all carry the factor 2 nu).  out is a HOST array of nrhs doubles (any
+ * nrhs >= 1), so the call synchronises the stream. */
 int stokes_dnu_dot(stokes_problem* pb, int nrhs, const double* lam_u, const double* u, double* out);
 
 /* Products with the assembled operators, for checks: y = Acal x (x, y [n_u + n_p]). */
@@ -265,7 +272,8 @@ int stokes_apply_precond(stokes_problem* pb, int precond, const double* r, doubl
 /* Copy the assembled matrices to HOST buffers (for checks).  which: 0 = saddle Acal
  * (rows n_u + n_p, columns sorted), 1 = the IC(0) factor L (rows n_u, lower triangle of
  * A's pattern, diagonal last), 2 = the IC(0) factor of the pressure mass matrix Q (rows
- * n_p, lower triangle of Q's pattern, diagonal last; factorised on first use, Sec. 6.4).  Pass NULL arrays to query *nnz only. rowptr is int64. */
+ * n_p, lower triangle of Q's pattern, diagonal last; factorised on first use, Sec. 6.4).
+ * Pass NULL arrays to query *nnz only. rowptr is int64. */
 int stokes_export_csr(stokes_problem* pb, int which, int64_t* nnz, int64_t* rowptr, int32_t* col,
                       double* val);
 

@@ -231,6 +231,10 @@ struct stokes_problem {
   double* partials = nullptr;
   unsigned int* counter = nullptr;
   std::map<int, Work> work;
+  // saddle product with non-temporal entry loads: only while the two FP64 triangular-solve
+  // schedules fit the 256 MB last-level cache (2 x 102 MB at N = 256, k' = 2), which the
+  // product's entries would otherwise evict every iteration
+  bool spmv_nt = true;
   double inner_tol = 1e-2;
   double refine_tol = 1e-4;
   int restarts = 0;  // inner-CG preconditioners: 0 = one MINRES run, else at most this many cycles
@@ -367,6 +371,7 @@ int build_fast_layout(stokes_problem* pb, const TrsvSchedHost& H, TrsvSchedDev& 
   }
   gb64[G] = off64;
   gb32[G] = off32;
+  F.bytes64 = off64;
   if (off64 >= (int64_t(1) << 31)) return 0;  // block offsets of a group must fit 32 bits
   const int64_t T = gsp[G];
   std::vector<unsigned char> b64(size_t(off64), 0), b32(size_t(off32), 0);
@@ -1018,7 +1023,7 @@ int minres_run(stokes_problem* pb, Work& W, int precond, double tol, int maxit, 
       const int p = (j - 1) & 1;
       {
         PROF_BEGIN(0);
-        CK(mr_spmv<T>(R, pb->rs_full, pb->rowptr, pb->col, val, z[p], q, s, p, st));
+        CK(mr_spmv<T>(R, pb->rs_full, pb->rowptr, pb->col, val, z[p], q, s, p, pb->spmv_nt, st));
         PROF_END();
       }
       {
@@ -1493,6 +1498,8 @@ static int stokes_setup_impl(int n, int p, int dim, double nu, int geometry, sto
     SchedPair* sp = nullptr;
     int rc = get_schedule(pb, 1, false, &sp);
     if (rc) return rc;
+    const int64_t sched_bytes = sp->fwd.fast.bytes64 + sp->bwd.fast.bytes64;
+    pb->spmv_nt = sp->fwd.fast.ok && sched_bytes <= (int64_t(256) << 20);
   }
   // Mapped domain: the constant function's pressure coefficients kappa = Q^{-1} w and
   // w1 = w . kappa = |Omega|.  kappa spans the kernel of B^T, so every right-hand side's

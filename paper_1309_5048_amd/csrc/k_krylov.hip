@@ -301,7 +301,7 @@ __global__ void k_mr_init_state(MrScalars s, double tol, int maxit) {
 // ---------------------------------------------------------------------------
 // q = Acal z~_j / gamma_j and delta partials.
 // ---------------------------------------------------------------------------
-template <typename T, int R>
+template <typename T, int R, bool NT>
 __global__ __launch_bounds__(kVT) void k_mr_spmv(const int32_t* __restrict__ split, const int32_t* __restrict__ rowptr,
                                                  const int32_t* __restrict__ col, const T* __restrict__ val,
                                                  const T* __restrict__ z, T* __restrict__ q, MrScalars s, int p) {
@@ -315,7 +315,7 @@ __global__ __launch_bounds__(kVT) void k_mr_spmv(const int32_t* __restrict__ spl
   double acc_d[R];
 #pragma unroll
   for (int c = 0; c < R; ++c) acc_d[c] = 0.0;
-  csr_rows<R, true, T>(split, rowptr, nullptr, col, val, z, [&](int64_t i, T (&acc)[R]) {
+  csr_rows<R, NT, T>(split, rowptr, nullptr, col, val, z, [&](int64_t i, T (&acc)[R]) {
     T qv[R], zv[R];
     load_cols<R>(z + (size_t)i * R, zv);
 #pragma unroll
@@ -821,9 +821,14 @@ hipError_t mr_init_state(int R, const MrScalars& s, double tol, int maxit, hipSt
 
 template <typename T>
 hipError_t mr_spmv(int R, const RowSplit& rs, const int32_t* rowptr, const int32_t* col, const T* val, const T* z, T* q,
-                   const MrScalars& s, int p, hipStream_t st) {
-  STK_R_SWITCH(R, hipLaunchKernelGGL((k_mr_spmv<T, RR>), dim3(rs.nb), dim3(kVT), 0, st, rs.split, rowptr, col, val, z,
-                                     q, s, p));
+                   const MrScalars& s, int p, bool nt, hipStream_t st) {
+  if (nt) {
+    STK_R_SWITCH(R, hipLaunchKernelGGL((k_mr_spmv<T, RR, true>), dim3(rs.nb), dim3(kVT), 0, st, rs.split, rowptr, col,
+                                       val, z, q, s, p));
+  } else {
+    STK_R_SWITCH(R, hipLaunchKernelGGL((k_mr_spmv<T, RR, false>), dim3(rs.nb), dim3(kVT), 0, st, rs.split, rowptr, col,
+                                       val, z, q, s, p));
+  }
   return hipGetLastError();
 }
 
@@ -978,7 +983,7 @@ hipError_t pcg_pupdate(int R, int64_t n_u, const T* z, T* pv, const PcgScalars& 
   template hipError_t mr_init_vec<T>(int, int64_t, int64_t, const T*, T*, T*, T*, T*, T*, T*, const double*,         \
                                      const double*, double, const MrScalars&, hipStream_t);                          \
   template hipError_t mr_spmv<T>(int, const RowSplit&, const int32_t*, const int32_t*, const T*, const T*, T*,      \
-                                 const MrScalars&, int, hipStream_t);                                               \
+                                 const MrScalars&, int, bool, hipStream_t);                                         \
   template hipError_t mr_lanczos<T>(int, int64_t, int64_t, const T*, const T*, T*, T*, const double*, const double*,  \
                                     double, const MrScalars&, int, hipStream_t);                                     \
   template hipError_t mr_update<T>(int, int64_t, const T*, const T*, T*, T*, const MrScalars&, int, hipStream_t);    \

@@ -139,6 +139,7 @@ struct FastRec32 {
 struct TrsvFastDev {
   bool ok = false;
   int nsteps = 0;                  // allocated steps (with padding and prefetch tail)
+  int64_t bytes64 = 0;             // bytes of the FP64 blocks
   int32_t* grp_step_ptr = nullptr; // [ngroups+1] allocated step ranges
   int32_t* grp_npad = nullptr;     // [ngroups] executed steps (multiple of the group's depth)
   int32_t* grp_ep = nullptr;       // [ngroups] 4 or 8
@@ -337,7 +338,10 @@ __device__ __forceinline__ T group_sum(T v) {
 }
 
 // Grid of the elementwise kernels: one item per thread up to kVecMaxBlocks blocks.
-constexpr int kVecMaxBlocks = 4096;
+// At most 1024 blocks: the last-block reductions take one device-scope ticket per block, and
+// thousands of tickets at the end of a short kernel serialise (2D, N = 512: the Lanczos
+// kernel took 45 us with 3,092 blocks for 30 MB).
+constexpr int kVecMaxBlocks = 1024;
 inline int vec_blocks(int64_t nitems) {
   int64_t b = (nitems + kVT - 1) / kVT;
   return int(std::max<int64_t>(1, std::min<int64_t>(b, kVecMaxBlocks)));
@@ -398,8 +402,10 @@ hipError_t mr_init_vec(int R, int64_t n, int64_t n_u, const T* b, T* v1, T* v0, 
                        const double* diagQ, const double* diagA, double two_nu, const MrScalars& s, hipStream_t st);
 hipError_t mr_init_state(int R, const MrScalars& s, double tol, int maxit, hipStream_t st);
 template <typename T>
+// nt: read the matrix entries with non-temporal loads (they then leave the last-level cache to
+// data that stays there, the triangular-solve schedules)
 hipError_t mr_spmv(int R, const RowSplit& rs, const int32_t* rowptr, const int32_t* col, const T* val, const T* z, T* q,
-                   const MrScalars& s, int p, hipStream_t st);
+                   const MrScalars& s, int p, bool nt, hipStream_t st);
 template <typename T>
 hipError_t mr_lanczos(int R, int64_t n, int64_t n_u, const T* q, const T* v, T* vprev_next, T* znext, const double* diagQ,
                       const double* diagA, double two_nu, const MrScalars& s, int p, hipStream_t st);
