@@ -151,6 +151,16 @@ int stokes_setup(int n, int p, int dim, double nu, stokes_problem** out);
 #define STOKES_GEOMETRY_ANNULUS 1
 int stokes_setup_geometry(int n, int p, int dim, double nu, int geometry, stokes_problem** out);
 
+/* The same with the Nitsche penalty constant of Sec. 4 chosen by the caller: the face terms
+ * penalise with 2 nu c_pen / h_F.  c_pen < 0 selects the value of the paper's experiments,
+ * C_pen = 5 (k'+1) (what stokes_setup and stokes_setup_geometry use); c_pen >= 0 is taken as
+ * given (a value too small for coercivity leaves A indefinite: IC(0) then breaks down and
+ * the shift retries of stokes_setup apply; ic_shift_steps reports how many were needed, and
+ * STOKES_EBREAKDOWN is returned when the last shift fails).  A non-finite c_pen:
+ * STOKES_EINVAL.  The same penalty enters the cavity load of stokes_load_cavity. */
+int stokes_setup_nitsche(int n, int p, int dim, double nu, int geometry, double c_pen,
+                         stokes_problem** out);
+
 /* Sizes: n_u velocity unknowns, n_p pressure unknowns. */
 int stokes_sizes(const stokes_problem* pb, int64_t* n_u, int64_t* n_p);
 

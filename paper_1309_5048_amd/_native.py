@@ -22,7 +22,7 @@ GEOMETRY_SQUARE, GEOMETRY_ANNULUS = 0, 1
 
 # every exported entry point declared in include/stokes.h
 EXPORTS = (
-    "stokes_setup", "stokes_setup_geometry", "stokes_sizes", "stokes_set_stream", "stokes_set_nu", "stokes_set_inner_tol",
+    "stokes_setup", "stokes_setup_geometry", "stokes_setup_nitsche", "stokes_sizes", "stokes_set_stream", "stokes_set_nu", "stokes_set_inner_tol",
     "stokes_set_refine_tol",
     "stokes_set_maxit", "stokes_set_restarts", "stokes_load", "stokes_load_cavity", "stokes_solve", "stokes_solve_batched", "stokes_solve_precision",
     "stokes_solve_noalloc",
@@ -64,6 +64,7 @@ def lib():
     sig = {
         "stokes_setup": (i32, [i32, i32, i32, dbl, P(vp)]),
         "stokes_setup_geometry": (i32, [i32, i32, i32, dbl, i32, P(vp)]),
+        "stokes_setup_nitsche": (i32, [i32, i32, i32, dbl, i32, dbl, P(vp)]),
         "stokes_sizes": (i32, [vp, P(i64), P(i64)]),
         "stokes_set_stream": (i32, [vp, vp]),
         "stokes_set_nu": (i32, [vp, dbl]),

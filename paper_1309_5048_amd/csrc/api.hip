@@ -163,6 +163,11 @@ struct FactorSched {
   const std::vector<int32_t>* lev_fwd = nullptr;
   std::vector<int32_t>* lev_bwd = nullptr;
   std::function<void(int, std::vector<int32_t>&, int*)> groups;
+  // rows [0, split) and [split, n) form two blocks (the velocity components of a 2D
+  // factor): the single-column solves then take the off-block dependencies of the block
+  // solved second as coupling values from `helpers` extra groups per strip (0: off)
+  int64_t split = 0;
+  int helpers = 0;
   std::vector<std::unique_ptr<SchedPair>> scheds;
 };
 
@@ -340,13 +345,15 @@ void prof_flush(stokes_problem* pb) {
 #define PROF_END() \
   if (_pt) (void)hipEventRecord(_pt->after, pb->stream);
 
-// Single-column layout of a schedule (see TrsvFastDev).  Returns 0 and leaves F.ok false
-// when a group needs more than 8 entries per lane (the general kernel then serves R = 1).
+// Single-column layout of a schedule H (see TrsvFastDev); H may have coupling rows and
+// helper groups.  Returns 0 and leaves F.ok false when a group needs more than 8 entries per
+// lane (the general kernel then serves R = 1).
 int build_fast_layout(stokes_problem* pb, const TrsvSchedHost& H, TrsvSchedDev& D, int64_t nrows, int64_t nnzL) {
   TrsvFastDev& F = D.fast;
   hipStream_t st = pb->stream;
   DevAlloc& m = pb->mem;
   const int G = H.ngroups, RPS = kTrsvRPS, E = H.E;
+  if (nrows + H.ncpl >= (int64_t(1) << 31)) return 0;
   if (nrows * 8 >= (int64_t(1) << 31) || nnzL >= (int64_t(1) << 31)) return 0;
   std::vector<int32_t> gsp(G + 1, 0), gnp(G, 0), gep(G, 4);
   std::vector<int64_t> gb64(G + 1, 0), gb32(G + 1, 0);
@@ -357,7 +364,7 @@ int build_fast_layout(stokes_problem* pb, const TrsvSchedHost& H, TrsvSchedDev& 
     for (int s = s0; s < s1; ++s)
       for (int e = 0; e < E; ++e)
         for (int l = 0; l < 64; ++l)
-          if (H.ent_perm[(size_t(s) * E + e) * 64 + l] >= 0) eg = std::max(eg, e + 1);
+          if (H.ent_perm[(size_t(s) * E + e) * 64 + l] != -1) eg = std::max(eg, e + 1);
     if (eg > 8) return 0;
     gep[g] = eg <= 4 ? 4 : 8;
     const int nreal = s1 - s0, dg = fast_depth(gep[g]);
@@ -401,8 +408,12 @@ int build_fast_layout(stokes_problem* pb, const TrsvSchedHost& H, TrsvSchedDev& 
         srow2[size_t(t) * RPS + rr] = (row >= 0 && !repeat_step) ? srow : ~srow;
         dsrc[size_t(t) * RPS + rr] = int32_t(H.sdiag_src[size_t(s) * RPS + src]);
         const int32_t slot = H.sslot[size_t(s) * RPS + src] > 0 ? H.sslot[size_t(s) * RPS + src] : H.nslots;
-        FastRec64 r64{0.0, int32_t(64 + slot * 8), int32_t(srow * 8)};
-        FastRec32 r32{0.0f, int32_t(64 + slot * 4), int32_t(srow * 4), 0};
+        // coupling rows are stored apart, from row nrows on (a group holds one kind only)
+        if ((srow >= nrows) != (H.grp_cpl[g] != 0))
+          return fail(pb, STOKES_EINVAL, "coupling row outside a helper group");
+        const int32_t orow = int32_t(srow >= nrows ? srow - nrows : srow);
+        FastRec64 r64{0.0, int32_t(64 + slot * 8), int32_t(orow * 8)};
+        FastRec32 r32{0.0f, int32_t(64 + slot * 4), int32_t(orow * 4), 0};
         std::memcpy(p64 + rr * 16, &r64, 16);
         std::memcpy(p32 + rr * 16, &r32, 16);
         for (int q = 0; q < kTrsvG; ++q) {
@@ -438,15 +449,29 @@ int build_fast_layout(stokes_problem* pb, const TrsvSchedHost& H, TrsvSchedDev& 
   F.dsrc = m.upload(dsrc, st);
   F.srow2 = m.upload(srow2, st);
   F.dyn = m.get<double>(size_t(T) * RPS * 2);
+  F.ngroups = G;
+  F.nslots = H.nslots;
+  F.nrows = int(nrows);
+  F.ncpl = int(H.ncpl);
+  F.grp_halo_ptr = m.upload(H.grp_halo_ptr, st);
+  F.halo_row = m.upload(H.halo_row, st);
+  F.halo_slot = m.upload(H.halo_slot, st);
+  F.halo_free = m.upload(H.halo_free, st);
+  F.grp_cpl = m.upload(H.grp_cpl, st);
+  F.cpl = m.get<double>(size_t(std::max<int64_t>(1, H.ncpl)));
+  F.done_count = m.get<unsigned int>(1);
+  F.partials = m.get<double>(size_t(G));
   if (m.err != hipSuccess) return fail_hip(pb, m.err, "single-column schedule upload", __LINE__);
+  CK(hipMemsetAsync(F.done_count, 0, sizeof(unsigned int), st));
   CK(hipStreamSynchronize(st));  // the host vectors must outlive the copies
   F.ok = true;
   return 0;
 }
 
-// Device form of a schedule of the factor Lval (nrows rows, nnzL entries).
-int upload_schedule(stokes_problem* pb, const TrsvSchedHost& H, TrsvSchedDev& D, int rmax, int64_t nrows,
-                    int64_t nnzL, const double* Lval) {
+// Device form of a schedule of the factor Lval (nrows rows, nnzL entries); the
+// single-column layout is built from X (H itself, or H's form with coupling rows).
+int upload_schedule(stokes_problem* pb, const TrsvSchedHost& H, const TrsvSchedHost& X, TrsvSchedDev& D, int rmax,
+                    int64_t nrows, int64_t nnzL, const double* Lval) {
   hipStream_t st = pb->stream;
   DevAlloc& m = pb->mem;
   D.ngroups = H.ngroups;
@@ -513,7 +538,7 @@ int upload_schedule(stokes_problem* pb, const TrsvSchedHost& H, TrsvSchedDev& D,
   CK(hipMemsetAsync(D.done_count, 0, sizeof(unsigned int), st));
   CK(hipMemsetAsync(D.err, 0, sizeof(int), st));
   CK(hipStreamSynchronize(st));  // host vectors must outlive the asynchronous copies
-  int rc = build_fast_layout(pb, H, D, nrows, nnzL);
+  int rc = build_fast_layout(pb, X, D, nrows, nnzL);
   if (rc) return rc;
   CK(launch_trsv_gather(D, Lval, st));
   CK(hipStreamSynchronize(st));
@@ -608,9 +633,24 @@ int make_schedule(stokes_problem* pb, FactorSched& fs, bool fp32, SchedPair** ou
     sp->rmax32 = resident(sp->rmax32, true);
     if (sp->rmax64 == 0 && sp->rmax32 == 0) continue;
     const int64_t nnzL = int64_t(fs.L->col.size());
-    int rc = upload_schedule(pb, hf, sp->fwd, std::max(sp->rmax64, sp->rmax32), fs.n, nnzL, fs.Lval);
+    // single-column layouts with coupling rows, when every group (helpers included) can be
+    // resident at once
+    TrsvSchedHost hfx, hbx;
+    bool coupled = false;
+    if (fs.split > 0 && fs.split < fs.n && fs.helpers > 0 && sp->rmax64 >= 1) {
+      coupled = build_trsv_schedule_coupled(*fs.L, fs.n, +1, fs.split, fs.helpers, group_of, ngroups, hfx, e) &&
+                build_trsv_schedule_coupled(*fs.L, fs.n, -1, fs.split, fs.helpers, group_of, ngroups, hbx, e);
+      if (coupled) {
+        const size_t sh = trsv_shmem_bytes(std::max(hfx.nslots, hbx.nslots), false, 1);
+        const int per_cu = int(std::max<size_t>(1, std::min<size_t>(8, pb->lds_per_cu / std::max<size_t>(sh, 1))));
+        coupled = sh <= pb->lds_max && std::max(hfx.ngroups, hbx.ngroups) <= per_cu * pb->num_cu;
+      }
+    }
+    int rc = upload_schedule(pb, hf, coupled ? hfx : hf, sp->fwd, std::max(sp->rmax64, sp->rmax32), fs.n, nnzL,
+                             fs.Lval);
     if (rc) return rc;
-    rc = upload_schedule(pb, hb, sp->bwd, std::max(sp->rmax64, sp->rmax32), fs.n, nnzL, fs.Lval);
+    rc = upload_schedule(pb, hb, coupled ? hbx : hb, sp->bwd, std::max(sp->rmax64, sp->rmax32), fs.n, nnzL,
+                         fs.Lval);
     if (rc) return rc;
     CK(hipStreamSynchronize(pb->stream));
     fs.scheds.push_back(std::move(sp));
@@ -1356,20 +1396,25 @@ int check_finite(stokes_problem* pb, int R, const double* interleaved, int64_t l
 // ===========================================================================
 extern "C" {
 
-static int stokes_setup_impl(int n, int p, int dim, double nu, int geometry, stokes_problem* pb);
+static int stokes_setup_impl(int n, int p, int dim, double nu, int geometry, double c_pen, stokes_problem* pb);
 
 int stokes_setup(int n, int p, int dim, double nu, stokes_problem** out) {
-  return stokes_setup_geometry(n, p, dim, nu, STOKES_GEOMETRY_SQUARE, out);
+  return stokes_setup_nitsche(n, p, dim, nu, STOKES_GEOMETRY_SQUARE, -1.0, out);
 }
 
 int stokes_setup_geometry(int n, int p, int dim, double nu, int geometry, stokes_problem** out) {
+  return stokes_setup_nitsche(n, p, dim, nu, geometry, -1.0, out);
+}
+
+int stokes_setup_nitsche(int n, int p, int dim, double nu, int geometry, double c_pen, stokes_problem** out) {
   if (out == nullptr) return STOKES_EINVAL;
   *out = nullptr;
   if (n < 1 || n > 4096 || p < 1 || p > 3 || (dim != 2 && dim != 3) || !(nu > 0.0) || !std::isfinite(nu))
     return STOKES_EINVAL;
   if (geometry != STOKES_GEOMETRY_SQUARE && !(geometry == STOKES_GEOMETRY_ANNULUS && dim == 2)) return STOKES_EINVAL;
+  if (!std::isfinite(c_pen)) return STOKES_EINVAL;
   stokes_problem* pb = new stokes_problem();
-  const int rc = stokes_setup_impl(n, p, dim, nu, geometry, pb);
+  const int rc = stokes_setup_impl(n, p, dim, nu, geometry, c_pen, pb);
   if (rc != 0) {
     if (!pb->err.empty()) fprintf(stderr, "stokes_setup: %s\n", pb->err.c_str());
     (void)hipStreamSynchronize(pb->stream);
@@ -1380,12 +1425,12 @@ int stokes_setup_geometry(int n, int p, int dim, double nu, int geometry, stokes
   return 0;
 }
 
-static int stokes_setup_impl(int n, int p, int dim, double nu, int geometry, stokes_problem* pb) {
+static int stokes_setup_impl(int n, int p, int dim, double nu, int geometry, double c_pen, stokes_problem* pb) {
   auto t0 = std::chrono::steady_clock::now();
   pb->S = make_spaces(n, p, dim);
   pb->S.geom = geometry;
   pb->nu = nu;
-  pb->cpen = 5.0 * (p + 1);
+  pb->cpen = c_pen < 0.0 ? 5.0 * (p + 1) : c_pen;
   int dev = 0;
   CK(hipGetDevice(&dev));
   hipDeviceProp_t prop;
@@ -1495,6 +1540,10 @@ static int stokes_setup_impl(int n, int p, int dim, double nu, int geometry, sto
     fs.lev_fwd = &pb->lev_fwd;
     fs.lev_bwd = &pb->lev_bwd;
     fs.groups = [pb](int strip, std::vector<int32_t>& g, int* ng) { strip_groups(pb->S, strip, g, ng); };
+    if (pb->S.dim == 2) {
+      fs.split = pb->S.voff[1];
+      fs.helpers = kTrsvHelpers;
+    }
     SchedPair* sp = nullptr;
     int rc = get_schedule(pb, 1, false, &sp);
     if (rc) return rc;

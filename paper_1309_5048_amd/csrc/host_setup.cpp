@@ -188,52 +188,203 @@ void forward_levels(const LowerPattern& L, int64_t n, std::vector<int32_t>& lev,
   *nlev = mx + 1;
 }
 
-bool build_trsv_schedule(const LowerPattern& L, int64_t n, int dir, const std::vector<int32_t>& group_of,
-                         int ngroups, TrsvSchedHost& S, std::string& err) {
-  // Dependencies: forward, row i needs rows j < i of row i of L; backward, row i needs
-  // rows j > i with L_ji != 0 (column i of L below the diagonal).
-  std::vector<int64_t> dptr(n + 1, 0);
+// Dependency lists of a triangular solve in processing order.  Forward, row i needs rows
+// j < i of row i of L; backward, row i needs rows j > i with L_ji != 0 (column i of L below
+// the diagonal).  dval holds the index of the coefficient in L's value array.
+struct TrsvDeps {
+  int64_t n = 0;                 // rows (with coupling rows: n_u + their number)
+  std::vector<int64_t> dptr;     // [n+1]
   std::vector<int32_t> dcol;
-  std::vector<int64_t> dval;  // index of L_ij (fwd) / L_ji (bwd) in L's value array
-  std::vector<int64_t> diag(n);
-  for (int64_t i = 0; i < n; ++i) diag[i] = L.rowptr[i + 1] - 1;
+  std::vector<int64_t> dval;
+  std::vector<int64_t> diag;     // [n] index of the diagonal value
+  std::vector<int32_t> order;    // [n] processing order
+};
+
+static void trsv_deps(const LowerPattern& L, int64_t n, int dir, TrsvDeps& D) {
+  D.n = n;
+  D.dptr.assign(n + 1, 0);
+  D.dcol.clear();
+  D.dval.clear();
+  D.diag.resize(n);
+  D.order.resize(n);
+  for (int64_t i = 0; i < n; ++i) {
+    D.diag[i] = L.rowptr[i + 1] - 1;
+    D.order[i] = int32_t(dir > 0 ? i : n - 1 - i);
+  }
   if (dir > 0) {
-    dcol.reserve(L.col.size());
-    dval.reserve(L.col.size());
+    D.dcol.reserve(L.col.size());
+    D.dval.reserve(L.col.size());
     for (int64_t i = 0; i < n; ++i) {
       for (int32_t k = L.rowptr[i]; k < L.rowptr[i + 1] - 1; ++k) {
-        dcol.push_back(L.col[k]);
-        dval.push_back(k);
+        D.dcol.push_back(L.col[k]);
+        D.dval.push_back(k);
       }
-      dptr[i + 1] = int64_t(dcol.size());
+      D.dptr[i + 1] = int64_t(D.dcol.size());
     }
   } else {
     std::vector<int64_t> cnt(n + 1, 0);
     for (int64_t i = 0; i < n; ++i)
       for (int32_t k = L.rowptr[i]; k < L.rowptr[i + 1] - 1; ++k) cnt[L.col[k] + 1]++;
-    for (int64_t i = 0; i < n; ++i) dptr[i + 1] = dptr[i] + cnt[i + 1];
-    dcol.resize(dptr[n]);
-    dval.resize(dptr[n]);
-    std::vector<int64_t> fill(dptr.begin(), dptr.end() - 1);
+    for (int64_t i = 0; i < n; ++i) D.dptr[i + 1] = D.dptr[i] + cnt[i + 1];
+    D.dcol.resize(D.dptr[n]);
+    D.dval.resize(D.dptr[n]);
+    std::vector<int64_t> fill(D.dptr.begin(), D.dptr.end() - 1);
     for (int64_t j = 0; j < n; ++j)
       for (int32_t k = L.rowptr[j]; k < L.rowptr[j + 1] - 1; ++k) {
         const int64_t i = L.col[k];
-        dcol[fill[i]] = int32_t(j);
-        dval[fill[i]] = k;
+        D.dcol[fill[i]] = int32_t(j);
+        D.dval[fill[i]] = k;
         fill[i]++;
       }
   }
-  // levels in processing order
-  std::vector<int32_t> lev(n, 0);
+}
+
+// Coupling rows.  With the rows split into two blocks at `split`, the rows of the block
+// solved second (forward: i >= split; backward: i < split) depend on rows of the other
+// block.  Each such row i gets a coupling row c_i = sum over those dependencies of the
+// coefficient times the value, written as one more row of the triangular system (its
+// dependencies with their coefficients, right-hand side 0, diagonal -1: (0 - sum)/(-1)),
+// and row i keeps its own block's dependencies plus c_i with coefficient 1.  Coupling rows
+// are processed between the two blocks.  cpl_row[k] is the row of coupling row n + k.
+static void trsv_couple(TrsvDeps& D, int64_t split, int dir, std::vector<int32_t>& cpl_row) {
+  const int64_t n = D.n;
+  auto dependent = [&](int64_t i) { return dir > 0 ? i >= split : i < split; };
+  auto source = [&](int64_t j) { return dir > 0 ? j < split : j >= split; };
+  cpl_row.clear();
+  for (int64_t i = 0; i < n; ++i) {
+    if (!dependent(i)) continue;
+    for (int64_t k = D.dptr[i]; k < D.dptr[i + 1]; ++k)
+      if (source(D.dcol[k])) {
+        cpl_row.push_back(int32_t(i));
+        break;
+      }
+  }
+  const int64_t nc = int64_t(cpl_row.size());
+  std::vector<int32_t> cpl_of(n, -1);
+  for (int64_t k = 0; k < nc; ++k) cpl_of[cpl_row[k]] = int32_t(n + k);
+  TrsvDeps X;
+  X.n = n + nc;
+  X.dptr.assign(X.n + 1, 0);
+  X.diag.resize(X.n);
+  X.dcol.reserve(D.dcol.size() + nc);
+  X.dval.reserve(D.dval.size() + nc);
+  for (int64_t i = 0; i < n; ++i) {
+    X.diag[i] = D.diag[i];
+    for (int64_t k = D.dptr[i]; k < D.dptr[i + 1]; ++k)
+      if (cpl_of[i] < 0 || !source(D.dcol[k])) {
+        X.dcol.push_back(D.dcol[k]);
+        X.dval.push_back(D.dval[k]);
+      }
+    if (cpl_of[i] >= 0) {
+      X.dcol.push_back(cpl_of[i]);
+      X.dval.push_back(kTrsvValOne);
+    }
+    X.dptr[i + 1] = int64_t(X.dcol.size());
+  }
+  for (int64_t c = 0; c < nc; ++c) {
+    const int64_t i = cpl_row[c];
+    X.diag[n + c] = kTrsvValMinusOne;
+    for (int64_t k = D.dptr[i]; k < D.dptr[i + 1]; ++k)
+      if (source(D.dcol[k])) {
+        X.dcol.push_back(D.dcol[k]);
+        X.dval.push_back(D.dval[k]);
+      }
+    X.dptr[n + c + 1] = int64_t(X.dcol.size());
+  }
+  // processing order: the source block, the coupling rows, the dependent block
+  X.order.clear();
+  X.order.reserve(X.n);
+  for (int32_t i : D.order)
+    if (!dependent(i)) X.order.push_back(i);
+  for (int64_t c = 0; c < nc; ++c) X.order.push_back(int32_t(n + c));
+  for (int32_t i : D.order)
+    if (dependent(i)) X.order.push_back(i);
+  D = std::move(X);
+}
+
+static std::vector<int32_t> trsv_levels(const TrsvDeps& D, int* nlevels) {
+  std::vector<int32_t> lev(D.n, 0);
   int maxlev = 0;
-  for (int64_t t = 0; t < n; ++t) {
-    const int64_t i = dir > 0 ? t : n - 1 - t;
+  for (int32_t i : D.order) {
     int l = 0;
-    for (int64_t k = dptr[i]; k < dptr[i + 1]; ++k) l = std::max(l, lev[dcol[k]] + 1);
+    for (int64_t k = D.dptr[i]; k < D.dptr[i + 1]; ++k) l = std::max(l, lev[D.dcol[k]] + 1);
     lev[i] = l;
     maxlev = std::max(maxlev, l);
   }
-  S.nlevels = maxlev + 1;
+  *nlevels = maxlev + 1;
+  return lev;
+}
+
+static bool schedule_core(const TrsvDeps& D, const std::vector<int32_t>& lev, int nlevels,
+                          const std::vector<int32_t>& group_of, int ngroups, const std::vector<char>& pack,
+                          TrsvSchedHost& S, std::string& err);
+
+bool build_trsv_schedule(const LowerPattern& L, int64_t n, int dir, const std::vector<int32_t>& group_of,
+                         int ngroups, TrsvSchedHost& S, std::string& err) {
+  TrsvDeps D;
+  trsv_deps(L, n, dir, D);
+  int nl = 0;
+  const std::vector<int32_t> lev = trsv_levels(D, &nl);
+  S.nrows = n;
+  S.ncpl = 0;
+  S.cpl_row.clear();
+  S.grp_cpl.assign(ngroups, 0);
+  return schedule_core(D, lev, nl, group_of, ngroups, std::vector<char>(ngroups, 0), S, err);
+}
+
+bool build_trsv_schedule_coupled(const LowerPattern& L, int64_t n, int dir, int64_t split, int helpers,
+                                 const std::vector<int32_t>& group_of, int ngroups, TrsvSchedHost& S,
+                                 std::string& err) {
+  TrsvDeps D;
+  trsv_deps(L, n, dir, D);
+  std::vector<int32_t> cpl_row;
+  trsv_couple(D, split, dir, cpl_row);
+  int nl = 0;
+  const std::vector<int32_t> lev = trsv_levels(D, &nl);
+  const int64_t nc = int64_t(cpl_row.size());
+  // helper groups: `helpers` per group of the dependent block; a group's coupling rows in
+  // (level, processing) order are dealt to its helpers in runs of one step
+  std::vector<int32_t> hbase(ngroups, -1);
+  int ng = ngroups;
+  for (int64_t c = 0; c < nc; ++c) {
+    const int g = group_of[cpl_row[c]];
+    if (hbase[g] < 0) {
+      hbase[g] = ng;
+      ng += helpers;
+    }
+  }
+  std::vector<int32_t> gx(group_of);
+  gx.resize(D.n, 0);
+  std::vector<std::vector<int32_t>> per(ngroups);
+  for (int32_t i : D.order)
+    if (i >= n) per[group_of[cpl_row[i - n]]].push_back(i);
+  for (int g = 0; g < ngroups; ++g) {
+    auto& v = per[g];
+    std::stable_sort(v.begin(), v.end(), [&](int32_t a, int32_t b) { return lev[a] < lev[b]; });
+    for (size_t r = 0; r < v.size(); ++r) gx[v[r]] = hbase[g] + int32_t((r / kTrsvRPS) % helpers);
+  }
+  std::vector<char> pack(ng, 0);
+  for (int g = ngroups; g < ng; ++g) pack[g] = 1;
+  S.nrows = n;
+  S.ncpl = nc;
+  S.cpl_row = cpl_row;
+  S.grp_cpl.assign(ng, 0);
+  for (int g = ngroups; g < ng; ++g) S.grp_cpl[g] = 1;
+  return schedule_core(D, lev, nl, gx, ng, pack, S, err);
+}
+
+// Steps, LDS slots and halo lists of a schedule.  A group's rows are taken in (level,
+// processing) order, in steps of <= kTrsvRPS rows of one level; a packed group (whose rows
+// do not depend on each other) fills every step regardless of level.
+static bool schedule_core(const TrsvDeps& D, const std::vector<int32_t>& lev, int nlevels,
+                          const std::vector<int32_t>& group_of, int ngroups, const std::vector<char>& pack,
+                          TrsvSchedHost& S, std::string& err) {
+  const int64_t n = D.n;
+  const std::vector<int64_t>& dptr = D.dptr;
+  const std::vector<int32_t>& dcol = D.dcol;
+  const std::vector<int64_t>& dval = D.dval;
+  const std::vector<int64_t>& diag = D.diag;
+  S.nlevels = nlevels;
   int maxdeg = 0;
   for (int64_t i = 0; i < n; ++i) maxdeg = std::max<int>(maxdeg, int(dptr[i + 1] - dptr[i]));
   S.max_deg = maxdeg;
@@ -247,10 +398,7 @@ bool build_trsv_schedule(const LowerPattern& L, int64_t n, int dir, const std::v
 
   // rows of each group sorted by (level, processing order); steps of <= RPS rows of one level
   std::vector<std::vector<int32_t>> grows(ngroups);
-  for (int64_t t = 0; t < n; ++t) {
-    const int64_t i = dir > 0 ? t : n - 1 - t;
-    grows[group_of[i]].push_back(int32_t(i));
-  }
+  for (int32_t i : D.order) grows[group_of[i]].push_back(i);
   std::vector<int32_t> step_of(n, -1);  // group-relative step of each row
   std::vector<std::vector<int32_t>> gstep_begin(ngroups);  // row offsets of steps in grows[g]
   for (int g = 0; g < ngroups; ++g) {
@@ -261,7 +409,7 @@ bool build_trsv_schedule(const LowerPattern& L, int64_t n, int dir, const std::v
     while (k < v.size()) {
       const int lv = lev[v[k]];
       size_t k1 = k;
-      while (k1 < v.size() && lev[v[k1]] == lv && int(k1 - k) < RPS) ++k1;
+      while (k1 < v.size() && (pack[g] || lev[v[k1]] == lv) && int(k1 - k) < RPS) ++k1;
       for (size_t r = k; r < k1; ++r) step_of[v[r]] = int32_t(sb.size());
       sb.push_back(int32_t(k));
       k = k1;

@@ -13,16 +13,21 @@ namespace stk {
 constexpr int kIcMaxRow = 128;
 constexpr int kIcWaves = 4;
 
-// L values initialised from A (with the diagonal shift alpha * A_ii).
-__global__ void k_ic0_init(int64_t nnzL, const int64_t* __restrict__ src, const int32_t* __restrict__ Lrowptr,
-                           int64_t n, const double* __restrict__ Aval, double alpha, double* __restrict__ Lval,
-                           int* __restrict__ flag) {
+// L values initialised from A, then the diagonal shift alpha * A_ii in a second launch
+// (a diagonal entry is also an entry of the copy: one writer per launch).
+__global__ void k_ic0_init(int64_t nnzL, const int64_t* __restrict__ src, const double* __restrict__ Aval,
+                           double* __restrict__ Lval, int* __restrict__ flag) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k == 0) *flag = -1;
   if (k < nnzL) Lval[k] = Aval[src[k]];
+}
+
+__global__ void k_ic0_shift(const int64_t* __restrict__ src, const int32_t* __restrict__ Lrowptr, int64_t n,
+                            const double* __restrict__ Aval, double alpha, double* __restrict__ Lval) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) {
     const int64_t d = Lrowptr[k + 1] - 1;
-    Lval[d] = Aval[src[d]] * (1.0 + alpha);
+    Lval[d] = Aval[src[d]] + alpha * Aval[src[d]];
   }
 }
 
@@ -118,9 +123,11 @@ __global__ __launch_bounds__(64 * kIcWaves) void k_ic0_level(const int32_t* __re
 hipError_t ic0_factor(int64_t n, int64_t nnzL, const int64_t* src, const int32_t* rowptr, const int32_t* col,
                       const double* Aval, double alpha, double* Lval, const int32_t* level_rows,
                       const std::vector<int32_t>& level_ptr, int* flag, hipStream_t st) {
-  const int64_t cnt = std::max(nnzL, n);
-  hipLaunchKernelGGL(k_ic0_init, dim3(unsigned((cnt + 255) / 256)), dim3(256), 0, st, nnzL, src, rowptr, n, Aval,
-                     alpha, Lval, flag);
+  hipLaunchKernelGGL(k_ic0_init, dim3(unsigned((std::max<int64_t>(nnzL, 1) + 255) / 256)), dim3(256), 0, st, nnzL,
+                     src, Aval, Lval, flag);
+  if (alpha != 0.0)
+    hipLaunchKernelGGL(k_ic0_shift, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, src, rowptr, n, Aval, alpha,
+                       Lval);
   for (size_t l = 0; l + 1 < level_ptr.size(); ++l) {
     const int nr = level_ptr[l + 1] - level_ptr[l];
     if (nr == 0) continue;

@@ -181,11 +181,13 @@ __device__ __forceinline__ int computed_steps(int* ctr) {
   }
 }
 
+// Rows nrows .. nrows + ncpl - 1 are coupling rows, read from cpl (R = 1 layouts only).
 template <typename T, int R, int NW = 0>
 __device__ __forceinline__ void halo_wave(const int32_t* __restrict__ grp_halo_ptr, const int32_t* __restrict__ halo_row,
                                           const int32_t* __restrict__ halo_slot,
                                           const int32_t* __restrict__ halo_free, int nrows, int nslots, int ld,
-                                          int* err, int g, int lane, int* ctr, T* xs, const T* out) {
+                                          int* err, int g, int lane, int* ctr, T* xs, const T* out,
+                                          const T* cpl = nullptr, int ncpl = 0) {
   const int h0 = grp_halo_ptr[g], h1 = grp_halo_ptr[g + 1];
   const int nhalo = h1 - h0;
   int pos = 0;
@@ -199,13 +201,14 @@ __device__ __forceinline__ void halo_wave(const int32_t* __restrict__ grp_halo_p
       slot = halo_slot[h0 + idx];
       fr = halo_free[h0 + idx];
     }
-    const bool inb = valid && row >= 0 && row < nrows && slot > 0 && slot < nslots;
+    const bool inb = valid && row >= 0 && row < nrows + ncpl && slot > 0 && slot < nslots;
     T v[R];
     bool ready = true;
     if (inb) {
+      const T* src = row < nrows ? out + (size_t)row * ld : cpl + (size_t)(row - nrows) * ld;
 #pragma unroll
       for (int c = 0; c < R; ++c) {
-        v[c] = dev_load(out + (size_t)row * ld + c);
+        v[c] = dev_load(src + c);
         ready = ready && !is_sentinel(v[c]);
       }
       ready = ready && computed_steps<NW>(ctr) >= fr;
@@ -642,12 +645,15 @@ struct FastArgs {
   const int32_t* halo_row;
   const int32_t* halo_slot;
   const int32_t* halo_free;
+  const int32_t* grp_cpl;
+  void* cpl;
   unsigned int* done_count;
   int* err;
   double* partials;
   int ngroups;
   int nslots;
   int nrows;
+  int ncpl;
 };
 
 template <typename T>
@@ -719,7 +725,10 @@ __device__ __forceinline__ double fast_compute(const FastArgs& a, const FastDyn<
   const int64_t b0 = uniform64(a.grp_blk[g]), b1 = uniform64(a.grp_blk[g + 1]);
   const __amdgpu_buffer_rsrc_t rb = make_rsrc(a.blk + b0, (uint32_t)(b1 - b0));
   const __amdgpu_buffer_rsrc_t rd = make_rsrc(dyn + (size_t)s0 * kTrsvRPS, (uint32_t)nalloc * DYN);
-  const __amdgpu_buffer_rsrc_t ro = make_rsrc(out, (uint32_t)a.nrows * (uint32_t)sizeof(T));
+  // a group's rows are all rows of the factor or all coupling rows (stored apart)
+  const bool cgrp = uniform32(a.grp_cpl[g]) != 0;
+  const __amdgpu_buffer_rsrc_t ro = cgrp ? make_rsrc(a.cpl, (uint32_t)a.ncpl * (uint32_t)sizeof(T))
+                                         : make_rsrc(out, (uint32_t)a.nrows * (uint32_t)sizeof(T));
   const int r = lane / kTrsvG;
   const uint32_t o_rec = (uint32_t)r * 16u;
   const uint32_t o_slot = (uint32_t)(OFF_SLOT + lane * EP * 4);
@@ -837,7 +846,7 @@ __global__ __launch_bounds__(kTrsvThreads) __attribute__((amdgpu_waves_per_eu(1,
       dacc = fast_compute<T, 8, fast_depth(8), kDot>(a, dyn, out, smem, g, lane);
   } else {
     halo_wave<T, 1>(a.grp_halo_ptr, a.halo_row, a.halo_slot, a.halo_free, a.nrows, a.nslots, 1, a.err, g, lane, ctr,
-                    xs, out);
+                    xs, out, reinterpret_cast<const T*>(a.cpl), a.ncpl);
   }
   __syncthreads();
   if (tid == 0 && lds_load(&ctr[CTR_ERR]) != 0) raise_err(a.err);
@@ -861,21 +870,28 @@ __global__ __launch_bounds__(kTrsvThreads) __attribute__((amdgpu_waves_per_eu(1,
 }
 
 // Per-solve {rhs, dot} pairs in the single-column step order (repeats carry dot = 0) and
-// the output rows reset to the sentinel.
+// the output rows reset to the sentinel.  Coupling rows (row >= nrows) have right-hand side
+// and dot entry 0; their outputs in cpl are reset too.
 template <typename T>
 __global__ void k_fast_gather_dyn(int64_t nrow_slots, const int32_t* __restrict__ srow2, const T* __restrict__ rhs,
                                   const T* __restrict__ dotv, FastDyn<T>* __restrict__ dyn, T* __restrict__ out,
-                                  const int* __restrict__ skip) {
+                                  T* __restrict__ cpl, int nrows, const int* __restrict__ skip) {
   if (skip != nullptr && *skip) return;
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nrow_slots;
        k += (int64_t)gridDim.x * blockDim.x) {
     const int r2 = srow2[k];
     const int row = r2 >= 0 ? r2 : ~r2;
     FastDyn<T> v;
-    v.rhs = rhs[row];
-    v.dot = (r2 >= 0 && dotv != nullptr) ? dotv[row] : T(0);
+    if (row < nrows) {
+      v.rhs = rhs[row];
+      v.dot = (r2 >= 0 && dotv != nullptr) ? dotv[row] : T(0);
+      if (r2 >= 0) out[row] = sentinel_value<T>();
+    } else {
+      v.rhs = T(0);
+      v.dot = T(0);
+      if (r2 >= 0) cpl[row - nrows] = sentinel_value<T>();
+    }
     dyn[k] = v;
-    if (r2 >= 0) out[row] = sentinel_value<T>();
   }
 }
 
@@ -895,7 +911,7 @@ __global__ void k_fast_gather_static(int64_t nsteps, const int64_t* __restrict__
     float* v32 = reinterpret_cast<float*>(blk32 + step_val32[s]) + lane * ep;
     for (int e = 0; e < ep; ++e) {
       const int32_t p = vperm[(s * 64 + lane) * 8 + e];
-      const double v = p >= 0 ? Lval[p] : 0.0;
+      const double v = p >= 0 ? Lval[p] : (p == (int32_t)kTrsvValOne ? 1.0 : 0.0);
       v64[e] = v;
       v32[e] = (float)v;
     }
@@ -903,8 +919,9 @@ __global__ void k_fast_gather_static(int64_t nsteps, const int64_t* __restrict__
       const int32_t p = dsrc[s * kTrsvRPS + lane];
       FastRec64* r64 = reinterpret_cast<FastRec64*>(blk64 + step_val64[s] - (kFastHdr + 64 * ep * 4)) + lane;
       FastRec32* r32 = reinterpret_cast<FastRec32*>(blk32 + step_val32[s] - (kFastHdr + 64 * ep * 4)) + lane;
-      r64->dinv = p >= 0 ? 1.0 / Lval[p] : 0.0;
-      r32->dinv = p >= 0 ? 1.0f / (float)Lval[p] : 0.0f;
+      const double dinv = p >= 0 ? 1.0 / Lval[p] : (p == (int32_t)kTrsvValMinusOne ? -1.0 : 0.0);
+      r64->dinv = dinv;
+      r32->dinv = p >= 0 ? 1.0f / (float)Lval[p] : (float)dinv;
     }
   }
 }
@@ -922,27 +939,30 @@ static hipError_t launch_trsv_fast(const TrsvSchedDev& S, const T* rhs, T* out, 
   a.grp_ep = F.grp_ep;
   a.grp_blk = sizeof(T) == 8 ? F.grp_blk64 : F.grp_blk32;
   a.blk = sizeof(T) == 8 ? F.blk64 : F.blk32;
-  a.grp_halo_ptr = S.grp_halo_ptr;
-  a.halo_row = S.halo_row;
-  a.halo_slot = S.halo_slot;
-  a.halo_free = S.halo_free;
-  a.done_count = S.done_count;
+  a.grp_halo_ptr = F.grp_halo_ptr;
+  a.halo_row = F.halo_row;
+  a.halo_slot = F.halo_slot;
+  a.halo_free = F.halo_free;
+  a.grp_cpl = F.grp_cpl;
+  a.cpl = F.cpl;
+  a.done_count = F.done_count;
   a.err = S.err;
-  a.partials = S.partials;
-  a.ngroups = S.ngroups;
-  a.nslots = S.nslots;
-  a.nrows = S.nrows;
+  a.partials = F.partials;
+  a.ngroups = F.ngroups;
+  a.nslots = F.nslots;
+  a.nrows = F.nrows;
+  a.ncpl = F.ncpl;
   FastDyn<T>* dyn = reinterpret_cast<FastDyn<T>*>(F.dyn);
   hipLaunchKernelGGL(k_fast_gather_dyn<T>, dim3(1024), dim3(256), 0, st, (int64_t)F.nsteps * kTrsvRPS, F.srow2, rhs,
-                     dotv, dyn, out, skip);
-  const size_t shmem = trsv_shmem_t<T, 1>(S.nslots);
+                     dotv, dyn, out, reinterpret_cast<T*>(F.cpl), F.nrows, skip);
+  const size_t shmem = trsv_shmem_t<T, 1>(F.nslots);
   const void* fn = dotv != nullptr ? (const void*)k_trsv_fast<T, true> : (const void*)k_trsv_fast<T, false>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
   if (e != hipSuccess) return e;
   const FastDyn<T>* dync = dyn;
   void* args[] = {&a, &dync, &out, &dot_out, &skip};
   if (tm && tm->before) (void)hipEventRecord(tm->before, st);
-  e = hipLaunchKernel(fn, dim3(S.ngroups), dim3(kTrsvThreads), args, shmem, st);
+  e = hipLaunchKernel(fn, dim3(F.ngroups), dim3(kTrsvThreads), args, shmem, st);
   if (tm && tm->after) (void)hipEventRecord(tm->after, st);
   return e;
 }

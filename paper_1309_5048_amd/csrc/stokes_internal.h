@@ -61,10 +61,24 @@ constexpr int kTrsvRPS = 64 / kTrsvG;      // rows per step (one compute wave)
 constexpr int kTrsvThreads = 128;          // compute wavefront + halo wavefront
 constexpr int kTrsvHaloLookahead = 16;     // steps before first use a halo slot is allocated
 constexpr int kLevelStride = 1 << 21;      // progress value = epoch * stride + level + 1
+#ifndef STOKES_TRSV_HELPERS
+#define STOKES_TRSV_HELPERS 2
+#endif
+constexpr int kTrsvHelpers = STOKES_TRSV_HELPERS;  // coupling-row groups per strip (2D solves)
+
+// Value codes of schedule entries that are not factor entries: -1 padding (value 0), and
+// for coupling rows the coefficient 1 of a coupling value in its row and the diagonal -1
+// of a coupling row.
+constexpr int64_t kTrsvValOne = -2;
+constexpr int64_t kTrsvValMinusOne = -3;
 
 struct TrsvSchedHost {
   int ngroups = 0, nsteps = 0, E = 0, nlevels = 0, nslots = 0, strip = 0;
   int max_deg = 0;
+  int64_t nrows = 0;                       // rows of the factor
+  int64_t ncpl = 0;                        // coupling rows (numbered nrows, nrows + 1, ...)
+  std::vector<int32_t> cpl_row;            // [ncpl] the row whose coupling value it is
+  std::vector<int32_t> grp_cpl;            // [ngroups] 1: the group computes coupling rows
   std::vector<int32_t> grp_step_ptr;       // [ngroups+1]
   std::vector<int32_t> grp_halo_ptr;       // [ngroups+1]
   std::vector<int32_t> halo_row;           // remote row (global index)
@@ -152,8 +166,16 @@ struct TrsvFastDev {
   int32_t* step_ep = nullptr;      // [nsteps]
   int32_t* vperm = nullptr;        // [nsteps][64][8] index in L values or -1
   int32_t* dsrc = nullptr;         // [nsteps * RPS] index of the diagonal in L values
-  int32_t* srow2 = nullptr;        // [nsteps * RPS] row, or ~row for a repeat
+  int32_t* srow2 = nullptr;        // [nsteps * RPS] row, or ~row for a repeat (rows >= nrows:
+                                   // coupling rows)
   void* dyn = nullptr;             // [nsteps * RPS] {rhs, dot} (16 bytes)
+  // Groups and halo lists of this layout (its own: with coupling rows it has helper groups)
+  int ngroups = 0, nslots = 0, nrows = 0, ncpl = 0;
+  int32_t *grp_halo_ptr = nullptr, *halo_row = nullptr, *halo_slot = nullptr, *halo_free = nullptr;
+  int32_t* grp_cpl = nullptr;      // [ngroups] 1: the group's rows are coupling rows
+  void* cpl = nullptr;             // [ncpl] coupling values (FP64; FP32 solves use the front half)
+  unsigned int* done_count = nullptr;
+  double* partials = nullptr;      // [ngroups]
 };
 
 struct TrsvSchedDev {
@@ -184,6 +206,13 @@ struct TrsvSchedDev {
 // of each row (spatial strips).  Returns false with err on failure.
 bool build_trsv_schedule(const LowerPattern& L, int64_t n, int dir, const std::vector<int32_t>& group_of,
                          int ngroups, TrsvSchedHost& S, std::string& err);
+
+// The same with the off-block dependencies of the block solved second moved into coupling
+// rows (rows are split into two blocks at `split`), computed by `helpers` extra groups per
+// group of that block.
+bool build_trsv_schedule_coupled(const LowerPattern& L, int64_t n, int dir, int64_t split, int helpers,
+                                 const std::vector<int32_t>& group_of, int ngroups, TrsvSchedHost& S,
+                                 std::string& err);
 
 // Strip partition of the velocity rows: component c, last-direction 1D index t -> group
 // offset_c + t / strip.

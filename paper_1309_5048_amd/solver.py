@@ -31,19 +31,20 @@ def _dev(t, name, numel=None):
 
 
 class StokesProblem:
-    """stokes_setup_geometry(n, p, dim, nu, geometry): n elements per direction, pressure
-    degree p (= k'), velocity degree p+1 with maximal continuity, on the unit square (dim 2)
-    or cube (dim 3), or (geometry = GEOMETRY_ANNULUS, 2D) on the 1/8 annulus."""
+    """stokes_setup_nitsche(n, p, dim, nu, geometry, c_pen): n elements per direction,
+    pressure degree p (= k'), velocity degree p+1 with maximal continuity, on the unit square
+    (dim 2) or cube (dim 3), or (geometry = GEOMETRY_ANNULUS, 2D) on the 1/8 annulus; c_pen < 0
+    selects the paper's Nitsche constant 5(k'+1)."""
 
-    def __init__(self, n, p, dim=2, nu=1.0, device=None, geometry=N.GEOMETRY_SQUARE):
+    def __init__(self, n, p, dim=2, nu=1.0, device=None, geometry=N.GEOMETRY_SQUARE, c_pen=-1.0):
         self._L = N.lib()
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self._h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
-            rc = self._L.stokes_setup_geometry(int(n), int(p), int(dim), float(nu), int(geometry),
-                                               ctypes.byref(self._h))
+            rc = self._L.stokes_setup_nitsche(int(n), int(p), int(dim), float(nu), int(geometry),
+                                              float(c_pen), ctypes.byref(self._h))
         if rc != 0 or not self._h:
-            raise StokesError(rc, "stokes_setup(%d, %d, %d, %g) failed" % (n, p, dim, nu))
+            raise StokesError(rc, "stokes_setup(%d, %d, %d, %g, c_pen %g) failed" % (n, p, dim, nu, c_pen))
         self.n, self.p, self.dim, self.nu, self.geometry = n, p, dim, nu, geometry
         a, b = ctypes.c_int64(), ctypes.c_int64()
         self._L.stokes_sizes(self._h, ctypes.byref(a), ctypes.byref(b))

@@ -1,11 +1,13 @@
 // CPU checks of the library's host-side integer logic (test support, not shipped):
 //  * export of the closed-form saddle sparsity pattern, for comparison with the oracle;
-//  * an emulator of the three-wave triangular-solve protocol that executes a schedule
-//    with interleaved group progress and verifies, for every LDS read, that the slot
-//    holds the value of the expected row (slot-lifetime allocation), that halo values
-//    are staged only after their producer published them, that no wait can deadlock,
-//    and that every index is inside its buffer; the result is compared with a direct
-//    triangular solve.
+//  * an emulator of the triangular-solve protocol (compute and halo wavefronts) that
+//    executes a schedule with interleaved group progress and verifies, for every LDS read,
+//    that the slot holds the value of the expected row (slot-lifetime allocation), that
+//    halo values are staged only after their producer wrote them (the kernels poll for the
+//    sentinel to be overwritten), that no wait can deadlock, and that every index is inside
+//    its buffer; the result is compared with a direct triangular solve.  Schedules with
+//    coupling rows (helper groups) are executed the same way, with the coupling values in
+//    rows n, n + 1, ... of the output.
 #include <cmath>
 #include <cstdio>
 #include <random>
@@ -30,9 +32,11 @@ std::vector<double> emulate(const TrsvSchedHost& S, const LowerPattern& L, const
                             const std::vector<int32_t>& lrow, int64_t n, int dir, const std::vector<double>& b,
                             Emu& emu, long* rounds_out) {
   const int G = S.ngroups, E = S.E, RPS = kTrsvRPS;
-  std::vector<double> out(n, std::nan(""));
-  std::vector<char> written(n, 0);
-  std::vector<long long> progress(G, -1);  // highest published level
+  const int64_t nx = n + S.ncpl;  // rows with the coupling rows
+  std::vector<int32_t> cpl_of(n, -1);
+  for (int64_t c = 0; c < S.ncpl; ++c) cpl_of[S.cpl_row[c]] = int32_t(n + c);
+  std::vector<double> out(nx, std::nan(""));
+  std::vector<char> written(nx, 0);
   std::vector<int> k(G, 0), hpos(G, 0);
   std::vector<std::vector<double>> xs(G, std::vector<double>(S.nslots, std::nan("")));
   std::vector<std::vector<int32_t>> tag(G, std::vector<int32_t>(S.nslots, -2));
@@ -50,15 +54,12 @@ std::vector<double> emulate(const TrsvSchedHost& S, const LowerPattern& L, const
       while (hpos[g] < nh) {
         const int e = h0 + hpos[g];
         const int prod = S.halo_grp[e], lvl = S.halo_lvl[e], slot = S.halo_slot[e], row = S.halo_row[e];
-        if (prod < 0 || prod >= G || slot <= 0 || slot >= S.nslots || row < 0 || row >= n) {
+        if (prod < 0 || prod >= G || slot <= 0 || slot >= S.nslots || row < 0 || row >= nx) {
           emu.bad("halo entry out of range");
           return out;
         }
-        if (!(progress[prod] >= lvl && k[g] >= S.halo_free[e])) break;
-        if (!written[row]) {
-          emu.bad("halo value staged before the producer wrote it");
-          return out;
-        }
+        (void)lvl;
+        if (!(written[row] && k[g] >= S.halo_free[e])) break;
         xs[g][slot] = out[row];
         tag[g][slot] = row;
         ++hpos[g];
@@ -72,7 +73,7 @@ std::vector<double> emulate(const TrsvSchedHost& S, const LowerPattern& L, const
           for (int r = 0; r < RPS; ++r) {
             const int row = S.srow[size_t(ss) * RPS + r];
             if (row < 0) continue;
-            if (row >= n) {
+            if (row >= nx || (row >= n) != (S.grp_cpl[g] != 0)) {
               emu.bad("step row out of range");
               return out;
             }
@@ -86,19 +87,39 @@ std::vector<double> emulate(const TrsvSchedHost& S, const LowerPattern& L, const
                   emu.bad("entry slot out of range");
                   return out;
                 }
-                if (perm < 0) {
+                if (perm == -1) {
                   if (src != 0) emu.bad("padding entry not on the zero slot");
                   continue;
                 }
-                const int32_t dep = dir > 0 ? L.col[perm] : lrow[perm];
+                int32_t dep;
+                double coef;
+                if (perm == kTrsvValOne) {
+                  if (row >= n || cpl_of[row] < 0) {
+                    emu.bad("coupling entry in a row without a coupling row");
+                    return out;
+                  }
+                  dep = cpl_of[row];
+                  coef = 1.0;
+                } else if (perm >= 0 && perm < int64_t(Lval.size())) {
+                  dep = dir > 0 ? L.col[perm] : lrow[perm];
+                  coef = Lval[perm];
+                } else {
+                  emu.bad("entry value index out of range");
+                  return out;
+                }
                 if (tag[g][src] != dep) {
                   emu.bad("LDS slot does not hold the expected dependency (slot reuse or unstaged halo)");
                   return out;
                 }
-                acc += Lval[perm] * xs[g][src];
+                acc += coef * xs[g][src];
               }
             const int64_t dsrc = S.sdiag_src[size_t(ss) * RPS + r];
-            const double x = (b[row] - acc) / Lval[dsrc];
+            const bool is_cpl = row >= n;
+            if (is_cpl != (dsrc == kTrsvValMinusOne)) {
+              emu.bad("coupling row without the diagonal -1, or the reverse");
+              return out;
+            }
+            const double x = ((is_cpl ? 0.0 : b[row]) - acc) / (is_cpl ? -1.0 : Lval[dsrc]);
             const int slot = S.sslot[size_t(ss) * RPS + r];
             if (slot < 0 || slot >= S.nslots) {
               emu.bad("result slot out of range");
@@ -111,7 +132,6 @@ std::vector<double> emulate(const TrsvSchedHost& S, const LowerPattern& L, const
             out[row] = x;
             written[row] = 1;
           }
-          if (S.step_publish[ss]) progress[g] = std::max<long long>(progress[g], S.step_level[ss]);
           ++k[g];
           moved = true;
         }
@@ -151,11 +171,14 @@ int hc_pattern(int N, int kp, int dim, int64_t* n_u, int64_t* n_p, int64_t* nnz,
   return 0;
 }
 
-// Build both schedules for a strip partition and emulate them on a random factor.
+// Build both schedules for a strip partition and emulate them on a random factor
+// (helpers > 0: with coupling rows for the second velocity component, that many helper
+// groups per strip).
 // stats: [0] fwd levels [1] bwd levels [2] groups [3] fwd steps [4] bwd steps [5] max slots
 //        [6] E [7] max rel error fwd [8] max rel error bwd [9] rounds fwd [10] rounds bwd
-//        [11] halo entries fwd [12] max deps per row
-int hc_schedule_check(int N, int kp, int dim, int strip, int seed, double* stats, char* msg, int msglen) {
+//        [11] halo entries fwd [12] max deps per row [13] coupling rows fwd
+int hc_schedule_check(int N, int kp, int dim, int strip, int seed, int helpers, double* stats, char* msg,
+                      int msglen) {
   Spaces S = make_spaces(N, kp, dim);
   SaddlePattern P;
   std::string err;
@@ -178,8 +201,11 @@ int hc_schedule_check(int N, int kp, int dim, int strip, int seed, double* stats
   int ngroups = 0;
   strip_groups(S, strip, group_of, &ngroups);
   TrsvSchedHost F, B;
-  if (!build_trsv_schedule(L, n, +1, group_of, ngroups, F, err) ||
-      !build_trsv_schedule(L, n, -1, group_of, ngroups, B, err)) {
+  const int64_t split = S.voff[1];
+  if (helpers > 0 ? (!build_trsv_schedule_coupled(L, n, +1, split, helpers, group_of, ngroups, F, err) ||
+                     !build_trsv_schedule_coupled(L, n, -1, split, helpers, group_of, ngroups, B, err))
+                  : (!build_trsv_schedule(L, n, +1, group_of, ngroups, F, err) ||
+                     !build_trsv_schedule(L, n, -1, group_of, ngroups, B, err))) {
     snprintf(msg, msglen, "%s", err.c_str());
     return -2;
   }
@@ -209,7 +235,7 @@ int hc_schedule_check(int N, int kp, int dim, int strip, int seed, double* stats
     }
   stats[0] = F.nlevels;
   stats[1] = B.nlevels;
-  stats[2] = ngroups;
+  stats[2] = F.ngroups;
   stats[3] = F.nsteps;
   stats[4] = B.nsteps;
   stats[5] = std::max(F.nslots, B.nslots);
@@ -220,6 +246,7 @@ int hc_schedule_check(int N, int kp, int dim, int strip, int seed, double* stats
   stats[10] = double(rb);
   stats[11] = double(F.halo_row.size());
   stats[12] = std::max(F.max_deg, B.max_deg);
+  stats[13] = double(F.ncpl);
   if (!emu.ok) {
     snprintf(msg, msglen, "%s", emu.msg);
     return -3;

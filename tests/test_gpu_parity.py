@@ -92,6 +92,54 @@ def test_ic0_factor(pair):
     assert np.abs(val - oval).max() <= 1e-12 * np.abs(oval).max()
 
 
+@pytest.mark.parametrize("N,kp,cpen,shift", [(8, 2, 1.7, 3), (8, 1, 0.45, 3), (8, 2, 2.0, 0), (8, 2, 1.0, None)],
+                         ids=["k2_cpen1.7", "k1_cpen0.45", "k2_cpen2", "k2_cpen1_breakdown"])
+def test_ic0_shift_policy(N, kp, cpen, shift):
+    """IC(0) of A with the setup's diagonal-shift retries (alpha = 1e-3, 1e-2, 1e-1 of
+    diag(A)) under a Nitsche constant below the paper's (Sec. 4 penalty 2 nu c_pen / h_F).
+    At c_pen 1.7 (k' = 2) and 0.45 (k' = 1) A is slightly indefinite (smallest eigenvalue
+    -0.014 and -0.030): IC(0) breaks down until the shift of 1e-1, on both sides.  At c_pen 2
+    no shift is needed; at 1.0 every shift fails and setup reports STOKES_EBREAKDOWN.  The
+    device matrix, shift count and factor against the oracle's, then the solve: stop counts
+    at tol 1e-8 within +-1 and solutions at tol 1e-12 within 1e-10 (reversing the oracle's
+    summation order moves them by 3e-12 at most)."""
+    from paper_1309_5048_amd import StokesError, StokesProblem
+    from paper_1309_5048_amd._native import STOKES_EBREAKDOWN
+    print("\n[case] N=%d k'=%d c_pen=%g" % (N, kp, cpen), flush=True)
+    o = Oracle(N, kp, 2, 1.0, cpen)
+    rc, so = o.ic0()
+    if shift is None:
+        assert rc == -4
+        with pytest.raises(StokesError) as e:
+            StokesProblem(N, kp, 2, 1.0, c_pen=cpen)
+        assert e.value.code == STOKES_EBREAKDOWN
+        return
+    assert rc == 0 and so == shift
+    gp = StokesProblem(N, kp, 2, 1.0, c_pen=cpen)
+    try:
+        ptr, col, val = gp.export_csr(0)
+        K = o.saddle().tocsr()
+        K.sort_indices()
+        assert np.array_equal(ptr, K.indptr) and np.array_equal(col, K.indices)
+        assert np.abs(val - K.data).max() <= 1e-13 * np.abs(K.data).max()
+        ptr, col, val = gp.export_csr(1)
+        optr, ocol, oval = o.csr("L")
+        assert np.array_equal(ptr, optr) and np.array_equal(col, ocol)
+        assert np.abs(val - oval).max() <= 1e-12 * np.abs(oval).max()
+        f = o.load(1)
+        u, p, info = gp.solve(_cuda(f), tol=1e-8)
+        assert info["ic_shift_steps"] == shift and info["status"] == 0
+        io = o.solve(f, tol=1e-8)[2]
+        assert abs(info["iters"] - io["iters"]) <= 1, (info["iters"], io["iters"])
+        u, p, info = gp.solve(_cuda(f), tol=1e-12)
+        uo, po, _ = o.solve(f, tol=1e-12)
+        assert info["status"] == 0
+        _close(u.cpu().numpy(), uo, 1e-10)
+        _close(p.cpu().numpy(), po, 1e-10)
+    finally:
+        gp.close()
+
+
 def test_saddle_product(pair):
     gp, o = pair
     x = random_vector(o.n, 11)

@@ -29,7 +29,7 @@ def hostcheck(tmp_path_factory):
     subprocess.check_call(cmd)
     L = ctypes.CDLL(out)
     L.hc_pattern.argtypes = [ctypes.c_int] * 3 + [ctypes.c_void_p] * 6
-    L.hc_schedule_check.argtypes = [ctypes.c_int] * 5 + [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int]
+    L.hc_schedule_check.argtypes = [ctypes.c_int] * 6 + [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int]
     L.hc_row_split.argtypes = [ctypes.c_int] * 5 + [ctypes.c_void_p] * 2
     return L
 
@@ -80,10 +80,29 @@ def test_saddle_pattern_equals_oracle(hostcheck, N, kp, dim):
 def test_trsv_schedule_emulation(hostcheck, N, kp, dim, strip):
     st = np.zeros(16)
     msg = ctypes.create_string_buffer(256)
-    rc = hostcheck.hc_schedule_check(N, kp, dim, strip, 7, st.ctypes.data, msg, 256)
+    rc = hostcheck.hc_schedule_check(N, kp, dim, strip, 7, 0, st.ctypes.data, msg, 256)
     assert rc == 0, msg.value.decode()
     assert st[7] < 1e-12 and st[8] < 1e-10, st[7:9]
     assert st[0] == st[1]  # forward and backward DAGs have the same depth
+
+
+@pytest.mark.parametrize("N,kp,strip,helpers", [(16, 1, 8, 2), (16, 1, 1, 1), (12, 2, 4, 2), (20, 3, 8, 3),
+                                                 (64, 2, 8, 2), (5, 2, 8, 2), (1, 1, 8, 2)])
+def test_trsv_schedule_emulation_coupled(hostcheck, N, kp, strip, helpers):
+    """Schedules whose second-velocity-component rows take their off-block dependencies as one
+    coupling value each, computed by helper groups (2D): the emulated solves reproduce the
+    direct ones, every LDS read holds its expected row, and no wait deadlocks.  The coupling
+    rows are one per row of the block solved second, and the level count grows by at most
+    one (a dependency path passes through at most one coupling row)."""
+    st = np.zeros(16)
+    msg = ctypes.create_string_buffer(256)
+    rc = hostcheck.hc_schedule_check(N, kp, 2, strip, 7, helpers, st.ctypes.data, msg, 256)
+    assert rc == 0, msg.value.decode()
+    assert st[7] < 1e-12 and st[8] < 1e-10, st[7:9]
+    st0 = np.zeros(16)
+    assert hostcheck.hc_schedule_check(N, kp, 2, strip, 7, 0, st0.ctypes.data, msg, 256) == 0
+    assert st0[0] <= st[0] <= st0[0] + 1 and st0[1] <= st[1] <= st0[1] + 1
+    assert st[2] > st0[2] and st[13] > 0
 
 
 @pytest.mark.slow
@@ -92,10 +111,15 @@ def test_trsv_schedule_headline_sizes(hostcheck):
     for N, kp, dim, strip, lev in ((256, 2, 2, 8, 1295), (32, 1, 3, 2, 341)):
         st = np.zeros(16)
         msg = ctypes.create_string_buffer(256)
-        rc = hostcheck.hc_schedule_check(N, kp, dim, strip, 3, st.ctypes.data, msg, 256)
+        rc = hostcheck.hc_schedule_check(N, kp, dim, strip, 3, 0, st.ctypes.data, msg, 256)
         assert rc == 0, msg.value.decode()
         assert int(st[0]) == lev
         assert st[7] < 1e-12 and st[8] < 1e-10
+    st = np.zeros(16)
+    msg = ctypes.create_string_buffer(256)
+    rc = hostcheck.hc_schedule_check(256, 2, 2, 8, 3, 2, st.ctypes.data, msg, 256)
+    assert rc == 0, msg.value.decode()
+    assert st[7] < 1e-12 and st[8] < 1e-10
 
 
 @pytest.mark.parametrize("N,kp,dim", [(1, 1, 2), (3, 2, 2), (16, 1, 2), (64, 2, 2), (256, 2, 2), (6, 1, 3), (16, 3, 3)])
