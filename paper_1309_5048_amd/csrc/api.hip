@@ -397,8 +397,7 @@ int build_fast_layout(stokes_problem* pb, const TrsvSchedHost& H, TrsvSchedDev& 
       sv32[t] = gb32[g] + int64_t(j) * sb32 + kFastHdr + 64 * ep * 4;
       sep[t] = ep;
       const int32_t need = H.step_halo_need[s];
-      std::memcpy(p64 + RPS * 16, &need, 4);
-      std::memcpy(p32 + RPS * 16, &need, 4);
+      if (need > kFastMaxField) return 0;  // the general kernel serves this schedule
       const int32_t row0 = H.srow[size_t(s) * RPS];
       if (row0 < 0) return fail(pb, STOKES_EINVAL, "triangular-solve step without rows");
       for (int rr = 0; rr < RPS; ++rr) {
@@ -412,8 +411,9 @@ int build_fast_layout(stokes_problem* pb, const TrsvSchedHost& H, TrsvSchedDev& 
         if ((srow >= nrows) != (H.grp_cpl[g] != 0))
           return fail(pb, STOKES_EINVAL, "coupling row outside a helper group");
         const int32_t orow = int32_t(srow >= nrows ? srow - nrows : srow);
-        FastRec64 r64{0.0, int32_t(64 + slot * 8), int32_t(orow * 8)};
-        FastRec32 r32{0.0f, int32_t(64 + slot * 4), int32_t(orow * 4), 0};
+        if (64 + slot * 8 > kFastMaxField) return 0;
+        FastRec64 r64{0.0, uint32_t(64 + slot * 8) | (uint32_t(need) << 16), int32_t(orow * 8)};
+        FastRec32 r32{0.0f, int32_t(64 + slot * 4), int32_t(orow * 4), need};
         std::memcpy(p64 + rr * 16, &r64, 16);
         std::memcpy(p32 + rr * 16, &r32, 16);
         for (int q = 0; q < kTrsvG; ++q) {

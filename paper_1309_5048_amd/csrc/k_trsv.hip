@@ -665,10 +665,14 @@ struct FastRec;
 template <>
 struct FastRec<double> {
   using type = FastRec64;
+  static __device__ __forceinline__ uint32_t slot(const FastRec64& r) { return r.slot_need & 0xffffu; }
+  static __device__ __forceinline__ int need(const FastRec64& r) { return (int)(r.slot_need >> 16); }
 };
 template <>
 struct FastRec<float> {
   using type = FastRec32;
+  static __device__ __forceinline__ uint32_t slot(const FastRec32& r) { return (uint32_t)r.slot_byte; }
+  static __device__ __forceinline__ int need(const FastRec32& r) { return r.need; }
 };
 
 // Buffer resources (raw, byte-addressed, bounds-checked against num_records) let every load
@@ -737,7 +741,6 @@ __device__ __forceinline__ double fast_compute(const FastArgs& a, const FastDyn<
   u32x4 pv[D][NVL];
   u32x4 ps[D][EP / 4];
   u32x4 prc[D];
-  unsigned pnd[D];
   FastDyn<T> pdy[D];
   auto load = [&](int d, int j) {
     const int sb = j * SB, sd = j * DYN;
@@ -746,7 +749,6 @@ __device__ __forceinline__ double fast_compute(const FastArgs& a, const FastDyn<
 #pragma unroll
     for (int k = 0; k < EP / 4; ++k) ps[d][k] = __builtin_amdgcn_raw_buffer_load_b128(rb, o_slot + 16 * k, sb, 0);
     prc[d] = __builtin_amdgcn_raw_buffer_load_b128(rb, o_rec, sb, 0);
-    pnd[d] = __builtin_amdgcn_raw_buffer_load_b32(rb, kTrsvRPS * 16, sb, 0);
     if constexpr (sizeof(T) == 8) {
       const u32x4 t = __builtin_amdgcn_raw_buffer_load_b128(rd, o_dyn, sd, 0);
       pdy[d].rhs = from_bits2<T>(t.xy);
@@ -771,7 +773,8 @@ __device__ __forceinline__ double fast_compute(const FastArgs& a, const FastDyn<
 #pragma unroll
       for (int d = 0; d < D; ++d) {
         const int jj = j + d;
-        const int need = __builtin_amdgcn_readfirstlane((int)pnd[d]);
+        const Rec rec = __builtin_bit_cast(Rec, prc[d]);
+        const int need = __builtin_amdgcn_readfirstlane(FastRec<T>::need(rec));
         if (need > halo_seen)
           halo_seen = __builtin_amdgcn_readfirstlane(
               lds_wait<false, false>(&ctr[CTR_HALO], need, &ctr[CTR_ERR], a.err));
@@ -801,7 +804,6 @@ __device__ __forceinline__ double fast_compute(const FastArgs& a, const FastDyn<
           else
             acc = fma(v, xv[e], acc);
         }
-        const Rec rec = __builtin_bit_cast(Rec, prc[d]);
         const T res = (pdy[d].rhs - octet_sum(acc + acc2)) * rec.dinv;
         if constexpr (sizeof(T) == 8)
           __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, res), ro, (uint32_t)rec.row_byte, 0,
@@ -810,7 +812,7 @@ __device__ __forceinline__ double fast_compute(const FastArgs& a, const FastDyn<
           __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, res), ro, (uint32_t)rec.row_byte, 0,
                                                 kStoreSc1);
         if (kDot) dacc = fma((double)res, (double)pdy[d].dot, dacc);
-        lds_put<T>((uint32_t)rec.slot_byte, res);
+        lds_put<T>(FastRec<T>::slot(rec), res);
         lds_signal(&ctr[CTR_COMPUTED], jj + 1);
       }
       j += D;

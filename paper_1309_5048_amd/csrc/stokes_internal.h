@@ -61,6 +61,7 @@ constexpr int kTrsvRPS = 64 / kTrsvG;      // rows per step (one compute wave)
 constexpr int kTrsvThreads = 128;          // compute wavefront + halo wavefront
 constexpr int kTrsvHaloLookahead = 16;     // steps before first use a halo slot is allocated
 constexpr int kLevelStride = 1 << 21;      // progress value = epoch * stride + level + 1
+
 #ifndef STOKES_TRSV_HELPERS
 #define STOKES_TRSV_HELPERS 2
 #endif
@@ -122,32 +123,41 @@ struct TrsvStep {
 // vector).  Each group has its own entries per lane, EP = 4 or 8 (the group's largest row
 // over kTrsvG lanes), and its steps are stored as one block each, read with a single
 // scalar base per step:
-//   [kTrsvRPS row records (16 bytes)][step header: halo prefix needed (16 bytes)]
+//   [kTrsvRPS row records (16 bytes)]
 //   [64 lanes x EP LDS byte addresses (uint32)][64 lanes x EP factor values]
 // A row record holds the reciprocal diagonal, the LDS byte address of the row's result
-// slot and the row's byte offset in the output vector.  Steps with fewer than kTrsvRPS
-// rows repeat their first row (the same arithmetic on the same data, so the repeated
-// stores are identical), and every group is padded to a multiple of its prefetch depth
-// with repeats of its last step; repeats add nothing to the fused dot product.  The
+// slot, the row's byte offset in the output vector and the step's halo prefix (entries
+// that must be staged before the step; the same in every record of a step), so that a
+// step is five 16-byte loads per lane for EP = 4 (values 2, addresses 1, record 1, and the
+// per-solve pair) and the prefetch window can hold more steps.  Steps with fewer than
+// kTrsvRPS rows repeat their first row (the same arithmetic on the same data, so the
+// repeated stores are identical), and every group is padded to a multiple of its prefetch
+// depth with repeats of its last step; repeats add nothing to the fused dot product.  The
 // per-solve right-hand side and dot-vector entries sit in a separate array of the same
 // step order.
-constexpr int kFastHdr = kTrsvRPS * 16 + 16;
+constexpr int kFastHdr = kTrsvRPS * 16;
 template <typename T>
 constexpr int fast_block_bytes(int ep) {
   return kFastHdr + 64 * ep * (4 + (int)sizeof(T));
 }
-constexpr int fast_depth(int ep) { return ep == 4 ? 9 : 7; }  // register buffers of prefetched steps
+#ifndef STOKES_FAST_DEPTH4
+#define STOKES_FAST_DEPTH4 11
+#endif
+// register buffers of prefetched steps (EP = 4: 5 loads per step; EP = 8: 8), within the
+// 63 vector-memory operations a wavefront can have outstanding
+constexpr int fast_depth(int ep) { return ep == 4 ? STOKES_FAST_DEPTH4 : 7; }
+constexpr int kFastMaxField = 65535;  // 16-bit LDS byte address and halo prefix (FP64 records)
 
 struct FastRec64 {
   double dinv;
-  int32_t slot_byte;
+  uint32_t slot_need;  // LDS byte address of the result (low 16 bits), halo prefix (high 16)
   int32_t row_byte;
 };
 struct FastRec32 {
   float dinv;
   int32_t slot_byte;
   int32_t row_byte;
-  int32_t pad;
+  int32_t need;
 };
 
 struct TrsvFastDev {
