@@ -163,10 +163,11 @@ struct FactorSched {
   const std::vector<int32_t>* lev_fwd = nullptr;
   std::vector<int32_t>* lev_bwd = nullptr;
   std::function<void(int, std::vector<int32_t>&, int*)> groups;
-  // rows [0, split) and [split, n) form two blocks (the velocity components of a 2D
-  // factor): the single-column solves then take the off-block dependencies of the block
-  // solved second as coupling values from `helpers` extra groups per strip (0: off)
-  int64_t split = 0;
+  // row blocks solved one after another (offsets; the velocity components of A's factor):
+  // the solves then take each row's dependencies on earlier blocks as coupling values from
+  // `helpers` extra groups per (strip, source block); fewer than two blocks or no helpers:
+  // off
+  std::vector<int64_t> blocks;
   int helpers = 0;
   std::vector<std::unique_ptr<SchedPair>> scheds;
 };
@@ -468,30 +469,51 @@ int build_fast_layout(stokes_problem* pb, const TrsvSchedHost& H, TrsvSchedDev& 
   return 0;
 }
 
-// Device form of a schedule of the factor Lval (nrows rows, nnzL entries); the
-// single-column layout is built from X (H itself, or H's form with coupling rows).
-int upload_schedule(stokes_problem* pb, const TrsvSchedHost& H, const TrsvSchedHost& X, TrsvSchedDev& D, int rmax,
-                    int64_t nrows, int64_t nnzL, const double* Lval) {
+// Device form of a schedule of the factor Lval (nrows rows, nnzL entries; rows from nrows on
+// are coupling rows).
+int upload_schedule(stokes_problem* pb, const TrsvSchedHost& H, TrsvSchedDev& D, int rmax, int64_t nrows,
+                    int64_t nnzL, const double* Lval) {
   hipStream_t st = pb->stream;
   DevAlloc& m = pb->mem;
   D.ngroups = H.ngroups;
   D.nsteps = H.nsteps;
   D.E = H.E;
-  D.EP = (H.E + 3) / 4 * 4;
   D.nlevels = H.nlevels;
   D.nslots = H.nslots;
   D.nrows = int(nrows);
   const size_t ns = size_t(H.nsteps);
-  // per-lane records: values (via a permutation into L) and 32-bit slot ids
-  std::vector<int64_t> vperm(ns * 64 * D.EP, -1);
-  std::vector<uint32_t> ssrc(ns * 64 * D.EP, 0);
-  for (size_t s = 0; s < ns; ++s)
-    for (int e = 0; e < H.E; ++e)
-      for (int l = 0; l < 64; ++l) {
-        const size_t from = (s * H.E + e) * 64 + l;
-        vperm[(s * 64 + l) * D.EP + e] = H.ent_perm[from];
-        ssrc[(s * 64 + l) * D.EP + e] = uint32_t(H.ent_src[from]);
-      }
+  // per-lane records: values (via a permutation into L) and 32-bit slot ids, EP per lane
+  // for each group (its widest row over kTrsvG lanes, a multiple of 4; 4 or the largest
+  // of the schedule, the two widths the kernels take), steps of a group contiguous
+  std::vector<int32_t> gep(H.ngroups, 4);
+  std::vector<int64_t> geoff(H.ngroups + 1, 0);
+  D.EP = 4;
+  for (int g = 0; g < H.ngroups; ++g) {
+    int eg = 1;
+    for (int s = H.grp_step_ptr[g]; s < H.grp_step_ptr[g + 1]; ++s)
+      for (int e = 0; e < H.E; ++e)
+        for (int l = 0; l < 64; ++l)
+          if (H.ent_perm[(size_t(s) * H.E + e) * 64 + l] != -1) eg = std::max(eg, e + 1);
+    gep[g] = (eg + 3) / 4 * 4;
+    D.EP = std::max(D.EP, gep[g]);
+  }
+  for (int g = 0; g < H.ngroups; ++g) {
+    if (gep[g] > 4) gep[g] = D.EP;
+    geoff[g + 1] = geoff[g] + int64_t(H.grp_step_ptr[g + 1] - H.grp_step_ptr[g]) * 64 * gep[g];
+  }
+  const size_t nent = size_t(geoff[H.ngroups]);
+  std::vector<int64_t> vperm(nent, -1);
+  std::vector<uint32_t> ssrc(nent, 0);
+  for (int g = 0; g < H.ngroups; ++g)
+    for (int s = H.grp_step_ptr[g]; s < H.grp_step_ptr[g + 1]; ++s)
+      for (int e = 0; e < std::min(H.E, gep[g]); ++e)
+        for (int l = 0; l < 64; ++l) {
+          const size_t from = (size_t(s) * H.E + e) * 64 + l;
+          const size_t to = size_t(geoff[g]) + (size_t(s - H.grp_step_ptr[g]) * 64 + l) * gep[g] + e;
+          vperm[to] = H.ent_perm[from];
+          ssrc[to] = uint32_t(H.ent_src[from]);
+        }
+  D.nent = int64_t(nent);
   std::vector<TrsvRow64> ri(ns * kTrsvRPS);
   std::vector<TrsvRow32> ri32(ns * kTrsvRPS);
   for (size_t k = 0; k < ns * kTrsvRPS; ++k) {
@@ -509,6 +531,8 @@ int upload_schedule(stokes_problem* pb, const TrsvSchedHost& H, const TrsvSchedH
   std::vector<TrsvStep> sst(ns);
   for (size_t s = 0; s < ns; ++s) sst[s] = TrsvStep{H.step_level[s], H.step_publish[s], H.step_halo_need[s], 0};
   D.grp_step_ptr = m.upload(H.grp_step_ptr, st);
+  D.grp_ep = m.upload(gep, st);
+  D.grp_eoff = m.upload(geoff, st);
   D.grp_halo_ptr = m.upload(H.grp_halo_ptr, st);
   D.halo_row = m.upload(H.halo_row, st);
   D.halo_grp = m.upload(H.halo_grp, st);
@@ -531,6 +555,8 @@ int upload_schedule(stokes_problem* pb, const TrsvSchedHost& H, const TrsvSchedH
   D.done_count = m.get<unsigned int>(1);
   D.err = m.get<int>(1);
   D.partials = m.get<double>(size_t(H.ngroups) * kRMax);
+  D.ncpl = int(H.ncpl);
+  D.cpl = H.ncpl > 0 ? m.get<double>(size_t(H.ncpl) * kRMax) : nullptr;
   D.rmax = rmax;
   if (m.err != hipSuccess) return fail_hip(pb, m.err, "schedule upload", __LINE__);
   CK(hipMemsetAsync(D.progress, 0, sizeof(unsigned long long) * H.ngroups, st));
@@ -538,7 +564,7 @@ int upload_schedule(stokes_problem* pb, const TrsvSchedHost& H, const TrsvSchedH
   CK(hipMemsetAsync(D.done_count, 0, sizeof(unsigned int), st));
   CK(hipMemsetAsync(D.err, 0, sizeof(int), st));
   CK(hipStreamSynchronize(st));  // host vectors must outlive the asynchronous copies
-  int rc = build_fast_layout(pb, X, D, nrows, nnzL);
+  int rc = build_fast_layout(pb, H, D, nrows, nnzL);
   if (rc) return rc;
   CK(launch_trsv_gather(D, Lval, st));
   CK(hipStreamSynchronize(st));
@@ -609,48 +635,70 @@ int make_schedule(stokes_problem* pb, FactorSched& fs, bool fp32, SchedPair** ou
     std::vector<int32_t> group_of;
     int ngroups = 0;
     fs.groups(strip, group_of, &ngroups);
-    TrsvSchedHost hf, hb;
     std::string e;
-    if (!build_trsv_schedule(*fs.L, fs.n, +1, group_of, ngroups, hf, e) ||
-        !build_trsv_schedule(*fs.L, fs.n, -1, group_of, ngroups, hb, e))
-      return fail(pb, STOKES_EINVAL, e);
-    const int nsl = std::max(hf.nslots, hb.nslots);
+    // all groups of a solve must be resident together (they wait on each other)
+    auto fits = [&](const TrsvSchedHost& hf, const TrsvSchedHost& hb, SchedPair& sp) {
+      const int nsl = std::max(hf.nslots, hb.nslots), ng = std::max(hf.ngroups, hb.ngroups);
+      sp.rmax64 = fit_rmax(pb, nsl, false);
+      sp.rmax32 = fit_rmax(pb, nsl, true);
+      auto resident = [&](int r, bool f32) {
+        if (r == 0) return 0;
+        const size_t sh = trsv_shmem_bytes(nsl, f32, r);
+        int per_cu = int(std::max<size_t>(1, std::min<size_t>(8, pb->lds_per_cu / std::max<size_t>(sh, 1))));
+        // the batched kernels' blocks (five wavefronts of up to 256 registers) fit once per CU
+        if (r >= 8) per_cu = 1;
+        if (ng <= per_cu * pb->num_cu) return r;
+        return (r >= 8 && ng <= pb->num_cu * 8) ? 1 : 0;  // then single columns only
+      };
+      sp.rmax64 = resident(sp.rmax64, false);
+      sp.rmax32 = resident(sp.rmax32, true);
+      return sp.rmax64 > 0 || sp.rmax32 > 0;
+    };
     auto sp = std::make_unique<SchedPair>();
     sp->strip = strip;
-    sp->rmax64 = fit_rmax(pb, nsl, false);
-    sp->rmax32 = fit_rmax(pb, nsl, true);
-    // all groups of a solve must be resident together (they wait on each other)
-    auto resident = [&](int r, bool f32) {
-      if (r == 0) return 0;
-      const size_t sh = trsv_shmem_bytes(nsl, f32, r);
-      int per_cu = int(std::max<size_t>(1, std::min<size_t>(8, pb->lds_per_cu / std::max<size_t>(sh, 1))));
-      // the batched kernels' blocks (five wavefronts of up to 256 registers) fit once per CU
-      if (r >= 8) per_cu = 1;
-      if (ngroups <= per_cu * pb->num_cu) return r;
-      return (r >= 8 && ngroups <= pb->num_cu * 8) ? 1 : 0;  // then single columns only
-    };
-    sp->rmax64 = resident(sp->rmax64, false);
-    sp->rmax32 = resident(sp->rmax32, true);
-    if (sp->rmax64 == 0 && sp->rmax32 == 0) continue;
-    const int64_t nnzL = int64_t(fs.L->col.size());
-    // single-column layouts with coupling rows, when every group (helpers included) can be
-    // resident at once
-    TrsvSchedHost hfx, hbx;
-    bool coupled = false;
-    if (fs.split > 0 && fs.split < fs.n && fs.helpers > 0 && sp->rmax64 >= 1) {
-      coupled = build_trsv_schedule_coupled(*fs.L, fs.n, +1, fs.split, fs.helpers, group_of, ngroups, hfx, e) &&
-                build_trsv_schedule_coupled(*fs.L, fs.n, -1, fs.split, fs.helpers, group_of, ngroups, hbx, e);
-      if (coupled) {
-        const size_t sh = trsv_shmem_bytes(std::max(hfx.nslots, hbx.nslots), false, 1);
-        const int per_cu = int(std::max<size_t>(1, std::min<size_t>(8, pb->lds_per_cu / std::max<size_t>(sh, 1))));
-        coupled = sh <= pb->lds_max && std::max(hfx.ngroups, hbx.ngroups) <= per_cu * pb->num_cu;
+    // Candidates: with coupling rows where the factor has row blocks (helpers per strip and
+    // source block, then one), then the plain schedules.  The first whose batch width is
+    // the widest any candidate allows is taken: more helpers shorten the chains of single
+    // solves, but batched solves need every group resident with its R columns of slots.
+    TrsvSchedHost hf, hb;
+    int best = -1;
+    {
+      std::vector<int> hs;
+      if (fs.blocks.size() > 2)
+        for (int h = fs.helpers; h >= 1; h = h > 1 ? 1 : 0) hs.push_back(h);
+      hs.push_back(0);  // plain
+      int best_r = 0;
+      for (size_t ci = 0; ci < hs.size(); ++ci) {
+        TrsvSchedHost cf, cb;
+        SchedPair t;
+        const bool built =
+            hs[ci] > 0
+                ? build_trsv_schedule_coupled(*fs.L, fs.n, +1, fs.blocks, hs[ci], group_of, ngroups, cf, e) &&
+                      build_trsv_schedule_coupled(*fs.L, fs.n, -1, fs.blocks, hs[ci], group_of, ngroups, cb, e)
+                : build_trsv_schedule(*fs.L, fs.n, +1, group_of, ngroups, cf, e) &&
+                      build_trsv_schedule(*fs.L, fs.n, -1, group_of, ngroups, cb, e);
+        if (!built) {
+          if (hs[ci] == 0) return fail(pb, STOKES_EINVAL, e);
+          continue;
+        }
+        if (!fits(cf, cb, t)) continue;
+        const int r = std::max(t.rmax64, t.rmax32);
+        if (r > best_r) {
+          best_r = r;
+          best = int(ci);
+          hf = std::move(cf);
+          hb = std::move(cb);
+          sp->rmax64 = t.rmax64;
+          sp->rmax32 = t.rmax32;
+        }
+        if (best_r >= kRMax) break;  // no candidate can do better
       }
     }
-    int rc = upload_schedule(pb, hf, coupled ? hfx : hf, sp->fwd, std::max(sp->rmax64, sp->rmax32), fs.n, nnzL,
-                             fs.Lval);
+    if (best < 0) continue;
+    const int64_t nnzL = int64_t(fs.L->col.size());
+    int rc = upload_schedule(pb, hf, sp->fwd, std::max(sp->rmax64, sp->rmax32), fs.n, nnzL, fs.Lval);
     if (rc) return rc;
-    rc = upload_schedule(pb, hb, coupled ? hbx : hb, sp->bwd, std::max(sp->rmax64, sp->rmax32), fs.n, nnzL,
-                         fs.Lval);
+    rc = upload_schedule(pb, hb, sp->bwd, std::max(sp->rmax64, sp->rmax32), fs.n, nnzL, fs.Lval);
     if (rc) return rc;
     CK(hipStreamSynchronize(pb->stream));
     fs.scheds.push_back(std::move(sp));
@@ -1540,10 +1588,8 @@ static int stokes_setup_impl(int n, int p, int dim, double nu, int geometry, dou
     fs.lev_fwd = &pb->lev_fwd;
     fs.lev_bwd = &pb->lev_bwd;
     fs.groups = [pb](int strip, std::vector<int32_t>& g, int* ng) { strip_groups(pb->S, strip, g, ng); };
-    if (pb->S.dim == 2) {
-      fs.split = pb->S.voff[1];
-      fs.helpers = kTrsvHelpers;
-    }
+    fs.blocks.assign(pb->S.voff, pb->S.voff + pb->S.dim + 1);  // the velocity components
+    fs.helpers = kTrsvHelpers;
     SchedPair* sp = nullptr;
     int rc = get_schedule(pb, 1, false, &sp);
     if (rc) return rc;

@@ -239,29 +239,41 @@ static void trsv_deps(const LowerPattern& L, int64_t n, int dir, TrsvDeps& D) {
   }
 }
 
-// Coupling rows.  With the rows split into two blocks at `split`, the rows of the block
-// solved second (forward: i >= split; backward: i < split) depend on rows of the other
-// block.  Each such row i gets a coupling row c_i = sum over those dependencies of the
-// coefficient times the value, written as one more row of the triangular system (its
-// dependencies with their coefficients, right-hand side 0, diagonal -1: (0 - sum)/(-1)),
-// and row i keeps its own block's dependencies plus c_i with coefficient 1.  Coupling rows
-// are processed between the two blocks.  cpl_row[k] is the row of coupling row n + k.
-static void trsv_couple(TrsvDeps& D, int64_t split, int dir, std::vector<int32_t>& cpl_row) {
+// Coupling rows.  The rows form consecutive blocks (blk: offsets, the velocity components),
+// solved one after another; a row depends on rows of its own block and of blocks solved
+// before it.  For each row i and each earlier block b it depends on, a coupling row
+// c_ib = sum over those dependencies of the coefficient times the value is written as one
+// more row of the triangular system (its dependencies with their coefficients, right-hand
+// side 0, diagonal -1: (0 - sum)/(-1)), and row i keeps its own block's dependencies plus
+// the c_ib with coefficient 1.  Processing order: each block, then the coupling rows whose
+// dependencies lie in it.  cpl_row[k] and cpl_src[k] are the row and the block of coupling
+// row n + k.
+static void trsv_couple(TrsvDeps& D, const std::vector<int64_t>& blk, int dir, std::vector<int32_t>& cpl_row,
+                        std::vector<int32_t>& cpl_src) {
   const int64_t n = D.n;
-  auto dependent = [&](int64_t i) { return dir > 0 ? i >= split : i < split; };
-  auto source = [&](int64_t j) { return dir > 0 ? j < split : j >= split; };
+  const int nb = int(blk.size()) - 1;
+  std::vector<int8_t> bof(n);
+  for (int b = 0; b < nb; ++b)
+    for (int64_t i = blk[b]; i < blk[b + 1]; ++i) bof[i] = int8_t(b);
+  std::vector<int> border(nb);
+  for (int b = 0; b < nb; ++b) border[b] = dir > 0 ? b : nb - 1 - b;
+  // coupling rows numbered by source block in solve order, then by the dependent row's
+  // processing position
   cpl_row.clear();
-  for (int64_t i = 0; i < n; ++i) {
-    if (!dependent(i)) continue;
-    for (int64_t k = D.dptr[i]; k < D.dptr[i + 1]; ++k)
-      if (source(D.dcol[k])) {
-        cpl_row.push_back(int32_t(i));
-        break;
-      }
-  }
+  cpl_src.clear();
+  std::vector<int32_t> cidx(size_t(n) * nb, -1);
+  for (int sb : border)
+    for (int32_t i : D.order) {
+      if (bof[i] == sb) continue;
+      for (int64_t k = D.dptr[i]; k < D.dptr[i + 1]; ++k)
+        if (bof[D.dcol[k]] == sb) {
+          cidx[size_t(i) * nb + sb] = int32_t(n + int64_t(cpl_row.size()));
+          cpl_row.push_back(i);
+          cpl_src.push_back(sb);
+          break;
+        }
+    }
   const int64_t nc = int64_t(cpl_row.size());
-  std::vector<int32_t> cpl_of(n, -1);
-  for (int64_t k = 0; k < nc; ++k) cpl_of[cpl_row[k]] = int32_t(n + k);
   TrsvDeps X;
   X.n = n + nc;
   X.dptr.assign(X.n + 1, 0);
@@ -271,34 +283,35 @@ static void trsv_couple(TrsvDeps& D, int64_t split, int dir, std::vector<int32_t
   for (int64_t i = 0; i < n; ++i) {
     X.diag[i] = D.diag[i];
     for (int64_t k = D.dptr[i]; k < D.dptr[i + 1]; ++k)
-      if (cpl_of[i] < 0 || !source(D.dcol[k])) {
+      if (bof[D.dcol[k]] == bof[i]) {
         X.dcol.push_back(D.dcol[k]);
         X.dval.push_back(D.dval[k]);
       }
-    if (cpl_of[i] >= 0) {
-      X.dcol.push_back(cpl_of[i]);
-      X.dval.push_back(kTrsvValOne);
-    }
+    for (int sb : border)
+      if (cidx[size_t(i) * nb + sb] >= 0) {
+        X.dcol.push_back(cidx[size_t(i) * nb + sb]);
+        X.dval.push_back(kTrsvValOne);
+      }
     X.dptr[i + 1] = int64_t(X.dcol.size());
   }
   for (int64_t c = 0; c < nc; ++c) {
     const int64_t i = cpl_row[c];
     X.diag[n + c] = kTrsvValMinusOne;
     for (int64_t k = D.dptr[i]; k < D.dptr[i + 1]; ++k)
-      if (source(D.dcol[k])) {
+      if (bof[D.dcol[k]] == cpl_src[c]) {
         X.dcol.push_back(D.dcol[k]);
         X.dval.push_back(D.dval[k]);
       }
     X.dptr[n + c + 1] = int64_t(X.dcol.size());
   }
-  // processing order: the source block, the coupling rows, the dependent block
   X.order.clear();
   X.order.reserve(X.n);
-  for (int32_t i : D.order)
-    if (!dependent(i)) X.order.push_back(i);
-  for (int64_t c = 0; c < nc; ++c) X.order.push_back(int32_t(n + c));
-  for (int32_t i : D.order)
-    if (dependent(i)) X.order.push_back(i);
+  int64_t c = 0;
+  for (int sb : border) {
+    for (int32_t i : D.order)
+      if (bof[i] == sb) X.order.push_back(i);
+    for (; c < nc && cpl_src[c] == sb; ++c) X.order.push_back(int32_t(n + c));
+  }
   D = std::move(X);
 }
 
@@ -332,36 +345,38 @@ bool build_trsv_schedule(const LowerPattern& L, int64_t n, int dir, const std::v
   return schedule_core(D, lev, nl, group_of, ngroups, std::vector<char>(ngroups, 0), S, err);
 }
 
-bool build_trsv_schedule_coupled(const LowerPattern& L, int64_t n, int dir, int64_t split, int helpers,
-                                 const std::vector<int32_t>& group_of, int ngroups, TrsvSchedHost& S,
+bool build_trsv_schedule_coupled(const LowerPattern& L, int64_t n, int dir, const std::vector<int64_t>& blk,
+                                 int helpers, const std::vector<int32_t>& group_of, int ngroups, TrsvSchedHost& S,
                                  std::string& err) {
   TrsvDeps D;
   trsv_deps(L, n, dir, D);
-  std::vector<int32_t> cpl_row;
-  trsv_couple(D, split, dir, cpl_row);
+  std::vector<int32_t> cpl_row, cpl_src;
+  trsv_couple(D, blk, dir, cpl_row, cpl_src);
   int nl = 0;
   const std::vector<int32_t> lev = trsv_levels(D, &nl);
   const int64_t nc = int64_t(cpl_row.size());
-  // helper groups: `helpers` per group of the dependent block; a group's coupling rows in
-  // (level, processing) order are dealt to its helpers in runs of one step
-  std::vector<int32_t> hbase(ngroups, -1);
+  const int nb = int(blk.size()) - 1;
+  // helper groups: `helpers` per (group of the dependent row, source block); the coupling
+  // rows of one such pair in (level, processing) order are dealt to its helpers in runs of
+  // one step
+  std::vector<int32_t> hbase(size_t(ngroups) * nb, -1);
   int ng = ngroups;
   for (int64_t c = 0; c < nc; ++c) {
-    const int g = group_of[cpl_row[c]];
-    if (hbase[g] < 0) {
-      hbase[g] = ng;
+    const size_t key = size_t(group_of[cpl_row[c]]) * nb + cpl_src[c];
+    if (hbase[key] < 0) {
+      hbase[key] = ng;
       ng += helpers;
     }
   }
   std::vector<int32_t> gx(group_of);
   gx.resize(D.n, 0);
-  std::vector<std::vector<int32_t>> per(ngroups);
+  std::vector<std::vector<int32_t>> per(size_t(ngroups) * nb);
   for (int32_t i : D.order)
-    if (i >= n) per[group_of[cpl_row[i - n]]].push_back(i);
-  for (int g = 0; g < ngroups; ++g) {
-    auto& v = per[g];
+    if (i >= n) per[size_t(group_of[cpl_row[i - n]]) * nb + cpl_src[i - n]].push_back(i);
+  for (size_t key = 0; key < per.size(); ++key) {
+    auto& v = per[key];
     std::stable_sort(v.begin(), v.end(), [&](int32_t a, int32_t b) { return lev[a] < lev[b]; });
-    for (size_t r = 0; r < v.size(); ++r) gx[v[r]] = hbase[g] + int32_t((r / kTrsvRPS) % helpers);
+    for (size_t r = 0; r < v.size(); ++r) gx[v[r]] = hbase[key] + int32_t((r / kTrsvRPS) % helpers);
   }
   std::vector<char> pack(ng, 0);
   for (int g = ngroups; g < ng; ++g) pack[g] = 1;
@@ -433,6 +448,7 @@ static bool schedule_core(const TrsvDeps& D, const std::vector<int32_t>& lev, in
   S.sdiag_src.clear();
   S.ent_src.clear();
   S.ent_perm.clear();
+  S.ent_dep.clear();
   S.nslots = 1;
 
   struct HaloTmp {
@@ -546,6 +562,7 @@ static bool schedule_core(const TrsvDeps& D, const std::vector<int32_t>& lev, in
       S.sdiag_src.resize(base_sr + RPS, -1);
       S.ent_src.resize(base_e + size_t(E) * 64, 0);
       S.ent_perm.resize(base_e + size_t(E) * 64, -1);
+      S.ent_dep.resize(base_e + size_t(E) * 64, -1);
       for (int32_t r = sb[k]; r < sb[k + 1]; ++r) {
         const int32_t i = v[r];
         const int rr = r - sb[k];
@@ -566,6 +583,7 @@ static bool schedule_core(const TrsvDeps& D, const std::vector<int32_t>& lev, in
           }
           S.ent_src[base_e + size_t(e) * 64 + lane] = src;
           S.ent_perm[base_e + size_t(e) * 64 + lane] = dval[q];
+          S.ent_dep[base_e + size_t(e) * 64 + lane] = j;
         }
       }
       S.step_level.push_back(lev[v[sb[k]]]);

@@ -28,6 +28,8 @@ namespace stk {
 
 struct TrsvArgs {
   const int32_t* grp_step_ptr;
+  const int32_t* grp_ep;    // entries per lane of each group's steps (4 or the schedule's EP)
+  const int64_t* grp_eoff;  // offset of each group's first step entries
   const int32_t* grp_halo_ptr;
   const int32_t* halo_row;
   const int32_t* halo_slot;
@@ -41,6 +43,8 @@ struct TrsvArgs {
   int nslots;
   int nrows;
   int ld;  // row stride of out (the full batch width; R columns are solved per launch)
+  void* cpl;  // coupling rows' values (rows nrows .., same stride and column offset as out)
+  int ncpl;
 };
 
 // Output sentinel (signalling NaN) and its test, on the bit patterns.
@@ -239,6 +243,21 @@ __device__ __forceinline__ void halo_wave(const int32_t* __restrict__ grp_halo_p
   }
 }
 
+// Prefetch depth (steps in flight) of the single-wave batched kernel: for R = 1 as deep as the
+// 63 outstanding vector memory operations (about 7 to 10 per step) and the register file
+// allow; with R columns the per-step records are R times larger and the depth is small.
+constexpr int batch_depth(int R, int EP, int tsize) {
+  return EP <= 4 ? (R == 1 ? 9 : (R == 8 ? 3 : 2))
+       : EP <= 8 ? (R == 1 ? (tsize == 8 ? 7 : 8) : (R == 8 ? 3 : 2))
+       : EP <= 12 ? (R == 1 ? 4 : 2)
+                  : (R == 1 ? 3 : 2);
+}
+
+// Prefetch depth of the column-split kernel (GC 16-byte gathers per entry and wave).
+constexpr int cols_depth(int GC, int EP) {
+  return GC == 1 ? (EP <= 4 ? 7 : (EP <= 8 ? 5 : (EP <= 12 ? 3 : 2))) : (EP <= 4 ? 5 : (EP <= 8 ? 3 : 2));
+}
+
 template <typename T, int R, int EP, int D>
 __global__ __launch_bounds__(kTrsvThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_trsv(
     TrsvArgs a, const T* __restrict__ sval, const typename RowRec<T>::type* __restrict__ srinfo,
@@ -269,27 +288,33 @@ __global__ __launch_bounds__(kTrsvThreads) __attribute__((amdgpu_waves_per_eu(1,
 
   if (wid == 0) {
     // ------------------------------ compute wave ------------------------------
+    // the group's entries per lane: 4, or the schedule's widest (EP)
+    auto compute = [&](auto ep_c) {
+    constexpr int EPX = decltype(ep_c)::value;
+    constexpr int NVX = EPX / VN;
+    constexpr int DX = EPX == EP ? D : batch_depth(R, EPX, sizeof(T));
     const int q = lane % kTrsvG;
     const int r = lane / kTrsvG;
-    V pv[D][NV];
-    uint4 ps[D][EP / 4];
-    typename RowRec<T>::type pri[D];
-    T prd[D][2 * R];  // right-hand side, dot-vector entries
-    int prow[D];
+    V pv[DX][NVX];
+    uint4 ps[DX][EPX / 4];
+    typename RowRec<T>::type pri[DX];
+    T prd[DX][2 * R];  // right-hand side, dot-vector entries
+    int prow[DX];
     int halo_seen = 0;
     // per-lane parts of the record addresses; the step part stays scalar
-    const T* sval_l = sval + (size_t)lane * EP;
-    const uint32_t* ssrc_l = a.ssrc + (size_t)lane * EP;
+    const int64_t eoff = a.grp_eoff[g] - (int64_t)s0 * 64 * EPX;  // step ss at eoff + ss * 64 * EPX
+    const T* sval_l = sval + eoff + (size_t)lane * EPX;
+    const uint32_t* ssrc_l = a.ssrc + eoff + (size_t)lane * EPX;
     const typename RowRec<T>::type* sri_l = srinfo + r;
     const T* rd_l = rd_s + (size_t)r * 2 * R;
     const int32_t* srow_l = a.srow + r;
     auto load = [&](int d, int ss) {
-      const V* vp = reinterpret_cast<const V*>(sval_l + (size_t)ss * 64 * EP);
+      const V* vp = reinterpret_cast<const V*>(sval_l + (size_t)ss * 64 * EPX);
 #pragma unroll
-      for (int k = 0; k < NV; ++k) pv[d][k] = vp[k];
-      const uint4* sp = reinterpret_cast<const uint4*>(ssrc_l + (size_t)ss * 64 * EP);
+      for (int k = 0; k < NVX; ++k) pv[d][k] = vp[k];
+      const uint4* sp = reinterpret_cast<const uint4*>(ssrc_l + (size_t)ss * 64 * EPX);
 #pragma unroll
-      for (int k = 0; k < EP / 4; ++k) ps[d][k] = sp[k];
+      for (int k = 0; k < EPX / 4; ++k) ps[d][k] = sp[k];
       pri[d] = sri_l[(size_t)ss * kTrsvRPS];
 #pragma unroll
       for (int c = 0; c < 2 * R; ++c) prd[d][c] = rd_l[(size_t)ss * kTrsvRPS * 2 * R + c];
@@ -308,14 +333,14 @@ __global__ __launch_bounds__(kTrsvThreads) __attribute__((amdgpu_waves_per_eu(1,
     // store to a dummy location.
     if (nsteps > 0) {
 #pragma unroll
-      for (int d = 0; d + 1 < D; ++d) {
+      for (int d = 0; d + 1 < DX; ++d) {
         load(d, min(s0 + d, s1 - 1));
         __builtin_amdgcn_sched_barrier(0);
       }
       int s = s0;
       do {
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
+        for (int d = 0; d < DX; ++d) {
           const int ss = s + d;
           const int k = ss - s0;
           const bool live = ss < s1;
@@ -331,14 +356,14 @@ __global__ __launch_bounds__(kTrsvThreads) __attribute__((amdgpu_waves_per_eu(1,
           };
           if constexpr (R == 1) {
             // gathers first, the next loads while they are in flight, then the FMAs
-            T xv[EP];
+            T xv[EPX];
 #pragma unroll
-            for (int e = 0; e < EP; ++e) xv[e] = *xaddr(e);
+            for (int e = 0; e < EPX; ++e) xv[e] = *xaddr(e);
             __builtin_amdgcn_sched_barrier(0);
-            load((d + D - 1) % D, min(ss + D - 1, s1 - 1));
+            load((d + DX - 1) % DX, min(ss + DX - 1, s1 - 1));
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int e = 0; e < EP; ++e) {
+            for (int e = 0; e < EPX; ++e) {
               const T v = reinterpret_cast<const T*>(&pv[d][e / VN])[e % VN];
               if (e & 1)
                 acc2[0] = fma(v, xv[e], acc2[0]);
@@ -348,7 +373,7 @@ __global__ __launch_bounds__(kTrsvThreads) __attribute__((amdgpu_waves_per_eu(1,
           } else {
             // R columns per entry: gather and accumulate entry by entry (register budget)
 #pragma unroll
-            for (int e = 0; e < EP; ++e) {
+            for (int e = 0; e < EPX; ++e) {
               const T v = reinterpret_cast<const T*>(&pv[d][e / VN])[e % VN];
               const T* xp = xaddr(e);
               if (e & 1) {
@@ -360,7 +385,7 @@ __global__ __launch_bounds__(kTrsvThreads) __attribute__((amdgpu_waves_per_eu(1,
               }
             }
             __builtin_amdgcn_sched_barrier(0);
-            load((d + D - 1) % D, min(ss + D - 1, s1 - 1));
+            load((d + DX - 1) % DX, min(ss + DX - 1, s1 - 1));
             __builtin_amdgcn_sched_barrier(0);
           }
           // Every lane of the octet holds the row's sum and result.  Rows whose value no
@@ -371,7 +396,9 @@ __global__ __launch_bounds__(kTrsvThreads) __attribute__((amdgpu_waves_per_eu(1,
 #pragma unroll
           for (int c = 0; c < R; ++c) res[c] = (prd[d][c] - octet_sum(acc[c] + acc2[c])) * pri[d].dinv;
           const bool real = live && prow[d] >= 0;
-          T* gp = real ? out + (size_t)prow[d] * a.ld : dummy;
+          T* gp = !real ? dummy
+                  : prow[d] < a.nrows ? out + (size_t)prow[d] * a.ld
+                                      : reinterpret_cast<T*>(a.cpl) + (size_t)(prow[d] - a.nrows) * a.ld;
           if constexpr (R == 1) {
             dev_store(gp, res[0]);
           } else {
@@ -403,13 +430,18 @@ __global__ __launch_bounds__(kTrsvThreads) __attribute__((amdgpu_waves_per_eu(1,
             }
           }
         }
-        s += D;
+        s += DX;
       } while (s < s1);
     }
+    };
+    if (a.grp_ep[g] == EP)
+      compute(std::integral_constant<int, EP>{});
+    else
+      compute(std::integral_constant<int, 4>{});
   } else {
     // ------------------------------- halo wave --------------------------------
     halo_wave<T, R>(a.grp_halo_ptr, a.halo_row, a.halo_slot, a.halo_free, a.nrows, a.nslots, a.ld, a.err, g, lane,
-                    ctr, xs, out);
+                    ctr, xs, out, reinterpret_cast<const T*>(a.cpl), a.ncpl);
   }
   __syncthreads();
   if (tid == 0 && lds_load(&ctr[CTR_ERR]) != 0) raise_err(a.err);
@@ -488,24 +520,30 @@ __global__ __launch_bounds__(64 * (W + 1)) void k_trsv_cols(
     double dotacc[RC];
 #pragma unroll
     for (int c = 0; c < RC; ++c) dotacc[c] = 0.0;
-    V pv[D][NV];
-    uint4 ps[D][EP / 4];
-    typename RowRec<T>::type pri[D];
-    V prh[D][G], pdt[D][G];  // right-hand side and dot-vector entries of this wave's columns
-    int prow[D];
+    // the group's entries per lane: 4, or the schedule's widest (EP)
+    auto compute = [&](auto ep_c) {
+    constexpr int EPX = decltype(ep_c)::value;
+    constexpr int NVX = EPX / VN;
+    constexpr int DX = EPX == EP ? D : cols_depth(G, EPX);
+    V pv[DX][NVX];
+    uint4 ps[DX][EPX / 4];
+    typename RowRec<T>::type pri[DX];
+    V prh[DX][G], pdt[DX][G];  // right-hand side and dot-vector entries of this wave's columns
+    int prow[DX];
     int halo_seen = 0;
-    const T* sval_l = sval + (size_t)lane * EP;
-    const uint32_t* ssrc_l = a.ssrc + (size_t)lane * EP;
+    const int64_t eoff = a.grp_eoff[g] - (int64_t)s0 * 64 * EPX;  // step ss at eoff + ss * 64 * EPX
+    const T* sval_l = sval + eoff + (size_t)lane * EPX;
+    const uint32_t* ssrc_l = a.ssrc + eoff + (size_t)lane * EPX;
     const typename RowRec<T>::type* sri_l = srinfo + r;
     const T* rd_l = rd_s + (size_t)r * 2 * R + cb;
     const int32_t* srow_l = a.srow + r;
     auto load = [&](int d, int ss) {
-      const V* vp = reinterpret_cast<const V*>(sval_l + (size_t)ss * 64 * EP);
+      const V* vp = reinterpret_cast<const V*>(sval_l + (size_t)ss * 64 * EPX);
 #pragma unroll
-      for (int k = 0; k < NV; ++k) pv[d][k] = vp[k];
-      const uint4* sp = reinterpret_cast<const uint4*>(ssrc_l + (size_t)ss * 64 * EP);
+      for (int k = 0; k < NVX; ++k) pv[d][k] = vp[k];
+      const uint4* sp = reinterpret_cast<const uint4*>(ssrc_l + (size_t)ss * 64 * EPX);
 #pragma unroll
-      for (int k = 0; k < EP / 4; ++k) ps[d][k] = sp[k];
+      for (int k = 0; k < EPX / 4; ++k) ps[d][k] = sp[k];
       pri[d] = sri_l[(size_t)ss * kTrsvRPS];
       const V* rp = reinterpret_cast<const V*>(rd_l + (size_t)ss * kTrsvRPS * 2 * R);
 #pragma unroll
@@ -519,35 +557,35 @@ __global__ __launch_bounds__(64 * (W + 1)) void k_trsv_cols(
     // of step ss + D - 1 issued between the gathers of step ss and their use.
     if (s1 > s0) {
 #pragma unroll
-      for (int d = 0; d + 1 < D; ++d) {
+      for (int d = 0; d + 1 < DX; ++d) {
         load(d, min(s0 + d, s1 - 1));
         __builtin_amdgcn_sched_barrier(0);
       }
       int s = s0;
       do {
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
+        for (int d = 0; d < DX; ++d) {
           const int ss = s + d;
           const int k = ss - s0;
           const bool live = ss < s1;
           if (live && pri[d].need > halo_seen)
             halo_seen = lds_wait<false, false>(&ctr[CTR_HALO], pri[d].need, &ctr[CTR_ERR], a.err);
-          V xv[EP][G];
+          V xv[EPX][G];
 #pragma unroll
-          for (int e = 0; e < EP; ++e) {
+          for (int e = 0; e < EPX; ++e) {
             const unsigned src = reinterpret_cast<const unsigned*>(&ps[d][e / 4])[e % 4];
             const V* xp = reinterpret_cast<const V*>(reinterpret_cast<const unsigned char*>(xs + cb) + (src << SH));
 #pragma unroll
             for (int k = 0; k < G; ++k) xv[e][k] = xp[k];
           }
           __builtin_amdgcn_sched_barrier(0);
-          load((d + D - 1) % D, min(ss + D - 1, s1 - 1));
+          load((d + DX - 1) % DX, min(ss + DX - 1, s1 - 1));
           __builtin_amdgcn_sched_barrier(0);
           T acc[RC], acc2[RC];
 #pragma unroll
           for (int c = 0; c < RC; ++c) acc[c] = acc2[c] = T(0);
 #pragma unroll
-          for (int e = 0; e < EP; ++e) {
+          for (int e = 0; e < EPX; ++e) {
             const T v = reinterpret_cast<const T*>(&pv[d][e / VN])[e % VN];
             const T* xe = reinterpret_cast<const T*>(&xv[e][0]);
 #pragma unroll
@@ -572,7 +610,10 @@ __global__ __launch_bounds__(64 * (W + 1)) void k_trsv_cols(
 #pragma unroll
           for (int c = 1; c < RC; ++c)
             if (cq == c) sv = res[c];
-          dev_store(real ? out + (size_t)prow[d] * a.ld + cb + cq : dummy, sv);
+          T* gp = !real ? dummy
+                  : prow[d] < a.nrows ? out + (size_t)prow[d] * a.ld + cb + cq
+                                      : reinterpret_cast<T*>(a.cpl) + (size_t)(prow[d] - a.nrows) * a.ld + cb + cq;
+          dev_store(gp, sv);
           if (live) {
             if (q == 0) {
               if (prow[d] >= 0) {
@@ -587,9 +628,14 @@ __global__ __launch_bounds__(64 * (W + 1)) void k_trsv_cols(
             if (lane == 0) lds_signal(&ctr[CTR_WAVE0 + wid], k + 1);
           }
         }
-        s += D;
+        s += DX;
       } while (s < s1);
     }
+    };
+    if (a.grp_ep[g] == EP)
+      compute(std::integral_constant<int, EP>{});
+    else
+      compute(std::integral_constant<int, 4>{});
     if (with_dot) {
 #pragma unroll
       for (int c = 0; c < RC; ++c) {
@@ -602,7 +648,7 @@ __global__ __launch_bounds__(64 * (W + 1)) void k_trsv_cols(
   } else {
     // ------------------------------- halo wave --------------------------------
     halo_wave<T, R, W>(a.grp_halo_ptr, a.halo_row, a.halo_slot, a.halo_free, a.nrows, a.nslots, a.ld, a.err, g,
-                       lane, ctr, xs, out);
+                       lane, ctr, xs, out, reinterpret_cast<const T*>(a.cpl), a.ncpl);
   }
   __syncthreads();
   if (tid == 0 && lds_load(&ctr[CTR_ERR]) != 0) raise_err(a.err);
@@ -975,16 +1021,21 @@ static hipError_t launch_trsv_fast(const TrsvSchedDev& S, const T* rhs, T* out, 
 template <typename T, int R>
 __global__ void k_trsv_gather_rhs(int64_t nrow_slots, const int32_t* __restrict__ srow, const T* __restrict__ rhs,
                                   const T* __restrict__ dotv, int ld, T* __restrict__ rd_s, T* __restrict__ out,
-                                  const int* __restrict__ skip) {
+                                  T* __restrict__ cpl, int nrows, const int* __restrict__ skip) {
   if (skip != nullptr && *skip) return;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nrow_slots * R;
        t += (int64_t)gridDim.x * blockDim.x) {
     const int64_t k = t / R;
     const int c = int(t % R);
     const int row = srow[k];
-    rd_s[k * 2 * R + c] = row >= 0 ? rhs[(size_t)row * ld + c] : T(0);
-    rd_s[k * 2 * R + R + c] = (row >= 0 && dotv != nullptr) ? dotv[(size_t)row * ld + c] : T(0);
-    if (row >= 0) out[(size_t)row * ld + c] = sentinel_value<T>();
+    // coupling rows (row >= nrows): right-hand side and dot entry 0, output in cpl
+    const bool own = row >= 0 && row < nrows;
+    rd_s[k * 2 * R + c] = own ? rhs[(size_t)row * ld + c] : T(0);
+    rd_s[k * 2 * R + R + c] = (own && dotv != nullptr) ? dotv[(size_t)row * ld + c] : T(0);
+    if (own)
+      out[(size_t)row * ld + c] = sentinel_value<T>();
+    else if (row >= nrows)
+      cpl[(size_t)(row - nrows) * ld + c] = sentinel_value<T>();
   }
 }
 
@@ -1013,10 +1064,12 @@ size_t trsv_shmem_bytes(int nslots, bool fp32, int R) {
 
 template <typename T, int R, int EP, int D>
 static hipError_t launch_trsv_t(const TrsvSchedDev& S, const T* sval, const typename RowRec<T>::type* srinfo,
-                                const T* rhs, T* out, const T* dotv, double* dot_out, int ld, const int* skip,
+                                const T* rhs, T* out, T* cpl, const T* dotv, double* dot_out, int ld, const int* skip,
                                 hipStream_t st, const TrsvTiming* tm) {
   TrsvArgs a;
   a.grp_step_ptr = S.grp_step_ptr;
+  a.grp_ep = S.grp_ep;
+  a.grp_eoff = S.grp_eoff;
   a.grp_halo_ptr = S.grp_halo_ptr;
   a.halo_row = S.halo_row;
   a.halo_slot = S.halo_slot;
@@ -1030,11 +1083,13 @@ static hipError_t launch_trsv_t(const TrsvSchedDev& S, const T* sval, const type
   a.nslots = S.nslots;
   a.nrows = S.nrows;
   a.ld = ld;
+  a.cpl = cpl;
+  a.ncpl = S.ncpl;
   T* rd_s = reinterpret_cast<T*>(S.rhs_s);
   T* dummy = reinterpret_cast<T*>(S.dummy);
   const int64_t nrow_slots = (int64_t)S.nsteps * kTrsvRPS;
   hipLaunchKernelGGL((k_trsv_gather_rhs<T, R>), dim3(1024), dim3(256), 0, st, nrow_slots, S.srow, rhs, dotv, ld,
-                     rd_s, out, skip);
+                     rd_s, out, cpl, S.nrows, skip);
   const size_t shmem = trsv_shmem_t<T, R>(S.nslots);
   // R >= 8 and at most 8 entries per lane (2D): the columns split over W compute wavefronts
   // of RC = max(16 bytes, R / 4) columns each (4 waves for R = 16, 4 or 2 for R = 8), with a
@@ -1044,8 +1099,7 @@ static hipError_t launch_trsv_t(const TrsvSchedDev& S, const T* sval, const type
   constexpr int RC = R / 4 > Vec16<T>::n ? R / 4 : Vec16<T>::n;
   constexpr int W = (R >= 8 && EP <= 8) ? R / RC : 0;
   constexpr int GC = RC / Vec16<T>::n;
-  constexpr int DC = GC == 1 ? (EP <= 4 ? 7 : (EP <= 8 ? 5 : (EP <= 12 ? 3 : 2)))
-                             : (EP <= 4 ? 5 : (EP <= 8 ? 3 : 2));
+  constexpr int DC = cols_depth(GC, EP);
   const void* fn;
   int threads;
   if constexpr (W > 0) {
@@ -1071,16 +1125,13 @@ static hipError_t launch_trsv_t(const TrsvSchedDev& S, const T* sval, const type
 
 template <typename T, int R>
 static hipError_t launch_trsv_r(const TrsvSchedDev& S, const T* sval, const typename RowRec<T>::type* srinfo,
-                                const T* rhs, T* out, const T* dotv, double* dot_out, int ld, const int* skip,
+                                const T* rhs, T* out, T* cpl, const T* dotv, double* dot_out, int ld, const int* skip,
                                 hipStream_t st, const TrsvTiming* tm) {
   switch (S.EP) {
-    // prefetch depth D (steps in flight): for R = 1 as deep as the 63 outstanding vector
-    // memory operations (about 7 to 10 per step) and the register file allow; with R
-    // columns the per-step records are R times larger and D is small
-    case 4: return launch_trsv_t<T, R, 4, (R == 1 ? 9 : (R == 8 ? 3 : 2))>(S, sval, srinfo, rhs, out, dotv, dot_out, ld, skip, st, tm);
-    case 8: return launch_trsv_t<T, R, 8, (R == 1 ? (sizeof(T) == 8 ? 7 : 8) : (R == 8 ? 3 : 2))>(S, sval, srinfo, rhs, out, dotv, dot_out, ld, skip, st, tm);
-    case 12: return launch_trsv_t<T, R, 12, (R == 1 ? 4 : 2)>(S, sval, srinfo, rhs, out, dotv, dot_out, ld, skip, st, tm);
-    case 16: return launch_trsv_t<T, R, 16, (R == 1 ? 3 : 2)>(S, sval, srinfo, rhs, out, dotv, dot_out, ld, skip, st, tm);
+    case 4: return launch_trsv_t<T, R, 4, batch_depth(R, 4, sizeof(T))>(S, sval, srinfo, rhs, out, cpl, dotv, dot_out, ld, skip, st, tm);
+    case 8: return launch_trsv_t<T, R, 8, batch_depth(R, 8, sizeof(T))>(S, sval, srinfo, rhs, out, cpl, dotv, dot_out, ld, skip, st, tm);
+    case 12: return launch_trsv_t<T, R, 12, batch_depth(R, 12, sizeof(T))>(S, sval, srinfo, rhs, out, cpl, dotv, dot_out, ld, skip, st, tm);
+    case 16: return launch_trsv_t<T, R, 16, batch_depth(R, 16, sizeof(T))>(S, sval, srinfo, rhs, out, cpl, dotv, dot_out, ld, skip, st, tm);
   }
   return hipErrorInvalidValue;
 }
@@ -1099,6 +1150,9 @@ static hipError_t launch_trsv_p(const TrsvSchedDev& S, const T* sval, const type
   while (Rc > 1 && (Rc > S.rmax || trsv_shmem_bytes(S.nslots, sizeof(T) == 4, Rc) + trsv_static_shmem(Rc) > (size_t)lds_max))
     Rc = Rc > 8 ? 8 : 1;
   if (R % Rc != 0) return hipErrorInvalidValue;
+  // coupling rows' values: [ncpl][R] in the schedule's buffer (sized for the widest batch)
+  T* cpl = reinterpret_cast<T*>(S.cpl);
+  if (S.ncpl > 0 && (cpl == nullptr || R > kRMax)) return hipErrorInvalidValue;
   for (int c0 = 0; c0 < R; c0 += Rc) {
     // timing events: before the first chunk, after the last
     TrsvTiming t;
@@ -1108,10 +1162,11 @@ static hipError_t launch_trsv_p(const TrsvSchedDev& S, const T* sval, const type
     }
     const T* dv = dotv ? dotv + c0 : nullptr;
     double* dout = dot_out ? dot_out + c0 : nullptr;
+    T* cc = cpl ? cpl + c0 : nullptr;
     switch (Rc) {
-      case 1: e = launch_trsv_r<T, 1>(S, sval, srinfo, rhs + c0, out + c0, dv, dout, R, skip, st, &t); break;
-      case 8: e = launch_trsv_r<T, 8>(S, sval, srinfo, rhs + c0, out + c0, dv, dout, R, skip, st, &t); break;
-      case 16: e = launch_trsv_r<T, 16>(S, sval, srinfo, rhs + c0, out + c0, dv, dout, R, skip, st, &t); break;
+      case 1: e = launch_trsv_r<T, 1>(S, sval, srinfo, rhs + c0, out + c0, cc, dv, dout, R, skip, st, &t); break;
+      case 8: e = launch_trsv_r<T, 8>(S, sval, srinfo, rhs + c0, out + c0, cc, dv, dout, R, skip, st, &t); break;
+      case 16: e = launch_trsv_r<T, 16>(S, sval, srinfo, rhs + c0, out + c0, cc, dv, dout, R, skip, st, &t); break;
       default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;
@@ -1138,7 +1193,7 @@ __global__ void k_trsv_gather(const int64_t* __restrict__ perm, int64_t n, const
                               double* __restrict__ out, float* __restrict__ out32) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t p = perm[i];
-    const double v = p >= 0 ? Lval[p] : 0.0;
+    const double v = p >= 0 ? Lval[p] : (p == kTrsvValOne ? 1.0 : 0.0);
     out[i] = v;
     out32[i] = (float)v;
   }
@@ -1148,13 +1203,13 @@ __global__ void k_trsv_gather_dinv(const int64_t* __restrict__ dsrc, int64_t n, 
                                    TrsvRow64* __restrict__ ri, TrsvRow32* __restrict__ ri32) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t p = dsrc[i];
-    ri[i].dinv = p >= 0 ? 1.0 / Lval[p] : 0.0;
-    ri32[i].dinv = p >= 0 ? 1.0f / (float)Lval[p] : 0.0f;
+    ri[i].dinv = p >= 0 ? 1.0 / Lval[p] : (p == kTrsvValMinusOne ? -1.0 : 0.0);
+    ri32[i].dinv = p >= 0 ? 1.0f / (float)Lval[p] : (p == kTrsvValMinusOne ? -1.0f : 0.0f);
   }
 }
 
 hipError_t launch_trsv_gather(const TrsvSchedDev& S, const double* Lval, hipStream_t st) {
-  const int64_t ne = (int64_t)S.nsteps * 64 * S.EP;
+  const int64_t ne = S.nent;
   const int64_t nd = (int64_t)S.nsteps * kTrsvRPS;
   hipLaunchKernelGGL(k_trsv_gather, dim3(1024), dim3(256), 0, st, S.vperm, ne, Lval, S.sval, S.sval32);
   hipLaunchKernelGGL(k_trsv_gather_dinv, dim3(256), dim3(256), 0, st, S.dsrc, nd, Lval, S.srinfo, S.srinfo32);

@@ -95,6 +95,7 @@ struct TrsvSchedHost {
   std::vector<int64_t> sdiag_src;          // [nsteps*RPS] index of the diagonal in L values
   std::vector<int32_t> ent_src;            // [nsteps*E*64] LDS slot of the dependency
   std::vector<int64_t> ent_perm;           // [nsteps*E*64] index in L values or -1 (pad)
+  std::vector<int32_t> ent_dep;            // [nsteps*E*64] the row read (checks), -1 (pad)
 };
 
 // Device layout of a schedule.  Per step the compute wave reads, per lane, EP factor
@@ -190,7 +191,10 @@ struct TrsvFastDev {
 
 struct TrsvSchedDev {
   int ngroups = 0, nsteps = 0, E = 0, EP = 0, nlevels = 0, nslots = 0, nrows = 0;
+  int64_t nent = 0;                // per-lane entries of all steps
   int32_t *grp_step_ptr = nullptr, *grp_halo_ptr = nullptr;
+  int32_t* grp_ep = nullptr;       // [ngroups] entries per lane of the group's steps (4 or EP)
+  int64_t* grp_eoff = nullptr;     // [ngroups+1] offset of the group's first step entries
   int32_t *halo_row = nullptr, *halo_grp = nullptr, *halo_lvl = nullptr, *halo_slot = nullptr, *halo_free = nullptr;
   int32_t* srow = nullptr;         // [nsteps*RPS] global row or -1 (rhs gather, writer)
   uint32_t* ssrc = nullptr;        // [nsteps][64][EP] LDS slot ids
@@ -208,6 +212,8 @@ struct TrsvSchedDev {
   unsigned int* done_count = nullptr;      // [1]
   int* err = nullptr;                      // [1] spin-limit flag
   double* partials = nullptr;              // [ngroups * 16]
+  void* cpl = nullptr;                     // [ncpl][kRMax] coupling rows' values (batched layout)
+  int ncpl = 0;
   int rmax = 0;                            // widest R the LDS budget allows
   TrsvFastDev fast;                        // single-column layout (fast.ok)
 };
@@ -217,11 +223,11 @@ struct TrsvSchedDev {
 bool build_trsv_schedule(const LowerPattern& L, int64_t n, int dir, const std::vector<int32_t>& group_of,
                          int ngroups, TrsvSchedHost& S, std::string& err);
 
-// The same with the off-block dependencies of the block solved second moved into coupling
-// rows (rows are split into two blocks at `split`), computed by `helpers` extra groups per
-// group of that block.
-bool build_trsv_schedule_coupled(const LowerPattern& L, int64_t n, int dir, int64_t split, int helpers,
-                                 const std::vector<int32_t>& group_of, int ngroups, TrsvSchedHost& S,
+// The same with each row's dependencies on other blocks (blk: offsets of consecutive row
+// blocks, solved in order) moved into coupling rows, one per (row, source block), computed
+// by `helpers` extra groups per (group, source block).
+bool build_trsv_schedule_coupled(const LowerPattern& L, int64_t n, int dir, const std::vector<int64_t>& blk,
+                                 int helpers, const std::vector<int32_t>& group_of, int ngroups, TrsvSchedHost& S,
                                  std::string& err);
 
 // Strip partition of the velocity rows: component c, last-direction 1D index t -> group

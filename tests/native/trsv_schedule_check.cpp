@@ -33,8 +33,6 @@ std::vector<double> emulate(const TrsvSchedHost& S, const LowerPattern& L, const
                             Emu& emu, long* rounds_out) {
   const int G = S.ngroups, E = S.E, RPS = kTrsvRPS;
   const int64_t nx = n + S.ncpl;  // rows with the coupling rows
-  std::vector<int32_t> cpl_of(n, -1);
-  for (int64_t c = 0; c < S.ncpl; ++c) cpl_of[S.cpl_row[c]] = int32_t(n + c);
   std::vector<double> out(nx, std::nan(""));
   std::vector<char> written(nx, 0);
   std::vector<int> k(G, 0), hpos(G, 0);
@@ -91,17 +89,20 @@ std::vector<double> emulate(const TrsvSchedHost& S, const LowerPattern& L, const
                   if (src != 0) emu.bad("padding entry not on the zero slot");
                   continue;
                 }
-                int32_t dep;
+                const int32_t dep = S.ent_dep[off];
                 double coef;
                 if (perm == kTrsvValOne) {
-                  if (row >= n || cpl_of[row] < 0) {
-                    emu.bad("coupling entry in a row without a coupling row");
+                  // a coupling value of this row
+                  if (row >= n || dep < n || dep >= nx || S.cpl_row[dep - n] != row) {
+                    emu.bad("coupling entry that is not one of the row's coupling rows");
                     return out;
                   }
-                  dep = cpl_of[row];
                   coef = 1.0;
                 } else if (perm >= 0 && perm < int64_t(Lval.size())) {
-                  dep = dir > 0 ? L.col[perm] : lrow[perm];
+                  if (dep != (dir > 0 ? L.col[perm] : lrow[perm])) {
+                    emu.bad("entry value and dependency disagree");
+                    return out;
+                  }
                   coef = Lval[perm];
                 } else {
                   emu.bad("entry value index out of range");
@@ -172,8 +173,8 @@ int hc_pattern(int N, int kp, int dim, int64_t* n_u, int64_t* n_p, int64_t* nnz,
 }
 
 // Build both schedules for a strip partition and emulate them on a random factor
-// (helpers > 0: with coupling rows for the second velocity component, that many helper
-// groups per strip).
+// (helpers > 0: with coupling rows for the dependencies on other velocity components, that
+// many helper groups per strip and source component).
 // stats: [0] fwd levels [1] bwd levels [2] groups [3] fwd steps [4] bwd steps [5] max slots
 //        [6] E [7] max rel error fwd [8] max rel error bwd [9] rounds fwd [10] rounds bwd
 //        [11] halo entries fwd [12] max deps per row [13] coupling rows fwd
@@ -201,9 +202,9 @@ int hc_schedule_check(int N, int kp, int dim, int strip, int seed, int helpers, 
   int ngroups = 0;
   strip_groups(S, strip, group_of, &ngroups);
   TrsvSchedHost F, B;
-  const int64_t split = S.voff[1];
-  if (helpers > 0 ? (!build_trsv_schedule_coupled(L, n, +1, split, helpers, group_of, ngroups, F, err) ||
-                     !build_trsv_schedule_coupled(L, n, -1, split, helpers, group_of, ngroups, B, err))
+  std::vector<int64_t> blk(S.voff, S.voff + dim + 1);  // the velocity components
+  if (helpers > 0 ? (!build_trsv_schedule_coupled(L, n, +1, blk, helpers, group_of, ngroups, F, err) ||
+                     !build_trsv_schedule_coupled(L, n, -1, blk, helpers, group_of, ngroups, B, err))
                   : (!build_trsv_schedule(L, n, +1, group_of, ngroups, F, err) ||
                      !build_trsv_schedule(L, n, -1, group_of, ngroups, B, err))) {
     snprintf(msg, msglen, "%s", err.c_str());

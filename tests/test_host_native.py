@@ -86,22 +86,24 @@ def test_trsv_schedule_emulation(hostcheck, N, kp, dim, strip):
     assert st[0] == st[1]  # forward and backward DAGs have the same depth
 
 
-@pytest.mark.parametrize("N,kp,strip,helpers", [(16, 1, 8, 2), (16, 1, 1, 1), (12, 2, 4, 2), (20, 3, 8, 3),
-                                                 (64, 2, 8, 2), (5, 2, 8, 2), (1, 1, 8, 2)])
-def test_trsv_schedule_emulation_coupled(hostcheck, N, kp, strip, helpers):
-    """Schedules whose second-velocity-component rows take their off-block dependencies as one
-    coupling value each, computed by helper groups (2D): the emulated solves reproduce the
-    direct ones, every LDS read holds its expected row, and no wait deadlocks.  The coupling
-    rows are one per row of the block solved second, and the level count grows by at most
-    one (a dependency path passes through at most one coupling row)."""
+@pytest.mark.parametrize("N,kp,dim,strip,helpers", [(16, 1, 2, 8, 2), (16, 1, 2, 1, 1), (12, 2, 2, 4, 2),
+                                                     (20, 3, 2, 8, 3), (64, 2, 2, 8, 2), (5, 2, 2, 8, 2),
+                                                     (1, 1, 2, 8, 2), (6, 1, 3, 2, 2), (8, 1, 3, 1, 1),
+                                                     (4, 1, 3, 4, 3), (1, 1, 3, 2, 2)])
+def test_trsv_schedule_emulation_coupled(hostcheck, N, kp, dim, strip, helpers):
+    """Schedules whose rows take their dependencies on earlier velocity components as one
+    coupling value per source component, computed by helper groups: the emulated solves
+    reproduce the direct ones, every LDS read holds its expected row, and no wait deadlocks.
+    A dependency path passes through at most one coupling row per component boundary, so
+    the level count grows by at most dim - 1."""
     st = np.zeros(16)
     msg = ctypes.create_string_buffer(256)
-    rc = hostcheck.hc_schedule_check(N, kp, 2, strip, 7, helpers, st.ctypes.data, msg, 256)
+    rc = hostcheck.hc_schedule_check(N, kp, dim, strip, 7, helpers, st.ctypes.data, msg, 256)
     assert rc == 0, msg.value.decode()
     assert st[7] < 1e-12 and st[8] < 1e-10, st[7:9]
     st0 = np.zeros(16)
-    assert hostcheck.hc_schedule_check(N, kp, 2, strip, 7, 0, st0.ctypes.data, msg, 256) == 0
-    assert st0[0] <= st[0] <= st0[0] + 1 and st0[1] <= st[1] <= st0[1] + 1
+    assert hostcheck.hc_schedule_check(N, kp, dim, strip, 7, 0, st0.ctypes.data, msg, 256) == 0
+    assert st0[0] <= st[0] <= st0[0] + dim - 1 and st0[1] <= st[1] <= st0[1] + dim - 1
     assert st[2] > st0[2] and st[13] > 0
 
 
