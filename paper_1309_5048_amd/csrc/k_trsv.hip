@@ -243,6 +243,24 @@ __device__ __forceinline__ void halo_wave(const int32_t* __restrict__ grp_halo_p
   }
 }
 
+// The last group's sum of the group partials partials[k R + c] (k < ngroups, c < R), by the
+// 64 lanes of one wavefront: lane l takes column l % R and groups l / R, l / R + 64 / R, ...,
+// then a fixed shuffle tree joins the lanes of a column (the same order on every run); lane
+// c < R writes out[c].  The lanes' loads are independent, so the tail is a few memory
+// latencies instead of one per group.
+template <int R>
+__device__ __forceinline__ void last_group_sum(const double* partials, int ngroups, double* out, int lane) {
+  static_assert(R >= 1 && 64 % R == 0, "R divides the wavefront");
+  constexpr int P = 64 / R;  // lanes per column
+  const int c = lane % R, j = lane / R;
+  double v = 0.0;
+#pragma unroll 4
+  for (int k = j; k < ngroups; k += P) v += dev_load(partials + (size_t)k * R + c);
+#pragma unroll
+  for (int off = 32; off >= R; off >>= 1) v += __shfl_xor(v, off, 64);
+  if (lane < R) out[lane] = v;
+}
+
 // Prefetch depth (steps in flight) of the single-wave batched kernel: for R = 1 as deep as the
 // 63 outstanding vector memory operations (about 7 to 10 per step) and the register file
 // allow; with R columns the per-step records are R times larger and the depth is small.
@@ -448,7 +466,7 @@ __global__ __launch_bounds__(kTrsvThreads) __attribute__((amdgpu_waves_per_eu(1,
 
   // ------------------------- epilogue: fused dot product -------------------------
   // The compute wave stores the group's dot partials (device scope), waits for their
-  // acknowledgement and takes a ticket; the last group adds the partials in group order.
+  // acknowledgement and takes a ticket; the last group adds the partials (last_group_sum).
   if (with_dot && wid == 0) {
 #pragma unroll
     for (int c = 0; c < R; ++c) {
@@ -457,17 +475,15 @@ __global__ __launch_bounds__(kTrsvThreads) __attribute__((amdgpu_waves_per_eu(1,
       for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
       if (lane == 0) dev_store(a.partials + (size_t)g * R + c, v);
     }
+    unsigned int prev = 0;
     if (lane == 0) {
       wait_vm_stores();
-      const unsigned int prev = __hip_atomic_fetch_add(a.done_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (prev == (unsigned int)(a.ngroups - 1)) {
-        for (int c = 0; c < R; ++c) {
-          double v = 0.0;
-          for (int k = 0; k < a.ngroups; ++k) v += dev_load(a.partials + (size_t)k * R + c);
-          dot_out[c] = v;
-        }
-        __hip_atomic_store(a.done_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
+      prev = __hip_atomic_fetch_add(a.done_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    prev = (unsigned int)__shfl((int)prev, 0, 64);
+    if (prev == (unsigned int)(a.ngroups - 1)) {
+      last_group_sum<R>(a.partials, a.ngroups, dot_out, lane);
+      if (lane == 0) __hip_atomic_store(a.done_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 }
@@ -654,20 +670,18 @@ __global__ __launch_bounds__(64 * (W + 1)) void k_trsv_cols(
   if (tid == 0 && lds_load(&ctr[CTR_ERR]) != 0) raise_err(a.err);
 
   // fused dot product: the group's partials of all R columns (device scope), then a ticket;
-  // the last group adds the partials in group order
+  // the last group adds the partials (last_group_sum)
   if (with_dot && wid == 0) {
     if (lane < R) dev_store(a.partials + (size_t)g * R + lane, sdot[lane]);
+    unsigned int prev = 0;
     if (lane == 0) {
       wait_vm_stores();
-      const unsigned int prev = __hip_atomic_fetch_add(a.done_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (prev == (unsigned int)(a.ngroups - 1)) {
-        for (int c = 0; c < R; ++c) {
-          double v = 0.0;
-          for (int k = 0; k < a.ngroups; ++k) v += dev_load(a.partials + (size_t)k * R + c);
-          dot_out[c] = v;
-        }
-        __hip_atomic_store(a.done_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
+      prev = __hip_atomic_fetch_add(a.done_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    prev = (unsigned int)__shfl((int)prev, 0, 64);
+    if (prev == (unsigned int)(a.ngroups - 1)) {
+      last_group_sum<R>(a.partials, a.ngroups, dot_out, lane);
+      if (lane == 0) __hip_atomic_store(a.done_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 }
@@ -903,16 +917,16 @@ __global__ __launch_bounds__(kTrsvThreads) __attribute__((amdgpu_waves_per_eu(1,
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) dacc += __shfl_xor(dacc, off, 64);
     dacc *= 1.0 / kTrsvG;
+    unsigned int prev = 0;
     if (lane == 0) {
       dev_store(a.partials + g, dacc);
       wait_vm_stores();
-      const unsigned int prev = __hip_atomic_fetch_add(a.done_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (prev == (unsigned int)(a.ngroups - 1)) {
-        double v = 0.0;
-        for (int k = 0; k < a.ngroups; ++k) v += dev_load(a.partials + k);
-        dot_out[0] = v;
-        __hip_atomic_store(a.done_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
+      prev = __hip_atomic_fetch_add(a.done_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    prev = (unsigned int)__shfl((int)prev, 0, 64);
+    if (prev == (unsigned int)(a.ngroups - 1)) {
+      last_group_sum<1>(a.partials, a.ngroups, dot_out, lane);
+      if (lane == 0) __hip_atomic_store(a.done_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 }

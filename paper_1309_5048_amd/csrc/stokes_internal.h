@@ -142,11 +142,11 @@ constexpr int fast_block_bytes(int ep) {
   return kFastHdr + 64 * ep * (4 + (int)sizeof(T));
 }
 #ifndef STOKES_FAST_DEPTH4
-#define STOKES_FAST_DEPTH4 11
+#define STOKES_FAST_DEPTH4 10
 #endif
 // register buffers of prefetched steps (EP = 4: 5 loads per step; EP = 8: 8), within the
 // 63 vector-memory operations a wavefront can have outstanding
-constexpr int fast_depth(int ep) { return ep == 4 ? STOKES_FAST_DEPTH4 : 7; }
+constexpr int fast_depth(int ep) { return ep == 4 ? STOKES_FAST_DEPTH4 : 6; }
 constexpr int kFastMaxField = 65535;  // 16-bit LDS byte address and halo prefix (FP64 records)
 
 struct FastRec64 {
