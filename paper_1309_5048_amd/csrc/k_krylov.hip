@@ -843,7 +843,7 @@ hipError_t mr_lanczos(int R, int64_t n, int64_t n_u, const T* q, const T* v, T* 
 template <typename T>
 hipError_t mr_update(int R, int64_t n, const T* z, const T* w, T* wprev_new, T* x, const MrScalars& s, int p,
                      hipStream_t st) {
-  STK_R_SWITCH(R, hipLaunchKernelGGL((k_mr_update<T, RR>), dim3(vec_blocks(n)), dim3(kVT), 0, st, n, z, w, wprev_new, x,
+  STK_R_SWITCH(R, hipLaunchKernelGGL((k_mr_update<T, RR>), dim3(vec_blocks_plain(n)), dim3(kVT), 0, st, n, z, w, wprev_new, x,
                                      s, p));
   return hipGetLastError();
 }
@@ -974,7 +974,7 @@ hipError_t pcg_jacobi(int R, int64_t n_u, const T* r, const double* diag, T* z, 
 
 template <typename T>
 hipError_t pcg_pupdate(int R, int64_t n_u, const T* z, T* pv, const PcgScalars& s, int ip, hipStream_t st) {
-  STK_R_SWITCH(R, hipLaunchKernelGGL((k_pcg_pupdate<T, RR>), dim3(vec_blocks(n_u)), dim3(kVT), 0, st, n_u, z, pv, s, ip));
+  STK_R_SWITCH(R, hipLaunchKernelGGL((k_pcg_pupdate<T, RR>), dim3(vec_blocks_plain(n_u)), dim3(kVT), 0, st, n_u, z, pv, s, ip));
   return hipGetLastError();
 }
 

@@ -382,15 +382,23 @@ __device__ __forceinline__ T group_sum(T v) {
   return v;
 }
 
-// Grid of the elementwise kernels: one item per thread up to kVecMaxBlocks blocks.
-// At most 1024 blocks: the last-block reductions take one device-scope ticket per block, and
-// thousands of tickets at the end of a short kernel serialise (2D, N = 512: the Lanczos
-// kernel took 45 us with 3,092 blocks for 30 MB).
+// Grid of the elementwise kernels with a reduction: kVecItems items per thread, at most
+// kVecMaxBlocks blocks
+// (grid-stride loops).  Few blocks: the last-block reductions take one device-scope ticket
+// per block, and the tickets serialise at about 10 ns each at the end of a short kernel
+// (2D, N = 512: the Lanczos kernel took 45 us with 3,092 blocks for 30 MB, 21.7 us with
+// 1,024).
+#ifndef STOKES_VEC_ITEMS
+#define STOKES_VEC_ITEMS 4
+#endif
 constexpr int kVecMaxBlocks = 1024;
-inline int vec_blocks(int64_t nitems) {
-  int64_t b = (nitems + kVT - 1) / kVT;
+constexpr int kVecItems = STOKES_VEC_ITEMS;
+inline int vec_blocks(int64_t nitems, int items = kVecItems) {
+  int64_t b = (nitems + int64_t(kVT) * items - 1) / (int64_t(kVT) * items);
   return int(std::max<int64_t>(1, std::min<int64_t>(b, kVecMaxBlocks)));
 }
+// Kernels without a reduction: one item per thread (more blocks in flight measured faster).
+inline int vec_blocks_plain(int64_t nitems) { return vec_blocks(nitems, 1); }
 
 struct PcgScalars {
   PcgState* st;     // [kRMax]
