@@ -549,7 +549,7 @@ int upload_schedule(stokes_problem* pb, const TrsvSchedHost& H, TrsvSchedDev& D,
   D.sval = m.get<double>(vperm.size());
   D.sval32 = m.get<float>(vperm.size());
   D.rhs_s = m.get<double>(H.srow.size() * 2 * std::max(1, rmax));
-  D.dummy = m.get<double>(64);
+  D.dummy = m.get<double>((size_t)kTrsvDummyGroups * 64);
   D.progress = m.get<unsigned long long>(H.ngroups);
   D.epoch = m.get<unsigned long long>(1);
   D.done_count = m.get<unsigned int>(1);

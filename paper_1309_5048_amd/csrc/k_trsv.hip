@@ -141,6 +141,55 @@ __device__ __forceinline__ T octet_sum(T v) {
   return v;
 }
 
+// Octet reduce-scatter of RC (1, 2, 4 or 8) columns: v[c] holds each lane's partial of
+// column c; lane q of the octet returns the octet's total of column octet_col<RC>(q).
+// Each stage halves the columns a lane keeps: lane and partner (mirror inside the half row,
+// then xor 2, then xor 1) keep opposite halves and add what the partner sends; once one
+// column is left the remaining stages are plain all-reduce steps.  8 / RC lanes end with
+// each column.
+template <int RC>
+__device__ __forceinline__ int octet_col(int q) {
+  return (q >= 4 ? RC / 2 : 0) + (((q >> 1) & 1) ? RC / 4 : 0) + ((q & 1) ? RC / 8 : 0);
+}
+
+template <int K, int CTRL, typename T>
+__device__ __forceinline__ void rs_stage(T (&v)[2 * K], T (&o)[K], bool hi) {
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    const T keep = hi ? v[K + i] : v[i];
+    const T send = hi ? v[i] : v[K + i];
+    o[i] = keep + dpp_mov<CTRL>(send);
+  }
+}
+
+template <typename T, int RC>
+__device__ __forceinline__ T octet_reduce_scatter(T (&v)[RC], int q) {
+  static_assert(RC == 1 || RC == 2 || RC == 4 || RC == 8, "columns per octet");
+  if constexpr (RC == 1) {
+    return octet_sum(v[0]);
+  } else if constexpr (RC == 2) {
+    T a[1];
+    rs_stage<1, 0x141>(v, a, q >= 4);
+    T x = a[0];
+    x += dpp_mov<0x4E>(x);
+    x += dpp_mov<0xB1>(x);
+    return x;
+  } else if constexpr (RC == 4) {
+    T a[2], b[1];
+    rs_stage<2, 0x141>(v, a, q >= 4);
+    rs_stage<1, 0x4E>(a, b, ((q >> 1) & 1) != 0);
+    T x = b[0];
+    x += dpp_mov<0xB1>(x);
+    return x;
+  } else {
+    T a[4], b[2], c[1];
+    rs_stage<4, 0x141>(v, a, q >= 4);
+    rs_stage<2, 0x4E>(a, b, ((q >> 1) & 1) != 0);
+    rs_stage<1, 0xB1>(b, c, (q & 1) != 0);
+    return c[0];
+  }
+}
+
 enum { CTR_COMPUTED = 0, CTR_HALO = 1, CTR_ERR = 3, CTR_WAVE0 = 4 };  // CTR_WAVE0 + w: compute wave w
 
 template <typename T>
@@ -168,6 +217,18 @@ struct Vec16<float> {
   static constexpr int n = 4;
 };
 
+// {right-hand side, dot-vector entry} pair of one column
+template <typename T>
+struct Pair2;
+template <>
+struct Pair2<double> {
+  using type = double2;
+};
+template <>
+struct Pair2<float> {
+  using type = float2;
+};
+
 // Halo wavefront: entries are staged in order; lane j of a round watches entry pos + j.
 // An entry is ready when its R values are no longer the sentinel and the compute wave has
 // finished the steps that still read the slot's previous occupant.
@@ -183,6 +244,15 @@ __device__ __forceinline__ int computed_steps(int* ctr) {
     for (int w = 1; w < NW; ++w) m = min(m, lds_load(&ctr[CTR_WAVE0 + w]));
     return m;
   }
+}
+
+// Bytes between consecutive LDS slots of an R-column batch.  R > 1 pads each slot by 16
+// bytes: with power-of-two slot sizes every lane of a column block reads the same few LDS
+// banks (the slot's low bits select nothing), with the pad consecutive slots start 4 banks
+// apart and the gathers of up to 16 different slots are conflict-free.
+template <typename T, int R>
+__host__ __device__ constexpr uint32_t slot_bytes() {
+  return R == 1 ? (uint32_t)sizeof(T) : (uint32_t)(R * sizeof(T) + 16);
 }
 
 // Rows nrows .. nrows + ncpl - 1 are coupling rows, read from cpl (R = 1 layouts only).
@@ -208,18 +278,31 @@ __device__ __forceinline__ void halo_wave(const int32_t* __restrict__ grp_halo_p
     const bool inb = valid && row >= 0 && row < nrows + ncpl && slot > 0 && slot < nslots;
     T v[R];
     bool ready = true;
+    const T* src = nullptr;
     if (inb) {
-      const T* src = row < nrows ? out + (size_t)row * ld : cpl + (size_t)(row - nrows) * ld;
-#pragma unroll
-      for (int c = 0; c < R; ++c) {
-        v[c] = dev_load(src + c);
-        ready = ready && !is_sentinel(v[c]);
-      }
-      ready = ready && computed_steps<NW>(ctr) >= fr;
+      src = row < nrows ? out + (size_t)row * ld : cpl + (size_t)(row - nrows) * ld;
+      // R > 1: one column probes the entry; the whole row is read only for the ready prefix
+      // (a poll of entries that are not ready yet then costs one load per lane, not R)
+      v[0] = dev_load(src);
+      ready = !is_sentinel(v[0]) && computed_steps<NW>(ctr) >= fr;
     }
-    const unsigned long long notready = __ballot(!ready);
+    unsigned long long notready = __ballot(!ready);
     int count = notready ? __ffsll((long long)notready) - 1 : 64;
     count = min(count, nhalo - pos);
+    if constexpr (R > 1) {
+      if (count > 0) {
+        bool full = true;
+        if (lane < count && inb) {
+#pragma unroll
+          for (int c = 1; c < R; ++c) {
+            v[c] = dev_load(src + c);
+            full = full && !is_sentinel(v[c]);
+          }
+        }
+        notready = __ballot(!full);
+        if (notready) count = min(count, __ffsll((long long)notready) - 1);
+      }
+    }
     if (count == 0) {
       ++spins;
       if ((spins & 63) == 0 && (spins > (kSpinLimit >> 6) || err_set(err) || lds_load(&ctr[CTR_ERR]) != 0)) {
@@ -234,7 +317,7 @@ __device__ __forceinline__ void halo_wave(const int32_t* __restrict__ grp_halo_p
       continue;
     }
     if (lane < count && inb) {
-      T* xp = xs + (size_t)slot * R;
+      T* xp = reinterpret_cast<T*>(reinterpret_cast<unsigned char*>(xs) + (size_t)slot * slot_bytes<T, R>());
 #pragma unroll
       for (int c = 0; c < R; ++c) xp[c] = v[c];
     }
@@ -283,8 +366,8 @@ __global__ __launch_bounds__(kTrsvThreads) __attribute__((amdgpu_waves_per_eu(1,
     double* __restrict__ dot_out, const int* __restrict__ skip) {
   using V = typename Vec16<T>::type;
   constexpr int VN = Vec16<T>::n;
-  constexpr int NV = EP / VN;                       // vector loads of factor values per lane and step
-  constexpr int SH = __builtin_ctz(R * sizeof(T));  // slot id -> byte offset in xs
+  constexpr int NV = EP / VN;  // vector loads of factor values per lane and step
+  constexpr uint32_t SB = slot_bytes<T, R>();  // slot id -> byte offset in xs
   extern __shared__ __align__(16) unsigned char smem[];
   if (skip != nullptr && *skip) return;
   int* ctr = reinterpret_cast<int*>(smem);
@@ -312,11 +395,15 @@ __global__ __launch_bounds__(kTrsvThreads) __attribute__((amdgpu_waves_per_eu(1,
     constexpr int NVX = EPX / VN;
     constexpr int DX = EPX == EP ? D : batch_depth(R, EPX, sizeof(T));
     const int q = lane % kTrsvG;
+    // padding rows and steps past the end store to a word of the workgroup's own (64 words
+    // per workgroup, kTrsvDummyGroups blocks; the lanes of a wavefront share theirs):
+    // device-scope stores of many workgroups to one shared word serialise
+    T* const dummy_l = dummy + (size_t)(g % kTrsvDummyGroups) * 64;
     const int r = lane / kTrsvG;
     V pv[DX][NVX];
     uint4 ps[DX][EPX / 4];
     typename RowRec<T>::type pri[DX];
-    T prd[DX][2 * R];  // right-hand side, dot-vector entries
+    T prd[DX][2 * R];  // {right-hand side, dot-vector entry} of each column
     int prow[DX];
     int halo_seen = 0;
     // per-lane parts of the record addresses; the step part stays scalar
@@ -370,7 +457,7 @@ __global__ __launch_bounds__(kTrsvThreads) __attribute__((amdgpu_waves_per_eu(1,
           for (int c = 0; c < R; ++c) acc[c] = acc2[c] = T(0);
           auto xaddr = [&](int e) {
             const unsigned src = reinterpret_cast<const unsigned*>(&ps[d][e / 4])[e % 4];
-            return reinterpret_cast<const T*>(reinterpret_cast<const unsigned char*>(xs) + (src << SH));
+            return reinterpret_cast<const T*>(reinterpret_cast<const unsigned char*>(xs) + src * SB);
           };
           if constexpr (R == 1) {
             // gathers first, the next loads while they are in flight, then the FMAs
@@ -412,9 +499,9 @@ __global__ __launch_bounds__(kTrsvThreads) __attribute__((amdgpu_waves_per_eu(1,
           // the end write to the dummy location).
           T res[R];
 #pragma unroll
-          for (int c = 0; c < R; ++c) res[c] = (prd[d][c] - octet_sum(acc[c] + acc2[c])) * pri[d].dinv;
+          for (int c = 0; c < R; ++c) res[c] = (prd[d][2 * c] - octet_sum(acc[c] + acc2[c])) * pri[d].dinv;
           const bool real = live && prow[d] >= 0;
-          T* gp = !real ? dummy
+          T* gp = !real ? dummy_l
                   : prow[d] < a.nrows ? out + (size_t)prow[d] * a.ld
                                       : reinterpret_cast<T*>(a.cpl) + (size_t)(prow[d] - a.nrows) * a.ld;
           if constexpr (R == 1) {
@@ -433,9 +520,9 @@ __global__ __launch_bounds__(kTrsvThreads) __attribute__((amdgpu_waves_per_eu(1,
           if (live) {
             if (q == 0 && prow[d] >= 0) {
 #pragma unroll
-              for (int c = 0; c < R; ++c) dotacc[c] += (double)res[c] * (double)prd[d][R + c];
+              for (int c = 0; c < R; ++c) dotacc[c] += (double)res[c] * (double)prd[d][2 * c + 1];
             }
-            T* xp = xs + (size_t)pri[d].slot * R;
+            T* xp = reinterpret_cast<T*>(reinterpret_cast<unsigned char*>(xs) + (size_t)pri[d].slot * SB);
             if constexpr (R == 1) {
               xp[0] = res[0];
               lds_signal(&ctr[CTR_COMPUTED], k + 1);
@@ -509,7 +596,7 @@ __global__ __launch_bounds__(64 * (W + 1)) void k_trsv_cols(
   constexpr int G = RC / VN;  // 16-byte gathers per entry
   static_assert(G >= 1 && G * VN == RC && W * RC == R && W <= 8 && D >= 2, "column split");
   constexpr int NV = EP / VN;
-  constexpr int SH = __builtin_ctz(R * sizeof(T));  // slot id -> byte offset in xs
+  constexpr uint32_t SB = slot_bytes<T, R>();  // slot id -> byte offset in xs
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double sdot[R];
   if (skip != nullptr && *skip) return;
@@ -532,26 +619,33 @@ __global__ __launch_bounds__(64 * (W + 1)) void k_trsv_cols(
     // ------------------------------ compute waves -----------------------------
     const int cb = wid * RC;
     const int q = lane % kTrsvG;
+    // padding rows and steps past the end store to a word of the workgroup's own (64 words
+    // per workgroup, kTrsvDummyGroups blocks; the lanes of a wavefront share theirs):
+    // device-scope stores of many workgroups to one shared word serialise
+    T* const dummy_l = dummy + (size_t)(g % kTrsvDummyGroups) * 64;
     const int r = lane / kTrsvG;
-    double dotacc[RC];
-#pragma unroll
-    for (int c = 0; c < RC; ++c) dotacc[c] = 0.0;
+    // the octet's reduce-scatter leaves column cq of the row in this lane; the first of the
+    // 8 / RC lanes with that column (lead) writes its LDS slot entry and accumulates its dot
+    const int cq = octet_col<RC>(q);
+    const bool lead = (q & (kTrsvG / RC - 1)) == 0;
+    double dotacc = 0.0;
     // the group's entries per lane: 4, or the schedule's widest (EP)
     auto compute = [&](auto ep_c) {
     constexpr int EPX = decltype(ep_c)::value;
     constexpr int NVX = EPX / VN;
     constexpr int DX = EPX == EP ? D : cols_depth(G, EPX);
+    using P = typename Pair2<T>::type;
     V pv[DX][NVX];
     uint4 ps[DX][EPX / 4];
     typename RowRec<T>::type pri[DX];
-    V prh[DX][G], pdt[DX][G];  // right-hand side and dot-vector entries of this wave's columns
+    P prd[DX];  // {right-hand side, dot-vector entry} of this lane's column
     int prow[DX];
     int halo_seen = 0;
     const int64_t eoff = a.grp_eoff[g] - (int64_t)s0 * 64 * EPX;  // step ss at eoff + ss * 64 * EPX
     const T* sval_l = sval + eoff + (size_t)lane * EPX;
     const uint32_t* ssrc_l = a.ssrc + eoff + (size_t)lane * EPX;
     const typename RowRec<T>::type* sri_l = srinfo + r;
-    const T* rd_l = rd_s + (size_t)r * 2 * R + cb;
+    const T* rd_l = rd_s + ((size_t)r * R + cb + cq) * 2;
     const int32_t* srow_l = a.srow + r;
     auto load = [&](int d, int ss) {
       const V* vp = reinterpret_cast<const V*>(sval_l + (size_t)ss * 64 * EPX);
@@ -561,12 +655,7 @@ __global__ __launch_bounds__(64 * (W + 1)) void k_trsv_cols(
 #pragma unroll
       for (int k = 0; k < EPX / 4; ++k) ps[d][k] = sp[k];
       pri[d] = sri_l[(size_t)ss * kTrsvRPS];
-      const V* rp = reinterpret_cast<const V*>(rd_l + (size_t)ss * kTrsvRPS * 2 * R);
-#pragma unroll
-      for (int k = 0; k < G; ++k) {
-        prh[d][k] = rp[k];
-        pdt[d][k] = rp[R / VN + k];
-      }
+      prd[d] = *reinterpret_cast<const P*>(rd_l + (size_t)ss * kTrsvRPS * 2 * R);
       prow[d] = srow_l[(size_t)ss * kTrsvRPS];
     };
     // The same software pipeline as the single-wave kernel: D register buffers, the loads
@@ -590,7 +679,7 @@ __global__ __launch_bounds__(64 * (W + 1)) void k_trsv_cols(
 #pragma unroll
           for (int e = 0; e < EPX; ++e) {
             const unsigned src = reinterpret_cast<const unsigned*>(&ps[d][e / 4])[e % 4];
-            const V* xp = reinterpret_cast<const V*>(reinterpret_cast<const unsigned char*>(xs + cb) + (src << SH));
+            const V* xp = reinterpret_cast<const V*>(reinterpret_cast<const unsigned char*>(xs + cb) + src * SB);
 #pragma unroll
             for (int k = 0; k < G; ++k) xv[e][k] = xp[k];
           }
@@ -612,34 +701,24 @@ __global__ __launch_bounds__(64 * (W + 1)) void k_trsv_cols(
                 acc[c] = fma(v, xe[c], acc[c]);
             }
           }
-          T res[RC];
-          const T* rh = reinterpret_cast<const T*>(&prh[d][0]);
+          T part[RC];
 #pragma unroll
-          for (int c = 0; c < RC; ++c) res[c] = (rh[c] - octet_sum(acc[c] + acc2[c])) * pri[d].dinv;
-          // lane q of the octet stores column q % RC of the row (RC <= 8 lanes; lanes with
-          // the same column store the same value; padding rows and steps past the end store
-          // to the dummy location), so the store is issued on every path
+          for (int c = 0; c < RC; ++c) part[c] = acc[c] + acc2[c];
+          const T res = (prd[d].x - octet_reduce_scatter<T, RC>(part, q)) * pri[d].dinv;
+          // every lane stores its column (lanes with the same column store the same value;
+          // padding rows and steps past the end store to the dummy location), so the store
+          // is issued on every path
           static_assert(RC <= kTrsvG, "one column per lane of the octet");
           const bool real = live && prow[d] >= 0;
-          const int cq = q % RC;
-          T sv = res[0];
-#pragma unroll
-          for (int c = 1; c < RC; ++c)
-            if (cq == c) sv = res[c];
-          T* gp = !real ? dummy
+          T* gp = !real ? dummy_l + cb
                   : prow[d] < a.nrows ? out + (size_t)prow[d] * a.ld + cb + cq
                                       : reinterpret_cast<T*>(a.cpl) + (size_t)(prow[d] - a.nrows) * a.ld + cb + cq;
-          dev_store(gp, sv);
+          dev_store(gp, res);
           if (live) {
-            if (q == 0) {
-              if (prow[d] >= 0) {
-                const T* dt = reinterpret_cast<const T*>(&pdt[d][0]);
-#pragma unroll
-                for (int c = 0; c < RC; ++c) dotacc[c] += (double)res[c] * (double)dt[c];
-              }
-              T* xp = xs + (size_t)pri[d].slot * R + cb;
-#pragma unroll
-              for (int c = 0; c < RC; ++c) xp[c] = res[c];
+            if (lead) {
+              if (prow[d] >= 0) dotacc += (double)res * (double)prd[d].y;
+              T* xp = reinterpret_cast<T*>(reinterpret_cast<unsigned char*>(xs) + (size_t)pri[d].slot * SB) + cb;
+              xp[cq] = res;
             }
             if (lane == 0) lds_signal(&ctr[CTR_WAVE0 + wid], k + 1);
           }
@@ -655,7 +734,7 @@ __global__ __launch_bounds__(64 * (W + 1)) void k_trsv_cols(
     if (with_dot) {
 #pragma unroll
       for (int c = 0; c < RC; ++c) {
-        double v = dotacc[c];
+        double v = (lead && cq == c) ? dotacc : 0.0;
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
         if (lane == 0) sdot[cb + c] = v;
@@ -1029,9 +1108,9 @@ static hipError_t launch_trsv_fast(const TrsvSchedDev& S, const T* rhs, T* out, 
   return e;
 }
 
-// Per-solve gather into schedule order, rd_s[(step*RPS + r)*2R + c] = rhs[row*ld + c] and
-// rd_s[... + R + c] = dotv[row*ld + c] (0 without a dot vector), and the output rows reset
-// to the sentinel (R columns of a batch of width ld; the pointers carry the column offset).
+// Per-solve gather into schedule order, rd_s[((step*RPS + r)*R + c)*2] = rhs[row*ld + c] and
+// rd_s[... + 1] = dotv[row*ld + c] (0 without a dot vector), and the output rows reset to
+// the sentinel (R columns of a batch of width ld; the pointers carry the column offset).
 template <typename T, int R>
 __global__ void k_trsv_gather_rhs(int64_t nrow_slots, const int32_t* __restrict__ srow, const T* __restrict__ rhs,
                                   const T* __restrict__ dotv, int ld, T* __restrict__ rd_s, T* __restrict__ out,
@@ -1044,8 +1123,8 @@ __global__ void k_trsv_gather_rhs(int64_t nrow_slots, const int32_t* __restrict_
     const int row = srow[k];
     // coupling rows (row >= nrows): right-hand side and dot entry 0, output in cpl
     const bool own = row >= 0 && row < nrows;
-    rd_s[k * 2 * R + c] = own ? rhs[(size_t)row * ld + c] : T(0);
-    rd_s[k * 2 * R + R + c] = (own && dotv != nullptr) ? dotv[(size_t)row * ld + c] : T(0);
+    rd_s[(k * R + c) * 2] = own ? rhs[(size_t)row * ld + c] : T(0);
+    rd_s[(k * R + c) * 2 + 1] = (own && dotv != nullptr) ? dotv[(size_t)row * ld + c] : T(0);
     if (own)
       out[(size_t)row * ld + c] = sentinel_value<T>();
     else if (row >= nrows)
@@ -1058,7 +1137,7 @@ __global__ void k_trsv_gather_rhs(int64_t nrow_slots, const int32_t* __restrict_
 // ---------------------------------------------------------------------------
 template <typename T, int R>
 size_t trsv_shmem_t(int nslots) {
-  return 64 + (size_t)(nslots + 1) * R * sizeof(T);
+  return 64 + (size_t)(nslots + 1) * slot_bytes<T, R>();
 }
 
 size_t trsv_shmem_bytes(int nslots, bool fp32, int R) {

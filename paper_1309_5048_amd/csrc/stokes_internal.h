@@ -60,6 +60,7 @@ constexpr int kTrsvG = 8;                  // lanes per row
 constexpr int kTrsvRPS = 64 / kTrsvG;      // rows per step (one compute wave)
 constexpr int kTrsvThreads = 128;          // compute wavefront + halo wavefront
 constexpr int kTrsvHaloLookahead = 16;     // steps before first use a halo slot is allocated
+constexpr int kTrsvDummyGroups = 256;      // workgroups with their own padding-store words
 constexpr int kLevelStride = 1 << 21;      // progress value = epoch * stride + level + 1
 
 #ifndef STOKES_TRSV_HELPERS
@@ -206,7 +207,7 @@ struct TrsvSchedDev {
   TrsvRow64* srinfo = nullptr;     // [nsteps*RPS]
   TrsvRow32* srinfo32 = nullptr;
   void* rhs_s = nullptr;           // rhs and dot vector in schedule order ([row slot][2][R_max] doubles)
-  void* dummy = nullptr;           // target of the stores of padding rows (64 doubles)
+  void* dummy = nullptr;           // targets of the stores of padding rows ([kTrsvDummyGroups][64] doubles)
   unsigned long long* progress = nullptr;  // [ngroups]
   unsigned long long* epoch = nullptr;     // [1]
   unsigned int* done_count = nullptr;      // [1]
