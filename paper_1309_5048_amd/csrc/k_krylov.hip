@@ -125,12 +125,50 @@ __device__ __forceinline__ void row_chunk(int32_t k0, int32_t ke, const int32_t*
   }
 }
 
+// Reduce-scatter of R = 8 or 16 columns over a row's kSG = 16 lanes: lane sub ends with the
+// group's total of column scatter_col<R>(sub).  Each stage halves the columns a lane keeps
+// (it keeps one half and adds the half its partner sends: mirror inside the row, mirror
+// inside the half row, xor 2, xor 1); with 8 columns the last stage is a plain sum, so
+// lanes sub and sub ^ 1 hold the same column.
+template <int R>
+__device__ __forceinline__ int scatter_col(int sub) {
+  return (sub >= 8 ? R / 2 : 0) + ((sub & 7) >= 4 ? R / 4 : 0) + (((sub >> 1) & 1) ? R / 8 : 0) +
+         ((sub & 1) ? R / 16 : 0);
+}
+template <int K, int CTRL, typename T>
+__device__ __forceinline__ void scatter_stage(const T (&v)[2 * K], T (&o)[K], bool hi) {
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    const T keep = hi ? v[K + i] : v[i];
+    const T send = hi ? v[i] : v[K + i];
+    o[i] = keep + dpp_mov_any<CTRL>(send);
+  }
+}
+template <int R, typename T>
+__device__ __forceinline__ T group_scatter(const T (&v)[R], int sub) {
+  static_assert(kSG == 16 && (R == 8 || R == 16), "16 lanes, 8 or 16 columns");
+  T a[R / 2], b[R / 4], c[R / 8];
+  scatter_stage<R / 2, 0x140>(v, a, sub >= 8);
+  scatter_stage<R / 4, 0x141>(a, b, (sub & 7) >= 4);
+  scatter_stage<R / 8, 0x4E>(b, c, ((sub >> 1) & 1) != 0);
+  if constexpr (R == 16) {
+    T d[1];
+    scatter_stage<1, 0xB1>(c, d, (sub & 1) != 0);
+    return d[0];
+  } else {
+    return c[0] + dpp_mov_any<0xB1>(c[0]);
+  }
+}
+
 // All rows of this block (entries rowptr[i] .. rowend[i]-1, or rowptr[i+1]-1 without
 // rowend), kSG lanes per row and spmv_rows_per_group rows per lane group.  The rows' entry
 // ranges are staged in LDS kStageRows at a time; the first chunk of every row of a pass is
 // loaded together (one row chunk for each of the group's rows), longer rows continue row
-// by row.  fin(i, acc) runs on lane 0 of the row's lane group with the row's sums.
-template <int R, bool NT, typename Acc, typename T, typename Fin>
+// by row.  fin(i, acc) runs on lane 0 of the row's lane group with the row's sums; with kRS
+// (R = 8 or 16) the group's lanes reduce-scatter the sums instead and fin(i, v, c) runs on
+// every lane of the group with column c's sum v (lanes holding the same column call it
+// with the same value).
+template <int R, bool NT, typename Acc, bool kRS = false, typename T, typename Fin>
 __device__ __forceinline__ void csr_rows(const int32_t* __restrict__ split, const int32_t* __restrict__ rowptr,
                                          const int32_t* __restrict__ rowend, const int32_t* __restrict__ col,
                                          const T* __restrict__ val, const T* __restrict__ x, Fin fin) {
@@ -194,10 +232,15 @@ __device__ __forceinline__ void csr_rows(const int32_t* __restrict__ split, cons
         for (int32_t k0 = kb[q] + sub + U * kSG; k0 < ke[q]; k0 += U * kSG) row_chunk<R, U, NT>(k0, ke[q], col, val, x, acc[q]);
 #pragma unroll
       for (int q = 0; q < RPG; ++q) {
-#pragma unroll
-        for (int c = 0; c < R; ++c) acc[q][c] = group_sum<kSG>(acc[q][c]);
         const int t = base + q * G + grp;
-        if (t < nrow && sub == 0) fin(c0 + t, acc[q]);
+        if constexpr (kRS) {
+          const Acc v = group_scatter<R>(acc[q], sub);
+          if (t < nrow) fin(c0 + t, v, scatter_col<R>(sub));
+        } else {
+#pragma unroll
+          for (int c = 0; c < R; ++c) acc[q][c] = group_sum<kSG>(acc[q][c]);
+          if (t < nrow && sub == 0) fin(c0 + t, acc[q]);
+        }
       }
     }
     __syncthreads();
@@ -306,6 +349,26 @@ __global__ __launch_bounds__(kVT) void k_mr_spmv(const int32_t* __restrict__ spl
                                                  const int32_t* __restrict__ col, const T* __restrict__ val,
                                                  const T* __restrict__ z, T* __restrict__ q, MrScalars s, int p) {
   if (s.alldone[p]) return;
+  if constexpr (R > 1) {
+    // the row's sums reduce-scattered over its 16 lanes: each lane finishes one column
+    const int sub = threadIdx.x & (kSG - 1);
+    const int cs = scatter_col<R>(sub);
+    const bool lead = R == kSG || (sub & 1) == 0;  // one lane per column adds to the dot
+    const MinresState& stc = s.st[p * kRMax + cs];
+    const double igc = (stc.done || stc.gamma == 0.0) ? 0.0 : 1.0 / stc.gamma;
+    double ad = 0.0;
+    csr_rows<R, NT, T, true>(split, rowptr, nullptr, col, val, z, [&](int64_t i, T acc, int c) {
+      const size_t k = (size_t)i * R + c;
+      const T qv = T((double)acc * igc);
+      if (lead) ad += (double)qv * (double)z[k] * igc;
+      q[k] = qv;
+    });
+    double acc_d[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) acc_d[k] = k == cs ? ad : 0.0;
+    reduce_last<R>(acc_d, s.partials, s.counter, [&](int k, double v) { red_at(s, p, RED_DELTA)[k] = v; });
+    return;
+  }
   double ig[R];
 #pragma unroll
   for (int c = 0; c < R; ++c) {
@@ -339,6 +402,43 @@ __global__ __launch_bounds__(kVT) void k_mr_lanczos(int64_t n, int64_t n_u, cons
                                                     const double* __restrict__ diagA, double two_nu, MrScalars s,
                                                     int p) {
   if (s.alldone[p]) return;
+  if constexpr (R > 1) {
+    // one vector element (row i, column c) per thread: the grid stride is a multiple of R,
+    // so a thread keeps its column and the loads of a wavefront are contiguous
+    const int c = threadIdx.x % R;
+    const MinresState& st = s.st[p * kRMax + c];
+    const bool live = !st.done;
+    const double ca = live ? red_at(s, p, RED_DELTA)[c] / st.gamma : 0.0;
+    const double cb = live ? st.gamma / st.gamma_prev : 0.0;
+    double ap = 0.0, au = 0.0;
+    if (live)
+      for (int64_t k = blockIdx.x * (int64_t)kVT + threadIdx.x; k < n * R; k += (int64_t)gridDim.x * kVT) {
+        const int64_t i = k / R;
+        const double vn = (double)q[k] - ca * (double)v[k] - cb * (double)vprev_next[k];
+        const T vnt = T(vn);
+        vprev_next[k] = vnt;
+        if (i >= n_u) {
+          const T zv = T(two_nu * (double)vnt / diagQ[i - n_u]);
+          znext[k] = zv;
+          ap += (double)vnt * (double)zv;
+        } else if (diagA != nullptr) {
+          const T zv = T((double)vnt / diagA[i]);
+          znext[k] = zv;
+          au += (double)vnt * (double)zv;
+        }
+      }
+    double acc[2 * R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      acc[k] = k == c ? ap : 0.0;
+      acc[R + k] = k == c ? au : 0.0;
+    }
+    reduce_last<2 * R>(acc, s.partials, s.counter, [&](int k, double val) {
+      if (k < R) red_at(s, p, RED_G2P)[k] = val;
+      else if (diagA != nullptr) red_at(s, p, RED_G2U)[k - R] = val;
+    });
+    return;
+  }
   double ca[R], cb[R];
   bool live[R];
 #pragma unroll
@@ -421,24 +521,29 @@ __global__ __launch_bounds__(kVT) void k_mr_update(int64_t n, const T* __restric
     }
     return;
   }
-  Givens G[R];
-  double ig[R];
-#pragma unroll
-  for (int c = 0; c < R; ++c) {
+  if constexpr (R > 1) {
+    // one vector element per thread (the grid stride is a multiple of R: a thread keeps
+    // its column)
+    const int c = threadIdx.x % R;
     const MinresState& st = s.st[p * kRMax + c];
-    const double g2 = red_at(s, p, RED_G2P)[c] + red_at(s, p, RED_G2U)[c];
-    G[c] = givens_step(st, red_at(s, p, RED_DELTA)[c], g2);
-    ig[c] = G[c].live ? 1.0 / st.gamma : 0.0;
-  }
-  for (int64_t i = blockIdx.x * (int64_t)kVT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVT) {
-#pragma unroll
-    for (int c = 0; c < R; ++c) {
-      if (!G[c].live) continue;
-      const size_t k = (size_t)i * R + c;
-      const double wn = ((double)z[k] * ig[c] - G[c].a3 * (double)wprev_new[k] - G[c].a2 * (double)w[k]) / G[c].a1;
-      wprev_new[k] = T(wn);
-      x[k] = T((double)x[k] + G[c].coef * wn);
-    }
+    const Givens G = givens_step(st, red_at(s, p, RED_DELTA)[c], red_at(s, p, RED_G2P)[c] + red_at(s, p, RED_G2U)[c]);
+    const double ig = G.live ? 1.0 / st.gamma : 0.0;
+    if (G.live)
+      for (int64_t k = blockIdx.x * (int64_t)kVT + threadIdx.x; k < n * R; k += (int64_t)gridDim.x * kVT) {
+        const double wn = ((double)z[k] * ig - G.a3 * (double)wprev_new[k] - G.a2 * (double)w[k]) / G.a1;
+        wprev_new[k] = T(wn);
+        x[k] = T((double)x[k] + G.coef * wn);
+      }
+  } else {
+    const MinresState& st = s.st[p * kRMax];
+    const Givens G = givens_step(st, red_at(s, p, RED_DELTA)[0], red_at(s, p, RED_G2P)[0] + red_at(s, p, RED_G2U)[0]);
+    const double ig = G.live ? 1.0 / st.gamma : 0.0;
+    if (G.live)
+      for (int64_t i = blockIdx.x * (int64_t)kVT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVT) {
+        const double wn = ((double)z[i] * ig - G.a3 * (double)wprev_new[i] - G.a2 * (double)w[i]) / G.a1;
+        wprev_new[i] = T(wn);
+        x[i] = T((double)x[i] + G.coef * wn);
+      }
   }
   if (blockIdx.x == 0) {
     __shared__ int nd;
@@ -835,7 +940,7 @@ hipError_t mr_spmv(int R, const RowSplit& rs, const int32_t* rowptr, const int32
 template <typename T>
 hipError_t mr_lanczos(int R, int64_t n, int64_t n_u, const T* q, const T* v, T* vprev_next, T* znext, const double* diagQ,
                       const double* diagA, double two_nu, const MrScalars& s, int p, hipStream_t st) {
-  STK_R_SWITCH(R, hipLaunchKernelGGL((k_mr_lanczos<T, RR>), dim3(vec_blocks(n)), dim3(kVT), 0, st, n, n_u, q, v,
+  STK_R_SWITCH(R, hipLaunchKernelGGL((k_mr_lanczos<T, RR>), dim3(vec_blocks(n * RR)), dim3(kVT), 0, st, n, n_u, q, v,
                                      vprev_next, znext, diagQ, diagA, two_nu, s, p));
   return hipGetLastError();
 }
@@ -843,7 +948,7 @@ hipError_t mr_lanczos(int R, int64_t n, int64_t n_u, const T* q, const T* v, T* 
 template <typename T>
 hipError_t mr_update(int R, int64_t n, const T* z, const T* w, T* wprev_new, T* x, const MrScalars& s, int p,
                      hipStream_t st) {
-  STK_R_SWITCH(R, hipLaunchKernelGGL((k_mr_update<T, RR>), dim3(vec_blocks_plain(n)), dim3(kVT), 0, st, n, z, w, wprev_new, x,
+  STK_R_SWITCH(R, hipLaunchKernelGGL((k_mr_update<T, RR>), dim3(vec_blocks_plain(n * RR)), dim3(kVT), 0, st, n, z, w, wprev_new, x,
                                      s, p));
   return hipGetLastError();
 }
