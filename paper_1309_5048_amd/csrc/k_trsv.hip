@@ -1184,12 +1184,12 @@ static hipError_t launch_trsv_t(const TrsvSchedDev& S, const T* sval, const type
   hipLaunchKernelGGL((k_trsv_gather_rhs<T, R>), dim3(1024), dim3(256), 0, st, nrow_slots, S.srow, rhs, dotv, ld,
                      rd_s, out, cpl, S.nrows, skip);
   const size_t shmem = trsv_shmem_t<T, R>(S.nslots);
-  // R >= 8 and at most 8 entries per lane (2D): the columns split over W compute wavefronts
-  // of RC = max(16 bytes, R / 4) columns each (4 waves for R = 16, 4 or 2 for R = 8), with a
-  // prefetch depth that keeps the step buffers in the 256 registers two waves per SIMD
-  // allow.  Longer rows (3D) keep one compute wavefront: there the split's shallow prefetch
-  // measured slower (3D, N = 32, k' = 1, R = 8: 1.57 ms against 1.28 ms per launch).
-  constexpr int RC = R / 4 > Vec16<T>::n ? R / 4 : Vec16<T>::n;
+  // R >= 8 and at most 8 entries per lane (coupled schedules, 2D and 3D): the columns split
+  // over W = 2 compute wavefronts of RC = R / 2 columns each (every wave reads the step's
+  // records, so fewer waves read fewer bytes; 4 waves of R / 4 columns measured 2-8 %
+  // slower, 8 waves of 2 columns 3.5x slower), with a prefetch depth that keeps the step
+  // buffers in 256 registers.  Rows with more entries per lane keep one compute wavefront.
+  constexpr int RC = R / 2 > Vec16<T>::n ? R / 2 : Vec16<T>::n;
   constexpr int W = (R >= 8 && EP <= 8) ? R / RC : 0;
   constexpr int GC = RC / Vec16<T>::n;
   constexpr int DC = cols_depth(GC, EP);
