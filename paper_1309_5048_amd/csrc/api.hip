@@ -645,7 +645,8 @@ int make_schedule(stokes_problem* pb, FactorSched& fs, bool fp32, SchedPair** ou
         if (r == 0) return 0;
         const size_t sh = trsv_shmem_bytes(nsl, f32, r);
         int per_cu = int(std::max<size_t>(1, std::min<size_t>(8, pb->lds_per_cu / std::max<size_t>(sh, 1))));
-        // the batched kernels' blocks (five wavefronts of up to 256 registers) fit once per CU
+        // the batched kernels' blocks (up to five wavefronts of up to 256 registers) are
+        // counted once per CU
         if (r >= 8) per_cu = 1;
         if (ng <= per_cu * pb->num_cu) return r;
         return (r >= 8 && ng <= pb->num_cu * 8) ? 1 : 0;  // then single columns only
