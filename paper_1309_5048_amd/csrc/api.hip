@@ -552,7 +552,7 @@ int upload_schedule(stokes_problem* pb, const TrsvSchedHost& H, TrsvSchedDev& D,
   D.dummy = m.get<double>((size_t)kTrsvDummyGroups * 64);
   D.progress = m.get<unsigned long long>(H.ngroups);
   D.epoch = m.get<unsigned long long>(1);
-  D.done_count = m.get<unsigned int>(1);
+  D.done_count = m.get<unsigned int>(2);  // one ticket per column block of a launch
   D.err = m.get<int>(1);
   D.partials = m.get<double>(size_t(H.ngroups) * kRMax);
   D.ncpl = int(H.ncpl);
@@ -561,7 +561,7 @@ int upload_schedule(stokes_problem* pb, const TrsvSchedHost& H, TrsvSchedDev& D,
   if (m.err != hipSuccess) return fail_hip(pb, m.err, "schedule upload", __LINE__);
   CK(hipMemsetAsync(D.progress, 0, sizeof(unsigned long long) * H.ngroups, st));
   CK(hipMemsetAsync(D.epoch, 0, sizeof(unsigned long long), st));
-  CK(hipMemsetAsync(D.done_count, 0, sizeof(unsigned int), st));
+  CK(hipMemsetAsync(D.done_count, 0, 2 * sizeof(unsigned int), st));
   CK(hipMemsetAsync(D.err, 0, sizeof(int), st));
   CK(hipStreamSynchronize(st));  // host vectors must outlive the asynchronous copies
   int rc = build_fast_layout(pb, H, D, nrows, nnzL);

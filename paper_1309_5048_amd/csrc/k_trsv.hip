@@ -45,6 +45,7 @@ struct TrsvArgs {
   int ld;  // row stride of out (the full batch width; R columns are solved per launch)
   void* cpl;  // coupling rows' values (rows nrows .., same stride and column offset as out)
   int ncpl;
+  int64_t nrow_slots;  // steps x kTrsvRPS: one column block's share of the gathered {rhs, dot} pairs
 };
 
 // Output sentinel (signalling NaN) and its test, on the bit patterns.
@@ -246,14 +247,23 @@ __device__ __forceinline__ int computed_steps(int* ctr) {
   }
 }
 
-// Bytes between consecutive LDS slots of an R-column batch.  R > 1 pads each slot by 16
-// bytes: with power-of-two slot sizes every lane of a column block reads the same few LDS
-// banks (the slot's low bits select nothing), with the pad consecutive slots start 4 banks
-// apart and the gathers of up to 16 different slots are conflict-free.
+// LDS slot addresses of an R-column batch.  With power-of-two slot sizes every lane of a
+// column block would read the same few LDS banks (the slot's low bits select nothing), so
+// a 16-byte pad follows every 2^ps slots: ps = 0 (every slot; the default) or kCompact
+// (every 256 / (R sizeof(T)) slots, about 6 % more LDS instead of 12-25 %, so that two
+// workgroups fit one CU).  Either way the gathers of up to 16 different slots spread over
+// all banks.
 template <typename T, int R>
-__host__ __device__ constexpr uint32_t slot_bytes() {
-  return R == 1 ? (uint32_t)sizeof(T) : (uint32_t)(R * sizeof(T) + 16);
-}
+struct SlotLayout {
+  static constexpr uint32_t kRow = (uint32_t)(R * sizeof(T));
+  static constexpr int kCompact = R == 1 ? 0 : __builtin_ctz(256u / kRow);
+  __host__ __device__ static constexpr uint32_t addr(uint32_t slot, int ps) {
+    return R == 1 ? slot * kRow : slot * kRow + (slot >> ps) * 16u;
+  }
+  __host__ __device__ static constexpr size_t bytes(int nslots, int ps) {
+    return (size_t)addr((uint32_t)nslots + 1u, ps) + 16u;
+  }
+};
 
 // Rows nrows .. nrows + ncpl - 1 are coupling rows, read from cpl (R = 1 layouts only).
 template <typename T, int R, int NW = 0>
@@ -261,7 +271,7 @@ __device__ __forceinline__ void halo_wave(const int32_t* __restrict__ grp_halo_p
                                           const int32_t* __restrict__ halo_slot,
                                           const int32_t* __restrict__ halo_free, int nrows, int nslots, int ld,
                                           int* err, int g, int lane, int* ctr, T* xs, const T* out,
-                                          const T* cpl = nullptr, int ncpl = 0) {
+                                          const T* cpl = nullptr, int ncpl = 0, int pad_shift = 0) {
   const int h0 = grp_halo_ptr[g], h1 = grp_halo_ptr[g + 1];
   const int nhalo = h1 - h0;
   int pos = 0;
@@ -317,7 +327,7 @@ __device__ __forceinline__ void halo_wave(const int32_t* __restrict__ grp_halo_p
       continue;
     }
     if (lane < count && inb) {
-      T* xp = reinterpret_cast<T*>(reinterpret_cast<unsigned char*>(xs) + (size_t)slot * slot_bytes<T, R>());
+      T* xp = reinterpret_cast<T*>(reinterpret_cast<unsigned char*>(xs) + SlotLayout<T, R>::addr((uint32_t)slot, pad_shift));
 #pragma unroll
       for (int c = 0; c < R; ++c) xp[c] = v[c];
     }
@@ -367,7 +377,7 @@ __global__ __launch_bounds__(kTrsvThreads) __attribute__((amdgpu_waves_per_eu(1,
   using V = typename Vec16<T>::type;
   constexpr int VN = Vec16<T>::n;
   constexpr int NV = EP / VN;  // vector loads of factor values per lane and step
-  constexpr uint32_t SB = slot_bytes<T, R>();  // slot id -> byte offset in xs
+  using SL = SlotLayout<T, R>;  // slot id -> byte offset in xs
   extern __shared__ __align__(16) unsigned char smem[];
   if (skip != nullptr && *skip) return;
   int* ctr = reinterpret_cast<int*>(smem);
@@ -457,7 +467,7 @@ __global__ __launch_bounds__(kTrsvThreads) __attribute__((amdgpu_waves_per_eu(1,
           for (int c = 0; c < R; ++c) acc[c] = acc2[c] = T(0);
           auto xaddr = [&](int e) {
             const unsigned src = reinterpret_cast<const unsigned*>(&ps[d][e / 4])[e % 4];
-            return reinterpret_cast<const T*>(reinterpret_cast<const unsigned char*>(xs) + src * SB);
+            return reinterpret_cast<const T*>(reinterpret_cast<const unsigned char*>(xs) + SL::addr(src, 0));
           };
           if constexpr (R == 1) {
             // gathers first, the next loads while they are in flight, then the FMAs
@@ -522,7 +532,7 @@ __global__ __launch_bounds__(kTrsvThreads) __attribute__((amdgpu_waves_per_eu(1,
 #pragma unroll
               for (int c = 0; c < R; ++c) dotacc[c] += (double)res[c] * (double)prd[d][2 * c + 1];
             }
-            T* xp = reinterpret_cast<T*>(reinterpret_cast<unsigned char*>(xs) + (size_t)pri[d].slot * SB);
+            T* xp = reinterpret_cast<T*>(reinterpret_cast<unsigned char*>(xs) + SL::addr((uint32_t)pri[d].slot, 0));
             if constexpr (R == 1) {
               xp[0] = res[0];
               lds_signal(&ctr[CTR_COMPUTED], k + 1);
@@ -546,7 +556,7 @@ __global__ __launch_bounds__(kTrsvThreads) __attribute__((amdgpu_waves_per_eu(1,
   } else {
     // ------------------------------- halo wave --------------------------------
     halo_wave<T, R>(a.grp_halo_ptr, a.halo_row, a.halo_slot, a.halo_free, a.nrows, a.nslots, a.ld, a.err, g, lane,
-                    ctr, xs, out, reinterpret_cast<const T*>(a.cpl), a.ncpl);
+                    ctr, xs, out, reinterpret_cast<const T*>(a.cpl), a.ncpl, 0);
   }
   __syncthreads();
   if (tid == 0 && lds_load(&ctr[CTR_ERR]) != 0) raise_err(a.err);
@@ -585,7 +595,7 @@ __global__ __launch_bounds__(kTrsvThreads) __attribute__((amdgpu_waves_per_eu(1,
 // compute wave has finished the steps that read its previous occupant (least of the
 // per-wave counters).
 // ---------------------------------------------------------------------------
-template <typename T, int R, int EP, int D, int W>
+template <typename T, int R, int EP, int D, int W, int PS>
 __global__ __launch_bounds__(64 * (W + 1)) void k_trsv_cols(
     TrsvArgs a, const T* __restrict__ sval, const typename RowRec<T>::type* __restrict__ srinfo,
     const T* __restrict__ rd_s, T* __restrict__ out, T* __restrict__ dummy, int with_dot,
@@ -596,14 +606,24 @@ __global__ __launch_bounds__(64 * (W + 1)) void k_trsv_cols(
   constexpr int G = RC / VN;  // 16-byte gathers per entry
   static_assert(G >= 1 && G * VN == RC && W * RC == R && W <= 8 && D >= 2, "column split");
   constexpr int NV = EP / VN;
-  constexpr uint32_t SB = slot_bytes<T, R>();  // slot id -> byte offset in xs
+  using SL = SlotLayout<T, R>;  // slot id -> byte offset in xs
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double sdot[R];
   if (skip != nullptr && *skip) return;
   int* ctr = reinterpret_cast<int*>(smem);
   T* xs = reinterpret_cast<T*>(smem + 64);
 
-  const int g = blockIdx.x;
+  // The launch may hold several column blocks of R columns each (a wide batch solved as
+  // independent R-column solves side by side): block b is group b % ngroups of column
+  // block b / ngroups, with its own columns, gathered pairs, dot partials and ticket.
+  const int g = blockIdx.x % a.ngroups;
+  const int hc = blockIdx.x / a.ngroups;
+  out += (size_t)hc * R;
+  rd_s += (size_t)hc * a.nrow_slots * 2 * R;
+  T* const cplh = reinterpret_cast<T*>(a.cpl) + (size_t)hc * R;
+  double* const partials_h = a.partials + (size_t)hc * a.ngroups * R;
+  unsigned int* const done_h = a.done_count + hc;
+  if (dot_out != nullptr) dot_out += hc * R;
   const int tid = threadIdx.x;
   const int wid = tid >> 6;
   const int lane = tid & 63;
@@ -622,7 +642,7 @@ __global__ __launch_bounds__(64 * (W + 1)) void k_trsv_cols(
     // padding rows and steps past the end store to a word of the workgroup's own (64 words
     // per workgroup, kTrsvDummyGroups blocks; the lanes of a wavefront share theirs):
     // device-scope stores of many workgroups to one shared word serialise
-    T* const dummy_l = dummy + (size_t)(g % kTrsvDummyGroups) * 64;
+    T* const dummy_l = dummy + (size_t)(blockIdx.x % kTrsvDummyGroups) * 64;
     const int r = lane / kTrsvG;
     // the octet's reduce-scatter leaves column cq of the row in this lane; the first of the
     // 8 / RC lanes with that column (lead) writes its LDS slot entry and accumulates its dot
@@ -679,7 +699,7 @@ __global__ __launch_bounds__(64 * (W + 1)) void k_trsv_cols(
 #pragma unroll
           for (int e = 0; e < EPX; ++e) {
             const unsigned src = reinterpret_cast<const unsigned*>(&ps[d][e / 4])[e % 4];
-            const V* xp = reinterpret_cast<const V*>(reinterpret_cast<const unsigned char*>(xs + cb) + src * SB);
+            const V* xp = reinterpret_cast<const V*>(reinterpret_cast<const unsigned char*>(xs + cb) + SL::addr(src, PS));
 #pragma unroll
             for (int k = 0; k < G; ++k) xv[e][k] = xp[k];
           }
@@ -712,12 +732,12 @@ __global__ __launch_bounds__(64 * (W + 1)) void k_trsv_cols(
           const bool real = live && prow[d] >= 0;
           T* gp = !real ? dummy_l + cb
                   : prow[d] < a.nrows ? out + (size_t)prow[d] * a.ld + cb + cq
-                                      : reinterpret_cast<T*>(a.cpl) + (size_t)(prow[d] - a.nrows) * a.ld + cb + cq;
+                                      : cplh + (size_t)(prow[d] - a.nrows) * a.ld + cb + cq;
           dev_store(gp, res);
           if (live) {
             if (lead) {
               if (prow[d] >= 0) dotacc += (double)res * (double)prd[d].y;
-              T* xp = reinterpret_cast<T*>(reinterpret_cast<unsigned char*>(xs) + (size_t)pri[d].slot * SB) + cb;
+              T* xp = reinterpret_cast<T*>(reinterpret_cast<unsigned char*>(xs) + SL::addr((uint32_t)pri[d].slot, PS)) + cb;
               xp[cq] = res;
             }
             if (lane == 0) lds_signal(&ctr[CTR_WAVE0 + wid], k + 1);
@@ -743,7 +763,7 @@ __global__ __launch_bounds__(64 * (W + 1)) void k_trsv_cols(
   } else {
     // ------------------------------- halo wave --------------------------------
     halo_wave<T, R, W>(a.grp_halo_ptr, a.halo_row, a.halo_slot, a.halo_free, a.nrows, a.nslots, a.ld, a.err, g,
-                       lane, ctr, xs, out, reinterpret_cast<const T*>(a.cpl), a.ncpl);
+                       lane, ctr, xs, out, cplh, a.ncpl, PS);
   }
   __syncthreads();
   if (tid == 0 && lds_load(&ctr[CTR_ERR]) != 0) raise_err(a.err);
@@ -751,16 +771,16 @@ __global__ __launch_bounds__(64 * (W + 1)) void k_trsv_cols(
   // fused dot product: the group's partials of all R columns (device scope), then a ticket;
   // the last group adds the partials (last_group_sum)
   if (with_dot && wid == 0) {
-    if (lane < R) dev_store(a.partials + (size_t)g * R + lane, sdot[lane]);
+    if (lane < R) dev_store(partials_h + (size_t)g * R + lane, sdot[lane]);
     unsigned int prev = 0;
     if (lane == 0) {
       wait_vm_stores();
-      prev = __hip_atomic_fetch_add(a.done_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      prev = __hip_atomic_fetch_add(done_h, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     prev = (unsigned int)__shfl((int)prev, 0, 64);
     if (prev == (unsigned int)(a.ngroups - 1)) {
-      last_group_sum<R>(a.partials, a.ngroups, dot_out, lane);
-      if (lane == 0) __hip_atomic_store(a.done_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      last_group_sum<R>(partials_h, a.ngroups, dot_out, lane);
+      if (lane == 0) __hip_atomic_store(done_h, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 }
@@ -1068,7 +1088,7 @@ __global__ void k_fast_gather_static(int64_t nsteps, const int64_t* __restrict__
 }
 
 template <typename T, int R>
-size_t trsv_shmem_t(int nslots);
+size_t trsv_shmem_t(int nslots, bool compact = false);
 
 template <typename T>
 static hipError_t launch_trsv_fast(const TrsvSchedDev& S, const T* rhs, T* out, const T* dotv, double* dot_out,
@@ -1136,29 +1156,31 @@ __global__ void k_trsv_gather_rhs(int64_t nrow_slots, const int32_t* __restrict_
 // Host launchers.
 // ---------------------------------------------------------------------------
 template <typename T, int R>
-size_t trsv_shmem_t(int nslots) {
-  return 64 + (size_t)(nslots + 1) * slot_bytes<T, R>();
+size_t trsv_shmem_t(int nslots, bool compact) {
+  return 64 + SlotLayout<T, R>::bytes(nslots, compact ? SlotLayout<T, R>::kCompact : 0);
 }
 
-size_t trsv_shmem_bytes(int nslots, bool fp32, int R) {
+size_t trsv_shmem_bytes(int nslots, bool fp32, int R, bool compact) {
   if (fp32) {
     switch (R) {
-      case 1: return trsv_shmem_t<float, 1>(nslots);
-      case 8: return trsv_shmem_t<float, 8>(nslots);
-      default: return trsv_shmem_t<float, 16>(nslots);
+      case 1: return trsv_shmem_t<float, 1>(nslots, compact);
+      case 8: return trsv_shmem_t<float, 8>(nslots, compact);
+      default: return trsv_shmem_t<float, 16>(nslots, compact);
     }
   }
   switch (R) {
-    case 1: return trsv_shmem_t<double, 1>(nslots);
-    case 8: return trsv_shmem_t<double, 8>(nslots);
-    default: return trsv_shmem_t<double, 16>(nslots);
+    case 1: return trsv_shmem_t<double, 1>(nslots, compact);
+    case 8: return trsv_shmem_t<double, 8>(nslots, compact);
+    default: return trsv_shmem_t<double, 16>(nslots, compact);
   }
 }
 
+// H column blocks of R columns each in one launch (H > 1: column-split kernel only; the
+// blocks' groups must all be resident, which the caller has checked).
 template <typename T, int R, int EP, int D>
 static hipError_t launch_trsv_t(const TrsvSchedDev& S, const T* sval, const typename RowRec<T>::type* srinfo,
                                 const T* rhs, T* out, T* cpl, const T* dotv, double* dot_out, int ld, const int* skip,
-                                hipStream_t st, const TrsvTiming* tm) {
+                                hipStream_t st, const TrsvTiming* tm, int H) {
   TrsvArgs a;
   a.grp_step_ptr = S.grp_step_ptr;
   a.grp_ep = S.grp_ep;
@@ -1181,9 +1203,12 @@ static hipError_t launch_trsv_t(const TrsvSchedDev& S, const T* sval, const type
   T* rd_s = reinterpret_cast<T*>(S.rhs_s);
   T* dummy = reinterpret_cast<T*>(S.dummy);
   const int64_t nrow_slots = (int64_t)S.nsteps * kTrsvRPS;
-  hipLaunchKernelGGL((k_trsv_gather_rhs<T, R>), dim3(1024), dim3(256), 0, st, nrow_slots, S.srow, rhs, dotv, ld,
-                     rd_s, out, cpl, S.nrows, skip);
-  const size_t shmem = trsv_shmem_t<T, R>(S.nslots);
+  a.nrow_slots = nrow_slots;
+  for (int h = 0; h < H; ++h)
+    hipLaunchKernelGGL((k_trsv_gather_rhs<T, R>), dim3(1024), dim3(256), 0, st, nrow_slots, S.srow, rhs + h * R,
+                       dotv ? dotv + h * R : nullptr, ld, rd_s + (size_t)h * nrow_slots * 2 * R, out + h * R,
+                       cpl ? cpl + h * R : nullptr, S.nrows, skip);
+  const size_t shmem = trsv_shmem_t<T, R>(S.nslots, H > 1);
   // R >= 8 and at most 8 entries per lane (coupled schedules, 2D and 3D): the columns split
   // over W = 2 compute wavefronts of RC = R / 2 columns each (every wave reads the step's
   // records, so fewer waves read fewer bytes; 4 waves of R / 4 columns measured 2-8 %
@@ -1196,9 +1221,12 @@ static hipError_t launch_trsv_t(const TrsvSchedDev& S, const T* sval, const type
   const void* fn;
   int threads;
   if constexpr (W > 0) {
-    fn = (const void*)k_trsv_cols<T, R, EP, DC, W>;
+    // two workgroups per CU (H > 1) need the compact slot padding
+    fn = H > 1 ? (const void*)k_trsv_cols<T, R, EP, DC, W, SlotLayout<T, R>::kCompact>
+               : (const void*)k_trsv_cols<T, R, EP, DC, W, 0>;
     threads = 64 * (W + 1);
   } else {
+    if (H != 1) return hipErrorInvalidValue;
     fn = (const void*)k_trsv<T, R, EP, D>;
     threads = kTrsvThreads;
   }
@@ -1211,7 +1239,7 @@ static hipError_t launch_trsv_t(const TrsvSchedDev& S, const T* sval, const type
   // An ordinary launch: the host has checked that every group fits on the chip at once,
   // so all groups are dispatched together (a cooperative launch adds tens of microseconds
   // of queue synchronisation around the kernel and is not needed for that).
-  e = hipLaunchKernel(fn, dim3(S.ngroups), dim3(threads), args, shmem, st);
+  e = hipLaunchKernel(fn, dim3(S.ngroups * H), dim3(threads), args, shmem, st);
   if (tm && tm->after) (void)hipEventRecord(tm->after, st);
   return e;
 }
@@ -1219,17 +1247,19 @@ static hipError_t launch_trsv_t(const TrsvSchedDev& S, const T* sval, const type
 template <typename T, int R>
 static hipError_t launch_trsv_r(const TrsvSchedDev& S, const T* sval, const typename RowRec<T>::type* srinfo,
                                 const T* rhs, T* out, T* cpl, const T* dotv, double* dot_out, int ld, const int* skip,
-                                hipStream_t st, const TrsvTiming* tm) {
+                                hipStream_t st, const TrsvTiming* tm, int H) {
   switch (S.EP) {
-    case 4: return launch_trsv_t<T, R, 4, batch_depth(R, 4, sizeof(T))>(S, sval, srinfo, rhs, out, cpl, dotv, dot_out, ld, skip, st, tm);
-    case 8: return launch_trsv_t<T, R, 8, batch_depth(R, 8, sizeof(T))>(S, sval, srinfo, rhs, out, cpl, dotv, dot_out, ld, skip, st, tm);
-    case 12: return launch_trsv_t<T, R, 12, batch_depth(R, 12, sizeof(T))>(S, sval, srinfo, rhs, out, cpl, dotv, dot_out, ld, skip, st, tm);
-    case 16: return launch_trsv_t<T, R, 16, batch_depth(R, 16, sizeof(T))>(S, sval, srinfo, rhs, out, cpl, dotv, dot_out, ld, skip, st, tm);
+    case 4: return launch_trsv_t<T, R, 4, batch_depth(R, 4, sizeof(T))>(S, sval, srinfo, rhs, out, cpl, dotv, dot_out, ld, skip, st, tm, H);
+    case 8: return launch_trsv_t<T, R, 8, batch_depth(R, 8, sizeof(T))>(S, sval, srinfo, rhs, out, cpl, dotv, dot_out, ld, skip, st, tm, H);
+    case 12: return launch_trsv_t<T, R, 12, batch_depth(R, 12, sizeof(T))>(S, sval, srinfo, rhs, out, cpl, dotv, dot_out, ld, skip, st, tm, H);
+    case 16: return launch_trsv_t<T, R, 16, batch_depth(R, 16, sizeof(T))>(S, sval, srinfo, rhs, out, cpl, dotv, dot_out, ld, skip, st, tm, H);
   }
   return hipErrorInvalidValue;
 }
 
-// R columns in chunks of the widest width whose LDS slots fit (R, 8 or 1), one launch each.
+// R columns in chunks of the widest width whose LDS slots fit (R, 8 or 1), one launch each;
+// a 16-column batch whose 8-column blocks fit two workgroups per CU instead runs as one
+// launch of two 8-column blocks side by side (each step then carries half the columns).
 template <typename T>
 static hipError_t launch_trsv_p(const TrsvSchedDev& S, const T* sval, const typename RowRec<T>::type* srinfo, int R,
                                 const T* rhs, T* out, const T* dotv, double* dot_out, const int* skip, hipStream_t st,
@@ -1243,23 +1273,38 @@ static hipError_t launch_trsv_p(const TrsvSchedDev& S, const T* sval, const type
   while (Rc > 1 && (Rc > S.rmax || trsv_shmem_bytes(S.nslots, sizeof(T) == 4, Rc) + trsv_static_shmem(Rc) > (size_t)lds_max))
     Rc = Rc > 8 ? 8 : 1;
   if (R % Rc != 0) return hipErrorInvalidValue;
+  int H = 1;
+  if (Rc == 16 && S.EP <= 8) {
+    int ncu = 0, lds_cu = 0;
+    e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
+    if (e != hipSuccess) return e;
+    const size_t lds8 = trsv_shmem_bytes(S.nslots, sizeof(T) == 4, 8, true) + trsv_static_shmem(8);
+    // two workgroups of three wavefronts (at most 256 registers each) per CU
+    const int per_cu = (int)std::min<size_t>(2, (size_t)lds_cu / lds8);
+    if (per_cu >= 2 && 2 * S.ngroups <= per_cu * ncu) {
+      Rc = 8;
+      H = 2;
+    }
+  }
   // coupling rows' values: [ncpl][R] in the schedule's buffer (sized for the widest batch)
   T* cpl = reinterpret_cast<T*>(S.cpl);
   if (S.ncpl > 0 && (cpl == nullptr || R > kRMax)) return hipErrorInvalidValue;
-  for (int c0 = 0; c0 < R; c0 += Rc) {
+  for (int c0 = 0; c0 < R; c0 += Rc * H) {
     // timing events: before the first chunk, after the last
     TrsvTiming t;
     if (tm != nullptr) {
       t.before = c0 == 0 ? tm->before : nullptr;
-      t.after = c0 + Rc >= R ? tm->after : nullptr;
+      t.after = c0 + Rc * H >= R ? tm->after : nullptr;
     }
     const T* dv = dotv ? dotv + c0 : nullptr;
     double* dout = dot_out ? dot_out + c0 : nullptr;
     T* cc = cpl ? cpl + c0 : nullptr;
     switch (Rc) {
-      case 1: e = launch_trsv_r<T, 1>(S, sval, srinfo, rhs + c0, out + c0, cc, dv, dout, R, skip, st, &t); break;
-      case 8: e = launch_trsv_r<T, 8>(S, sval, srinfo, rhs + c0, out + c0, cc, dv, dout, R, skip, st, &t); break;
-      case 16: e = launch_trsv_r<T, 16>(S, sval, srinfo, rhs + c0, out + c0, cc, dv, dout, R, skip, st, &t); break;
+      case 1: e = launch_trsv_r<T, 1>(S, sval, srinfo, rhs + c0, out + c0, cc, dv, dout, R, skip, st, &t, 1); break;
+      case 8: e = launch_trsv_r<T, 8>(S, sval, srinfo, rhs + c0, out + c0, cc, dv, dout, R, skip, st, &t, H); break;
+      case 16: e = launch_trsv_r<T, 16>(S, sval, srinfo, rhs + c0, out + c0, cc, dv, dout, R, skip, st, &t, 1); break;
       default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;

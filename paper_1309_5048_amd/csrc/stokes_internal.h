@@ -210,7 +210,7 @@ struct TrsvSchedDev {
   void* dummy = nullptr;           // targets of the stores of padding rows ([kTrsvDummyGroups][64] doubles)
   unsigned long long* progress = nullptr;  // [ngroups]
   unsigned long long* epoch = nullptr;     // [1]
-  unsigned int* done_count = nullptr;      // [1]
+  unsigned int* done_count = nullptr;      // [2]: one ticket per column block of a launch
   int* err = nullptr;                      // [1] spin-limit flag
   double* partials = nullptr;              // [ngroups * 16]
   void* cpl = nullptr;                     // [ncpl][kRMax] coupling rows' values (batched layout)
@@ -432,7 +432,7 @@ struct TrsvTiming {
 hipError_t launch_trsv(const TrsvSchedDev& S, bool fp32, int R, const void* rhs, void* out, const void* dotv,
                        double* dot_out, const int* skip, hipStream_t st, const TrsvTiming* tm = nullptr);
 hipError_t launch_trsv_gather(const TrsvSchedDev& S, const double* Lval, hipStream_t st);
-size_t trsv_shmem_bytes(int nslots, bool fp32, int R);
+size_t trsv_shmem_bytes(int nslots, bool fp32, int R, bool compact = false);
 // Static LDS of the solve kernels beside the dynamic part (the batched kernels' dot partials).
 inline size_t trsv_static_shmem(int R) { return R >= 8 ? 256 : 0; }
 
